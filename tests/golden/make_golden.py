@@ -1,0 +1,110 @@
+"""Writes tests/golden/tiny_exact.json: exact-rational results of one transfer step.
+
+The stored values are computed only by ``oracle/exact.py`` (exact rational
+arithmetic, normal-equation least squares, no orthogonality assumed).  The
+paper prints no worked numeric example, so these tiny hand-placed cases stand
+in for one; they cover the stencil offsets t = -1/2 (degenerate weights),
+t = 0 and t = 1/2 - 2^-20, unequal masses, and all four mode counts.
+
+Run:  python tests/golden/make_golden.py
+"""
+from __future__ import annotations
+
+import json
+import os
+import sys
+from fractions import Fraction as Fr
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+sys.path.insert(0, ROOT)
+
+from oracle import exact  # noqa: E402
+
+OUT = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tiny_exact.json")
+
+# grid: 4 cells per axis -> 8 nodes per axis, dx = 1/4, origin 0, domain [0.5, 1.5)
+NODES = (8, 8, 8)
+DX = Fr(1, 4)
+INV_DX = Fr(4)
+ORIGIN = (Fr(0), Fr(0), Fr(0))
+DT = Fr(1, 1024)
+GRAVITY = (Fr(0), Fr(-49, 5), Fr(0))
+BC_LAYERS = 1
+
+
+def particles():
+    """Six particles, positions given by their grid coordinate u (x = u * dx)."""
+    tiny = Fr(1, 2 ** 20)
+    us = [
+        (Fr(7, 2), Fr(4), Fr(9, 2) - tiny),          # t = (-1/2, 0, 1/2 - 2^-20)
+        (Fr(4) + Fr(3, 16), Fr(3) + Fr(5, 8), Fr(4) - Fr(1, 32)),
+        (Fr(3) + Fr(1, 2) + Fr(1, 64), Fr(7, 2), Fr(4) + Fr(7, 32)),   # t_y = -1/2
+        (Fr(4) + Fr(11, 32), Fr(4) + Fr(5, 16), Fr(3) + Fr(9, 16)),
+        (Fr(5) + Fr(1, 4), Fr(4) + Fr(15, 32), Fr(4) + Fr(3, 8)),
+        (Fr(2) + Fr(3, 8), Fr(5) + Fr(1, 2) - tiny, Fr(3) + Fr(1, 2)),  # near low x wall
+    ]
+    xs = [tuple(u * DX for u in p) for p in us]
+    masses = [Fr(1), Fr(3, 2), Fr(1), Fr(5, 4), Fr(1), Fr(3, 4)]
+    # dyadic coefficients: c[a][r] = small integers / 16, deterministic pattern
+    rng = np.random.default_rng(7)
+    coeffs = []
+    for _ in xs:
+        c = [[Fr(int(v), 16) for v in rng.integers(-24, 25, size=27)] for _ in range(3)]
+        coeffs.append(c)
+    return xs, masses, coeffs
+
+
+def fstr(v: Fr) -> str:
+    return f"{v.numerator}/{v.denominator}"
+
+
+def main():
+    xs, masses, coeffs = particles()
+    for x in xs:
+        for a in range(3):
+            assert Fr(float(np.float32(float(x[a])))) == x[a], "positions must be float32-exact"
+    cases = []
+    lo = [ORIGIN[a] + 2 * DX for a in range(3)]
+    for n_modes in (1, 4, 8, 27):
+        grid = exact.p2g(xs, ORIGIN, INV_DX, coeffs, masses, n_modes)
+        vel = exact.grid_update(grid, NODES, DT, GRAVITY, BC_LAYERS)
+        cs = exact.g2p(xs, ORIGIN, INV_DX, vel, n_modes)
+        x_out = []
+        for x, c in zip(xs, cs):
+            row = []
+            for a in range(3):
+                xn = exact.float32_round(x[a] + DT * c[a][0])
+                top = np.float32(float(ORIGIN[a] + (NODES[a] - 2) * DX))
+                hi = np.nextafter(top, np.float32(-np.inf))
+                xn = min(max(xn, np.float32(float(lo[a]))), hi)
+                row.append(float(xn))
+            x_out.append(row)
+        nodes = sorted(grid.keys())
+        cases.append(dict(
+            n_modes=n_modes,
+            nodes=[list(nd) for nd in nodes],
+            grid_mass=[fstr(grid[nd][0]) for nd in nodes],
+            grid_mom=[[fstr(v) for v in grid[nd][1]] for nd in nodes],
+            grid_vel=[[fstr(v) for v in vel[nd]] for nd in nodes],
+            coeff=[[[fstr(v) for v in c[a]] for a in range(3)] for c in cs],
+            x_out=x_out,
+        ))
+    doc = dict(
+        description="Exact-rational P2G -> grid update -> G2P on 6 hand-placed particles "
+                    "(written by tests/golden/make_golden.py from oracle/exact.py)",
+        nodes=list(NODES), dx=fstr(DX), inv_dx=fstr(INV_DX), origin=[fstr(o) for o in ORIGIN],
+        dt=fstr(DT), gravity=[fstr(g) for g in GRAVITY], bc_layers=BC_LAYERS,
+        x=[[fstr(v) for v in x] for x in xs],
+        mass=[fstr(m) for m in masses],
+        coeff_in=[[[fstr(v) for v in c[a]] for a in range(3)] for c in coeffs],
+        cases=cases,
+    )
+    with open(OUT, "w") as f:
+        json.dump(doc, f, indent=1)
+    print("wrote", OUT)
+
+
+if __name__ == "__main__":
+    main()
