@@ -1,0 +1,189 @@
+/*
+ * polypic.h -- C ABI of the PolyPIC transfer library for AMD Instinct MI355X (gfx950).
+ *
+ * The library implements the particle/grid transfers of the Polynomial
+ * Particle-in-Cell method as used for liquid and fabric in Dennison & Maddock,
+ * "Using The Polynomial Particle-in-Cell Method for Liquid-Fabric Interaction"
+ * (section 3): P2G (Eq. 1, 4, 13; Eq. 15-16 and 18-19 for the fluid and the
+ * solid-plus-absorbed-fluid sets), the grid velocity of Eq. 5 with a light
+ * explicit update, and G2P (Eq. 6-8 generalised to the weighted least-squares
+ * fit of the polynomial modes, section 3.3).  APIC (section 3.2) is the
+ * 4-mode case, PIC (section 3.1) the 1-mode case.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Memory      Every array argument is a DEVICE pointer owned by the caller.  The
+ *             library allocates no device memory; scratch comes from a caller
+ *             workspace whose size is queried first.  The polypic_grid struct
+ *             and the gravity vector are HOST pointers, read during the call.
+ * Streams     `stream` is a hipStream_t (NULL = the default stream).  Every
+ *             call only enqueues work on it and never synchronises; buffers must
+ *             stay alive until that work has completed.
+ * Status      Calls return POLYPIC_OK or a host-detected error code below; on an
+ *             error nothing is enqueued.  Conditions found on the device (a
+ *             particle whose stencil leaves the grid) are OR-ed as POLYPIC_FLAG_*
+ *             bits into the optional caller-owned `int32_t* status_dev` (device
+ *             memory, may be NULL); the offending particle is skipped, never
+ *             written out of bounds.  The library never aborts the process.
+ * Layouts     SoA float32.  Positions x[3][P] (all x, then all y, then all z).
+ *             Coefficients coeff[3][n_modes][P]: component a, mode r, particle p
+ *             at ((a * n_modes) + r) * P + p.  Grid arrays grid_mass[N] and
+ *             grid_mom[3][N] / grid_vel[3][N] with N = nx * ny * nz and node
+ *             (ix, iy, iz) at (iz * ny + iy) * nx + ix (x fastest).
+ *             Deformation gradients F[9][P], entry (a, b) of particle p at
+ *             (3a + b) * P + p.
+ * Grid        Collocated: node (ix, iy, iz) sits at origin + (ix, iy, iz) * dx.
+ *             The paper's runs use MAC grids (section 3); this library uses the
+ *             collocated form, where the per-face quantities of Table 1 become
+ *             per-node quantities.
+ * Stencil     Quadratic B-spline weights (section 3.1 leaves N(x) unnamed) over
+ *             the 3x3x3 nodes b, b+1, b+2 per axis, where, in float32 with
+ *             round-to-nearest and no contraction,
+ *                 u = (x - origin) * inv_dx,   b = floor(u - 1/2),   t = u - b - 1
+ *             (t in [-1/2, 1/2) is the offset from the nearest node b + 1).  A
+ *             particle is in range when 0 <= b <= n_axis - 3 on every axis.
+ * Modes       s_r = phi_kx(zx) phi_ky(zy) phi_kz(zz) evaluated at
+ *             z = (x_i - x_p) / dx (the particle's current position; the affine
+ *             map of Eq. 12 is not applied) with phi_0 = 1, phi_1 = z and
+ *             phi_2 = ghat(z) = z^2 - t (1 - 4 t^2) z - 1/4, the orthogonalised
+ *             quadratic of Eq. 14 in units of dx.  Mode order (r -> kx ky kz):
+ *               0:000  1:100  2:010  3:001  4:110  5:101  6:011  7:111
+ *               8:200  9:020 10:002 11:210 12:201 13:120 14:021 15:102 16:012
+ *              17:211 18:121 19:112 20:220 21:202 22:022 23:221 24:212 25:122
+ *              26:222
+ *             so n_modes = 1, 4, 8, 27 is PIC, APIC, multilinear (the paper's
+ *             8 modes, section 4) and the full quadratic basis.  Coefficients are
+ *             in these normalised units: mode 0 is the particle velocity, and
+ *             the APIC matrix of section 3.2 is C_ab = coeff[a][1 + b] / dx.
+ * Sizes       P <= 2^31 - 1 particles; 3 <= n_axis <= 1026 nodes per axis.
+ * Threads     All entry points are reentrant; calls on different streams may
+ *             run concurrently on disjoint outputs.
+ */
+#ifndef POLYPIC_H
+#define POLYPIC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes (return values) ---- */
+#define POLYPIC_OK 0
+#define POLYPIC_EINVAL 1   /* null pointer, bad size, n_modes not in {1, 4, 8, 27}, ... */
+#define POLYPIC_ERANGE 2   /* host-detected range problem (e.g. grid too large for the keys) */
+#define POLYPIC_EDEVICE 3  /* a HIP call failed (launch error, no device) */
+#define POLYPIC_ENOSPACE 4 /* the workspace is smaller than the queried size */
+#define POLYPIC_ENOTSUP 5  /* valid request this build does not support */
+
+/* ---- device status flags, OR-ed into *status_dev ---- */
+#define POLYPIC_FLAG_RANGE 1 /* a particle's stencil left the grid; it was skipped */
+
+/* Collocated grid description (host struct, passed by pointer). */
+typedef struct polypic_grid {
+  int32_t nx, ny, nz; /* node counts per axis, each in [3, 1026] */
+  float dx;           /* node spacing (> 0) */
+  float inv_dx;       /* the float32 factor used in u = (x - origin) * inv_dx */
+  float origin[3];    /* world position of node (0, 0, 0) */
+} polypic_grid;
+
+/* Human-readable name of a status code (static string, never NULL). */
+const char* polypic_strerror(int32_t code);
+
+/* Library ABI version: major * 10000 + minor * 100 + patch. */
+int32_t polypic_version(void);
+
+/* Name of the HIP error behind the last POLYPIC_EDEVICE returned on the calling
+ * thread ("no error" if none).  Static string owned by the library. */
+const char* polypic_last_device_error(void);
+
+/* ------------------------------------------------------------------------
+ * Cell-key sort (not part of the paper: it orders particles so that P2G can
+ * accumulate neighbouring particles in on-chip grid bricks).
+ *
+ * key(p) = Morton code of the stencil base node b(p): bit k of b_x, b_y, b_z
+ * goes to key bits 3k, 3k+1, 3k+2.  The sort is a stable LSD radix sort:
+ * keys_out[i] = key(perm_out[i]), ascending, ties in input order.  Particles
+ * out of range get the key of their clamped base node and raise
+ * POLYPIC_FLAG_RANGE.
+ *
+ * x[3][P] in; keys_out[P], perm_out[P] out (device).  ws: device workspace of
+ * at least polypic_sort_workspace_bytes() bytes, contents scratch.
+ * ------------------------------------------------------------------------ */
+int32_t polypic_sort_workspace_bytes(const polypic_grid* grid, int64_t P, size_t* bytes);
+int32_t polypic_sort(const polypic_grid* grid, int64_t P, const float* x, uint32_t* keys_out,
+                     int32_t* perm_out, void* ws, size_t ws_bytes, int32_t* status_dev,
+                     void* stream);
+
+/* ------------------------------------------------------------------------
+ * P2G scatter.  Section 3.1 Eq. 1 and 4 (mass), Eq. 13 (momentum), summed over
+ * particles as in Eq. 3; for a fluid set Eq. 15-16, for a fabric set Eq. 18-19
+ * with the per-point mass m_s + m_f folded into `mass`:
+ *     grid_mass[i]    (+)= sum_p m_p W_ip
+ *     grid_mom[a][i]  (+)= sum_p m_p W_ip sum_{r < n_modes} coeff[a][r][p] s_r(z_ip)
+ * with W_ip = w_x w_y w_z the product of quadratic B-spline weights.
+ *
+ * P             particle count (0 is allowed: only the clear happens).
+ * n_modes       1, 4, 8 or 27.
+ * x[3][P]       positions.  mass[P] per-particle mass, or NULL for uniform_mass.
+ * coeff         [3][n_modes][P] coefficients.
+ * perm          NULL, or the processing order (a permutation of 0..P-1, e.g.
+ *               from polypic_sort): slot i handles particle perm[i].  Results
+ *               do not depend on the order beyond float summation order; a
+ *               cell-sorted order is what makes the on-chip bricks effective.
+ * grid_mass[N], grid_mom[3][N]   outputs (device).
+ * accumulate    0: outputs are zeroed first; 1: sums are added to their contents.
+ * Summation order is not fixed (float atomics), so results are deterministic
+ * only up to rounding.
+ * ------------------------------------------------------------------------ */
+int32_t polypic_p2g(const polypic_grid* grid, int64_t P, int32_t n_modes, const float* x,
+                    const float* mass, float uniform_mass, const float* coeff, const int32_t* perm,
+                    float* grid_mass, float* grid_mom, int32_t accumulate, int32_t* status_dev,
+                    void* stream);
+
+/* ------------------------------------------------------------------------
+ * Grid update.  Eq. 5 (v = (mv) / m) followed by an explicit update that the
+ * paper delegates to its host model: gravity and separating slip walls.
+ *     v_i = grid_mom[i] / grid_mass[i] + dt * gravity   where grid_mass[i] > 0
+ *     v_i = 0                                           where grid_mass[i] == 0
+ * then, if bc_layers > 0, per axis a with storage index i_a along it:
+ *     v_a = max(v_a, 0)  where i_a <= 1 + bc_layers
+ *     v_a = min(v_a, 0)  where i_a >= n_a - 1 - bc_layers
+ * gravity: HOST float[3].  grid_vel[3][N] out; may not alias the inputs.
+ * ------------------------------------------------------------------------ */
+int32_t polypic_grid_update(const polypic_grid* grid, float dt, const float* gravity,
+                            int32_t bc_layers, const float* grid_mass, const float* grid_mom,
+                            float* grid_vel, void* stream);
+
+/* ------------------------------------------------------------------------
+ * G2P gather + projection.  Eq. 6-8 generalised as in section 3.3: the
+ * coefficients minimise sum_i W_ip (v_i - sum_r c_r s_r(z_ip))^2.  The modes
+ * are W-orthogonal (Eq. 14), so mode by mode
+ *     coeff_out[a][r][i] = <v_a, s_r>_W / <s_r, s_r>_W
+ * On an axis where the mode is quadratic the common factor of numerator and
+ * denominator, K(t) = (1 - 4t^2)^2 (3 - 4t^2) / 32, is cancelled; this also
+ * defines the coefficient at t = -1/2, where K vanishes, as the limit from
+ * t > -1/2.
+ *
+ * Output slot i belongs to particle perm[i] (identity when perm is NULL), so
+ * with a sort permutation every output comes out in sorted order.
+ * x_out[3][P]   optional (NULL: no advection): clamp(x + dt * coeff_out[.][0]),
+ *               each axis kept in [origin + 2 dx, origin + (n_a - 2) dx) -- the
+ *               lower bound, or the largest float32 below the upper bound.
+ * F_in, F_out   optional [9][P] (both or neither): F' = (I + dt C) F with
+ *               C_ab = coeff_out[a][1 + b] / dx (C = 0 when n_modes == 1).
+ * mass_in, mass_out  optional [P] (both or neither): mass_out[i] = mass_in[perm[i]]
+ *               so a per-particle mass follows the new order.
+ * Outputs may not alias inputs.
+ * ------------------------------------------------------------------------ */
+int32_t polypic_g2p(const polypic_grid* grid, int64_t P, int32_t n_modes, float dt,
+                    const float* grid_vel, const float* x_in, const int32_t* perm, float* x_out,
+                    float* coeff_out, const float* F_in, float* F_out, const float* mass_in,
+                    float* mass_out, int32_t* status_dev, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* POLYPIC_H */

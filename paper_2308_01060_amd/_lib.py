@@ -1,0 +1,99 @@
+"""ctypes loader for libpolypic.so and the C declarations of its entry points.
+
+The library must have been built (``python -m paper_2308_01060_amd.build`` or
+``__graft_entry__.build()``); importing this module without it raises, so no
+caller can run without the HIP code.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libpolypic.so")
+
+POLYPIC_OK = 0
+POLYPIC_EINVAL = 1
+POLYPIC_ERANGE = 2
+POLYPIC_EDEVICE = 3
+POLYPIC_ENOSPACE = 4
+POLYPIC_ENOTSUP = 5
+POLYPIC_FLAG_RANGE = 1
+
+EXPORTED = (
+    "polypic_strerror",
+    "polypic_version",
+    "polypic_last_device_error",
+    "polypic_sort_workspace_bytes",
+    "polypic_sort",
+    "polypic_p2g",
+    "polypic_grid_update",
+    "polypic_g2p",
+)
+
+
+class polypic_grid(ctypes.Structure):
+    """Mirror of ``struct polypic_grid`` (include/polypic.h)."""
+
+    _fields_ = [
+        ("nx", ctypes.c_int32),
+        ("ny", ctypes.c_int32),
+        ("nz", ctypes.c_int32),
+        ("dx", ctypes.c_float),
+        ("inv_dx", ctypes.c_float),
+        ("origin", ctypes.c_float * 3),
+    ]
+
+
+class PolyPICError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        self.code = code
+        detail = ""
+        if code == POLYPIC_EDEVICE:
+            detail = " [" + load().polypic_last_device_error().decode() + "]"
+        super().__init__(f"{where}: {strerror(code)} (status {code}){detail}")
+
+
+_lib = None
+
+
+def load() -> ctypes.CDLL:
+    """Load libpolypic.so once and declare the signatures; raises if it is not built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(
+            f"{LIB_PATH} is missing: build the HIP library first "
+            "(python paper_2308_01060_amd/build.py)")
+    lib = ctypes.CDLL(LIB_PATH)
+    P = ctypes.c_void_p
+    i32, i64, f32, sz = ctypes.c_int32, ctypes.c_int64, ctypes.c_float, ctypes.c_size_t
+    G = ctypes.POINTER(polypic_grid)
+    lib.polypic_strerror.restype = ctypes.c_char_p
+    lib.polypic_strerror.argtypes = [i32]
+    lib.polypic_version.restype = i32
+    lib.polypic_version.argtypes = []
+    lib.polypic_last_device_error.restype = ctypes.c_char_p
+    lib.polypic_last_device_error.argtypes = []
+    lib.polypic_sort_workspace_bytes.restype = i32
+    lib.polypic_sort_workspace_bytes.argtypes = [G, i64, ctypes.POINTER(sz)]
+    lib.polypic_sort.restype = i32
+    lib.polypic_sort.argtypes = [G, i64, P, P, P, P, sz, P, P]
+    lib.polypic_p2g.restype = i32
+    lib.polypic_p2g.argtypes = [G, i64, i32, P, P, f32, P, P, P, P, i32, P, P]
+    lib.polypic_grid_update.restype = i32
+    lib.polypic_grid_update.argtypes = [G, f32, ctypes.POINTER(f32), i32, P, P, P, P]
+    lib.polypic_g2p.restype = i32
+    lib.polypic_g2p.argtypes = [G, i64, i32, f32, P, P, P, P, P, P, P, P, P, P, P]
+    _lib = lib
+    return lib
+
+
+def strerror(code: int) -> str:
+    return load().polypic_strerror(int(code)).decode()
+
+
+def check(code: int, where: str) -> None:
+    if code != POLYPIC_OK:
+        raise PolyPICError(code, where)

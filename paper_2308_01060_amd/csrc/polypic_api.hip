@@ -1,0 +1,202 @@
+// C ABI layer: argument validation, launch configuration and dispatch.
+// Every entry point only enqueues work on the caller's stream.
+#include <math.h>
+
+#include "polypic.h"
+#include "polypic_internal.hpp"
+
+using namespace polypic;
+
+namespace {
+
+constexpr int32_t kVersion = 100;  // 0.1.0
+
+bool valid_modes(int32_t n) { return n == 1 || n == 4 || n == 8 || n == 27; }
+
+int32_t check_grid(const polypic_grid* g) {
+  if (!g) return POLYPIC_EINVAL;
+  const int32_t d[3] = {g->nx, g->ny, g->nz};
+  for (int a = 0; a < 3; ++a) {
+    if (d[a] < 3) return POLYPIC_EINVAL;
+    if (d[a] > 1026) return POLYPIC_ENOTSUP;  // 10-bit base node per axis in the keys
+  }
+  if (!(g->dx > 0.0f) || !isfinite(g->dx) || !(g->inv_dx > 0.0f) || !isfinite(g->inv_dx))
+    return POLYPIC_EINVAL;
+  for (int a = 0; a < 3; ++a)
+    if (!isfinite(g->origin[a])) return POLYPIC_EINVAL;
+  return POLYPIC_OK;
+}
+
+GridDev to_dev(const polypic_grid* g) {
+  GridDev d;
+  d.nx = g->nx;
+  d.ny = g->ny;
+  d.nz = g->nz;
+  d.inv_dx = g->inv_dx;
+  d.ox = g->origin[0];
+  d.oy = g->origin[1];
+  d.oz = g->origin[2];
+  return d;
+}
+
+int32_t check_P(int64_t P) {
+  if (P < 0 || P > (int64_t)INT32_MAX) return POLYPIC_EINVAL;
+  return POLYPIC_OK;
+}
+
+// Name of the last HIP error an entry point of this thread reported as EDEVICE.
+thread_local const char* g_last_device_error = "no error";
+
+int32_t from_hip(hipError_t e) {
+  if (e == hipSuccess) return POLYPIC_OK;
+  g_last_device_error = hipGetErrorName(e);
+  return POLYPIC_EDEVICE;
+}
+
+// HIP keeps a per-thread "last error" that any runtime call may set (including
+// calls made by other libraries in the process).  Entry points discard it before
+// launching so that the status they return describes their own launches only.
+void discard_stale_error() { (void)hipGetLastError(); }
+
+int64_t n_nodes(const polypic_grid* g) { return (int64_t)g->nx * g->ny * g->nz; }
+
+}  // namespace
+
+extern "C" {
+
+const char* polypic_strerror(int32_t code) {
+  switch (code) {
+    case POLYPIC_OK: return "ok";
+    case POLYPIC_EINVAL: return "invalid argument";
+    case POLYPIC_ERANGE: return "value out of range";
+    case POLYPIC_EDEVICE: return "HIP device error";
+    case POLYPIC_ENOSPACE: return "workspace too small";
+    case POLYPIC_ENOTSUP: return "not supported";
+    default: return "unknown status code";
+  }
+}
+
+int32_t polypic_version(void) { return kVersion; }
+
+const char* polypic_last_device_error(void) { return g_last_device_error; }
+
+int32_t polypic_sort_workspace_bytes(const polypic_grid* grid, int64_t P, size_t* bytes) {
+  int32_t st = check_grid(grid);
+  if (st) return st;
+  if ((st = check_P(P))) return st;
+  if (!bytes) return POLYPIC_EINVAL;
+  *bytes = sort_workspace_bytes(P);
+  return POLYPIC_OK;
+}
+
+int32_t polypic_sort(const polypic_grid* grid, int64_t P, const float* x, uint32_t* keys_out,
+                     int32_t* perm_out, void* ws, size_t ws_bytes, int32_t* status_dev,
+                     void* stream) {
+  int32_t st = check_grid(grid);
+  if (st) return st;
+  if ((st = check_P(P))) return st;
+  if (P == 0) return POLYPIC_OK;
+  if (!x || !keys_out || !perm_out || !ws) return POLYPIC_EINVAL;
+  if (ws_bytes < sort_workspace_bytes(P)) return POLYPIC_ENOSPACE;
+  discard_stale_error();
+  return from_hip(launch_sort(to_dev(grid), P, x, keys_out, perm_out, ws, status_dev,
+                              (hipStream_t)stream));
+}
+
+int32_t polypic_p2g(const polypic_grid* grid, int64_t P, int32_t n_modes, const float* x,
+                    const float* mass, float uniform_mass, const float* coeff, const int32_t* perm,
+                    float* grid_mass, float* grid_mom, int32_t accumulate, int32_t* status_dev,
+                    void* stream) {
+  int32_t st = check_grid(grid);
+  if (st) return st;
+  if ((st = check_P(P))) return st;
+  if (!valid_modes(n_modes)) return POLYPIC_EINVAL;
+  if (!grid_mass || !grid_mom) return POLYPIC_EINVAL;
+  if (P > 0 && (!x || !coeff)) return POLYPIC_EINVAL;
+  if (!mass && !isfinite(uniform_mass)) return POLYPIC_EINVAL;
+  const hipStream_t s = (hipStream_t)stream;
+  const int64_t N = n_nodes(grid);
+  discard_stale_error();
+  if (!accumulate) {
+    if ((st = from_hip(launch_grid_clear(grid_mass, grid_mom, N, s)))) return st;
+  }
+  P2GArgs a;
+  a.g = to_dev(grid);
+  a.P = P;
+  a.x = x;
+  a.mass = mass;
+  a.uniform_mass = uniform_mass;
+  a.coeff = coeff;
+  a.perm = perm;
+  a.gm = grid_mass;
+  a.gp0 = grid_mom;
+  a.gp1 = grid_mom + N;
+  a.gp2 = grid_mom + 2 * N;
+  a.status = status_dev;
+  return from_hip(launch_p2g(a, n_modes, p2g_default_config(), s));
+}
+
+int32_t polypic_grid_update(const polypic_grid* grid, float dt, const float* gravity,
+                            int32_t bc_layers, const float* grid_mass, const float* grid_mom,
+                            float* grid_vel, void* stream) {
+  int32_t st = check_grid(grid);
+  if (st) return st;
+  if (!gravity || !grid_mass || !grid_mom || !grid_vel) return POLYPIC_EINVAL;
+  if (!isfinite(dt) || bc_layers < 0) return POLYPIC_EINVAL;
+  for (int a = 0; a < 3; ++a)
+    if (!isfinite(gravity[a])) return POLYPIC_EINVAL;
+  GridUpdateArgs a;
+  a.nx = grid->nx;
+  a.ny = grid->ny;
+  a.nz = grid->nz;
+  a.dt = dt;
+  a.g0 = gravity[0];
+  a.g1 = gravity[1];
+  a.g2 = gravity[2];
+  a.bc_layers = bc_layers;
+  a.gm = grid_mass;
+  a.gp = grid_mom;
+  a.gv = grid_vel;
+  discard_stale_error();
+  return from_hip(launch_grid_update(a, (hipStream_t)stream));
+}
+
+int32_t polypic_g2p(const polypic_grid* grid, int64_t P, int32_t n_modes, float dt,
+                    const float* grid_vel, const float* x_in, const int32_t* perm, float* x_out,
+                    float* coeff_out, const float* F_in, float* F_out, const float* mass_in,
+                    float* mass_out, int32_t* status_dev, void* stream) {
+  int32_t st = check_grid(grid);
+  if (st) return st;
+  if ((st = check_P(P))) return st;
+  if (!valid_modes(n_modes) || !isfinite(dt)) return POLYPIC_EINVAL;
+  if (P == 0) return POLYPIC_OK;
+  if (!grid_vel || !x_in || !coeff_out) return POLYPIC_EINVAL;
+  if ((F_in == nullptr) != (F_out == nullptr)) return POLYPIC_EINVAL;
+  if ((mass_in == nullptr) != (mass_out == nullptr)) return POLYPIC_EINVAL;
+  G2PArgs a;
+  a.g = to_dev(grid);
+  a.P = P;
+  a.dt = dt;
+  a.dx = grid->dx;
+  const int32_t d[3] = {grid->nx, grid->ny, grid->nz};
+  for (int ax = 0; ax < 3; ++ax) {
+    // [origin + 2 dx, origin + (n - 2) dx): bounds rounded from double
+    a.lo[ax] = (float)((double)grid->origin[ax] + 2.0 * (double)grid->dx);
+    const float top = (float)((double)grid->origin[ax] + (double)(d[ax] - 2) * (double)grid->dx);
+    a.hi[ax] = nextafterf(top, -INFINITY);
+  }
+  a.gv = grid_vel;
+  a.x_in = x_in;
+  a.perm = perm;
+  a.x_out = x_out;
+  a.coeff_out = coeff_out;
+  a.F_in = F_in;
+  a.F_out = F_out;
+  a.mass_in = mass_in;
+  a.mass_out = mass_out;
+  a.status = status_dev;
+  discard_stale_error();
+  return from_hip(launch_g2p(a, n_modes, (hipStream_t)stream));
+}
+
+}  // extern "C"

@@ -1,0 +1,167 @@
+// Device-side building blocks shared by the PolyPIC kernels (gfx950, wave64).
+//
+// Stencil, quadratic B-spline weights, the 1-D mode factors of Eq. 11 with the
+// orthogonalised quadratic of Eq. 14, the G2P projection rows, the mode
+// order, and the Morton key.  Everything is float32; the closed forms are the
+// factored ones, which keep full relative accuracy as |t| -> 1/2.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace polypic {
+
+constexpr int kWave = 64;
+
+// Device flags (mirrors POLYPIC_FLAG_* of the public header).
+constexpr int kFlagRange = 1;
+
+struct GridDev {
+  int nx, ny, nz;
+  float inv_dx;
+  float ox, oy, oz;
+};
+
+// ---------------------------------------------------------------- mode order
+// r -> (kx, ky, kz), graded so that the prefixes 1, 4, 8, 27 are PIC, APIC,
+// multilinear and the full quadratic basis.
+__host__ __device__ constexpr int mode_code(int r) {
+  // code = kx * 9 + ky * 3 + kz
+  return r == 0    ? 0
+         : r == 1  ? 9
+         : r == 2  ? 3
+         : r == 3  ? 1
+         : r == 4  ? 12
+         : r == 5  ? 10
+         : r == 6  ? 4
+         : r == 7  ? 13
+         : r == 8  ? 18
+         : r == 9  ? 6
+         : r == 10 ? 2
+         : r == 11 ? 21
+         : r == 12 ? 19
+         : r == 13 ? 15
+         : r == 14 ? 7
+         : r == 15 ? 11
+         : r == 16 ? 5
+         : r == 17 ? 22
+         : r == 18 ? 16
+         : r == 19 ? 14
+         : r == 20 ? 24
+         : r == 21 ? 20
+         : r == 22 ? 8
+         : r == 23 ? 25
+         : r == 24 ? 23
+         : r == 25 ? 17
+                   : 26;
+}
+
+// (kx, ky, kz) -> r
+__host__ __device__ constexpr int mode_index(int kx, int ky, int kz) {
+  int code = kx * 9 + ky * 3 + kz;
+  int r = 0;
+  for (int i = 0; i < 27; ++i)
+    if (mode_code(i) == code) r = i;
+  return r;
+}
+
+// Is mode (kx, ky, kz) among the first NR modes?
+template <int NR>
+__host__ __device__ constexpr bool has_mode(int kx, int ky, int kz) {
+  return mode_index(kx, ky, kz) < NR;
+}
+
+// ---------------------------------------------------------------- stencil
+// u = (x - o) * inv_dx, b = floor(u - 1/2), t = u - b - 1, each a single
+// round-to-nearest float32 operation (t is exact).  Returns false when b is
+// outside [0, n - 3] (or the position is not finite).
+__device__ __forceinline__ bool stencil_axis(float x, float o, float inv_dx, int n, int& b,
+                                             float& t) {
+  const float u = __fmul_rn(__fsub_rn(x, o), inv_dx);
+  const float f = floorf(__fsub_rn(u, 0.5f));
+  const bool ok = (f >= 0.0f) && (f <= (float)(n - 3));
+  b = ok ? (int)f : 0;
+  t = ok ? __fsub_rn(u, f + 1.0f) : 0.0f;
+  return ok;
+}
+
+// 1-D factors for P2G at the three stencil nodes j = 0, 1, 2:
+// w_j (quadratic B-spline), z_j = j - 1 - t, g_j = ghat(z_j) of Eq. 14.
+struct Basis1D {
+  float w[3];
+  float z[3];
+  float g[3];
+};
+
+__device__ __forceinline__ Basis1D basis_p2g(float t) {
+  Basis1D B;
+  const float h0 = 0.5f - t;  // exact
+  const float h2 = 0.5f + t;  // exact
+  const float q = h0 * h2;    // (1 - 4 t^2) / 4
+  const float s3 = 2.0f + 4.0f * q;  // 3 - 4 t^2
+  B.w[0] = 0.5f * h0 * h0;
+  B.w[1] = 0.5f + q;
+  B.w[2] = 0.5f * h2 * h2;
+  B.z[0] = -1.0f - t;
+  B.z[1] = -t;
+  B.z[2] = 1.0f - t;
+  // ghat_j = zhat_j^2 - t (1 - 4 t^2) zhat_j - 1/4 in factored form
+  B.g[0] = h2 * h2 * s3;
+  B.g[1] = -4.0f * q * q;
+  B.g[2] = h0 * h0 * s3;
+  return B;
+}
+
+// 1-D G2P projection rows pr[k][j]: coefficient k of a 1-D field f_j is
+// sum_j pr[k][j] f_j, with pr[0] = w, pr[1] = 4 w z (since sum w z^2 = 1/4),
+// pr[2] = (1/2, -1, 1/2) (since w_j ghat_j = K (1, -2, 1) and
+// sum_j (1, -2, 1)_j ghat_j = 2).
+struct Proj1D {
+  float pr[3][3];
+};
+
+__device__ __forceinline__ Proj1D proj_g2p(float t) {
+  Proj1D P;
+  const float h0 = 0.5f - t;
+  const float h2 = 0.5f + t;
+  const float w0 = 0.5f * h0 * h0;
+  const float w1 = 0.5f + h0 * h2;
+  const float w2 = 0.5f * h2 * h2;
+  P.pr[0][0] = w0;
+  P.pr[0][1] = w1;
+  P.pr[0][2] = w2;
+  P.pr[1][0] = -2.0f * h0 * h0 * (1.0f + t);
+  P.pr[1][1] = -4.0f * t * w1;
+  P.pr[1][2] = 2.0f * h2 * h2 * (1.0f - t);
+  P.pr[2][0] = 0.5f;
+  P.pr[2][1] = -1.0f;
+  P.pr[2][2] = 0.5f;
+  return P;
+}
+
+// ---------------------------------------------------------------- Morton key
+__device__ __forceinline__ uint32_t spread_bits3(uint32_t v) {
+  v &= 0x3ffu;
+  v = (v | (v << 16)) & 0x030000FFu;
+  v = (v | (v << 8)) & 0x0300F00Fu;
+  v = (v | (v << 4)) & 0x030C30C3u;
+  v = (v | (v << 2)) & 0x09249249u;
+  return v;
+}
+
+__device__ __forceinline__ uint32_t morton3(int bx, int by, int bz) {
+  return spread_bits3((uint32_t)bx) | (spread_bits3((uint32_t)by) << 1) |
+         (spread_bits3((uint32_t)bz) << 2);
+}
+
+// popcount of the bits of `mask` below this lane
+__device__ __forceinline__ int lanes_below(unsigned long long mask) {
+  return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
+                                        __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+
+__device__ __forceinline__ void raise_flag(int32_t* status, int flag) {
+  if (status) atomicOr(status, flag);
+}
+
+}  // namespace polypic

@@ -1,0 +1,175 @@
+// G2P gather + projection (Eq. 6-8 and section 3.3) with advection and the
+// optional F update, for gfx950.
+//
+// One thread per output slot i, reading particle perm[i].  Per velocity
+// component the 27 node values are gathered and projected onto the first
+// n_modes modes by the separable product of 1-D projection rows
+// (x, then y, then z); rows and modes beyond n_modes are skipped at compile
+// time.  All outputs are written at slot i, so with a sort permutation the
+// particle arrays come out in cell order.
+#include "polypic_internal.hpp"
+
+namespace polypic {
+
+namespace {
+
+template <int NR>
+__device__ constexpr bool need_kx(int kx) {
+  return has_mode<NR>(kx, 0, 0) || has_mode<NR>(kx, 0, 1) || has_mode<NR>(kx, 0, 2) ||
+         has_mode<NR>(kx, 1, 0) || has_mode<NR>(kx, 1, 1) || has_mode<NR>(kx, 1, 2) ||
+         has_mode<NR>(kx, 2, 0) || has_mode<NR>(kx, 2, 1) || has_mode<NR>(kx, 2, 2);
+}
+
+template <int NR>
+__device__ constexpr bool need_kxky(int kx, int ky) {
+  return has_mode<NR>(kx, ky, 0) || has_mode<NR>(kx, ky, 1) || has_mode<NR>(kx, ky, 2);
+}
+
+// c[r] = sum_j Px[kx][jx] Py[ky][jy] Pz[kz][jz] v[jx + 3 jy + 9 jz] for r < NR
+template <int NR>
+__device__ __forceinline__ void project_modes(const float (&v)[27], const Proj1D& px,
+                                              const Proj1D& py, const Proj1D& pz,
+                                              float (&c)[27]) {
+  float A[3][3][3];  // [kx][jy][jz]
+#pragma unroll
+  for (int kx = 0; kx < 3; ++kx) {
+    if (!need_kx<NR>(kx)) continue;
+#pragma unroll
+    for (int jy = 0; jy < 3; ++jy)
+#pragma unroll
+      for (int jz = 0; jz < 3; ++jz) {
+        const float* vv = v + 3 * jy + 9 * jz;
+        if (kx == 2)  // (1/2, -1, 1/2): additions only
+          A[kx][jy][jz] = 0.5f * (vv[0] + vv[2]) - vv[1];
+        else
+          A[kx][jy][jz] = fmaf(px.pr[kx][2], vv[2], fmaf(px.pr[kx][1], vv[1], px.pr[kx][0] * vv[0]));
+      }
+  }
+  float B[3][3][3];  // [kx][ky][jz]
+#pragma unroll
+  for (int kx = 0; kx < 3; ++kx)
+#pragma unroll
+    for (int ky = 0; ky < 3; ++ky) {
+      if (!need_kxky<NR>(kx, ky)) continue;
+#pragma unroll
+      for (int jz = 0; jz < 3; ++jz) {
+        if (ky == 2)
+          B[kx][ky][jz] = 0.5f * (A[kx][0][jz] + A[kx][2][jz]) - A[kx][1][jz];
+        else
+          B[kx][ky][jz] = fmaf(py.pr[ky][2], A[kx][2][jz],
+                               fmaf(py.pr[ky][1], A[kx][1][jz], py.pr[ky][0] * A[kx][0][jz]));
+      }
+    }
+#pragma unroll
+  for (int kx = 0; kx < 3; ++kx)
+#pragma unroll
+    for (int ky = 0; ky < 3; ++ky)
+#pragma unroll
+      for (int kz = 0; kz < 3; ++kz) {
+        if (!has_mode<NR>(kx, ky, kz)) continue;
+        float s;
+        if (kz == 2)
+          s = 0.5f * (B[kx][ky][0] + B[kx][ky][2]) - B[kx][ky][1];
+        else
+          s = fmaf(pz.pr[kz][2], B[kx][ky][2],
+                   fmaf(pz.pr[kz][1], B[kx][ky][1], pz.pr[kz][0] * B[kx][ky][0]));
+        c[mode_index(kx, ky, kz)] = s;
+      }
+}
+
+template <int NR, int BS>
+__global__ __launch_bounds__(BS) void g2p_kernel(G2PArgs a) {
+  const int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x;
+  if (i >= a.P) return;
+  const size_t Ps = (size_t)a.P;
+  const int nx = a.g.nx, ny = a.g.ny, nz = a.g.nz;
+  // a caller permutation is clamped into [0, P): a bad one gives wrong results, never a fault
+  const int p = a.perm ? min(max(a.perm[i], 0), (int)(a.P - 1)) : (int)i;
+  const float xp[3] = {a.x_in[p], a.x_in[Ps + p], a.x_in[2 * Ps + p]};
+  int b0, b1, b2;
+  float t0, t1, t2;
+  bool ok = stencil_axis(xp[0], a.g.ox, a.g.inv_dx, nx, b0, t0);
+  ok &= stencil_axis(xp[1], a.g.oy, a.g.inv_dx, ny, b1, t1);
+  ok &= stencil_axis(xp[2], a.g.oz, a.g.inv_dx, nz, b2, t2);
+  if (!ok) raise_flag(a.status, kFlagRange);
+
+  const Proj1D px = proj_g2p(t0);
+  const Proj1D py = proj_g2p(t1);
+  const Proj1D pz = proj_g2p(t2);
+  const size_t N = (size_t)nx * ny * nz;
+  const int nxny = nx * ny;
+  const int gbase = (b2 * ny + b1) * nx + b0;
+
+  float lin[3][3];  // lin[a][b] = coefficient of mode 1 + b for component a
+  float F[9];
+  if (a.F_in) {
+#pragma unroll
+    for (int e = 0; e < 9; ++e) F[e] = a.F_in[(size_t)e * Ps + p];
+  }
+#pragma unroll
+  for (int ax = 0; ax < 3; ++ax) {
+    float c[27];
+    if (ok) {
+      const float* vg = a.gv + (size_t)ax * N + gbase;
+      float v[27];
+#pragma unroll
+      for (int jz = 0; jz < 3; ++jz)
+#pragma unroll
+        for (int jy = 0; jy < 3; ++jy)
+#pragma unroll
+          for (int jx = 0; jx < 3; ++jx) v[jx + 3 * jy + 9 * jz] = vg[jz * nxny + jy * nx + jx];
+      project_modes<NR>(v, px, py, pz, c);
+    } else {
+#pragma unroll
+      for (int r = 0; r < 27; ++r) c[r] = 0.0f;
+    }
+    float* co = a.coeff_out + (size_t)ax * NR * Ps + i;
+#pragma unroll
+    for (int r = 0; r < NR; ++r) co[(size_t)r * Ps] = c[r];
+    if (a.x_out) {
+      float xn = fmaf(a.dt, c[0], xp[ax]);
+      xn = fmaxf(xn, a.lo[ax]);
+      xn = fminf(xn, a.hi[ax]);
+      a.x_out[(size_t)ax * Ps + i] = xn;
+    }
+#pragma unroll
+    for (int b = 0; b < 3; ++b) lin[ax][b] = (NR >= 4) ? c[1 + b] : 0.0f;
+  }
+  if (a.F_out) {
+    // F' = F + dt C F with C_ab = lin[a][b] / dx
+    const float s = a.dt / a.dx;
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+      for (int col = 0; col < 3; ++col) {
+        float acc = 0.0f;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) acc = fmaf(lin[r][k], F[3 * k + col], acc);
+        a.F_out[(size_t)(3 * r + col) * Ps + i] = fmaf(s, acc, F[3 * r + col]);
+      }
+  }
+  if (a.mass_out) a.mass_out[i] = a.mass_in[p];
+}
+
+template <int NR>
+hipError_t launch_nr(const G2PArgs& a, hipStream_t stream) {
+  constexpr int BS = 256;
+  const unsigned blocks = (unsigned)((a.P + BS - 1) / BS);
+  g2p_kernel<NR, BS><<<blocks, BS, 0, stream>>>(a);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_g2p(const G2PArgs& a, int n_modes, hipStream_t stream) {
+  if (a.P == 0) return hipSuccess;
+  switch (n_modes) {
+    case 1: return launch_nr<1>(a, stream);
+    case 4: return launch_nr<4>(a, stream);
+    case 8: return launch_nr<8>(a, stream);
+    case 27: return launch_nr<27>(a, stream);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace polypic

@@ -1,0 +1,46 @@
+// Grid update: v = (mv) / m (Eq. 5) where m > 0, plus gravity and separating
+// slip walls, for gfx950.  One thread per node along x; y and z come from the
+// block grid, so the wall tests need no division.
+#include "polypic_internal.hpp"
+
+namespace polypic {
+
+namespace {
+
+__global__ __launch_bounds__(256) void grid_update_kernel(GridUpdateArgs a) {
+  const int ix = blockIdx.x * blockDim.x + threadIdx.x;
+  const int iy = blockIdx.y;
+  const int iz = blockIdx.z;
+  if (ix >= a.nx) return;
+  const size_t N = (size_t)a.nx * a.ny * a.nz;
+  const size_t n = ((size_t)iz * a.ny + iy) * a.nx + ix;
+  const float m = a.gm[n];
+  float v0 = 0.0f, v1 = 0.0f, v2 = 0.0f;
+  if (m > 0.0f) {
+    v0 = a.gp[n] / m + a.dt * a.g0;
+    v1 = a.gp[N + n] / m + a.dt * a.g1;
+    v2 = a.gp[2 * N + n] / m + a.dt * a.g2;
+  }
+  if (a.bc_layers > 0) {
+    const int L = a.bc_layers;
+    if (ix <= 1 + L) v0 = fmaxf(v0, 0.0f);
+    if (ix >= a.nx - 1 - L) v0 = fminf(v0, 0.0f);
+    if (iy <= 1 + L) v1 = fmaxf(v1, 0.0f);
+    if (iy >= a.ny - 1 - L) v1 = fminf(v1, 0.0f);
+    if (iz <= 1 + L) v2 = fmaxf(v2, 0.0f);
+    if (iz >= a.nz - 1 - L) v2 = fminf(v2, 0.0f);
+  }
+  a.gv[n] = v0;
+  a.gv[N + n] = v1;
+  a.gv[2 * N + n] = v2;
+}
+
+}  // namespace
+
+hipError_t launch_grid_update(const GridUpdateArgs& a, hipStream_t stream) {
+  dim3 grid((unsigned)((a.nx + 255) / 256), (unsigned)a.ny, (unsigned)a.nz);
+  grid_update_kernel<<<grid, 256, 0, stream>>>(a);
+  return hipGetLastError();
+}
+
+}  // namespace polypic

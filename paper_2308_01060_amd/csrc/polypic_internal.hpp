@@ -1,0 +1,79 @@
+// Internal launch interface between the C ABI layer and the kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "polypic_device.hpp"
+
+namespace polypic {
+
+inline size_t align_up(size_t n, size_t a = 256) { return (n + a - 1) / a * a; }
+
+// ---- sort
+size_t sort_workspace_bytes(int64_t P);
+int sort_key_bits(const GridDev& g);
+hipError_t launch_sort(const GridDev& g, int64_t P, const float* x, uint32_t* keys_out,
+                       int32_t* perm_out, void* ws, int32_t* status, hipStream_t stream);
+
+// ---- P2G
+struct P2GArgs {
+  GridDev g;
+  int64_t P;
+  const float* x;      // [3][P]
+  const float* mass;   // [P] or nullptr
+  float uniform_mass;
+  const float* coeff;  // [3][NR][P]
+  const int32_t* perm; // [P] or nullptr
+  float* gm;           // grid mass [N]
+  float* gp0;          // grid momentum, one pointer per component
+  float* gp1;
+  float* gp2;
+  int32_t* status;
+};
+
+// Launch configuration chosen by the host (autotuned or default).
+struct P2GConfig {
+  int tile_log2;   // brick edge = 1 << tile_log2 cells
+  int block;       // threads per block = particles per block
+};
+
+P2GConfig p2g_default_config();
+bool p2g_config_supported(const P2GConfig& c);
+hipError_t launch_grid_clear(float* gm, float* gp, int64_t n_nodes, hipStream_t stream);
+hipError_t launch_p2g(const P2GArgs& a, int n_modes, const P2GConfig& cfg, hipStream_t stream);
+
+// ---- grid update
+struct GridUpdateArgs {
+  int nx, ny, nz;
+  float dt;
+  float g0, g1, g2;
+  int bc_layers;
+  const float* gm;
+  const float* gp;  // [3][N]
+  float* gv;        // [3][N]
+};
+hipError_t launch_grid_update(const GridUpdateArgs& a, hipStream_t stream);
+
+// ---- G2P
+struct G2PArgs {
+  GridDev g;
+  int64_t P;
+  float dt;
+  float dx;
+  float lo[3], hi[3];   // clamp bounds for advection
+  const float* gv;      // [3][N]
+  const float* x_in;    // [3][P]
+  const int32_t* perm;  // [P] or nullptr
+  float* x_out;         // [3][P] or nullptr
+  float* coeff_out;     // [3][NR][P]
+  const float* F_in;    // [9][P] or nullptr
+  float* F_out;
+  const float* mass_in; // [P] or nullptr
+  float* mass_out;
+  int32_t* status;
+};
+hipError_t launch_g2p(const G2PArgs& a, int n_modes, hipStream_t stream);
+
+}  // namespace polypic

@@ -1,0 +1,126 @@
+"""Torch-facing binding of the C ABI: same entry-point names, argument marshalling only.
+
+Tensors must be CUDA (HIP) float32 / int32 / uint32 tensors, contiguous, with
+the layouts of include/polypic.h.  Work is enqueued on torch's current stream;
+nothing here computes any part of the transfers.
+"""
+from __future__ import annotations
+
+import ctypes
+from typing import Optional, Sequence, Tuple
+
+import torch
+
+from . import _lib
+from ._lib import check, polypic_grid
+
+ALLOWED_N_MODES = (1, 4, 8, 27)
+
+
+def make_grid(nodes: Sequence[int], dx: float, origin: Sequence[float] = (0.0, 0.0, 0.0),
+              inv_dx: Optional[float] = None) -> polypic_grid:
+    """Build the C grid struct; inv_dx defaults to 1/dx rounded to float32."""
+    g = polypic_grid()
+    g.nx, g.ny, g.nz = (int(n) for n in nodes)
+    g.dx = float(dx)
+    g.inv_dx = float(1.0 / dx if inv_dx is None else inv_dx)
+    for a in range(3):
+        g.origin[a] = float(origin[a])
+    return g
+
+
+def grid_from_spec(spec) -> polypic_grid:
+    """C grid struct from a workloads.GridSpec (duck-typed: nodes, dx, inv_dx, origin)."""
+    return make_grid(spec.nodes, spec.dx, spec.origin, spec.inv_dx)
+
+
+def n_nodes(g: polypic_grid) -> int:
+    return int(g.nx) * int(g.ny) * int(g.nz)
+
+
+def _stream() -> int:
+    return int(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t: Optional[torch.Tensor], dtype: torch.dtype, numel: int, name: str) -> Optional[int]:
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch.Tensor")
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a device tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if t.numel() != numel:
+        raise ValueError(f"{name} has {t.numel()} elements, expected {numel}")
+    return t.data_ptr()
+
+
+def polypic_sort_workspace_bytes(grid: polypic_grid, P: int) -> int:
+    out = ctypes.c_size_t(0)
+    check(_lib.load().polypic_sort_workspace_bytes(ctypes.byref(grid), int(P), ctypes.byref(out)),
+          "polypic_sort_workspace_bytes")
+    return int(out.value)
+
+
+def polypic_sort(grid: polypic_grid, x: torch.Tensor, keys_out: torch.Tensor,
+                 perm_out: torch.Tensor, ws: torch.Tensor,
+                 status_dev: Optional[torch.Tensor] = None) -> None:
+    P = x.numel() // 3
+    check(_lib.load().polypic_sort(
+        ctypes.byref(grid), P, _ptr(x, torch.float32, 3 * P, "x"),
+        _ptr(keys_out, torch.int32, P, "keys_out") if keys_out.dtype == torch.int32
+        else _ptr(keys_out, torch.uint32, P, "keys_out"),
+        _ptr(perm_out, torch.int32, P, "perm_out"),
+        _ptr(ws, torch.uint8, ws.numel(), "ws"), ws.numel(),
+        _ptr(status_dev, torch.int32, 1, "status_dev"), _stream()), "polypic_sort")
+
+
+def polypic_p2g(grid: polypic_grid, n_modes: int, x: torch.Tensor, coeff: torch.Tensor,
+                grid_mass: torch.Tensor, grid_mom: torch.Tensor,
+                mass: Optional[torch.Tensor] = None, uniform_mass: float = 1.0,
+                perm: Optional[torch.Tensor] = None, accumulate: bool = False,
+                status_dev: Optional[torch.Tensor] = None) -> None:
+    P = x.numel() // 3
+    N = n_nodes(grid)
+    check(_lib.load().polypic_p2g(
+        ctypes.byref(grid), P, int(n_modes), _ptr(x, torch.float32, 3 * P, "x"),
+        _ptr(mass, torch.float32, P, "mass"), float(uniform_mass),
+        _ptr(coeff, torch.float32, 3 * int(n_modes) * P, "coeff"),
+        _ptr(perm, torch.int32, P, "perm"),
+        _ptr(grid_mass, torch.float32, N, "grid_mass"),
+        _ptr(grid_mom, torch.float32, 3 * N, "grid_mom"), int(bool(accumulate)),
+        _ptr(status_dev, torch.int32, 1, "status_dev"), _stream()), "polypic_p2g")
+
+
+def polypic_grid_update(grid: polypic_grid, dt: float, gravity: Sequence[float], bc_layers: int,
+                        grid_mass: torch.Tensor, grid_mom: torch.Tensor,
+                        grid_vel: torch.Tensor) -> None:
+    N = n_nodes(grid)
+    g3 = (ctypes.c_float * 3)(*[float(v) for v in gravity])
+    check(_lib.load().polypic_grid_update(
+        ctypes.byref(grid), float(dt), g3, int(bc_layers),
+        _ptr(grid_mass, torch.float32, N, "grid_mass"),
+        _ptr(grid_mom, torch.float32, 3 * N, "grid_mom"),
+        _ptr(grid_vel, torch.float32, 3 * N, "grid_vel"), _stream()), "polypic_grid_update")
+
+
+def polypic_g2p(grid: polypic_grid, n_modes: int, dt: float, grid_vel: torch.Tensor,
+                x_in: torch.Tensor, coeff_out: torch.Tensor,
+                perm: Optional[torch.Tensor] = None, x_out: Optional[torch.Tensor] = None,
+                F_in: Optional[torch.Tensor] = None, F_out: Optional[torch.Tensor] = None,
+                mass_in: Optional[torch.Tensor] = None, mass_out: Optional[torch.Tensor] = None,
+                status_dev: Optional[torch.Tensor] = None) -> None:
+    P = x_in.numel() // 3
+    N = n_nodes(grid)
+    check(_lib.load().polypic_g2p(
+        ctypes.byref(grid), P, int(n_modes), float(dt),
+        _ptr(grid_vel, torch.float32, 3 * N, "grid_vel"),
+        _ptr(x_in, torch.float32, 3 * P, "x_in"), _ptr(perm, torch.int32, P, "perm"),
+        _ptr(x_out, torch.float32, 3 * P, "x_out"),
+        _ptr(coeff_out, torch.float32, 3 * int(n_modes) * P, "coeff_out"),
+        _ptr(F_in, torch.float32, 9 * P, "F_in"), _ptr(F_out, torch.float32, 9 * P, "F_out"),
+        _ptr(mass_in, torch.float32, P, "mass_in"), _ptr(mass_out, torch.float32, P, "mass_out"),
+        _ptr(status_dev, torch.int32, 1, "status_dev"), _stream()), "polypic_g2p")

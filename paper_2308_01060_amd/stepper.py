@@ -1,0 +1,102 @@
+"""A particle set on its grid, stepped through the C ABI.
+
+``ParticleSet`` owns the device buffers of one particle set (double-buffered
+positions / coefficients / optional mass and F), its grid arrays and the sort
+workspace, and runs one transfer step as four library calls on the current
+stream:
+
+    polypic_sort -> polypic_p2g -> polypic_grid_update -> polypic_g2p
+
+G2P writes the new state in sorted order, so after a step the arrays are in
+cell order and the next sort is close to the identity.  ``order`` tracks the
+original index of each slot.
+"""
+from __future__ import annotations
+
+from typing import Optional, Sequence
+
+import torch
+
+from . import ops
+
+
+class ParticleSet:
+    def __init__(self, grid, n_modes: int, x: torch.Tensor, coeff: torch.Tensor,
+                 mass: Optional[torch.Tensor] = None, uniform_mass: float = 1.0,
+                 F: Optional[torch.Tensor] = None, dt: float = 1e-4,
+                 gravity: Sequence[float] = (0.0, -9.8, 0.0), bc_layers: int = 1,
+                 device: str = "cuda"):
+        if n_modes not in ops.ALLOWED_N_MODES:
+            raise ValueError("n_modes must be one of 1, 4, 8, 27")
+        self.grid = grid
+        self.n_modes = int(n_modes)
+        self.dt = float(dt)
+        self.gravity = tuple(float(g) for g in gravity)
+        self.bc_layers = int(bc_layers)
+        self.uniform_mass = float(uniform_mass)
+        P = int(x.shape[-1])
+        self.P = P
+        dev = torch.device(device)
+        f32 = dict(dtype=torch.float32, device=dev)
+        self.x = x.to(**f32).contiguous().reshape(3, P)
+        c = coeff.to(**f32)
+        if c.shape[1] != self.n_modes:
+            c = c[:, : self.n_modes]
+        self.coeff = c.contiguous()
+        self.mass = None if mass is None else mass.to(**f32).contiguous()
+        self.F = None if F is None else F.to(**f32).contiguous().reshape(9, P)
+        self.x_next = torch.empty_like(self.x)
+        self.coeff_next = torch.empty_like(self.coeff)
+        self.mass_next = None if self.mass is None else torch.empty_like(self.mass)
+        self.F_next = None if self.F is None else torch.empty_like(self.F)
+        N = ops.n_nodes(grid)
+        self.grid_mass = torch.empty(N, **f32)
+        self.grid_mom = torch.empty(3 * N, **f32)
+        self.grid_vel = torch.empty(3 * N, **f32)
+        self.keys = torch.empty(P, dtype=torch.int32, device=dev)
+        self.perm = torch.empty(P, dtype=torch.int32, device=dev)
+        self.ws = torch.empty(max(1, ops.polypic_sort_workspace_bytes(grid, P)),
+                              dtype=torch.uint8, device=dev)
+        self.status = torch.zeros(1, dtype=torch.int32, device=dev)
+        self.order = torch.arange(P, dtype=torch.int64, device=dev)
+
+    # -- the four calls of one step
+    def sort(self):
+        ops.polypic_sort(self.grid, self.x, self.keys, self.perm, self.ws, self.status)
+
+    def p2g(self, use_perm: bool = True):
+        ops.polypic_p2g(self.grid, self.n_modes, self.x, self.coeff, self.grid_mass,
+                        self.grid_mom, mass=self.mass, uniform_mass=self.uniform_mass,
+                        perm=self.perm if use_perm else None, status_dev=self.status)
+
+    def grid_update(self):
+        ops.polypic_grid_update(self.grid, self.dt, self.gravity, self.bc_layers,
+                                self.grid_mass, self.grid_mom, self.grid_vel)
+
+    def g2p(self, use_perm: bool = True, advect: bool = True):
+        ops.polypic_g2p(self.grid, self.n_modes, self.dt, self.grid_vel, self.x, self.coeff_next,
+                        perm=self.perm if use_perm else None,
+                        x_out=self.x_next if advect else None,
+                        F_in=self.F, F_out=self.F_next,
+                        mass_in=self.mass, mass_out=self.mass_next, status_dev=self.status)
+
+    def swap(self, use_perm: bool = True):
+        self.x, self.x_next = self.x_next, self.x
+        self.coeff, self.coeff_next = self.coeff_next, self.coeff
+        if self.mass is not None:
+            self.mass, self.mass_next = self.mass_next, self.mass
+        if self.F is not None:
+            self.F, self.F_next = self.F_next, self.F
+        if use_perm:
+            self.order = self.order[self.perm.long()]
+
+    def step(self):
+        """One full step: sort, P2G, grid update, G2P + advection, then swap buffers."""
+        self.sort()
+        self.p2g()
+        self.grid_update()
+        self.g2p()
+        self.swap()
+
+    def status_flags(self) -> int:
+        return int(self.status.item())

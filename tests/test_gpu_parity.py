@@ -1,0 +1,303 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle.
+
+Bars: sort keys and permutation bit-exact; grid mass, grid momentum and
+particle coefficients within 1e-5 normwise relative error; positions within
+2 float32 ulps of the domain extent.  Inputs are the seeded workloads of the
+`workloads` package (single-step 32^3 case, random and ragged scenes).
+"""
+import json
+import os
+from fractions import Fraction as Fr
+
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+from oracle import polypic_oracle as O
+from tests.gpu_util import (TOL_NORMWISE, dev, host, note, oracle_grid, rel, require_gpu,
+                            ulp_ok)
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "tiny_exact.json")
+
+
+def particle_set(scene, n_modes, dt=None, gravity=None, bc_layers=None, with_mass=True):
+    pp = require_gpu()
+    g = pp.grid_from_spec(scene.grid)
+    ps = pp.ParticleSet(
+        g, n_modes, dev(scene.x), dev(scene.coeff[:, :n_modes]),
+        mass=dev(scene.mass) if (with_mass and scene.mass is not None) else None,
+        uniform_mass=scene.uniform_mass,
+        F=dev(scene.F) if scene.F is not None else None,
+        dt=scene.dt if dt is None else dt,
+        gravity=scene.gravity if gravity is None else gravity,
+        bc_layers=scene.bc_layers if bc_layers is None else bc_layers)
+    return pp, g, ps
+
+
+# ---------------------------------------------------------------- sort
+
+@pytest.mark.parametrize("case", ["config0", "random_ragged", "tiny"])
+def test_sort_bit_exact(case):
+    if case == "config0":
+        s = W.config0(0)
+    elif case == "random_ragged":
+        s = W.random_scene(3, 40, 20000 + 37)
+    else:
+        s = W.random_scene(4, 8, 5)
+    note(f"sort parity: {case} P={s.P}")
+    pp, g, ps = particle_set(s, 1)
+    ps.sort()
+    torch.cuda.synchronize()
+    keys_ref, perm_ref = O.sort_keys(oracle_grid(g), s.x)
+    assert np.array_equal(host(ps.keys).view(np.uint32), keys_ref)
+    assert np.array_equal(host(ps.perm), perm_ref)
+    assert ps.status_flags() == 0
+
+
+def test_sort_presorted_and_reversed():
+    """Already-sorted input gives the identity; duplicated keys keep input order."""
+    s = W.config0(1)
+    g0 = O.grid_from_spec(s.grid)
+    _, perm = O.sort_keys(g0, s.x)
+    xs = s.x[:, perm]
+    pp, g, ps = particle_set(W.Scene("sorted", s.grid, xs, s.coeff[:, :, perm], None), 1)
+    ps.sort()
+    torch.cuda.synchronize()
+    assert np.array_equal(host(ps.perm), np.arange(s.P, dtype=np.int32))
+    xr = xs[:, ::-1].copy()
+    pp, g, ps = particle_set(W.Scene("rev", s.grid, xr, s.coeff[:, :, ::-1].copy(), None), 1)
+    ps.sort()
+    torch.cuda.synchronize()
+    _, perm_ref = O.sort_keys(g0, xr)
+    assert np.array_equal(host(ps.perm), perm_ref)
+
+
+# ---------------------------------------------------------------- P2G
+
+@pytest.mark.parametrize("n_modes", O.ALLOWED_N_MODES)
+@pytest.mark.parametrize("order", ["sorted", "unsorted"])
+def test_p2g_parity(n_modes, order):
+    s = W.config0(0)
+    note(f"p2g parity: config0 P={s.P} n_modes={n_modes} order={order}")
+    pp, g, ps = particle_set(s, n_modes)
+    if order == "sorted":
+        ps.sort()
+    ps.p2g(use_perm=(order == "sorted"))
+    torch.cuda.synchronize()
+    M_ref, Q_ref = O.p2g(oracle_grid(g), s.x, s.coeff, n_modes)
+    M = host(ps.grid_mass).reshape(M_ref.shape)
+    Q = host(ps.grid_mom).reshape(Q_ref.shape)
+    em, ep = rel(M, M_ref), rel(Q, Q_ref)
+    note(f"  mass {em:.2e}  momentum {ep:.2e}")
+    assert em <= TOL_NORMWISE and ep <= TOL_NORMWISE
+    assert ps.status_flags() == 0
+
+
+def test_p2g_random_masses_and_accumulate():
+    """Per-particle masses (Eq. 18's m_s + m_f) and accumulate = 1 adding a second pass."""
+    s = W.random_scene(5, 24, 9001, mass_random=True)
+    note(f"p2g mass/accumulate: P={s.P}")
+    pp, g, ps = particle_set(s, 27)
+    ps.sort()
+    ps.p2g()
+    pp.polypic_p2g(g, 27, ps.x, ps.coeff, ps.grid_mass, ps.grid_mom, mass=ps.mass,
+                   perm=ps.perm, accumulate=True)
+    torch.cuda.synchronize()
+    M_ref, Q_ref = O.p2g(oracle_grid(g), s.x, s.coeff, 27, s.mass)
+    assert rel(host(ps.grid_mass).reshape(M_ref.shape), 2 * M_ref) <= TOL_NORMWISE
+    assert rel(host(ps.grid_mom).reshape(Q_ref.shape), 2 * Q_ref) <= TOL_NORMWISE
+
+
+# ---------------------------------------------------------------- grid update + G2P
+
+@pytest.mark.parametrize("bc_layers", [0, 1, 2])
+def test_grid_update_parity(bc_layers):
+    s = W.config0(2)
+    pp, g, ps = particle_set(s, 8, dt=1e-3, bc_layers=bc_layers)
+    ps.sort()
+    ps.p2g()
+    ps.grid_update()
+    torch.cuda.synchronize()
+    og = oracle_grid(g)
+    M = host(ps.grid_mass).astype(np.float64).reshape(og.nz, og.ny, og.nx)
+    Q = host(ps.grid_mom).astype(np.float64).reshape(3, og.nz, og.ny, og.nx)
+    v_ref = O.grid_update(og, M, Q, 1e-3, s.gravity, bc_layers)
+    v = host(ps.grid_vel).reshape(v_ref.shape)
+    assert rel(v, v_ref) <= 1e-6
+    assert np.array_equal(v[:, M == 0], np.zeros_like(v[:, M == 0]))
+
+
+@pytest.mark.parametrize("n_modes", O.ALLOWED_N_MODES)
+def test_g2p_parity(n_modes):
+    """G2P from the device grid velocity (teacher-forced) against the oracle."""
+    s = W.config0(3)
+    note(f"g2p parity: config0 P={s.P} n_modes={n_modes}")
+    pp, g, ps = particle_set(s, n_modes, dt=1e-3, bc_layers=1)
+    ps.sort()
+    ps.p2g()
+    ps.grid_update()
+    ps.g2p()
+    torch.cuda.synchronize()
+    og = oracle_grid(g)
+    v = host(ps.grid_vel).astype(np.float64).reshape(3, og.nz, og.ny, og.nx)
+    perm = host(ps.perm)
+    xs = s.x[:, perm]
+    c_ref, x_ref, _ = O.g2p(og, v, xs, n_modes, dt=1e-3)
+    c = host(ps.coeff_next).reshape(3, n_modes, s.P)
+    ec = rel(c, c_ref)
+    per_mode = [rel(c[:, r], c_ref[:, r]) for r in range(n_modes)]
+    note(f"  coeff {ec:.2e}  worst mode {max(per_mode):.2e}")
+    assert ec <= TOL_NORMWISE
+    norms = [np.linalg.norm(c_ref[:, r]) for r in range(n_modes)]
+    for r in range(n_modes):
+        if norms[r] >= 1e-3 * norms[0]:
+            assert per_mode[r] <= TOL_NORMWISE, (r, per_mode[r])
+    assert ulp_ok(host(ps.x_next), x_ref, 2, 1.0 + 4 / 32)
+
+
+@pytest.mark.parametrize("n_modes", O.ALLOWED_N_MODES)
+@pytest.mark.parametrize("variant", ["dt0_nowalls", "gravity_walls"])
+def test_full_step_parity(n_modes, variant):
+    """Single-step parity case: sort -> P2G -> update -> G2P + advection on 32,768
+    particles, against the oracle's own step (its own sort, P2G, update, G2P)."""
+    s = W.config0(0)
+    dt, grav, bc = (0.0, (0.0, 0.0, 0.0), 0) if variant == "dt0_nowalls" else \
+        (1e-4, (0.0, -9.8, 0.0), 1)
+    note(f"step parity: config0 n_modes={n_modes} {variant}")
+    pp, g, ps = particle_set(s, n_modes, dt=dt, gravity=grav, bc_layers=bc)
+    ps.step()
+    torch.cuda.synchronize()
+    ref = O.step(oracle_grid(g), s.x, s.coeff, n_modes, dt, grav, bc, sort=True)
+    assert np.array_equal(host(ps.order), ref["perm"].astype(np.int64))
+    assert rel(host(ps.grid_mass).reshape(ref["grid_mass"].shape), ref["grid_mass"]) <= TOL_NORMWISE
+    assert rel(host(ps.grid_mom).reshape(ref["grid_mom"].shape), ref["grid_mom"]) <= TOL_NORMWISE
+    c = host(ps.coeff).reshape(3, n_modes, s.P)
+    assert rel(c, ref["coeff"]) <= TOL_NORMWISE
+    assert ulp_ok(host(ps.x), ref["x"], 2, 1.0 + 4 / 32)
+
+
+def test_f_and_mass_follow_the_permutation():
+    """Fabric-style set: per-point masses and deformation gradients (F' = (I + dt C) F)."""
+    s = W.config2_fabric(0, n=64, side=120)
+    note(f"fabric F update: P={s.P}")
+    pp, g, ps = particle_set(s, 27)
+    ps.step()
+    torch.cuda.synchronize()
+    ref = O.step(oracle_grid(g), s.x, s.coeff, 27, s.dt, s.gravity, s.bc_layers, mass=s.mass,
+                 F=s.F, sort=True)
+    assert np.array_equal(host(ps.mass), s.mass[ref["perm"]])
+    assert rel(host(ps.coeff).reshape(3, 27, s.P), ref["coeff"]) <= TOL_NORMWISE
+    assert rel(host(ps.F), ref["F"]) <= 1e-6
+    assert rel(host(ps.grid_mass).reshape(ref["grid_mass"].shape), ref["grid_mass"]) <= TOL_NORMWISE
+
+
+# ---------------------------------------------------------------- exact fixture and edges
+
+@pytest.mark.parametrize("case_idx", range(4))
+def test_exact_golden_fixture(case_idx):
+    """Six hand-placed particles (t = -1/2, 0, 1/2 - 2^-20) against exact rationals."""
+    pp = require_gpu()
+    with open(GOLDEN) as f:
+        doc = json.load(f)
+    case = doc["cases"][case_idx]
+    n_modes = case["n_modes"]
+    fr = lambda v: float(Fr(v))  # noqa: E731
+    g = pp.make_grid(doc["nodes"], fr(doc["dx"]), [fr(o) for o in doc["origin"]],
+                     fr(doc["inv_dx"]))
+    x = np.array([[fr(v) for v in p] for p in doc["x"]], np.float32).T.copy()
+    mass = np.array([fr(m) for m in doc["mass"]], np.float32)
+    cin = np.array([[[fr(v) for v in ca] for ca in c] for c in doc["coeff_in"]])
+    cin = np.ascontiguousarray(np.transpose(cin, (1, 2, 0))[:, :n_modes]).astype(np.float32)
+    ps = pp.ParticleSet(g, n_modes, dev(x), dev(cin), mass=dev(mass), dt=fr(doc["dt"]),
+                        gravity=[fr(v) for v in doc["gravity"]], bc_layers=doc["bc_layers"])
+    ps.p2g(use_perm=False)
+    ps.grid_update()
+    ps.g2p(use_perm=False)
+    torch.cuda.synchronize()
+    nx, ny, nz = doc["nodes"]
+    M = host(ps.grid_mass).reshape(nz, ny, nx)
+    Q = host(ps.grid_mom).reshape(3, nz, ny, nx)
+    m_ref = np.zeros_like(M, dtype=np.float64)
+    q_ref = np.zeros_like(Q, dtype=np.float64)
+    for nd, ms, psx in zip(case["nodes"], case["grid_mass"], case["grid_mom"]):
+        m_ref[nd[2], nd[1], nd[0]] = fr(ms)
+        q_ref[:, nd[2], nd[1], nd[0]] = [fr(v) for v in psx]
+    assert rel(M, m_ref) <= TOL_NORMWISE and rel(Q, q_ref) <= TOL_NORMWISE
+    c_ref = np.array([[[fr(v) for v in ca] for ca in cp] for cp in case["coeff"]])
+    c = np.transpose(host(ps.coeff_next).reshape(3, n_modes, -1), (2, 0, 1))
+    assert rel(c, c_ref) <= TOL_NORMWISE
+    assert ulp_ok(host(ps.x_next), np.array(case["x_out"], np.float32).T, 2, 2.0)
+
+
+def test_empty_and_single_particle():
+    pp = require_gpu()
+    g = pp.make_grid((12, 12, 12), 1 / 8)
+    gm = torch.full((12 ** 3,), 7.0, device="cuda")
+    gp = torch.full((3 * 12 ** 3,), 7.0, device="cuda")
+    x0 = torch.empty(0, device="cuda")
+    c0 = torch.empty(0, device="cuda")
+    pp.polypic_p2g(g, 27, x0, c0, gm, gp)          # P = 0: only the clear
+    torch.cuda.synchronize()
+    assert float(gm.abs().max()) == 0.0 and float(gp.abs().max()) == 0.0
+    x = np.array([[0.61], [0.7], [0.83]], np.float32)
+    c = np.random.default_rng(0).standard_normal((3, 27, 1)).astype(np.float32)
+    ps = pp.ParticleSet(g, 27, dev(x), dev(c), dt=0.0, gravity=(0, 0, 0), bc_layers=0)
+    ps.step()
+    torch.cuda.synchronize()
+    # one particle alone: the 27-mode round trip returns its own coefficients
+    assert rel(host(ps.coeff).reshape(3, 27, 1), c) <= 1e-5
+
+
+def test_degenerate_offsets_t_minus_half():
+    """Particles exactly on u = k + 1/2 (t = -1/2 on one or more axes)."""
+    pp = require_gpu()
+    n = 16
+    g = pp.make_grid((n + 4,) * 3, 1 / n)
+    rng = np.random.default_rng(1)
+    P = 4096
+    u = rng.integers(4, n, size=(3, P)) + rng.integers(0, 8, size=(3, P)) / 8.0
+    u[:, : P // 2] = np.floor(u[:, : P // 2]) + 0.5      # t = -1/2 on all axes
+    u[0, P // 2:] = np.floor(u[0, P // 2:]) + 0.5        # t = -1/2 on x only
+    x = (u / n).astype(np.float32)
+    c = (rng.standard_normal((3, 27, P)) * 0.3).astype(np.float32)
+    ps = pp.ParticleSet(g, 27, dev(x), dev(c), dt=1e-4, bc_layers=1)
+    ps.step()
+    torch.cuda.synchronize()
+    og = oracle_grid(g)
+    ref = O.step(og, x, c, 27, 1e-4, (0.0, -9.8, 0.0), 1, sort=True)
+    assert rel(host(ps.grid_mom).reshape(ref["grid_mom"].shape), ref["grid_mom"]) <= TOL_NORMWISE
+    assert rel(host(ps.coeff).reshape(3, 27, P), ref["coeff"]) <= TOL_NORMWISE
+
+
+def test_out_of_range_particle_is_flagged_and_skipped():
+    pp = require_gpu()
+    g = pp.make_grid((12, 12, 12), 1 / 8)
+    x = np.array([[0.6, 0.01, 0.7], [0.6, 0.6, 0.7], [0.6, 0.6, 5.0]], np.float32)
+    c = np.ones((3, 4, 3), np.float32)
+    ps = pp.ParticleSet(g, 4, dev(x), dev(c), dt=0.0, gravity=(0, 0, 0), bc_layers=0)
+    ps.p2g(use_perm=False)
+    torch.cuda.synchronize()
+    assert ps.status_flags() & 1
+    assert abs(float(ps.grid_mass.sum()) - 1.0) < 1e-6   # only the in-range particle
+    ps.status.zero_()
+    ps.sort()
+    torch.cuda.synchronize()
+    assert ps.status_flags() & 1
+    assert sorted(host(ps.perm).tolist()) == [0, 1, 2]
+
+
+def test_invalid_permutation_never_faults():
+    """A caller permutation with out-of-range entries is clamped (wrong data, no fault)."""
+    pp = require_gpu()
+    s = W.random_scene(8, 16, 1000)
+    g = pp.grid_from_spec(s.grid)
+    ps = pp.ParticleSet(g, 4, dev(s.x), dev(s.coeff[:, :4]))
+    bad = torch.full((s.P,), 1 << 30, dtype=torch.int32, device="cuda")
+    bad[::2] = -7
+    pp.polypic_p2g(g, 4, ps.x, ps.coeff, ps.grid_mass, ps.grid_mom, perm=bad)
+    pp.polypic_g2p(g, 4, 1e-4, ps.grid_vel.zero_(), ps.x, ps.coeff_next, perm=bad)
+    torch.cuda.synchronize()
+    assert torch.isfinite(ps.grid_mass).all()

@@ -167,7 +167,8 @@ def config2_fluid(seed: int = 0, n: int = 256) -> Scene:
 
 
 def config2_fabric(seed: int = 0, n: int = 256, side: int = 1000) -> Scene:
-    """Fabric sheet: side x side lattice, spacing dx/4, in the x-z plane at y = 64.3 cells.
+    """Fabric sheet: side x side lattice, spacing dx/4, in the x-z plane at y = n/4 + 0.3 cells
+    (64.3 cells on the 256^3 grid).
 
     Per-point mass = m_s + m_f with m_s = 1 and absorbed fluid m_f ~ U[0, 0.5];
     F = I + N(0, 0.01) per entry.
@@ -181,7 +182,7 @@ def config2_fabric(seed: int = 0, n: int = 256, side: int = 1000) -> Scene:
     P = side * side
     x = np.empty((3, P), np.float32)
     x[0] = (g.origin[0] + (2.0 + start + kk.ravel() * spacing) * g.dx).astype(np.float32)
-    x[1] = np.float32(g.origin[1] + (2.0 + 64.3) * g.dx)
+    x[1] = np.float32(g.origin[1] + (2.0 + n / 4.0 + 0.3) * g.dx)
     x[2] = (g.origin[2] + (2.0 + start + ii.ravel() * spacing) * g.dx).astype(np.float32)
     c = _coefficients(rng, P, 1.0, 0.1)
     m_f = rng.random(P) * 0.5
