@@ -66,6 +66,12 @@ def load() -> ctypes.CDLL:
         raise ImportError(
             f"{LIB_PATH} is missing: build the HIP library first "
             "(python paper_2308_01060_amd/build.py)")
+    # torch ships its own HIP runtime under the same soname (libamdhip64.so.7).
+    # Loading torch first makes libpolypic.so bind to that runtime, so the
+    # library and torch share one HIP context, its devices, memory and streams.
+    # Loaded the other way round, the process would hold two HIP runtimes and
+    # the library's would see no device.
+    import torch  # noqa: F401
     lib = ctypes.CDLL(LIB_PATH)
     P = ctypes.c_void_p
     i32, i64, f32, sz = ctypes.c_int32, ctypes.c_int64, ctypes.c_float, ctypes.c_size_t
