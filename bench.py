@@ -1,0 +1,261 @@
+#!/usr/bin/env python3
+"""Benchmark of the PolyPIC transfer step on one MI355X.
+
+Workload: the dam-break case -- a 128^3-cell grid (132^3 nodes, dx = 1/128) with a
+64 x 128 x 64-cell block of fluid at 8 particles per cell (4,194,304 particles,
+jittered, at rest), 27 polynomial modes, dt = 1e-4, gravity -9.8, slip walls.
+Synthetic seeded inputs (workloads.config1); no dataset is involved.
+
+A step is one pass of the whole transfer path on device-resident data:
+    cell-key radix sort -> P2G (27 modes) -> grid update -> G2P + advection
+The timed region is K consecutive steps between two device synchronisations;
+per-phase times come from HIP events recorded on the stream the kernels run on.
+
+Prints one JSON line.  `value` = particles x steps / wall time of the timed
+region (whole-step throughput); the P2G + G2P-only rate, per-phase times, the
+4-mode (APIC) comparison, the roofline of the dominant kernel and the oracle's
+CPU rate on a bounded sample are reported beside it.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1]
+    python bench.py --calib-copy      # plain device copy, for rocprofv3 byte calibration
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "particle transfers/sec (P2G+G2P, 27 modes, FP32) + bwd/fwd time ratio"
+UNIT = "particle-transfers/s"
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E peak (AMD published figure)
+PROFILES = os.path.join(ROOT, "profiles")
+
+# Algorithmic bytes per particle (float32, one pass over each stream):
+#   P2G reads x (12 B), mass or the sort permutation (4 B) and 3 * n_modes coefficients;
+#   G2P reads x (12 B), writes 3 * n_modes coefficients and x (12 B).
+def p2g_bytes_per_particle(n_modes: int) -> int:
+    return 12 + 4 + 12 * n_modes
+
+
+def g2p_bytes_per_particle(n_modes: int) -> int:
+    return 12 + 12 * n_modes + 12
+
+
+KERNEL_SOURCES = {
+    "p2g": "paper_2308_01060_amd/csrc/polypic_p2g.hip",
+    "g2p": "paper_2308_01060_amd/csrc/polypic_g2p.hip",
+}
+
+
+def source_digest(kernel: str) -> str:
+    with open(os.path.join(ROOT, KERNEL_SOURCES[kernel]), "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def measured_traffic(kernel: str, workload: str):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, or None.
+
+    profiles/traffic_<kernel>_<workload>.txt holds key = value lines, among them
+    source_sha (digest of the kernel source when the counters were taken) and
+    bytes_per_launch.  A changed source makes the figure stale: None.
+    """
+    path = os.path.join(PROFILES, f"traffic_{kernel}_{workload}.txt")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    with open(path) as f:
+        for line in f:
+            if "=" in line and not line.lstrip().startswith("#"):
+                k, v = line.split("=", 1)
+                vals[k.strip()] = v.strip()
+    if vals.get("source_sha") != source_digest(kernel):
+        return None
+    try:
+        return float(vals["bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def parse_args():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawTextHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--n-modes", type=int, default=27)
+    ap.add_argument("--cells", type=int, default=128, help="grid cells per axis (dam break)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample", type=int, default=262144,
+                    help="particles in the oracle's timed sample")
+    ap.add_argument("--no-apic", action="store_true", help="skip the 4-mode comparison run")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="run only a plain device copy of known size (counter calibration)")
+    return ap.parse_args()
+
+
+def calib_copy():
+    import torch
+
+    n = 256 * 1024 * 1024  # 1 GiB of float32
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(5):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"calib_copy_bytes_read_per_launch": 4 * n,
+                      "calib_copy_bytes_written_per_launch": 4 * n, "launches": 5}))
+
+
+def time_steps(ps, steps: int, torch):
+    """Run `steps` full steps; returns (wall_s, per-phase mean ms dict)."""
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(5)] for _ in range(steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(steps):
+        e = ev[k]
+        e[0].record()
+        ps.sort()
+        e[1].record()
+        ps.p2g()
+        e[2].record()
+        ps.grid_update()
+        e[3].record()
+        ps.g2p()
+        e[4].record()
+        ps.swap()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    names = ("sort", "p2g", "grid_update", "g2p")
+    phase = {n: 0.0 for n in names}
+    for e in ev:
+        for j, n in enumerate(names):
+            phase[n] += e[j].elapsed_time(e[j + 1])
+    return wall, {n: v / steps for n, v in phase.items()}
+
+
+def cpu_baseline(scene, n_modes: int, sample: int):
+    """The FP64 oracle, as it is, timed on host cores over a bounded sample."""
+    from oracle import polypic_oracle as O
+
+    og = O.grid_from_spec(scene.grid)
+    S = min(sample, scene.P)
+    xs = scene.x[:, :S]
+    cs = scene.coeff[:, :n_modes, :S]
+    t0 = time.perf_counter()
+    M, Q = O.p2g(og, xs, cs, n_modes)
+    v = O.grid_update(og, M, Q, scene.dt, scene.gravity, scene.bc_layers)
+    O.g2p(og, v, xs, n_modes, scene.dt)
+    t = time.perf_counter() - t0
+    return {
+        "value": S / t,
+        "unit": UNIT,
+        "cores": 1,
+        "kind": "oracle",
+        "sample": f"{S} particles (the first {S // (scene.P // (scene.grid.cells[2] // 2))} "
+                  f"z-layers of cells of the dam-break block), one P2G + grid update + G2P at "
+                  f"{n_modes} modes in float64 numpy, {t:.1f} s",
+    }
+
+
+def main():
+    args = parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU "
+              "sharding of this path is a design note, not a measured configuration.",
+              file=sys.stderr)
+        sys.exit(2)
+    if args.calib_copy:
+        calib_copy()
+        return
+
+    import numpy as np
+    import torch
+
+    import paper_2308_01060_amd as pp
+    import workloads as W
+
+    torch.cuda.set_device(0)
+    scene = W.config1(0, n=args.cells)
+    n_modes = args.n_modes
+    P = scene.P
+    workload = f"dambreak_{args.cells}cube_{P}"
+    g = pp.grid_from_spec(scene.grid)
+    x = torch.from_numpy(scene.x).cuda()
+    c = torch.from_numpy(np.ascontiguousarray(scene.coeff[:, :n_modes])).cuda()
+    ps = pp.ParticleSet(g, n_modes, x, c, dt=scene.dt, gravity=scene.gravity,
+                        bc_layers=scene.bc_layers, track_order=False)
+    for _ in range(args.warmup):
+        ps.step()
+    torch.cuda.synchronize()
+    wall, phase = time_steps(ps, args.steps, torch)
+    if ps.status_flags() != 0:
+        raise RuntimeError(f"device status flags {ps.status_flags()} during the benchmark")
+    ms_per_step = wall * 1e3 / args.steps
+    value = P * args.steps / wall
+    transfer_ms = phase["p2g"] + phase["g2p"]
+
+    # 4-mode (APIC) comparison at the same size
+    apic = None
+    if not args.no_apic and n_modes != 4:
+        c4 = torch.from_numpy(np.ascontiguousarray(scene.coeff[:, :4])).cuda()
+        ps4 = pp.ParticleSet(g, 4, torch.from_numpy(scene.x).cuda(), c4, dt=scene.dt,
+                             gravity=scene.gravity, bc_layers=scene.bc_layers,
+                             track_order=False)
+        for _ in range(args.warmup):
+            ps4.step()
+        w4, ph4 = time_steps(ps4, args.steps, torch)
+        apic = {"n_modes": 4, "ms_per_step": w4 * 1e3 / args.steps,
+                "transfers_per_s": P * args.steps / w4,
+                "p2g_g2p_transfers_per_s": P / ((ph4["p2g"] + ph4["g2p"]) * 1e-3),
+                "phase_ms": {k: round(v, 4) for k, v in ph4.items()}}
+        del ps4, c4
+
+    # roofline of the dominant kernel (HIP-event durations of its launches)
+    dom = "p2g" if phase["p2g"] >= phase["g2p"] else "g2p"
+    bpp = p2g_bytes_per_particle(n_modes) if dom == "p2g" else g2p_bytes_per_particle(n_modes)
+    achieved = bpp * P / (phase[dom] * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": measured_traffic(dom, workload), "kernel": dom,
+                "bytes_per_particle": bpp,
+                "note": ("event time of the polypic_p2g call (grid clear + P2G kernel)"
+                         if dom == "p2g" else "event time of the polypic_g2p call (one kernel)")}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(scene, n_modes, args.cpu_sample)
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": UNIT,
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic (seeded jittered dam-break block, workloads.config1)",
+        "config": {"workload": workload, "n_modes": n_modes, "particles": P,
+                   "grid_nodes": list(scene.grid.nodes), "ppc": 8, "dt": scene.dt,
+                   "step": "sort + p2g + grid_update + g2p(+advection)"},
+        "p2g_g2p_transfers_per_s": P / (transfer_ms * 1e-3),
+        "phase_ms": {k: round(v, 4) for k, v in phase.items()},
+        "apic_4mode": apic,
+        "bwd_fwd_ratio": None,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

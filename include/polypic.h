@@ -128,19 +128,29 @@ int32_t polypic_sort(const polypic_grid* grid, int64_t P, const float* x, uint32
  * n_modes       1, 4, 8 or 27.
  * x[3][P]       positions.  mass[P] per-particle mass, or NULL for uniform_mass.
  * coeff         [3][n_modes][P] coefficients.
- * perm          NULL, or the processing order (a permutation of 0..P-1, e.g.
- *               from polypic_sort): slot i handles particle perm[i].  Results
- *               do not depend on the order beyond float summation order; a
- *               cell-sorted order is what makes the on-chip bricks effective.
+ * perm          NULL, or the processing order (a permutation of 0..P-1): slot i
+ *               handles particle perm[i].
+ * keys_sorted   NULL, or the sorted cell keys of that order (keys_sorted and
+ *               perm as returned together by polypic_sort for this x and grid).
+ *               With them P2G takes its fast path: particles of one cell are
+ *               reduced in registers, cells of a 4^3 tile in LDS, and every
+ *               grid node is written with one atomic per tile.  Without them
+ *               every particle adds its 27 nodes through LDS/HBM float atomics
+ *               (correct for any order, much slower).
+ * ws, ws_bytes  device workspace, at least polypic_p2g_workspace_bytes(); used
+ *               only with keys_sorted (may be NULL otherwise).
  * grid_mass[N], grid_mom[3][N]   outputs (device).
  * accumulate    0: outputs are zeroed first; 1: sums are added to their contents.
  * Summation order is not fixed (float atomics), so results are deterministic
- * only up to rounding.
+ * only up to rounding.  A particle whose stencil leaves the grid (or, on the
+ * fast path, whose key does not match its position) is skipped and raises
+ * POLYPIC_FLAG_RANGE.
  * ------------------------------------------------------------------------ */
+int32_t polypic_p2g_workspace_bytes(const polypic_grid* grid, int64_t P, size_t* bytes);
 int32_t polypic_p2g(const polypic_grid* grid, int64_t P, int32_t n_modes, const float* x,
                     const float* mass, float uniform_mass, const float* coeff, const int32_t* perm,
-                    float* grid_mass, float* grid_mom, int32_t accumulate, int32_t* status_dev,
-                    void* stream);
+                    const uint32_t* keys_sorted, void* ws, size_t ws_bytes, float* grid_mass,
+                    float* grid_mom, int32_t accumulate, int32_t* status_dev, void* stream);
 
 /* ------------------------------------------------------------------------
  * Grid update.  Eq. 5 (v = (mv) / m) followed by an explicit update that the

@@ -26,6 +26,7 @@ EXPORTED = (
     "polypic_last_device_error",
     "polypic_sort_workspace_bytes",
     "polypic_sort",
+    "polypic_p2g_workspace_bytes",
     "polypic_p2g",
     "polypic_grid_update",
     "polypic_g2p",
@@ -86,8 +87,10 @@ def load() -> ctypes.CDLL:
     lib.polypic_sort_workspace_bytes.argtypes = [G, i64, ctypes.POINTER(sz)]
     lib.polypic_sort.restype = i32
     lib.polypic_sort.argtypes = [G, i64, P, P, P, P, sz, P, P]
+    lib.polypic_p2g_workspace_bytes.restype = i32
+    lib.polypic_p2g_workspace_bytes.argtypes = [G, i64, ctypes.POINTER(sz)]
     lib.polypic_p2g.restype = i32
-    lib.polypic_p2g.argtypes = [G, i64, i32, P, P, f32, P, P, P, P, i32, P, P]
+    lib.polypic_p2g.argtypes = [G, i64, i32, P, P, f32, P, P, P, P, sz, P, P, i32, P, P]
     lib.polypic_grid_update.restype = i32
     lib.polypic_grid_update.argtypes = [G, f32, ctypes.POINTER(f32), i32, P, P, P, P]
     lib.polypic_g2p.restype = i32

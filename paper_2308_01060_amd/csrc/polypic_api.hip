@@ -103,10 +103,19 @@ int32_t polypic_sort(const polypic_grid* grid, int64_t P, const float* x, uint32
                               (hipStream_t)stream));
 }
 
+int32_t polypic_p2g_workspace_bytes(const polypic_grid* grid, int64_t P, size_t* bytes) {
+  int32_t st = check_grid(grid);
+  if (st) return st;
+  if ((st = check_P(P))) return st;
+  if (!bytes) return POLYPIC_EINVAL;
+  *bytes = p2g_workspace_bytes(to_dev(grid), P);
+  return POLYPIC_OK;
+}
+
 int32_t polypic_p2g(const polypic_grid* grid, int64_t P, int32_t n_modes, const float* x,
                     const float* mass, float uniform_mass, const float* coeff, const int32_t* perm,
-                    float* grid_mass, float* grid_mom, int32_t accumulate, int32_t* status_dev,
-                    void* stream) {
+                    const uint32_t* keys_sorted, void* ws, size_t ws_bytes, float* grid_mass,
+                    float* grid_mom, int32_t accumulate, int32_t* status_dev, void* stream) {
   int32_t st = check_grid(grid);
   if (st) return st;
   if ((st = check_P(P))) return st;
@@ -114,11 +123,17 @@ int32_t polypic_p2g(const polypic_grid* grid, int64_t P, int32_t n_modes, const 
   if (!grid_mass || !grid_mom) return POLYPIC_EINVAL;
   if (P > 0 && (!x || !coeff)) return POLYPIC_EINVAL;
   if (!mass && !isfinite(uniform_mass)) return POLYPIC_EINVAL;
+  const bool sorted = keys_sorted != nullptr;
+  if (sorted) {
+    if (!perm || !ws) return POLYPIC_EINVAL;
+    if (ws_bytes < p2g_workspace_bytes(to_dev(grid), P)) return POLYPIC_ENOSPACE;
+  }
   const hipStream_t s = (hipStream_t)stream;
   const int64_t N = n_nodes(grid);
   discard_stale_error();
+  uint32_t* counter = sorted ? (uint32_t*)ws : nullptr;
   if (!accumulate) {
-    if ((st = from_hip(launch_grid_clear(grid_mass, grid_mom, N, s)))) return st;
+    if ((st = from_hip(launch_grid_clear(grid_mass, grid_mom, N, counter, s)))) return st;
   }
   P2GArgs a;
   a.g = to_dev(grid);
@@ -133,6 +148,10 @@ int32_t polypic_p2g(const polypic_grid* grid, int64_t P, int32_t n_modes, const 
   a.gp1 = grid_mom + N;
   a.gp2 = grid_mom + 2 * N;
   a.status = status_dev;
+  a.keys = keys_sorted;
+  a.tile_list = nullptr;
+  a.tile_count = nullptr;
+  if (sorted) return from_hip(launch_p2g_sorted(a, n_modes, ws, !accumulate, s));
   return from_hip(launch_p2g(a, n_modes, p2g_default_config(), s));
 }
 

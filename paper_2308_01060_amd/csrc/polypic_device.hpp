@@ -139,6 +139,87 @@ __device__ __forceinline__ Proj1D proj_g2p(float t) {
   return P;
 }
 
+// ---------------------------------------------------------------- P2G mode evaluation
+template <int NR>
+__device__ constexpr bool any_kz(int kx, int ky) {
+  return has_mode<NR>(kx, ky, 0) || has_mode<NR>(kx, ky, 1) || has_mode<NR>(kx, ky, 2);
+}
+
+template <int NR>
+__device__ constexpr bool any_kykz(int kx) {
+  return any_kz<NR>(kx, 0) || any_kz<NR>(kx, 1) || any_kz<NR>(kx, 2);
+}
+
+__device__ __forceinline__ float phi_1d(const Basis1D& B, int k, int j) {
+  return k == 0 ? 1.0f : (k == 1 ? B.z[j] : B.g[j]);
+}
+
+// V[jx + 3 jy + 9 jz] = sum_{r < NR} c[r] s_r(node j)
+template <int NR>
+__device__ __forceinline__ void eval_modes(const float (&c)[27], const Basis1D& bx,
+                                           const Basis1D& by, const Basis1D& bz, float (&V)[27]) {
+  float A[3][3][3];  // [kx][ky][jz]
+#pragma unroll
+  for (int kx = 0; kx < 3; ++kx)
+#pragma unroll
+    for (int ky = 0; ky < 3; ++ky) {
+      if (!any_kz<NR>(kx, ky)) continue;
+#pragma unroll
+      for (int jz = 0; jz < 3; ++jz) {
+        float s = 0.0f;
+        bool first = true;
+#pragma unroll
+        for (int kz = 0; kz < 3; ++kz) {
+          if (!has_mode<NR>(kx, ky, kz)) continue;
+          const float term = c[mode_index(kx, ky, kz)];
+          s = first ? (kz == 0 ? term : term * phi_1d(bz, kz, jz))
+                    : (kz == 0 ? s + term : fmaf(term, phi_1d(bz, kz, jz), s));
+          first = false;
+        }
+        A[kx][ky][jz] = s;
+      }
+    }
+  float Bm[3][3][3];  // [kx][jy][jz]
+#pragma unroll
+  for (int kx = 0; kx < 3; ++kx) {
+    if (!any_kykz<NR>(kx)) continue;
+#pragma unroll
+    for (int jy = 0; jy < 3; ++jy)
+#pragma unroll
+      for (int jz = 0; jz < 3; ++jz) {
+        float s = 0.0f;
+        bool first = true;
+#pragma unroll
+        for (int ky = 0; ky < 3; ++ky) {
+          if (!any_kz<NR>(kx, ky)) continue;
+          const float term = A[kx][ky][jz];
+          s = first ? (ky == 0 ? term : term * phi_1d(by, ky, jy))
+                    : (ky == 0 ? s + term : fmaf(term, phi_1d(by, ky, jy), s));
+          first = false;
+        }
+        Bm[kx][jy][jz] = s;
+      }
+  }
+#pragma unroll
+  for (int jx = 0; jx < 3; ++jx)
+#pragma unroll
+    for (int jy = 0; jy < 3; ++jy)
+#pragma unroll
+      for (int jz = 0; jz < 3; ++jz) {
+        float s = 0.0f;
+        bool first = true;
+#pragma unroll
+        for (int kx = 0; kx < 3; ++kx) {
+          if (!any_kykz<NR>(kx)) continue;
+          const float term = Bm[kx][jy][jz];
+          s = first ? (kx == 0 ? term : term * phi_1d(bx, kx, jx))
+                    : (kx == 0 ? s + term : fmaf(term, phi_1d(bx, kx, jx), s));
+          first = false;
+        }
+        V[jx + 3 * jy + 9 * jz] = s;
+      }
+}
+
 // ---------------------------------------------------------------- Morton key
 __device__ __forceinline__ uint32_t spread_bits3(uint32_t v) {
   v &= 0x3ffu;
@@ -146,6 +227,15 @@ __device__ __forceinline__ uint32_t spread_bits3(uint32_t v) {
   v = (v | (v << 8)) & 0x0300F00Fu;
   v = (v | (v << 4)) & 0x030C30C3u;
   v = (v | (v << 2)) & 0x09249249u;
+  return v;
+}
+
+__device__ __forceinline__ uint32_t compact_bits3(uint32_t v) {
+  v &= 0x09249249u;
+  v = (v | (v >> 2)) & 0x030C30C3u;
+  v = (v | (v >> 4)) & 0x0300F00Fu;
+  v = (v | (v >> 8)) & 0x030000FFu;
+  v = (v | (v >> 16)) & 0x000003FFu;
   return v;
 }
 

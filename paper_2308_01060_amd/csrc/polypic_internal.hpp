@@ -31,6 +31,9 @@ struct P2GArgs {
   float* gp1;
   float* gp2;
   int32_t* status;
+  const uint32_t* keys;        // sorted cell keys (cell-gather path) or nullptr
+  const uint32_t* tile_list;   // set by the launcher
+  const uint32_t* tile_count;
 };
 
 // Launch configuration chosen by the host (autotuned or default).
@@ -41,8 +44,15 @@ struct P2GConfig {
 
 P2GConfig p2g_default_config();
 bool p2g_config_supported(const P2GConfig& c);
-hipError_t launch_grid_clear(float* gm, float* gp, int64_t n_nodes, hipStream_t stream);
+// zeroes grid mass/momentum and, if given, the cell-gather tile counter
+hipError_t launch_grid_clear(float* gm, float* gp, int64_t n_nodes, uint32_t* counter,
+                             hipStream_t stream);
 hipError_t launch_p2g(const P2GArgs& a, int n_modes, const P2GConfig& cfg, hipStream_t stream);
+int64_t p2g_max_tiles(const GridDev& g, int64_t P);
+size_t p2g_workspace_bytes(const GridDev& g, int64_t P);
+// sorted-input path; ws holds the tile counter and list (p2g_workspace_bytes)
+hipError_t launch_p2g_sorted(const P2GArgs& a, int n_modes, void* ws, bool counter_zeroed,
+                             hipStream_t stream);
 
 // ---- grid update
 struct GridUpdateArgs {

@@ -1,117 +1,69 @@
 // P2G scatter (Eq. 1, 4 and 13) for gfx950.
 //
-// One thread per particle, particles taken in the caller's processing order
-// (a cell sort makes neighbours adjacent).  Per particle, in registers:
-// the stencil, the quadratic B-spline weights and the 1-D mode factors of
-// Eq. 11 / Eq. 14, then the nodal values sum_r c_r s_r at the 27 stencil nodes
-// by a separable 3-stage contraction (z, then y, then x) that skips the
-// modes beyond n_modes at compile time.
+// Per particle, in registers: the stencil, the quadratic B-spline weights and
+// the 1-D mode factors of Eq. 11 / Eq. 14, then the nodal values
+// sum_r c_r s_r at the 27 stencil nodes by a separable 3-stage contraction
+// that skips the modes beyond n_modes at compile time.
 //
-// Accumulation: the block's particles are split into runs that share a brick
-// tile (an aligned cube of 2^tile_log2 cells, keyed by the base node).  Each
-// run accumulates mass and momentum into an LDS brick of (T + 2)^3 nodes with
-// LDS float atomics; a block-wide flush then adds every non-zero brick node to
-// HBM with one global atomic per channel.  Runs beyond the LDS brick budget
-// (unsorted input) add straight to HBM.
+// Two accumulation strategies:
+//
+// * Cell runs (sorted input: perm and sorted keys from polypic_sort).  One
+//   workgroup per occupied tile of 4^3 cells (a Morton-aligned run of 64 cell
+//   keys); each of its 4 wavefronts owns one channel (mass, 3 momentum
+//   components) and walks the tile's particles in rounds of 64, one particle
+//   per lane (coalesced loads).  Per round a wave writes its channel's 27
+//   nodal values to a wave-private LDS buffer, finds the runs of equal cells
+//   (particles of a cell are contiguous in sorted order and share one base
+//   node) with ballots, sums each (run, stencil node) pair and adds it to an
+//   FP64 brick of 6^3 nodes with one LDS double atomic -- eight times fewer
+//   atomics than per particle, and mostly on distinct addresses, where
+//   gfx950's LDS double atomics are fast (float ones are not: about 190
+//   cycles per wavefront instruction).  The waves of a workgroup meet only at
+//   the end of the tile, where the bricks go to HBM with one coalesced float
+//   atomic per node and channel.
+//
+// * Brick scatter (any order; perm from polypic_sort makes it effective).  One
+//   thread per particle in processing order; runs of particles in the same 4^3
+//   tile accumulate into FP64 LDS bricks with LDS double atomics (each lane
+//   starting its node loop at a different node so that particles of one cell
+//   do not collide on an address), and the bricks are added to HBM with one
+//   float atomic per node and channel.  Runs beyond the LDS budget (unsorted
+//   input) add straight to HBM.
 #include "polypic_internal.hpp"
 
 namespace polypic {
 
 namespace {
 
-template <int NR>
-__device__ constexpr bool any_kz(int kx, int ky) {
-  return has_mode<NR>(kx, ky, 0) || has_mode<NR>(kx, ky, 1) || has_mode<NR>(kx, ky, 2);
-}
-
-template <int NR>
-__device__ constexpr bool any_kykz(int kx) {
-  return any_kz<NR>(kx, 0) || any_kz<NR>(kx, 1) || any_kz<NR>(kx, 2);
-}
-
-__device__ __forceinline__ float phi(const Basis1D& B, int k, int j) {
-  return k == 0 ? 1.0f : (k == 1 ? B.z[j] : B.g[j]);
-}
-
-// V[jx + 3 jy + 9 jz] = sum_{r < NR} c[r] s_r(node j)
-template <int NR>
-__device__ __forceinline__ void eval_modes(const float (&c)[27], const Basis1D& bx,
-                                           const Basis1D& by, const Basis1D& bz, float (&V)[27]) {
-  float A[3][3][3];  // [kx][ky][jz]
-#pragma unroll
-  for (int kx = 0; kx < 3; ++kx)
-#pragma unroll
-    for (int ky = 0; ky < 3; ++ky) {
-      if (!any_kz<NR>(kx, ky)) continue;
-#pragma unroll
-      for (int jz = 0; jz < 3; ++jz) {
-        float s = 0.0f;
-        bool first = true;
-#pragma unroll
-        for (int kz = 0; kz < 3; ++kz) {
-          if (!has_mode<NR>(kx, ky, kz)) continue;
-          const float term = c[mode_index(kx, ky, kz)];
-          s = first ? (kz == 0 ? term : term * phi(bz, kz, jz))
-                    : (kz == 0 ? s + term : fmaf(term, phi(bz, kz, jz), s));
-          first = false;
-        }
-        A[kx][ky][jz] = s;
-      }
-    }
-  float Bm[3][3][3];  // [kx][jy][jz]
-#pragma unroll
-  for (int kx = 0; kx < 3; ++kx) {
-    if (!any_kykz<NR>(kx)) continue;
-#pragma unroll
-    for (int jy = 0; jy < 3; ++jy)
-#pragma unroll
-      for (int jz = 0; jz < 3; ++jz) {
-        float s = 0.0f;
-        bool first = true;
-#pragma unroll
-        for (int ky = 0; ky < 3; ++ky) {
-          if (!any_kz<NR>(kx, ky)) continue;
-          const float term = A[kx][ky][jz];
-          s = first ? (ky == 0 ? term : term * phi(by, ky, jy))
-                    : (ky == 0 ? s + term : fmaf(term, phi(by, ky, jy), s));
-          first = false;
-        }
-        Bm[kx][jy][jz] = s;
-      }
-  }
-#pragma unroll
-  for (int jx = 0; jx < 3; ++jx)
-#pragma unroll
-    for (int jy = 0; jy < 3; ++jy)
-#pragma unroll
-      for (int jz = 0; jz < 3; ++jz) {
-        float s = 0.0f;
-        bool first = true;
-#pragma unroll
-        for (int kx = 0; kx < 3; ++kx) {
-          if (!any_kykz<NR>(kx)) continue;
-          const float term = Bm[kx][jy][jz];
-          s = first ? (kx == 0 ? term : term * phi(bx, kx, jx))
-                    : (kx == 0 ? s + term : fmaf(term, phi(bx, kx, jx), s));
-          first = false;
-        }
-        V[jx + 3 * jy + 9 * jz] = s;
-      }
-}
-
 template <int TB>
 constexpr int kmax_for() {
-  return TB == 1 ? 16 : (TB == 2 ? 6 : 2);
+  return TB == 1 ? 16 : (TB == 2 ? 4 : 1);
+}
+
+// Rotates v left by r (0 <= r < 8): out[j] = v[(j + r) % 27], as a 3-stage barrel
+// shifter of selects (registers cannot be indexed by a per-lane value).
+__device__ __forceinline__ void rotate27(float (&v)[27], int r) {
+  float t[27];
+#pragma unroll
+  for (int j = 0; j < 27; ++j) t[j] = (r & 1) ? v[(j + 1) % 27] : v[j];
+#pragma unroll
+  for (int j = 0; j < 27; ++j) v[j] = (r & 2) ? t[(j + 2) % 27] : t[j];
+#pragma unroll
+  for (int j = 0; j < 27; ++j) t[j] = (r & 4) ? v[(j + 4) % 27] : v[j];
+#pragma unroll
+  for (int j = 0; j < 27; ++j) v[j] = t[j];
 }
 
 template <int NR, int TB, int BS>
-__global__ __launch_bounds__(BS) void p2g_kernel(P2GArgs a) {
+__global__ __launch_bounds__(BS) void p2g_brick_kernel(P2GArgs a) {
   constexpr int T = 1 << TB;
   constexpr int E = T + 2;          // brick edge in nodes
   constexpr int BV = E * E * E;     // brick volume in nodes
   constexpr int KMAX = kmax_for<TB>();
   constexpr int NW = BS / kWave;
-  __shared__ float brick[4 * KMAX * BV];  // [channel][brick][node]
+  // Bricks accumulate in FP64: LDS double atomics run at about 8 cycles per
+  // wavefront instruction on gfx950, float ones at about 190.
+  __shared__ double brick[4 * KMAX * BV];  // [channel][brick][node]
   __shared__ uint32_t tile_of[BS];
   __shared__ uint32_t seg_tile[KMAX];
   __shared__ int wave_heads[NW];
@@ -143,7 +95,7 @@ __global__ __launch_bounds__(BS) void p2g_kernel(P2GArgs a) {
                                  ((uint32_t)(b2 >> TB) << 20))
                               : 0xFFFFFFFFu;
   tile_of[tid] = tile;
-  for (int k = tid; k < 4 * KMAX * BV; k += BS) brick[k] = 0.0f;
+  for (int k = tid; k < 4 * KMAX * BV; k += BS) brick[k] = 0.0;
   __syncthreads();
 
   // runs of equal tiles in processing order -> segment index per particle
@@ -168,54 +120,66 @@ __global__ __launch_bounds__(BS) void p2g_kernel(P2GArgs a) {
     const Basis1D bz = basis_p2g(t2);
     const float m = a.mass ? a.mass[p] : a.uniform_mass;
     const bool lds = seg < KMAX;
-    const int lbase = lds ? ((((b2 & (T - 1)) * E) + (b1 & (T - 1))) * E + (b0 & (T - 1))) : 0;
-    float* lb = brick + (lds ? seg : 0) * BV + lbase;
-    const int nxny = nx * ny;
-    const int gbase = (b2 * ny + b1) * nx + b0;
-    float* gch[4] = {a.gm + gbase, a.gp0 + gbase, a.gp1 + gbase, a.gp2 + gbase};
-
+    // Lanes of one cell (adjacent in sorted order) would hit the same brick
+    // addresses in the same instruction; each lane instead starts its node loop
+    // at a different node (rotation lane % 8), which spreads them out.
+    const int rot = lds ? (lane & 7) : 0;
+    int off[27];  // brick (LDS) or grid (HBM) offset of stencil node (j + rot) % 27
+    {
+      const int lbase = (((b2 & (T - 1)) * E) + (b1 & (T - 1))) * E + (b0 & (T - 1));
+      const int gbase = (b2 * ny + b1) * nx + b0;
+#pragma unroll
+      for (int j = 0; j < 27; ++j) {
+        int q = j + rot;
+        q = q >= 27 ? q - 27 : q;
+        const int jz = q / 9, jy = (q / 3) % 3, jx = q % 3;
+        off[j] = lds ? lbase + (jz * E + jy) * E + jx : gbase + (jz * ny + jy) * nx + jx;
+      }
+    }
+    double* const lb = brick + (lds ? seg : 0) * BV;
+    float* const gch[4] = {a.gm, a.gp0, a.gp1, a.gp2};
     float wyz[9];
 #pragma unroll
     for (int jz = 0; jz < 3; ++jz)
 #pragma unroll
       for (int jy = 0; jy < 3; ++jy) wyz[jy + 3 * jz] = m * by.w[jy] * bz.w[jz];
 
-    // mass channel (Eq. 1, 4)
 #pragma unroll
-    for (int jz = 0; jz < 3; ++jz)
+    for (int ch = 0; ch < 4; ++ch) {
+      float val[27];
+      if (ch == 0) {
 #pragma unroll
-      for (int jy = 0; jy < 3; ++jy)
+        for (int jz = 0; jz < 3; ++jz)
 #pragma unroll
-        for (int jx = 0; jx < 3; ++jx) {
-          const float val = wyz[jy + 3 * jz] * bx.w[jx];
-          if (lds)
-            atomicAdd(lb + (jz * E + jy) * E + jx, val);
-          else
-            atomicAdd(gch[0] + jz * nxny + jy * nx + jx, val);
-        }
-
-    // momentum channels (Eq. 13)
+          for (int jy = 0; jy < 3; ++jy)
 #pragma unroll
-    for (int ax = 0; ax < 3; ++ax) {
-      float c[27];
-      const float* cp = a.coeff + (size_t)ax * NR * Ps + p;
+            for (int jx = 0; jx < 3; ++jx) val[jx + 3 * jy + 9 * jz] = wyz[jy + 3 * jz] * bx.w[jx];
+      } else {
+        float cf[27];
+        const float* cp = a.coeff + (size_t)(ch - 1) * NR * Ps + p;
 #pragma unroll
-      for (int r = 0; r < 27; ++r) c[r] = (r < NR) ? cp[(size_t)r * Ps] : 0.0f;
-      float V[27];
-      eval_modes<NR>(c, bx, by, bz, V);
-      float* lbc = lb + (1 + ax) * KMAX * BV;
+        for (int r = 0; r < 27; ++r) cf[r] = (r < NR) ? cp[(size_t)r * Ps] : 0.0f;
+        float V[27];
+        eval_modes<NR>(cf, bx, by, bz, V);
 #pragma unroll
-      for (int jz = 0; jz < 3; ++jz)
+        for (int jz = 0; jz < 3; ++jz)
 #pragma unroll
-        for (int jy = 0; jy < 3; ++jy)
+          for (int jy = 0; jy < 3; ++jy)
 #pragma unroll
-          for (int jx = 0; jx < 3; ++jx) {
-            const float val = wyz[jy + 3 * jz] * bx.w[jx] * V[jx + 3 * jy + 9 * jz];
-            if (lds)
-              atomicAdd(lbc + (jz * E + jy) * E + jx, val);
-            else
-              atomicAdd(gch[1 + ax] + jz * nxny + jy * nx + jx, val);
-          }
+            for (int jx = 0; jx < 3; ++jx) {
+              const int j = jx + 3 * jy + 9 * jz;
+              val[j] = (wyz[jy + 3 * jz] * bx.w[jx]) * V[j];
+            }
+      }
+      if (lds) {
+        rotate27(val, rot);
+        double* const lbc = lb + ch * KMAX * BV;
+#pragma unroll
+        for (int j = 0; j < 27; ++j) atomicAdd(lbc + off[j], (double)val[j]);
+      } else {
+#pragma unroll
+        for (int j = 0; j < 27; ++j) atomicAdd(gch[ch] + off[j], val[j]);
+      }
     }
   }
   __syncthreads();
@@ -225,32 +189,29 @@ __global__ __launch_bounds__(BS) void p2g_kernel(P2GArgs a) {
   for (int k = tid; k < nb * BV; k += BS) {
     const int s = k / BV;
     const int loc = k - s * BV;
-    const float vm = brick[(0 * KMAX + s) * BV + loc];
-    const float v0 = brick[(1 * KMAX + s) * BV + loc];
-    const float v1 = brick[(2 * KMAX + s) * BV + loc];
-    const float v2 = brick[(3 * KMAX + s) * BV + loc];
-    if (vm != 0.0f || v0 != 0.0f || v1 != 0.0f || v2 != 0.0f) {
-      const uint32_t tl = seg_tile[s];
-      const int lz = loc / (E * E);
-      const int rem = loc - lz * E * E;
-      const int ly = rem / E;
-      const int lx = rem - ly * E;
-      const int gx = (int)(tl & 1023u) * T + lx;
-      const int gy = (int)((tl >> 10) & 1023u) * T + ly;
-      const int gz = (int)(tl >> 20) * T + lz;
-      if (gx < nx && gy < ny && gz < nz) {
-        const int node = (gz * ny + gy) * nx + gx;
-        atomicAdd(a.gm + node, vm);
-        atomicAdd(a.gp0 + node, v0);
-        atomicAdd(a.gp1 + node, v1);
-        atomicAdd(a.gp2 + node, v2);
+    const uint32_t tl = seg_tile[s];
+    const int lz = loc / (E * E);
+    const int rem = loc - lz * E * E;
+    const int ly = rem / E;
+    const int lx = rem - ly * E;
+    const int gx = (int)(tl & 1023u) * T + lx;
+    const int gy = (int)((tl >> 10) & 1023u) * T + ly;
+    const int gz = (int)(tl >> 20) * T + lz;
+    if (gx < nx && gy < ny && gz < nz) {
+      const int node = (gz * ny + gy) * nx + gx;
+#pragma unroll
+      for (int ch = 0; ch < 4; ++ch) {
+        const float v = (float)brick[(ch * KMAX + s) * BV + loc];
+        if (v != 0.0f) atomicAdd((ch == 0 ? a.gm : ch == 1 ? a.gp0 : ch == 2 ? a.gp1 : a.gp2) + node, v);
       }
     }
   }
 }
 
 __global__ __launch_bounds__(256) void grid_clear_kernel(float* __restrict__ gm,
-                                                         float* __restrict__ gp, int64_t n) {
+                                                         float* __restrict__ gp, int64_t n,
+                                                         uint32_t* __restrict__ counter) {
+  if (counter && blockIdx.x == 0 && threadIdx.x == 0) *counter = 0u;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += stride) {
     gm[k] = 0.0f;
@@ -260,10 +221,192 @@ __global__ __launch_bounds__(256) void grid_clear_kernel(float* __restrict__ gm,
   }
 }
 
+
+__global__ __launch_bounds__(64) void zero_counter_kernel(uint32_t* __restrict__ counter) {
+  if (threadIdx.x == 0) *counter = 0u;
+}
+
+// Start index (in sorted order) of every occupied 4^3-cell tile, appended in
+// arbitrary order.  A tile is a run of 64 consecutive cell keys.
+__global__ __launch_bounds__(256) void p2g_tiles_kernel(const uint32_t* __restrict__ keys,
+                                                        int64_t P, uint32_t* __restrict__ list,
+                                                        uint32_t* __restrict__ count) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= P) return;
+  const uint32_t t = keys[i] >> 6;
+  if (i == 0 || (keys[i - 1] >> 6) != t) list[atomicAdd(count, 1u)] = (uint32_t)i;
+}
+
+// local Morton index of a cell inside its 4^3 tile
+__device__ __forceinline__ int morton_local4(int cx, int cy, int cz) {
+  return (cx & 1) | ((cy & 1) << 1) | ((cz & 1) << 2) | ((cx >> 1) << 3) | ((cy >> 1) << 4) |
+         ((cz >> 1) << 5);
+}
+
+constexpr int kCellT = 4;                         // tile edge in cells
+constexpr int kCellC = kCellT * kCellT * kCellT;  // cells per tile
+constexpr int kCellE = kCellT + 2;                // brick edge in nodes
+constexpr int kCellBV = kCellE * kCellE * kCellE;
+constexpr int kCellThreads = 4 * kWave;           // one wave per channel
+constexpr int kRow = kWave + 1;                   // padded LDS row (conflict-free writes)
+
+// Orders this wavefront's LDS accesses: LDS operations of one wave complete in
+// issue order, so a compiler-level fence between writes and reads by other
+// lanes of the same wave is all that is needed.
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <int NR>
+__global__ __launch_bounds__(kCellThreads) void p2g_cell_kernel(P2GArgs a) {
+  __shared__ float buf[4][27 * kRow];      // per wave: one channel's nodal values of a round
+  __shared__ double brick[4][kCellBV];     // per channel: the tile's 6^3 brick, FP64
+  __shared__ int run_lo[4][kWave + 1];     // per wave: first lane of each run (+ end)
+  __shared__ int run_cell[4][kWave];       // per wave: cell (local Morton index) of each run
+
+  const int lane = threadIdx.x & (kWave - 1);
+  const int ch = threadIdx.x / kWave;  // 0 mass, 1..3 momentum components
+  float* const wbuf = buf[ch];
+  double* const wbrick = brick[ch];
+  const size_t Ps = (size_t)a.P;
+  const int nx = a.g.nx, ny = a.g.ny, nz = a.g.nz;
+  const uint32_t ntiles = *a.tile_count;
+
+  for (uint32_t w = blockIdx.x; w < ntiles; w += gridDim.x) {
+    const int64_t ts = a.tile_list[w];
+    const uint32_t key0 = a.keys[ts] & ~(uint32_t)(kCellC - 1);
+    const uint32_t tkey = key0 >> 6;
+    const int ox = (int)compact_bits3(key0);  // tile origin (base-node coordinates)
+    const int oy = (int)compact_bits3(key0 >> 1);
+    const int oz = (int)compact_bits3(key0 >> 2);
+    for (int n = lane; n < kCellBV; n += kWave) wbrick[n] = 0.0;
+
+    for (int64_t r0 = ts;; r0 += kWave) {
+      const int64_t k = r0 + lane;
+      const uint32_t kk = k < a.P ? a.keys[k] : 0xFFFFFFFFu;
+      const bool inside = k < a.P && (kk >> 6) == tkey;  // a prefix of the wave
+      const uint32_t kprev = (lane > 0 && k < a.P) ? a.keys[k - 1] : 0xFFFFFFFFu;
+      const bool head = inside && (lane == 0 || kprev != kk);
+      const unsigned long long hb = __ballot(head);
+      const int n_runs = __popcll(hb);
+      const int n_in = __popcll(__ballot(inside));
+      const bool more = __ballot(lane == kWave - 1 && inside) != 0ull;
+      if (head) {
+        const int r = lanes_below(hb);
+        run_lo[ch][r] = lane;
+        run_cell[ch][r] = (int)(kk & (kCellC - 1));
+      }
+      if (lane == 0) run_lo[ch][n_runs] = n_in;
+
+      bool valid = inside;
+      int p = 0;
+      int b0 = 0, b1 = 0, b2 = 0;
+      float t0 = 0.f, t1 = 0.f, t2 = 0.f;
+      if (valid) {
+        p = a.perm ? min(max(a.perm[k], 0), (int)(a.P - 1)) : (int)k;
+        bool ok = stencil_axis(a.x[p], a.g.ox, a.g.inv_dx, nx, b0, t0);
+        ok &= stencil_axis(a.x[Ps + p], a.g.oy, a.g.inv_dx, ny, b1, t1);
+        ok &= stencil_axis(a.x[2 * Ps + p], a.g.oz, a.g.inv_dx, nz, b2, t2);
+        // the particle's base node must be the cell its key names
+        const int cl = (int)(kk & (kCellC - 1));
+        const int cx = (cl & 1) | (((cl >> 3) & 1) << 1);
+        const int cy = ((cl >> 1) & 1) | (((cl >> 4) & 1) << 1);
+        const int cz = ((cl >> 2) & 1) | (((cl >> 5) & 1) << 1);
+        if (!ok || b0 != ox + cx || b1 != oy + cy || b2 != oz + cz) {
+          if (ch == 0) raise_flag(a.status, kFlagRange);
+          valid = false;
+        }
+      }
+      const Basis1D bx = basis_p2g(t0);
+      const Basis1D by = basis_p2g(t1);
+      const Basis1D bz = basis_p2g(t2);
+      const float m = valid ? (a.mass ? a.mass[p] : a.uniform_mass) : 0.0f;
+      float wyz[9];
+#pragma unroll
+      for (int jz = 0; jz < 3; ++jz)
+#pragma unroll
+        for (int jy = 0; jy < 3; ++jy) wyz[jy + 3 * jz] = m * by.w[jy] * bz.w[jz];
+      float val[27];
+      if (ch == 0) {
+#pragma unroll
+        for (int jz = 0; jz < 3; ++jz)
+#pragma unroll
+          for (int jy = 0; jy < 3; ++jy)
+#pragma unroll
+            for (int jx = 0; jx < 3; ++jx) val[jx + 3 * jy + 9 * jz] = wyz[jy + 3 * jz] * bx.w[jx];
+      } else {
+        float cf[27];
+        const float* cp = a.coeff + (size_t)(ch - 1) * NR * Ps + p;
+#pragma unroll
+        for (int r = 0; r < 27; ++r) cf[r] = (r < NR && valid) ? cp[(size_t)r * Ps] : 0.0f;
+        float V[27];
+        eval_modes<NR>(cf, bx, by, bz, V);
+#pragma unroll
+        for (int jz = 0; jz < 3; ++jz)
+#pragma unroll
+          for (int jy = 0; jy < 3; ++jy)
+#pragma unroll
+            for (int jx = 0; jx < 3; ++jx) {
+              const int j = jx + 3 * jy + 9 * jz;
+              val[j] = (wyz[jy + 3 * jz] * bx.w[jx]) * V[j];
+            }
+      }
+#pragma unroll
+      for (int j = 0; j < 27; ++j) wbuf[j * kRow + lane] = val[j];
+      wave_lds_sync();
+
+      // (run, stencil node) pairs: sum the run's lanes, add to the brick node
+      for (int q = lane; q < n_runs * 27; q += kWave) {
+        const int r = q / 27;
+        const int j = q - r * 27;
+        const int lo = run_lo[ch][r];
+        const int hi = run_lo[ch][r + 1];
+        const float* row = wbuf + j * kRow;
+        float sum = 0.0f;
+        for (int i0 = lo; i0 < hi; i0 += 8) {
+#pragma unroll
+          for (int d = 0; d < 8; ++d) {
+            const int i = i0 + d;
+            const float v = row[min(i, kWave - 1)];
+            sum += (i < hi) ? v : 0.0f;
+          }
+        }
+        const int cl = run_cell[ch][r];
+        const int jz = j / 9, jy = (j / 3) % 3, jx = j % 3;
+        const int lx = ((cl & 1) | (((cl >> 3) & 1) << 1)) + jx;
+        const int ly = (((cl >> 1) & 1) | (((cl >> 4) & 1) << 1)) + jy;
+        const int lz = (((cl >> 2) & 1) | (((cl >> 5) & 1) << 1)) + jz;
+        atomicAdd(wbrick + (lz * kCellE + ly) * kCellE + lx, (double)sum);
+      }
+      wave_lds_sync();
+      if (!more) break;
+    }
+    __syncthreads();
+
+    // flush the four channel bricks with one global atomic per non-zero node
+    float* const dst[4] = {a.gm, a.gp0, a.gp1, a.gp2};
+    for (int q = threadIdx.x; q < 4 * kCellBV; q += kCellThreads) {
+      const int chq = q / kCellBV;
+      const int n = q - chq * kCellBV;
+      const float v = (float)brick[chq][n];
+      if (v != 0.0f) {
+        const int lz = n / (kCellE * kCellE);
+        const int ly = (n / kCellE) % kCellE;
+        const int lx = n % kCellE;
+        const int gx = ox + lx, gy = oy + ly, gz = oz + lz;
+        if (gx < nx && gy < ny && gz < nz) atomicAdd(dst[chq] + ((gz * ny + gy) * nx + gx), v);
+      }
+    }
+    __syncthreads();  // the bricks are cleared by the next tile
+  }
+}
+
 template <int NR, int TB, int BS>
 hipError_t launch_cfg(const P2GArgs& a, hipStream_t stream) {
   const unsigned blocks = (unsigned)((a.P + BS - 1) / BS);
-  p2g_kernel<NR, TB, BS><<<blocks, BS, 0, stream>>>(a);
+  p2g_brick_kernel<NR, TB, BS><<<blocks, BS, 0, stream>>>(a);
   return hipGetLastError();
 }
 
@@ -283,6 +426,12 @@ hipError_t launch_nr(const P2GArgs& a, const P2GConfig& c, hipStream_t stream) {
 
 }  // namespace
 
+template <int NR>
+hipError_t launch_cell_nr(const P2GArgs& a, int blocks, hipStream_t stream) {
+  p2g_cell_kernel<NR><<<blocks, kCellThreads, 0, stream>>>(a);
+  return hipGetLastError();
+}
+
 P2GConfig p2g_default_config() { return P2GConfig{2, 256}; }
 
 bool p2g_config_supported(const P2GConfig& c) {
@@ -291,12 +440,48 @@ bool p2g_config_supported(const P2GConfig& c) {
          code == 3256 || code == 3512;
 }
 
-hipError_t launch_grid_clear(float* gm, float* gp, int64_t n_nodes, hipStream_t stream) {
-  if (n_nodes == 0) return hipSuccess;
+hipError_t launch_grid_clear(float* gm, float* gp, int64_t n_nodes, uint32_t* counter,
+                             hipStream_t stream) {
   int64_t blocks = (n_nodes + 255) / 256;
   if (blocks > 65536) blocks = 65536;
-  grid_clear_kernel<<<(unsigned)blocks, 256, 0, stream>>>(gm, gp, n_nodes);
+  if (blocks < 1) blocks = 1;
+  grid_clear_kernel<<<(unsigned)blocks, 256, 0, stream>>>(gm, gp, n_nodes, counter);
   return hipGetLastError();
+}
+
+int64_t p2g_max_tiles(const GridDev& g, int64_t P) {
+  // tiles are indexed by base node >> 2 per axis, base node in [0, n - 3]
+  const int64_t t = (int64_t)(((g.nx - 3) >> 2) + 1) * (((g.ny - 3) >> 2) + 1) *
+                    (((g.nz - 3) >> 2) + 1);
+  return P < t ? P : t;
+}
+
+size_t p2g_workspace_bytes(const GridDev& g, int64_t P) {
+  return align_up(sizeof(uint32_t)) + align_up((size_t)p2g_max_tiles(g, P) * sizeof(uint32_t));
+}
+
+hipError_t launch_p2g_sorted(const P2GArgs& a0, int n_modes, void* ws, bool counter_zeroed,
+                             hipStream_t stream) {
+  if (a0.P == 0) return hipSuccess;
+  P2GArgs a = a0;
+  uint32_t* count = (uint32_t*)ws;
+  uint32_t* list = (uint32_t*)((char*)ws + align_up(sizeof(uint32_t)));
+  a.tile_count = count;
+  a.tile_list = list;
+  if (!counter_zeroed) {
+    zero_counter_kernel<<<1, 64, 0, stream>>>(count);
+  }
+  p2g_tiles_kernel<<<(unsigned)((a.P + 255) / 256), 256, 0, stream>>>(a.keys, a.P, list, count);
+  // persistent grid over the occupied tiles (their number is only known on the device)
+  int64_t blocks = p2g_max_tiles(a.g, a.P);
+  if (blocks > 2048) blocks = 2048;
+  switch (n_modes) {
+    case 1: return launch_cell_nr<1>(a, (int)blocks, stream);
+    case 4: return launch_cell_nr<4>(a, (int)blocks, stream);
+    case 8: return launch_cell_nr<8>(a, (int)blocks, stream);
+    case 27: return launch_cell_nr<27>(a, (int)blocks, stream);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 hipError_t launch_p2g(const P2GArgs& a, int n_modes, const P2GConfig& cfg, hipStream_t stream) {

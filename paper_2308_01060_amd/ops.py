@@ -65,23 +65,38 @@ def polypic_sort_workspace_bytes(grid: polypic_grid, P: int) -> int:
     return int(out.value)
 
 
+def _keys_ptr(keys: Optional[torch.Tensor], P: int) -> Optional[int]:
+    """Cell keys are uint32 in the C ABI; an int32 tensor holds the same bits."""
+    if keys is None:
+        return None
+    dtype = torch.int32 if keys.dtype == torch.int32 else torch.uint32
+    return _ptr(keys, dtype, P, "keys")
+
+
 def polypic_sort(grid: polypic_grid, x: torch.Tensor, keys_out: torch.Tensor,
                  perm_out: torch.Tensor, ws: torch.Tensor,
                  status_dev: Optional[torch.Tensor] = None) -> None:
     P = x.numel() // 3
     check(_lib.load().polypic_sort(
         ctypes.byref(grid), P, _ptr(x, torch.float32, 3 * P, "x"),
-        _ptr(keys_out, torch.int32, P, "keys_out") if keys_out.dtype == torch.int32
-        else _ptr(keys_out, torch.uint32, P, "keys_out"),
+        _keys_ptr(keys_out, P),
         _ptr(perm_out, torch.int32, P, "perm_out"),
         _ptr(ws, torch.uint8, ws.numel(), "ws"), ws.numel(),
         _ptr(status_dev, torch.int32, 1, "status_dev"), _stream()), "polypic_sort")
 
 
+def polypic_p2g_workspace_bytes(grid: polypic_grid, P: int) -> int:
+    out = ctypes.c_size_t(0)
+    check(_lib.load().polypic_p2g_workspace_bytes(ctypes.byref(grid), int(P), ctypes.byref(out)),
+          "polypic_p2g_workspace_bytes")
+    return int(out.value)
+
+
 def polypic_p2g(grid: polypic_grid, n_modes: int, x: torch.Tensor, coeff: torch.Tensor,
                 grid_mass: torch.Tensor, grid_mom: torch.Tensor,
                 mass: Optional[torch.Tensor] = None, uniform_mass: float = 1.0,
-                perm: Optional[torch.Tensor] = None, accumulate: bool = False,
+                perm: Optional[torch.Tensor] = None, keys_sorted: Optional[torch.Tensor] = None,
+                ws: Optional[torch.Tensor] = None, accumulate: bool = False,
                 status_dev: Optional[torch.Tensor] = None) -> None:
     P = x.numel() // 3
     N = n_nodes(grid)
@@ -89,7 +104,9 @@ def polypic_p2g(grid: polypic_grid, n_modes: int, x: torch.Tensor, coeff: torch.
         ctypes.byref(grid), P, int(n_modes), _ptr(x, torch.float32, 3 * P, "x"),
         _ptr(mass, torch.float32, P, "mass"), float(uniform_mass),
         _ptr(coeff, torch.float32, 3 * int(n_modes) * P, "coeff"),
-        _ptr(perm, torch.int32, P, "perm"),
+        _ptr(perm, torch.int32, P, "perm"), _keys_ptr(keys_sorted, P),
+        _ptr(ws, torch.uint8, ws.numel() if ws is not None else 0, "ws"),
+        0 if ws is None else ws.numel(),
         _ptr(grid_mass, torch.float32, N, "grid_mass"),
         _ptr(grid_mom, torch.float32, 3 * N, "grid_mom"), int(bool(accumulate)),
         _ptr(status_dev, torch.int32, 1, "status_dev"), _stream()), "polypic_p2g")

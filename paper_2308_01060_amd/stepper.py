@@ -9,7 +9,8 @@ stream:
 
 G2P writes the new state in sorted order, so after a step the arrays are in
 cell order and the next sort is close to the identity.  ``order`` tracks the
-original index of each slot.
+original index of each slot (bookkeeping done with a torch gather; switch it off
+with ``track_order=False`` when only the transfers matter).
 """
 from __future__ import annotations
 
@@ -25,7 +26,7 @@ class ParticleSet:
                  mass: Optional[torch.Tensor] = None, uniform_mass: float = 1.0,
                  F: Optional[torch.Tensor] = None, dt: float = 1e-4,
                  gravity: Sequence[float] = (0.0, -9.8, 0.0), bc_layers: int = 1,
-                 device: str = "cuda"):
+                 device: str = "cuda", track_order: bool = True):
         if n_modes not in ops.ALLOWED_N_MODES:
             raise ValueError("n_modes must be one of 1, 4, 8, 27")
         self.grid = grid
@@ -57,17 +58,24 @@ class ParticleSet:
         self.perm = torch.empty(P, dtype=torch.int32, device=dev)
         self.ws = torch.empty(max(1, ops.polypic_sort_workspace_bytes(grid, P)),
                               dtype=torch.uint8, device=dev)
+        self.p2g_ws = torch.empty(max(1, ops.polypic_p2g_workspace_bytes(grid, P)),
+                                  dtype=torch.uint8, device=dev)
         self.status = torch.zeros(1, dtype=torch.int32, device=dev)
+        self.track_order = bool(track_order)
         self.order = torch.arange(P, dtype=torch.int64, device=dev)
 
     # -- the four calls of one step
     def sort(self):
         ops.polypic_sort(self.grid, self.x, self.keys, self.perm, self.ws, self.status)
 
-    def p2g(self, use_perm: bool = True):
+    def p2g(self, use_perm: bool = True, use_keys: bool = True):
+        """P2G; with use_perm and use_keys (after sort()) it takes the cell-gather path."""
+        sorted_ = use_perm and use_keys
         ops.polypic_p2g(self.grid, self.n_modes, self.x, self.coeff, self.grid_mass,
                         self.grid_mom, mass=self.mass, uniform_mass=self.uniform_mass,
-                        perm=self.perm if use_perm else None, status_dev=self.status)
+                        perm=self.perm if use_perm else None,
+                        keys_sorted=self.keys if sorted_ else None,
+                        ws=self.p2g_ws if sorted_ else None, status_dev=self.status)
 
     def grid_update(self):
         ops.polypic_grid_update(self.grid, self.dt, self.gravity, self.bc_layers,
@@ -87,7 +95,7 @@ class ParticleSet:
             self.mass, self.mass_next = self.mass_next, self.mass
         if self.F is not None:
             self.F, self.F_next = self.F_next, self.F
-        if use_perm:
+        if use_perm and self.track_order:
             self.order = self.order[self.perm.long()]
 
     def step(self):

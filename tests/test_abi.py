@@ -58,34 +58,42 @@ def test_workspace_query():
 FAKE = ctypes.c_void_p(0x1000)  # never dereferenced: every call below fails validation
 
 
+def p2g_call(g, P=10, n_modes=4, x=FAKE, mass=None, umass=1.0, coeff=FAKE, perm=None, keys=None,
+             ws=None, ws_bytes=0, gm=FAKE, gp=FAKE, acc=0):
+    lib = _lib.load()
+    return lib.polypic_p2g(ctypes.byref(g), P, n_modes, x, mass, umass, coeff, perm, keys, ws,
+                           ws_bytes, gm, gp, acc, None, None)
+
+
 @pytest.mark.parametrize("n_modes", [0, 2, 5, 9, 26, 28])
 def test_p2g_rejects_bad_mode_count(n_modes):
-    lib = _lib.load()
-    g = grid()
-    st = lib.polypic_p2g(ctypes.byref(g), 10, n_modes, FAKE, None, 1.0, FAKE, None, FAKE, FAKE,
-                         0, None, None)
-    assert st == _lib.POLYPIC_EINVAL
+    assert p2g_call(grid(), n_modes=n_modes) == _lib.POLYPIC_EINVAL
 
 
 def test_p2g_rejects_null_and_bad_sizes():
-    lib = _lib.load()
     g = grid()
-    assert lib.polypic_p2g(ctypes.byref(g), 10, 4, None, None, 1.0, FAKE, None, FAKE, FAKE, 0,
-                           None, None) == 1
-    assert lib.polypic_p2g(ctypes.byref(g), 10, 4, FAKE, None, 1.0, FAKE, None, None, FAKE, 0,
-                           None, None) == 1
-    assert lib.polypic_p2g(ctypes.byref(g), -5, 4, FAKE, None, 1.0, FAKE, None, FAKE, FAKE, 0,
-                           None, None) == 1
-    assert lib.polypic_p2g(ctypes.byref(g), 1 << 31, 4, FAKE, None, 1.0, FAKE, None, FAKE, FAKE,
-                           0, None, None) == 1
-    bad = grid(2, 36, 36)
-    assert lib.polypic_p2g(ctypes.byref(bad), 10, 4, FAKE, None, 1.0, FAKE, None, FAKE, FAKE, 0,
-                           None, None) == 1
-    neg = grid(dx=-1.0)
-    assert lib.polypic_p2g(ctypes.byref(neg), 10, 4, FAKE, None, 1.0, FAKE, None, FAKE, FAKE, 0,
-                           None, None) == 1
-    assert lib.polypic_p2g(ctypes.byref(g), 10, 4, FAKE, None, float("nan"), FAKE, None, FAKE,
-                           FAKE, 0, None, None) == 1
+    assert p2g_call(g, x=None) == 1
+    assert p2g_call(g, gm=None) == 1
+    assert p2g_call(g, P=-5) == 1
+    assert p2g_call(g, P=1 << 31) == 1
+    assert p2g_call(grid(2, 36, 36)) == 1
+    assert p2g_call(grid(dx=-1.0)) == 1
+    assert p2g_call(g, umass=float("nan")) == 1
+    # sorted path: keys need perm and a workspace of the queried size
+    assert p2g_call(g, keys=FAKE, perm=None, ws=FAKE, ws_bytes=1 << 20) == 1
+    assert p2g_call(g, keys=FAKE, perm=FAKE, ws=None) == 1
+    assert p2g_call(g, keys=FAKE, perm=FAKE, ws=FAKE, ws_bytes=8) == _lib.POLYPIC_ENOSPACE
+
+
+def test_p2g_workspace_query():
+    lib = _lib.load()
+    out = ctypes.c_size_t(0)
+    g = grid(132, 132, 132, 1 / 128)
+    assert lib.polypic_p2g_workspace_bytes(ctypes.byref(g), 4194304, ctypes.byref(out)) == 0
+    tiles = (129 // 4 + 1) ** 3
+    assert out.value >= 4 + 4 * tiles
+    assert lib.polypic_p2g_workspace_bytes(ctypes.byref(g), 10, ctypes.byref(out)) == 0
+    assert out.value <= 1024
 
 
 def test_g2p_rejects_bad_arguments():

@@ -78,14 +78,16 @@ def test_sort_presorted_and_reversed():
 # ---------------------------------------------------------------- P2G
 
 @pytest.mark.parametrize("n_modes", O.ALLOWED_N_MODES)
-@pytest.mark.parametrize("order", ["sorted", "unsorted"])
-def test_p2g_parity(n_modes, order):
+@pytest.mark.parametrize("path", ["cells", "bricks", "unsorted"])
+def test_p2g_parity(n_modes, path):
+    """P2G on all three paths: cell gather (sorted keys), brick scatter in sorted
+    order (perm only), brick scatter in input order."""
     s = W.config0(0)
-    note(f"p2g parity: config0 P={s.P} n_modes={n_modes} order={order}")
+    note(f"p2g parity: config0 P={s.P} n_modes={n_modes} path={path}")
     pp, g, ps = particle_set(s, n_modes)
-    if order == "sorted":
+    if path != "unsorted":
         ps.sort()
-    ps.p2g(use_perm=(order == "sorted"))
+    ps.p2g(use_perm=(path != "unsorted"), use_keys=(path == "cells"))
     torch.cuda.synchronize()
     M_ref, Q_ref = O.p2g(oracle_grid(g), s.x, s.coeff, n_modes)
     M = host(ps.grid_mass).reshape(M_ref.shape)
@@ -97,18 +99,21 @@ def test_p2g_parity(n_modes, order):
 
 
 def test_p2g_random_masses_and_accumulate():
-    """Per-particle masses (Eq. 18's m_s + m_f) and accumulate = 1 adding a second pass."""
+    """Per-particle masses (Eq. 18's m_s + m_f) and accumulate = 1 adding a second and
+    third pass (cell-gather and brick paths)."""
     s = W.random_scene(5, 24, 9001, mass_random=True)
     note(f"p2g mass/accumulate: P={s.P}")
     pp, g, ps = particle_set(s, 27)
     ps.sort()
     ps.p2g()
     pp.polypic_p2g(g, 27, ps.x, ps.coeff, ps.grid_mass, ps.grid_mom, mass=ps.mass,
+                   perm=ps.perm, keys_sorted=ps.keys, ws=ps.p2g_ws, accumulate=True)
+    pp.polypic_p2g(g, 27, ps.x, ps.coeff, ps.grid_mass, ps.grid_mom, mass=ps.mass,
                    perm=ps.perm, accumulate=True)
     torch.cuda.synchronize()
     M_ref, Q_ref = O.p2g(oracle_grid(g), s.x, s.coeff, 27, s.mass)
-    assert rel(host(ps.grid_mass).reshape(M_ref.shape), 2 * M_ref) <= TOL_NORMWISE
-    assert rel(host(ps.grid_mom).reshape(Q_ref.shape), 2 * Q_ref) <= TOL_NORMWISE
+    assert rel(host(ps.grid_mass).reshape(M_ref.shape), 3 * M_ref) <= TOL_NORMWISE
+    assert rel(host(ps.grid_mom).reshape(Q_ref.shape), 3 * Q_ref) <= TOL_NORMWISE
 
 
 # ---------------------------------------------------------------- grid update + G2P
@@ -301,3 +306,43 @@ def test_invalid_permutation_never_faults():
     pp.polypic_g2p(g, 4, 1e-4, ps.grid_vel.zero_(), ps.x, ps.coeff_next, perm=bad)
     torch.cuda.synchronize()
     assert torch.isfinite(ps.grid_mass).all()
+
+
+def test_stale_keys_are_flagged_not_trusted():
+    """Keys that no longer match the positions: those particles are skipped and flagged."""
+    pp = require_gpu()
+    s = W.config0(5)
+    pp_, g, ps = particle_set(s, 8)
+    ps.sort()
+    moved = ps.perm[:100].long()
+    ps.x[0, moved] += 1.5 / 32   # moves 100 particles by 1.5 cells along x
+    ps.p2g()
+    torch.cuda.synchronize()
+    assert ps.status_flags() & 1
+    total = float(ps.grid_mass.double().sum())
+    assert abs(total - (s.P - 100)) < 1e-3
+
+
+def test_cell_path_with_sparse_and_dense_cells():
+    """Cells holding 1 .. 40 particles, tiles split across the sorted array."""
+    pp = require_gpu()
+    rng = np.random.default_rng(12)
+    n = 24
+    counts = rng.integers(0, 41, size=200)
+    cells = rng.integers(3, n - 3, size=(200, 3))
+    xs = []
+    for cnt, cc in zip(counts, cells):
+        xs.append((cc[:, None] + 2 + rng.random((3, cnt))) / n)
+    x = np.concatenate(xs, axis=1).astype(np.float32)
+    P = x.shape[1]
+    c = (rng.standard_normal((3, 27, P)) * 0.3).astype(np.float32)
+    mass = (0.5 + rng.random(P)).astype(np.float32)
+    g = pp.make_grid((n + 4,) * 3, 1 / n)
+    ps = pp.ParticleSet(g, 27, dev(x), dev(c), mass=dev(mass))
+    ps.sort()
+    ps.p2g()
+    torch.cuda.synchronize()
+    M_ref, Q_ref = O.p2g(oracle_grid(g), x, c, 27, mass)
+    assert rel(host(ps.grid_mass).reshape(M_ref.shape), M_ref) <= TOL_NORMWISE
+    assert rel(host(ps.grid_mom).reshape(Q_ref.shape), Q_ref) <= TOL_NORMWISE
+    assert ps.status_flags() == 0

@@ -89,27 +89,25 @@ def jittered_block(rng: np.random.Generator, grid: GridSpec, lo_cell, shape_cell
     Cells are enumerated z-major, then y, then x; inside a cell the sub-cells in
     the same nesting.  P = prod(shape_cells) * prod(sub).
     """
-    lo = np.asarray(lo_cell, np.int64)
-    sh = np.asarray(shape_cells, np.int64)
-    sb = np.asarray(sub, np.int64)
-    fine = sh * sb  # sub-cell lattice extent per axis
-    # sub-cell integer coordinates in (z, y, x) nesting order
-    gz, gy, gx = np.meshgrid(np.arange(fine[2]), np.arange(fine[1]), np.arange(fine[0]),
-                             indexing="ij")
-    # order: cell (z,y,x) major, sub-cell minor
-    cz, sz = np.divmod(gz, sb[2])
-    cy, sy = np.divmod(gy, sb[1])
-    cx, sx = np.divmod(gx, sb[0])
-    key = (((cz * sh[1] + cy) * sh[0] + cx) * sb[2] + sz) * sb[1] * sb[0] + sy * sb[0] + sx
-    order = np.argsort(key.ravel(), kind="stable")
-    sub_idx = np.stack([gx.ravel()[order], gy.ravel()[order], gz.ravel()[order]])
-    P = sub_idx.shape[1]
+    sh = [int(v) for v in shape_cells]
+    sb = [int(v) for v in sub]
+    P = int(np.prod(sh)) * int(np.prod(sb))
     jitter = rng.random((3, P))
+    # index grid of shape (cz, cy, cx, sz, sy, sx), flattened in C order
+    full = (sh[2], sh[1], sh[0], sb[2], sb[1], sb[0])
     x = np.empty((3, P), np.float32)
     for a in range(3):
-        cell_coord = lo[a] + (sub_idx[a] + jitter[a]) / sb[a]   # in domain cells
-        world = grid.origin[a] + (2.0 + cell_coord) * grid.dx
-        x[a] = world.astype(np.float32)
+        cell_axis = 2 - a          # position of this axis' cell index in `full`
+        sub_axis = 5 - a           # position of this axis' sub-cell index
+        shape = [1] * 6
+        shape[cell_axis] = full[cell_axis]
+        cidx = np.arange(full[cell_axis]).reshape(shape)
+        shape = [1] * 6
+        shape[sub_axis] = full[sub_axis]
+        sidx = np.arange(full[sub_axis]).reshape(shape)
+        fine = np.broadcast_to(cidx * sb[a] + sidx, full).reshape(-1)
+        cell_coord = lo_cell[a] + (fine + jitter[a]) / sb[a]      # in domain cells
+        x[a] = (grid.origin[a] + (2.0 + cell_coord) * grid.dx).astype(np.float32)
     return x
 
 
