@@ -23,55 +23,48 @@
 //   atomic per node and channel.
 //
 // * Brick scatter (any order; perm from polypic_sort makes it effective).  One
-//   thread per particle in processing order; runs of particles in the same 4^3
-//   tile accumulate into FP64 LDS bricks with LDS double atomics (each lane
-//   starting its node loop at a different node so that particles of one cell
-//   do not collide on an address), and the bricks are added to HBM with one
-//   float atomic per node and channel.  Runs beyond the LDS budget (unsorted
-//   input) add straight to HBM.
+//   thread per particle, the lanes of a wavefront spread over the workgroup's
+//   chunk of the processing order so that they fall in different cells; runs
+//   of particles in the same 4^3 tile accumulate into FP64 LDS bricks with LDS
+//   double atomics, and the bricks are added to HBM with one float atomic per
+//   node and channel.  Runs beyond the LDS budget (unsorted input) add
+//   straight to HBM.
 #include "polypic_internal.hpp"
 
 namespace polypic {
 
 namespace {
 
-template <int TB>
-constexpr int kmax_for() {
-  return TB == 1 ? 16 : (TB == 2 ? 4 : 1);
-}
+// FP64 brick of a 4^3-cell tile: 6^3 nodes stored with strides (1, 8, 68)
+// doubles.  With lanes spread over the 64 cells of a tile (see below), the 32
+// cells handled by each half-wavefront then fall on 32 distinct LDS bank pairs
+// for every stencil node.
+constexpr int kBrickT = 4;                       // tile edge in cells
+constexpr int kBrickSY = 8;
+constexpr int kBrickSZ = 68;
+constexpr int kBrickV = 5 + 5 * kBrickSY + 5 * kBrickSZ + 1;  // 386 doubles per channel
+constexpr int kBrickKMAX = 3;                    // bricks (tiles) per workgroup in LDS
 
-// Rotates v left by r (0 <= r < 8): out[j] = v[(j + r) % 27], as a 3-stage barrel
-// shifter of selects (registers cannot be indexed by a per-lane value).
-__device__ __forceinline__ void rotate27(float (&v)[27], int r) {
-  float t[27];
-#pragma unroll
-  for (int j = 0; j < 27; ++j) t[j] = (r & 1) ? v[(j + 1) % 27] : v[j];
-#pragma unroll
-  for (int j = 0; j < 27; ++j) v[j] = (r & 2) ? t[(j + 2) % 27] : t[j];
-#pragma unroll
-  for (int j = 0; j < 27; ++j) t[j] = (r & 4) ? v[(j + 4) % 27] : v[j];
-#pragma unroll
-  for (int j = 0; j < 27; ++j) v[j] = t[j];
-}
-
-template <int NR, int TB, int BS>
+template <int NR, int BS>
 __global__ __launch_bounds__(BS) void p2g_brick_kernel(P2GArgs a) {
-  constexpr int T = 1 << TB;
-  constexpr int E = T + 2;          // brick edge in nodes
-  constexpr int BV = E * E * E;     // brick volume in nodes
-  constexpr int KMAX = kmax_for<TB>();
   constexpr int NW = BS / kWave;
-  // Bricks accumulate in FP64: LDS double atomics run at about 8 cycles per
-  // wavefront instruction on gfx950, float ones at about 190.
-  __shared__ double brick[4 * KMAX * BV];  // [channel][brick][node]
-  __shared__ uint32_t tile_of[BS];
-  __shared__ uint32_t seg_tile[KMAX];
+  // LDS double atomics run at about 8 cycles per wavefront instruction on
+  // gfx950 when their addresses avoid bank conflicts; float ones at about 190
+  // whatever the addresses.
+  __shared__ double brick[kBrickKMAX * 4 * kBrickV];  // [brick][channel][node]
+  __shared__ uint32_t tile_of[BS];  // by processing slot
+  __shared__ int seg_of[BS];        // by processing slot
+  __shared__ uint32_t seg_tile[kBrickKMAX];
   __shared__ int wave_heads[NW];
 
   const int tid = threadIdx.x;
   const int lane = tid & (kWave - 1);
   const int wv = tid / kWave;
-  const int64_t i = (int64_t)blockIdx.x * BS + tid;
+  // Slot of this thread's particle: the lanes of a wavefront take every NW-th
+  // slot, so that in sorted order (about 8 particles per cell) they sit in
+  // different cells and their brick atomics do not collide.
+  const int slot = lane * NW + wv;
+  const int64_t i = (int64_t)blockIdx.x * BS + slot;
   const size_t Ps = (size_t)a.P;
   const int nx = a.g.nx, ny = a.g.ny, nz = a.g.nz;
 
@@ -91,53 +84,43 @@ __global__ __launch_bounds__(BS) void p2g_brick_kernel(P2GArgs a) {
       valid = false;
     }
   }
-  const uint32_t tile = valid ? ((uint32_t)(b0 >> TB) | ((uint32_t)(b1 >> TB) << 10) |
-                                 ((uint32_t)(b2 >> TB) << 20))
-                              : 0xFFFFFFFFu;
-  tile_of[tid] = tile;
-  for (int k = tid; k < 4 * KMAX * BV; k += BS) brick[k] = 0.0;
+  tile_of[slot] = valid ? ((uint32_t)(b0 >> 2) | ((uint32_t)(b1 >> 2) << 10) |
+                           ((uint32_t)(b2 >> 2) << 20))
+                        : 0xFFFFFFFFu;
+  for (int k = tid; k < kBrickKMAX * 4 * kBrickV; k += BS) brick[k] = 0.0;
   __syncthreads();
 
-  // runs of equal tiles in processing order -> segment index per particle
-  const bool head = valid && (tid == 0 || tile_of[tid - 1] != tile);
-  const unsigned long long hb = __ballot(head);
-  if (lane == 0) wave_heads[wv] = __popcll(hb);
-  __syncthreads();
-  int pre = 0, nseg = 0;
+  // runs of equal tiles in slot order (thread t looks at slot t) -> segments
+  {
+    const uint32_t tt = tile_of[tid];
+    const bool head = tt != 0xFFFFFFFFu && (tid == 0 || tile_of[tid - 1] != tt);
+    const unsigned long long hb = __ballot(head);
+    if (lane == 0) wave_heads[wv] = __popcll(hb);
+    __syncthreads();
+    int pre = 0;
 #pragma unroll
-  for (int w = 0; w < NW; ++w) {
-    const int h = wave_heads[w];
-    pre += (w < wv) ? h : 0;
-    nseg += h;
+    for (int w = 0; w < NW; ++w) pre += (w < wv) ? wave_heads[w] : 0;
+    const int sg = pre + lanes_below(hb) + (head ? 1 : 0) - 1;
+    seg_of[tid] = sg;
+    if (head && sg < kBrickKMAX) seg_tile[sg] = tt;
   }
-  const int seg = pre + lanes_below(hb) + (head ? 1 : 0) - 1;
-  if (head && seg < KMAX) seg_tile[seg] = tile;
   __syncthreads();
+  int nseg = 0;
+#pragma unroll
+  for (int w = 0; w < NW; ++w) nseg += wave_heads[w];
+  const int seg = seg_of[slot];
 
   if (valid) {
     const Basis1D bx = basis_p2g(t0);
     const Basis1D by = basis_p2g(t1);
     const Basis1D bz = basis_p2g(t2);
     const float m = a.mass ? a.mass[p] : a.uniform_mass;
-    const bool lds = seg < KMAX;
-    // Lanes of one cell (adjacent in sorted order) would hit the same brick
-    // addresses in the same instruction; each lane instead starts its node loop
-    // at a different node (rotation lane % 8), which spreads them out.
-    const int rot = lds ? (lane & 7) : 0;
-    int off[27];  // brick (LDS) or grid (HBM) offset of stencil node (j + rot) % 27
-    {
-      const int lbase = (((b2 & (T - 1)) * E) + (b1 & (T - 1))) * E + (b0 & (T - 1));
-      const int gbase = (b2 * ny + b1) * nx + b0;
-#pragma unroll
-      for (int j = 0; j < 27; ++j) {
-        int q = j + rot;
-        q = q >= 27 ? q - 27 : q;
-        const int jz = q / 9, jy = (q / 3) % 3, jx = q % 3;
-        off[j] = lds ? lbase + (jz * E + jy) * E + jx : gbase + (jz * ny + jy) * nx + jx;
-      }
-    }
-    double* const lb = brick + (lds ? seg : 0) * BV;
-    float* const gch[4] = {a.gm, a.gp0, a.gp1, a.gp2};
+    const bool lds = seg < kBrickKMAX;
+    const int lbase = (b0 & 3) + kBrickSY * (b1 & 3) + kBrickSZ * (b2 & 3);
+    const int gbase = (b2 * ny + b1) * nx + b0;
+    double* const lb = brick + (lds ? seg : 0) * 4 * kBrickV + lbase;
+    float* const gch[4] = {a.gm + gbase, a.gp0 + gbase, a.gp1 + gbase, a.gp2 + gbase};
+    const int nxny = nx * ny;
     float wyz[9];
 #pragma unroll
     for (int jz = 0; jz < 3; ++jz)
@@ -172,38 +155,48 @@ __global__ __launch_bounds__(BS) void p2g_brick_kernel(P2GArgs a) {
             }
       }
       if (lds) {
-        rotate27(val, rot);
-        double* const lbc = lb + ch * KMAX * BV;
+        double* const lbc = lb + ch * kBrickV;
 #pragma unroll
-        for (int j = 0; j < 27; ++j) atomicAdd(lbc + off[j], (double)val[j]);
+        for (int jz = 0; jz < 3; ++jz)
+#pragma unroll
+          for (int jy = 0; jy < 3; ++jy)
+#pragma unroll
+            for (int jx = 0; jx < 3; ++jx)
+              atomicAdd(lbc + jx + kBrickSY * jy + kBrickSZ * jz, (double)val[jx + 3 * jy + 9 * jz]);
       } else {
 #pragma unroll
-        for (int j = 0; j < 27; ++j) atomicAdd(gch[ch] + off[j], val[j]);
+        for (int jz = 0; jz < 3; ++jz)
+#pragma unroll
+          for (int jy = 0; jy < 3; ++jy)
+#pragma unroll
+            for (int jx = 0; jx < 3; ++jx)
+              atomicAdd(gch[ch] + jz * nxny + jy * nx + jx, val[jx + 3 * jy + 9 * jz]);
       }
     }
   }
   __syncthreads();
 
-  // flush the bricks: one global atomic per channel per non-zero node
-  const int nb = nseg < KMAX ? nseg : KMAX;
-  for (int k = tid; k < nb * BV; k += BS) {
-    const int s = k / BV;
-    const int loc = k - s * BV;
+  // flush: one global float atomic per channel per non-zero brick node
+  const int nb = nseg < kBrickKMAX ? nseg : kBrickKMAX;
+  for (int k = tid; k < nb * 4 * kBrickV; k += BS) {
+    const int sc = k / kBrickV;  // brick * 4 + channel
+    const int idx = k - sc * kBrickV;
+    const int s = sc >> 2;
+    const int ch = sc & 3;
+    const int lz = idx / kBrickSZ;
+    const int rem = idx - lz * kBrickSZ;
+    const int ly = rem / kBrickSY;
+    const int lx = rem - ly * kBrickSY;
+    if (lx > kBrickT + 1 || ly > kBrickT + 1) continue;  // padding
+    const float v = (float)brick[k];
+    if (v == 0.0f) continue;
     const uint32_t tl = seg_tile[s];
-    const int lz = loc / (E * E);
-    const int rem = loc - lz * E * E;
-    const int ly = rem / E;
-    const int lx = rem - ly * E;
-    const int gx = (int)(tl & 1023u) * T + lx;
-    const int gy = (int)((tl >> 10) & 1023u) * T + ly;
-    const int gz = (int)(tl >> 20) * T + lz;
+    const int gx = (int)(tl & 1023u) * kBrickT + lx;
+    const int gy = (int)((tl >> 10) & 1023u) * kBrickT + ly;
+    const int gz = (int)(tl >> 20) * kBrickT + lz;
     if (gx < nx && gy < ny && gz < nz) {
-      const int node = (gz * ny + gy) * nx + gx;
-#pragma unroll
-      for (int ch = 0; ch < 4; ++ch) {
-        const float v = (float)brick[(ch * KMAX + s) * BV + loc];
-        if (v != 0.0f) atomicAdd((ch == 0 ? a.gm : ch == 1 ? a.gp0 : ch == 2 ? a.gp1 : a.gp2) + node, v);
-      }
+      float* const d = ch == 0 ? a.gm : ch == 1 ? a.gp0 : ch == 2 ? a.gp1 : a.gp2;
+      atomicAdd(d + ((gz * ny + gy) * nx + gx), v);
     }
   }
 }
@@ -403,28 +396,21 @@ __global__ __launch_bounds__(kCellThreads) void p2g_cell_kernel(P2GArgs a) {
   }
 }
 
-template <int NR, int TB, int BS>
+template <int NR, int BS>
 hipError_t launch_cfg(const P2GArgs& a, hipStream_t stream) {
   const unsigned blocks = (unsigned)((a.P + BS - 1) / BS);
-  p2g_brick_kernel<NR, TB, BS><<<blocks, BS, 0, stream>>>(a);
+  p2g_brick_kernel<NR, BS><<<blocks, BS, 0, stream>>>(a);
   return hipGetLastError();
 }
 
 template <int NR>
 hipError_t launch_nr(const P2GArgs& a, const P2GConfig& c, hipStream_t stream) {
-  switch (c.tile_log2 * 1000 + c.block) {
-    case 1128: return launch_cfg<NR, 1, 128>(a, stream);
-    case 1256: return launch_cfg<NR, 1, 256>(a, stream);
-    case 2128: return launch_cfg<NR, 2, 128>(a, stream);
-    case 2256: return launch_cfg<NR, 2, 256>(a, stream);
-    case 2512: return launch_cfg<NR, 2, 512>(a, stream);
-    case 3256: return launch_cfg<NR, 3, 256>(a, stream);
-    case 3512: return launch_cfg<NR, 3, 512>(a, stream);
+  switch (c.block) {
+    case 256: return launch_cfg<NR, 256>(a, stream);
+    case 512: return launch_cfg<NR, 512>(a, stream);
     default: return hipErrorInvalidValue;
   }
 }
-
-}  // namespace
 
 template <int NR>
 hipError_t launch_cell_nr(const P2GArgs& a, int blocks, hipStream_t stream) {
@@ -432,12 +418,12 @@ hipError_t launch_cell_nr(const P2GArgs& a, int blocks, hipStream_t stream) {
   return hipGetLastError();
 }
 
-P2GConfig p2g_default_config() { return P2GConfig{2, 256}; }
+}  // namespace
+
+P2GConfig p2g_default_config() { return P2GConfig{2, 512}; }
 
 bool p2g_config_supported(const P2GConfig& c) {
-  const int code = c.tile_log2 * 1000 + c.block;
-  return code == 1128 || code == 1256 || code == 2128 || code == 2256 || code == 2512 ||
-         code == 3256 || code == 3512;
+  return c.tile_log2 == 2 && (c.block == 256 || c.block == 512);
 }
 
 hipError_t launch_grid_clear(float* gm, float* gp, int64_t n_nodes, uint32_t* counter,
