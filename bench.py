@@ -91,7 +91,7 @@ def parse_args():
     ap.add_argument("--n-modes", type=int, default=27)
     ap.add_argument("--cells", type=int, default=128, help="grid cells per axis (dam break)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample", type=int, default=262144,
+    ap.add_argument("--cpu-sample", type=int, default=1048576,
                     help="particles in the oracle's timed sample")
     ap.add_argument("--no-apic", action="store_true", help="skip the 4-mode comparison run")
     ap.add_argument("--calib-copy", action="store_true",
@@ -192,6 +192,7 @@ def main():
                         bc_layers=scene.bc_layers, track_order=False)
     for _ in range(args.warmup):
         ps.step()
+    p2g_choice = ps.autotune()  # library autotuner, outside the timed region
     torch.cuda.synchronize()
     wall, phase = time_steps(ps, args.steps, torch)
     if ps.status_flags() != 0:
@@ -209,10 +210,13 @@ def main():
                              track_order=False)
         for _ in range(args.warmup):
             ps4.step()
+        choice4 = ps4.autotune()
         w4, ph4 = time_steps(ps4, args.steps, torch)
         apic = {"n_modes": 4, "ms_per_step": w4 * 1e3 / args.steps,
                 "transfers_per_s": P * args.steps / w4,
                 "p2g_g2p_transfers_per_s": P / ((ph4["p2g"] + ph4["g2p"]) * 1e-3),
+                "p2g_config": {"path": "cells" if choice4[0] == 1 else "bricks",
+                               "block": choice4[1]},
                 "phase_ms": {k: round(v, 4) for k, v in ph4.items()}}
         del ps4, c4
 
@@ -224,7 +228,7 @@ def main():
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": measured_traffic(dom, workload), "kernel": dom,
                 "bytes_per_particle": bpp,
-                "note": ("event time of the polypic_p2g call (grid clear + P2G kernel)"
+                "note": ("event time of the polypic_p2g call (grid clear, tile list and P2G kernels)"
                          if dom == "p2g" else "event time of the polypic_g2p call (one kernel)")}
 
     cpu = None
@@ -248,6 +252,8 @@ def main():
                    "grid_nodes": list(scene.grid.nodes), "ppc": 8, "dt": scene.dt,
                    "step": "sort + p2g + grid_update + g2p(+advection)"},
         "p2g_g2p_transfers_per_s": P / (transfer_ms * 1e-3),
+        "p2g_config": {"path": "cells" if p2g_choice[0] == 1 else "bricks", "block": p2g_choice[1],
+                       "chosen_by": "polypic_autotune_p2g"},
         "phase_ms": {k: round(v, 4) for k, v in phase.items()},
         "apic_4mode": apic,
         "bwd_fwd_ratio": None,

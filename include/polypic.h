@@ -153,6 +153,36 @@ int32_t polypic_p2g(const polypic_grid* grid, int64_t P, int32_t n_modes, const 
                     float* grid_mom, int32_t accumulate, int32_t* status_dev, void* stream);
 
 /* ------------------------------------------------------------------------
+ * P2G launch configuration and autotuner (a runtime choice, no effect on
+ * results beyond float summation order).
+ *
+ * path   POLYPIC_P2G_BRICKS: per-particle scatter into FP64 LDS bricks of 4^3
+ *        cells (needs only perm); POLYPIC_P2G_CELLS: per-cell run sums (needs
+ *        keys_sorted).  block: workgroup size of the brick path (256 or 512).
+ * The choice is kept per n_modes in a process-wide, mutex-guarded table.
+ * Without an entry polypic_p2g uses the cell path when keys_sorted is given
+ * and the brick path (block 512) otherwise; the cell path is never chosen
+ * without keys_sorted.
+ *
+ * polypic_autotune_p2g runs P2G once per candidate configuration on the given
+ * inputs (same arguments as polypic_p2g, keys_sorted may be NULL), times each
+ * with HIP events on `stream`, stores the fastest and returns it in
+ * *path_out / *block_out (host pointers, may be NULL).  Unlike the other
+ * entry points it SYNCHRONISES the stream.  On return grid_mass / grid_mom
+ * hold a P2G result (accumulate = 0).
+ * ------------------------------------------------------------------------ */
+#define POLYPIC_P2G_DEFAULT (-1)
+#define POLYPIC_P2G_BRICKS 0
+#define POLYPIC_P2G_CELLS 1
+int32_t polypic_set_p2g_config(int32_t n_modes, int32_t path, int32_t block);
+int32_t polypic_get_p2g_config(int32_t n_modes, int32_t* path, int32_t* block);
+int32_t polypic_autotune_p2g(const polypic_grid* grid, int64_t P, int32_t n_modes, const float* x,
+                             const float* mass, float uniform_mass, const float* coeff,
+                             const int32_t* perm, const uint32_t* keys_sorted, void* ws,
+                             size_t ws_bytes, float* grid_mass, float* grid_mom,
+                             int32_t* path_out, int32_t* block_out, void* stream);
+
+/* ------------------------------------------------------------------------
  * Grid update.  Eq. 5 (v = (mv) / m) followed by an explicit update that the
  * paper delegates to its host model: gravity and separating slip walls.
  *     v_i = grid_mom[i] / grid_mass[i] + dt * gravity   where grid_mass[i] > 0

@@ -15,6 +15,9 @@ load()  # fail loudly here if the HIP library is missing
 
 from . import ops  # noqa: E402
 from .ops import (  # noqa: E402
+    polypic_autotune_p2g,
+    polypic_get_p2g_config,
+    polypic_set_p2g_config,
     grid_from_spec,
     make_grid,
     polypic_g2p,
@@ -28,5 +31,6 @@ from .stepper import ParticleSet  # noqa: E402
 __all__ = [
     "LIB_PATH", "PolyPICError", "polypic_grid", "ops", "make_grid", "grid_from_spec",
     "polypic_sort", "polypic_sort_workspace_bytes", "polypic_p2g", "polypic_grid_update",
-    "polypic_g2p", "ParticleSet",
+    "polypic_g2p", "polypic_autotune_p2g", "polypic_get_p2g_config", "polypic_set_p2g_config",
+    "ParticleSet",
 ]

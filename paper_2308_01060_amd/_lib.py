@@ -19,6 +19,9 @@ POLYPIC_EDEVICE = 3
 POLYPIC_ENOSPACE = 4
 POLYPIC_ENOTSUP = 5
 POLYPIC_FLAG_RANGE = 1
+POLYPIC_P2G_DEFAULT = -1
+POLYPIC_P2G_BRICKS = 0
+POLYPIC_P2G_CELLS = 1
 
 EXPORTED = (
     "polypic_strerror",
@@ -28,6 +31,9 @@ EXPORTED = (
     "polypic_sort",
     "polypic_p2g_workspace_bytes",
     "polypic_p2g",
+    "polypic_set_p2g_config",
+    "polypic_get_p2g_config",
+    "polypic_autotune_p2g",
     "polypic_grid_update",
     "polypic_g2p",
 )
@@ -91,6 +97,13 @@ def load() -> ctypes.CDLL:
     lib.polypic_p2g_workspace_bytes.argtypes = [G, i64, ctypes.POINTER(sz)]
     lib.polypic_p2g.restype = i32
     lib.polypic_p2g.argtypes = [G, i64, i32, P, P, f32, P, P, P, P, sz, P, P, i32, P, P]
+    lib.polypic_set_p2g_config.restype = i32
+    lib.polypic_set_p2g_config.argtypes = [i32, i32, i32]
+    lib.polypic_get_p2g_config.restype = i32
+    lib.polypic_get_p2g_config.argtypes = [i32, ctypes.POINTER(i32), ctypes.POINTER(i32)]
+    lib.polypic_autotune_p2g.restype = i32
+    lib.polypic_autotune_p2g.argtypes = [G, i64, i32, P, P, f32, P, P, P, P, sz, P, P,
+                                         ctypes.POINTER(i32), ctypes.POINTER(i32), P]
     lib.polypic_grid_update.restype = i32
     lib.polypic_grid_update.argtypes = [G, f32, ctypes.POINTER(f32), i32, P, P, P, P]
     lib.polypic_g2p.restype = i32

@@ -2,6 +2,10 @@
 // Every entry point only enqueues work on the caller's stream.
 #include <math.h>
 
+#include <algorithm>
+#include <mutex>
+#include <vector>
+
 #include "polypic.h"
 #include "polypic_internal.hpp"
 
@@ -59,6 +63,59 @@ int32_t from_hip(hipError_t e) {
 void discard_stale_error() { (void)hipGetLastError(); }
 
 int64_t n_nodes(const polypic_grid* g) { return (int64_t)g->nx * g->ny * g->nz; }
+
+// ---- P2G launch-configuration table (per n_modes), shared by the process
+struct P2GChoice {
+  int path = POLYPIC_P2G_DEFAULT;
+  int block = 512;
+};
+std::mutex g_tune_mutex;
+P2GChoice g_tune[28];
+
+P2GChoice get_choice(int n_modes) {
+  std::lock_guard<std::mutex> lock(g_tune_mutex);
+  return g_tune[n_modes];
+}
+
+void set_choice(int n_modes, P2GChoice c) {
+  std::lock_guard<std::mutex> lock(g_tune_mutex);
+  g_tune[n_modes] = c;
+}
+
+// Enqueue one P2G with an explicit configuration (arguments already validated).
+int32_t run_p2g(const polypic_grid* grid, int64_t P, int32_t n_modes, const float* x,
+                const float* mass, float uniform_mass, const float* coeff, const int32_t* perm,
+                const uint32_t* keys_sorted, void* ws, float* grid_mass, float* grid_mom,
+                int32_t accumulate, int32_t* status_dev, hipStream_t s, P2GChoice c) {
+  int32_t st;
+  const int64_t N = n_nodes(grid);
+  const bool cells = keys_sorted != nullptr &&
+                     (c.path == POLYPIC_P2G_CELLS || c.path == POLYPIC_P2G_DEFAULT);
+  uint32_t* counter = cells ? (uint32_t*)ws : nullptr;
+  if (!accumulate) {
+    if ((st = from_hip(launch_grid_clear(grid_mass, grid_mom, N, counter, s)))) return st;
+  }
+  P2GArgs a;
+  a.g = to_dev(grid);
+  a.P = P;
+  a.x = x;
+  a.mass = mass;
+  a.uniform_mass = uniform_mass;
+  a.coeff = coeff;
+  a.perm = perm;
+  a.gm = grid_mass;
+  a.gp0 = grid_mom;
+  a.gp1 = grid_mom + N;
+  a.gp2 = grid_mom + 2 * N;
+  a.status = status_dev;
+  a.keys = keys_sorted;
+  a.tile_list = nullptr;
+  a.tile_count = nullptr;
+  if (cells) return from_hip(launch_p2g_sorted(a, n_modes, ws, !accumulate, s));
+  P2GConfig cfg = p2g_default_config();
+  cfg.block = c.block;
+  return from_hip(launch_p2g(a, n_modes, cfg, s));
+}
 
 }  // namespace
 
@@ -128,31 +185,99 @@ int32_t polypic_p2g(const polypic_grid* grid, int64_t P, int32_t n_modes, const 
     if (!perm || !ws) return POLYPIC_EINVAL;
     if (ws_bytes < p2g_workspace_bytes(to_dev(grid), P)) return POLYPIC_ENOSPACE;
   }
-  const hipStream_t s = (hipStream_t)stream;
-  const int64_t N = n_nodes(grid);
   discard_stale_error();
-  uint32_t* counter = sorted ? (uint32_t*)ws : nullptr;
-  if (!accumulate) {
-    if ((st = from_hip(launch_grid_clear(grid_mass, grid_mom, N, counter, s)))) return st;
+  return run_p2g(grid, P, n_modes, x, mass, uniform_mass, coeff, perm, keys_sorted, ws, grid_mass,
+                 grid_mom, accumulate, status_dev, (hipStream_t)stream, get_choice(n_modes));
+}
+
+int32_t polypic_set_p2g_config(int32_t n_modes, int32_t path, int32_t block) {
+  if (!valid_modes(n_modes)) return POLYPIC_EINVAL;
+  if (path != POLYPIC_P2G_DEFAULT && path != POLYPIC_P2G_BRICKS && path != POLYPIC_P2G_CELLS)
+    return POLYPIC_EINVAL;
+  if (block != 256 && block != 512) return POLYPIC_EINVAL;
+  P2GChoice c;
+  c.path = path;
+  c.block = block;
+  set_choice(n_modes, c);
+  return POLYPIC_OK;
+}
+
+int32_t polypic_get_p2g_config(int32_t n_modes, int32_t* path, int32_t* block) {
+  if (!valid_modes(n_modes)) return POLYPIC_EINVAL;
+  const P2GChoice c = get_choice(n_modes);
+  if (path) *path = c.path;
+  if (block) *block = c.block;
+  return POLYPIC_OK;
+}
+
+int32_t polypic_autotune_p2g(const polypic_grid* grid, int64_t P, int32_t n_modes, const float* x,
+                             const float* mass, float uniform_mass, const float* coeff,
+                             const int32_t* perm, const uint32_t* keys_sorted, void* ws,
+                             size_t ws_bytes, float* grid_mass, float* grid_mom,
+                             int32_t* path_out, int32_t* block_out, void* stream) {
+  int32_t st = check_grid(grid);
+  if (st) return st;
+  if ((st = check_P(P))) return st;
+  if (!valid_modes(n_modes)) return POLYPIC_EINVAL;
+  if (!grid_mass || !grid_mom) return POLYPIC_EINVAL;
+  if (P > 0 && (!x || !coeff)) return POLYPIC_EINVAL;
+  if (!mass && !isfinite(uniform_mass)) return POLYPIC_EINVAL;
+  if (keys_sorted) {
+    if (!perm || !ws) return POLYPIC_EINVAL;
+    if (ws_bytes < p2g_workspace_bytes(to_dev(grid), P)) return POLYPIC_ENOSPACE;
   }
-  P2GArgs a;
-  a.g = to_dev(grid);
-  a.P = P;
-  a.x = x;
-  a.mass = mass;
-  a.uniform_mass = uniform_mass;
-  a.coeff = coeff;
-  a.perm = perm;
-  a.gm = grid_mass;
-  a.gp0 = grid_mom;
-  a.gp1 = grid_mom + N;
-  a.gp2 = grid_mom + 2 * N;
-  a.status = status_dev;
-  a.keys = keys_sorted;
-  a.tile_list = nullptr;
-  a.tile_count = nullptr;
-  if (sorted) return from_hip(launch_p2g_sorted(a, n_modes, ws, !accumulate, s));
-  return from_hip(launch_p2g(a, n_modes, p2g_default_config(), s));
+  const hipStream_t s = (hipStream_t)stream;
+  std::vector<P2GChoice> cand;
+  for (int block : {256, 512}) {
+    P2GChoice c;
+    c.path = POLYPIC_P2G_BRICKS;
+    c.block = block;
+    cand.push_back(c);
+  }
+  if (keys_sorted) {
+    P2GChoice c;
+    c.path = POLYPIC_P2G_CELLS;
+    cand.push_back(c);
+  }
+  discard_stale_error();
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess) return POLYPIC_EDEVICE;
+  if (hipEventCreate(&e1) != hipSuccess) {
+    hipEventDestroy(e0);
+    return POLYPIC_EDEVICE;
+  }
+  P2GChoice best;
+  float best_ms = -1.0f;
+  constexpr int kReps = 3;
+  for (const P2GChoice& c : cand) {
+    // one untimed run, then the median of kReps timed runs
+    float t[kReps];
+    for (int rep = -1; rep < kReps && st == POLYPIC_OK; ++rep) {
+      if (rep >= 0 && hipEventRecord(e0, s) != hipSuccess) st = POLYPIC_EDEVICE;
+      if (!st)
+        st = run_p2g(grid, P, n_modes, x, mass, uniform_mass, coeff, perm, keys_sorted, ws,
+                     grid_mass, grid_mom, 0, nullptr, s, c);
+      if (!st && rep >= 0) {
+        if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+            hipEventElapsedTime(&t[rep], e0, e1) != hipSuccess)
+          st = POLYPIC_EDEVICE;
+      }
+    }
+    if (st) break;
+    std::sort(t, t + kReps);
+    if (best_ms < 0.0f || t[kReps / 2] < best_ms) {
+      best_ms = t[kReps / 2];
+      best = c;
+    }
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  if (st) return st;
+  if (hipStreamSynchronize(s) != hipSuccess) return POLYPIC_EDEVICE;
+  set_choice(n_modes, best);
+  if (path_out) *path_out = best.path;
+  if (block_out) *block_out = best.block;
+  return POLYPIC_OK;
 }
 
 int32_t polypic_grid_update(const polypic_grid* grid, float dt, const float* gravity,

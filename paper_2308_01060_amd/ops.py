@@ -112,6 +112,41 @@ def polypic_p2g(grid: polypic_grid, n_modes: int, x: torch.Tensor, coeff: torch.
         _ptr(status_dev, torch.int32, 1, "status_dev"), _stream()), "polypic_p2g")
 
 
+def polypic_set_p2g_config(n_modes: int, path: int, block: int = 512) -> None:
+    check(_lib.load().polypic_set_p2g_config(int(n_modes), int(path), int(block)),
+          "polypic_set_p2g_config")
+
+
+def polypic_get_p2g_config(n_modes: int) -> Tuple[int, int]:
+    path, block = ctypes.c_int32(0), ctypes.c_int32(0)
+    check(_lib.load().polypic_get_p2g_config(int(n_modes), ctypes.byref(path), ctypes.byref(block)),
+          "polypic_get_p2g_config")
+    return int(path.value), int(block.value)
+
+
+def polypic_autotune_p2g(grid: polypic_grid, n_modes: int, x: torch.Tensor, coeff: torch.Tensor,
+                         grid_mass: torch.Tensor, grid_mom: torch.Tensor,
+                         mass: Optional[torch.Tensor] = None, uniform_mass: float = 1.0,
+                         perm: Optional[torch.Tensor] = None,
+                         keys_sorted: Optional[torch.Tensor] = None,
+                         ws: Optional[torch.Tensor] = None) -> Tuple[int, int]:
+    """Times every P2G configuration on these inputs; returns the chosen (path, block)."""
+    P = x.numel() // 3
+    N = n_nodes(grid)
+    path, block = ctypes.c_int32(0), ctypes.c_int32(0)
+    check(_lib.load().polypic_autotune_p2g(
+        ctypes.byref(grid), P, int(n_modes), _ptr(x, torch.float32, 3 * P, "x"),
+        _ptr(mass, torch.float32, P, "mass"), float(uniform_mass),
+        _ptr(coeff, torch.float32, 3 * int(n_modes) * P, "coeff"),
+        _ptr(perm, torch.int32, P, "perm"), _keys_ptr(keys_sorted, P),
+        _ptr(ws, torch.uint8, ws.numel() if ws is not None else 0, "ws"),
+        0 if ws is None else ws.numel(),
+        _ptr(grid_mass, torch.float32, N, "grid_mass"),
+        _ptr(grid_mom, torch.float32, 3 * N, "grid_mom"),
+        ctypes.byref(path), ctypes.byref(block), _stream()), "polypic_autotune_p2g")
+    return int(path.value), int(block.value)
+
+
 def polypic_grid_update(grid: polypic_grid, dt: float, gravity: Sequence[float], bc_layers: int,
                         grid_mass: torch.Tensor, grid_mom: torch.Tensor,
                         grid_vel: torch.Tensor) -> None:

@@ -77,6 +77,14 @@ class ParticleSet:
                         keys_sorted=self.keys if sorted_ else None,
                         ws=self.p2g_ws if sorted_ else None, status_dev=self.status)
 
+    def autotune(self):
+        """Sort, then let the library time its P2G configurations on this set (synchronises)."""
+        self.sort()
+        return ops.polypic_autotune_p2g(self.grid, self.n_modes, self.x, self.coeff, self.grid_mass,
+                                        self.grid_mom, mass=self.mass,
+                                        uniform_mass=self.uniform_mass, perm=self.perm,
+                                        keys_sorted=self.keys, ws=self.p2g_ws)
+
     def grid_update(self):
         ops.polypic_grid_update(self.grid, self.dt, self.gravity, self.bc_layers,
                                 self.grid_mass, self.grid_mom, self.grid_vel)

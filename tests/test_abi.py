@@ -128,3 +128,17 @@ def test_grid_update_and_sort_reject_bad_arguments():
     assert lib.polypic_sort(ctypes.byref(g), 100, None, FAKE, FAKE, FAKE, 1 << 20, None,
                             None) == 1
     assert lib.polypic_sort(ctypes.byref(g), 0, None, None, None, None, 0, None, None) == 0
+
+
+def test_p2g_config_table_validation():
+    lib = _lib.load()
+    path, block = ctypes.c_int32(0), ctypes.c_int32(0)
+    assert lib.polypic_set_p2g_config(5, 0, 512) == 1            # bad n_modes
+    assert lib.polypic_set_p2g_config(27, 7, 512) == 1           # bad path
+    assert lib.polypic_set_p2g_config(27, 0, 300) == 1           # bad block
+    assert lib.polypic_set_p2g_config(8, _lib.POLYPIC_P2G_BRICKS, 256) == 0
+    assert lib.polypic_get_p2g_config(8, ctypes.byref(path), ctypes.byref(block)) == 0
+    assert (path.value, block.value) == (_lib.POLYPIC_P2G_BRICKS, 256)
+    assert lib.polypic_set_p2g_config(8, _lib.POLYPIC_P2G_DEFAULT, 512) == 0
+    assert lib.polypic_get_p2g_config(8, ctypes.byref(path), ctypes.byref(block)) == 0
+    assert path.value == _lib.POLYPIC_P2G_DEFAULT
