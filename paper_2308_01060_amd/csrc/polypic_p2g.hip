@@ -225,9 +225,16 @@ __global__ __launch_bounds__(256) void p2g_tiles_kernel(const uint32_t* __restri
                                                         int64_t P, uint32_t* __restrict__ list,
                                                         uint32_t* __restrict__ count) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= P) return;
-  const uint32_t t = keys[i] >> 6;
-  if (i == 0 || (keys[i - 1] >> 6) != t) list[atomicAdd(count, 1u)] = (uint32_t)i;
+  const bool head = i < P && (i == 0 || (keys[i - 1] >> 6) != (keys[i] >> 6));
+  // one counter atomic per wavefront; heads take consecutive slots after it
+  const unsigned long long hb = __ballot(head);
+  if (hb == 0ull) return;
+  const int leader = __builtin_ctzll(hb);
+  const int lane = threadIdx.x & (kWave - 1);
+  uint32_t base = 0;
+  if (lane == leader) base = atomicAdd(count, (uint32_t)__popcll(hb));
+  base = __shfl(base, leader, kWave);
+  if (head) list[base + (uint32_t)lanes_below(hb)] = (uint32_t)i;
 }
 
 // local Morton index of a cell inside its 4^3 tile
