@@ -94,6 +94,9 @@ def parse_args():
     ap.add_argument("--cpu-sample", type=int, default=1048576,
                     help="particles in the oracle's timed sample")
     ap.add_argument("--no-apic", action="store_true", help="skip the 4-mode comparison run")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the bwd/fwd timing")
+    ap.add_argument("--adjoint-steps", type=int, default=10,
+                    help="differentiable steps in the bwd/fwd timing")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run only a plain device copy of known size (counter calibration)")
     return ap.parse_args()
@@ -137,6 +140,103 @@ def time_steps(ps, steps: int, torch):
         for j, n in enumerate(names):
             phase[n] += e[j].elapsed_time(e[j + 1])
     return wall, {n: v / steps for n, v in phase.items()}
+
+
+def adjoint_timing(pp, torch, W, cells: int, n_modes: int, n_steps: int, reps: int = 3):
+    """Forward and backward time of `n_steps` differentiable steps (polypic_steps).
+
+    Scene: the dam-break geometry with moving state (c0 ~ N(0,1), higher modes
+    ~ N(0,0.1)).  The upstream gradients are those of the velocity-matching loss
+    1/2 sum_p |c_p0 - v*(x_p)|^2 on the final state, taken once outside the timed
+    region; the timed backward is the library's reverse pass alone (per step:
+    recompute sort + P2G + grid update, then G2P, grid-update and P2G adjoints).
+    Returns the median over `reps` repetitions, plus event times of the three
+    adjoint calls of one step.
+    """
+    import numpy as np
+
+    s = W.config1_moving(0, n=cells)
+    g = pp.grid_from_spec(s.grid)
+    x0 = torch.from_numpy(s.x).cuda().requires_grad_(True)
+    c0 = torch.from_numpy(np.ascontiguousarray(s.coeff[:, :n_modes])).cuda().requires_grad_(True)
+    A, kap, ph = (torch.tensor(v, dtype=torch.float32, device="cuda")
+                  for v in W.target_field_params(0))
+
+    def upstream(xS, cS):
+        xd = xS.detach().requires_grad_(True)
+        cd = cS.detach().requires_grad_(True)
+        vstar = A.T @ torch.sin(2 * np.pi * (kap @ xd) + ph.reshape(-1, 1))
+        L = 0.5 * ((cd[:, 0] - vstar) ** 2).sum()
+        return torch.autograd.grad(L, (xd, cd))
+
+    fwd, bwd = [], []
+    for rep in range(reps + 1):          # the first repetition warms up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        xS, cS = pp.polypic_steps(x0, c0, g, n_modes, n_steps, s.dt, s.gravity, s.bc_layers)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        gx, gc = upstream(xS, cS)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        torch.autograd.backward((xS, cS), (gx, gc))
+        torch.cuda.synchronize()
+        t3 = time.perf_counter()
+        if rep > 0:
+            fwd.append(t1 - t0)
+            bwd.append(t3 - t2)
+        x0.grad = None
+        c0.grad = None
+        del xS, cS, gx, gc
+
+    # per-call event times of one step's adjoint
+    ps = pp.ParticleSet(g, n_modes, x0.detach(), c0.detach(), dt=s.dt, gravity=s.gravity,
+                        bc_layers=s.bc_layers, track_order=False)
+    N = pp.ops.n_nodes(g)
+    gvb = torch.empty(3 * N, device="cuda")
+    gmb = torch.empty(N, device="cuda")
+    gpb = torch.empty(3 * N, device="cuda")
+    gxo = torch.randn(3, s.P, device="cuda")
+    gco = torch.randn(3, n_modes, s.P, device="cuda")
+    gxi = torch.zeros(3, s.P, device="cuda")
+    gci = torch.empty(3, n_modes, s.P, device="cuda")
+    ps.sort()
+    ps.p2g()
+    ps.grid_update()
+    names = ("g2p_backward", "grid_update_backward", "p2g_backward")
+    acc = {n: [] for n in names}
+    for rep in range(6):
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+        ev[0].record()
+        pp.ops.polypic_g2p_backward(g, n_modes, s.dt, ps.grid_vel, ps.x, gco, gvb, gxi,
+                                    perm=ps.perm, x_out_grad=gxo, status_dev=ps.status)
+        ev[1].record()
+        pp.ops.polypic_grid_update_backward(g, s.dt, s.gravity, s.bc_layers, ps.grid_mass,
+                                            ps.grid_mom, gvb, gmb, gpb)
+        ev[2].record()
+        pp.ops.polypic_p2g_backward(g, n_modes, ps.x, ps.coeff, gmb, gpb, gci, gxi,
+                                    perm=ps.perm, status_dev=ps.status)
+        ev[3].record()
+        torch.cuda.synchronize()
+        if rep > 0:
+            for j, n in enumerate(names):
+                acc[n].append(ev[j].elapsed_time(ev[j + 1]))
+    if ps.status_flags() != 0:
+        raise RuntimeError(f"device status flags {ps.status_flags()} in the adjoint timing")
+    f = float(np.median(fwd))
+    b = float(np.median(bwd))
+    return {
+        "bwd_fwd_ratio": b / f,
+        "fwd_ms": f * 1e3,
+        "bwd_ms": b * 1e3,
+        "n_steps": n_steps,
+        "particles": s.P,
+        "n_modes": n_modes,
+        "workload": s.name,
+        "bwd_step_phase_ms": {n: round(float(np.median(v)), 4) for n, v in acc.items()},
+        "note": "forward keeps one (x, c) checkpoint per step; backward recomputes each step's "
+                "sort, P2G and grid update before its adjoint calls",
+    }
 
 
 def cpu_baseline(scene, n_modes: int, sample: int):
@@ -231,6 +331,10 @@ def main():
                 "note": ("event time of the polypic_p2g call (grid clear, tile list and P2G kernels)"
                          if dom == "p2g" else "event time of the polypic_g2p call (one kernel)")}
 
+    adj = None
+    if not args.no_adjoint:
+        adj = adjoint_timing(pp, torch, W, args.cells, n_modes, args.adjoint_steps)
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(scene, n_modes, args.cpu_sample)
@@ -256,7 +360,8 @@ def main():
                        "chosen_by": "polypic_autotune_p2g"},
         "phase_ms": {k: round(v, 4) for k, v in phase.items()},
         "apic_4mode": apic,
-        "bwd_fwd_ratio": None,
+        "bwd_fwd_ratio": None if adj is None else round(adj["bwd_fwd_ratio"], 3),
+        "adjoint": adj,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

@@ -222,6 +222,50 @@ int32_t polypic_g2p(const polypic_grid* grid, int64_t P, int32_t n_modes, float 
                     float* coeff_out, const float* F_in, float* F_out, const float* mass_in,
                     float* mass_out, int32_t* status_dev, void* stream);
 
+/* ------------------------------------------------------------------------
+ * Adjoint (reverse mode) of one step.  For a scalar loss L of the step's
+ * outputs, these propagate dL/d(output) to dL/d(input) through the same
+ * operations as above, in reverse order:
+ *
+ *   polypic_g2p_backward(dL/dcoeff_out, dL/dx_out) -> dL/dgrid_vel, += dL/dx_in
+ *   polypic_grid_update_backward(dL/dgrid_vel)       -> dL/dgrid_mass, dL/dgrid_mom
+ *   polypic_p2g_backward(dL/dgrid_mass, dL/dgrid_mom) -> dL/dcoeff, += dL/dx, dL/dmass
+ *
+ * Their inputs are the forward inputs of the step (recomputed or kept by the
+ * caller -- no weights are stored) and, for the grid update and G2P, the
+ * forward grid quantities.  Gradient arrays use the layouts of the forward
+ * arrays they belong to.  Derivatives are taken almost everywhere: the stencil
+ * base node b is treated as constant (it is piecewise constant in x), a wall
+ * clamp or the advection clamp passes zero gradient to the clamped component,
+ * empty grid nodes (mass 0) pass none, and the F update is not differentiated.
+ * The sort permutation only reorders; pass the perm used in the forward step.
+ * Out-of-range particles raise POLYPIC_FLAG_RANGE and get zero gradient.
+ *
+ * polypic_g2p_backward: coeff_out_grad [3][n_modes][P] and x_out_grad [3][P]
+ *   (NULL: no dependence on x_out) are in output-slot order (slot i belongs to
+ *   particle perm[i]); grid_vel_grad [3][N] receives dL/dv (zeroed first unless
+ *   accumulate); x_in_grad [3][P] is ADDED to at perm[i] (caller zeroes it).
+ * polypic_grid_update_backward: writes grid_mass_grad [N], grid_mom_grad [3][N]
+ *   from grid_vel_grad and the forward grid_mass / grid_mom.
+ * polypic_p2g_backward: writes coeff_grad [3][n_modes][P] and, when not NULL,
+ *   mass_grad [P]; ADDS to x_grad [3][P].  perm (NULL allowed) only sets the
+ *   processing order.
+ * ------------------------------------------------------------------------ */
+int32_t polypic_g2p_backward(const polypic_grid* grid, int64_t P, int32_t n_modes, float dt,
+                             const float* grid_vel, const float* x_in, const int32_t* perm,
+                             const float* coeff_out_grad, const float* x_out_grad,
+                             float* grid_vel_grad, int32_t accumulate, float* x_in_grad,
+                             int32_t* status_dev, void* stream);
+int32_t polypic_grid_update_backward(const polypic_grid* grid, float dt, const float* gravity,
+                                     int32_t bc_layers, const float* grid_mass,
+                                     const float* grid_mom, const float* grid_vel_grad,
+                                     float* grid_mass_grad, float* grid_mom_grad, void* stream);
+int32_t polypic_p2g_backward(const polypic_grid* grid, int64_t P, int32_t n_modes, const float* x,
+                             const float* mass, float uniform_mass, const float* coeff,
+                             const int32_t* perm, const float* grid_mass_grad,
+                             const float* grid_mom_grad, float* coeff_grad, float* x_grad,
+                             float* mass_grad, int32_t* status_dev, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

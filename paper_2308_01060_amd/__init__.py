@@ -27,10 +27,11 @@ from .ops import (  # noqa: E402
     polypic_sort_workspace_bytes,
 )
 from .stepper import ParticleSet  # noqa: E402
+from .autograd import PolyPICSteps, polypic_steps  # noqa: E402
 
 __all__ = [
     "LIB_PATH", "PolyPICError", "polypic_grid", "ops", "make_grid", "grid_from_spec",
     "polypic_sort", "polypic_sort_workspace_bytes", "polypic_p2g", "polypic_grid_update",
     "polypic_g2p", "polypic_autotune_p2g", "polypic_get_p2g_config", "polypic_set_p2g_config",
-    "ParticleSet",
+    "ParticleSet", "PolyPICSteps", "polypic_steps",
 ]

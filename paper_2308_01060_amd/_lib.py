@@ -36,6 +36,9 @@ EXPORTED = (
     "polypic_autotune_p2g",
     "polypic_grid_update",
     "polypic_g2p",
+    "polypic_g2p_backward",
+    "polypic_grid_update_backward",
+    "polypic_p2g_backward",
 )
 
 
@@ -108,6 +111,13 @@ def load() -> ctypes.CDLL:
     lib.polypic_grid_update.argtypes = [G, f32, ctypes.POINTER(f32), i32, P, P, P, P]
     lib.polypic_g2p.restype = i32
     lib.polypic_g2p.argtypes = [G, i64, i32, f32, P, P, P, P, P, P, P, P, P, P, P]
+    lib.polypic_g2p_backward.restype = i32
+    lib.polypic_g2p_backward.argtypes = [G, i64, i32, f32, P, P, P, P, P, P, i32, P, P, P]
+    lib.polypic_grid_update_backward.restype = i32
+    lib.polypic_grid_update_backward.argtypes = [G, f32, ctypes.POINTER(f32), i32, P, P, P, P, P,
+                                                 P]
+    lib.polypic_p2g_backward.restype = i32
+    lib.polypic_p2g_backward.argtypes = [G, i64, i32, P, P, f32, P, P, P, P, P, P, P, P, P]
     _lib = lib
     return lib
 

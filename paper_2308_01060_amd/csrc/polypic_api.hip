@@ -64,6 +64,17 @@ void discard_stale_error() { (void)hipGetLastError(); }
 
 int64_t n_nodes(const polypic_grid* g) { return (int64_t)g->nx * g->ny * g->nz; }
 
+// Advection clamp bounds [origin + 2 dx, origin + (n - 2) dx): the lower bound and
+// the largest float below the upper one, both rounded from double.
+void clamp_bounds(const polypic_grid* grid, float lo[3], float hi[3]) {
+  const int32_t d[3] = {grid->nx, grid->ny, grid->nz};
+  for (int ax = 0; ax < 3; ++ax) {
+    lo[ax] = (float)((double)grid->origin[ax] + 2.0 * (double)grid->dx);
+    const float top = (float)((double)grid->origin[ax] + (double)(d[ax] - 2) * (double)grid->dx);
+    hi[ax] = nextafterf(top, -INFINITY);
+  }
+}
+
 // ---- P2G launch-configuration table (per n_modes), shared by the process
 struct P2GChoice {
   int path = POLYPIC_P2G_DEFAULT;
@@ -322,13 +333,7 @@ int32_t polypic_g2p(const polypic_grid* grid, int64_t P, int32_t n_modes, float 
   a.P = P;
   a.dt = dt;
   a.dx = grid->dx;
-  const int32_t d[3] = {grid->nx, grid->ny, grid->nz};
-  for (int ax = 0; ax < 3; ++ax) {
-    // [origin + 2 dx, origin + (n - 2) dx): bounds rounded from double
-    a.lo[ax] = (float)((double)grid->origin[ax] + 2.0 * (double)grid->dx);
-    const float top = (float)((double)grid->origin[ax] + (double)(d[ax] - 2) * (double)grid->dx);
-    a.hi[ax] = nextafterf(top, -INFINITY);
-  }
+  clamp_bounds(grid, a.lo, a.hi);
   a.gv = grid_vel;
   a.x_in = x_in;
   a.perm = perm;
@@ -341,6 +346,99 @@ int32_t polypic_g2p(const polypic_grid* grid, int64_t P, int32_t n_modes, float 
   a.status = status_dev;
   discard_stale_error();
   return from_hip(launch_g2p(a, n_modes, (hipStream_t)stream));
+}
+
+int32_t polypic_g2p_backward(const polypic_grid* grid, int64_t P, int32_t n_modes, float dt,
+                             const float* grid_vel, const float* x_in, const int32_t* perm,
+                             const float* coeff_out_grad, const float* x_out_grad,
+                             float* grid_vel_grad, int32_t accumulate, float* x_in_grad,
+                             int32_t* status_dev, void* stream) {
+  int32_t st = check_grid(grid);
+  if (st) return st;
+  if ((st = check_P(P))) return st;
+  if (!valid_modes(n_modes) || !isfinite(dt)) return POLYPIC_EINVAL;
+  if (!grid_vel_grad) return POLYPIC_EINVAL;
+  if (P > 0 && (!grid_vel || !x_in || !coeff_out_grad || !x_in_grad)) return POLYPIC_EINVAL;
+  const hipStream_t s = (hipStream_t)stream;
+  discard_stale_error();
+  if (!accumulate) {
+    if ((st = from_hip(launch_zero(grid_vel_grad, 3 * n_nodes(grid), s)))) return st;
+  }
+  if (P == 0) return POLYPIC_OK;
+  G2PBackArgs a;
+  a.g = to_dev(grid);
+  a.P = P;
+  a.dt = dt;
+  clamp_bounds(grid, a.lo, a.hi);
+  a.gv = grid_vel;
+  a.x_in = x_in;
+  a.perm = perm;
+  a.coeff_out_grad = coeff_out_grad;
+  a.x_out_grad = x_out_grad;
+  a.gvb = grid_vel_grad;
+  a.x_in_grad = x_in_grad;
+  a.status = status_dev;
+  return from_hip(launch_g2p_backward(a, n_modes, s));
+}
+
+int32_t polypic_grid_update_backward(const polypic_grid* grid, float dt, const float* gravity,
+                                     int32_t bc_layers, const float* grid_mass,
+                                     const float* grid_mom, const float* grid_vel_grad,
+                                     float* grid_mass_grad, float* grid_mom_grad, void* stream) {
+  int32_t st = check_grid(grid);
+  if (st) return st;
+  if (!gravity || !grid_mass || !grid_mom || !grid_vel_grad || !grid_mass_grad || !grid_mom_grad)
+    return POLYPIC_EINVAL;
+  if (!isfinite(dt) || bc_layers < 0) return POLYPIC_EINVAL;
+  for (int a = 0; a < 3; ++a)
+    if (!isfinite(gravity[a])) return POLYPIC_EINVAL;
+  GridUpdateBackArgs a;
+  a.nx = grid->nx;
+  a.ny = grid->ny;
+  a.nz = grid->nz;
+  a.dt = dt;
+  a.g0 = gravity[0];
+  a.g1 = gravity[1];
+  a.g2 = gravity[2];
+  a.bc_layers = bc_layers;
+  a.gm = grid_mass;
+  a.gp = grid_mom;
+  a.gvb = grid_vel_grad;
+  a.gmb = grid_mass_grad;
+  a.gpb = grid_mom_grad;
+  discard_stale_error();
+  return from_hip(launch_grid_update_backward(a, (hipStream_t)stream));
+}
+
+int32_t polypic_p2g_backward(const polypic_grid* grid, int64_t P, int32_t n_modes, const float* x,
+                             const float* mass, float uniform_mass, const float* coeff,
+                             const int32_t* perm, const float* grid_mass_grad,
+                             const float* grid_mom_grad, float* coeff_grad, float* x_grad,
+                             float* mass_grad, int32_t* status_dev, void* stream) {
+  int32_t st = check_grid(grid);
+  if (st) return st;
+  if ((st = check_P(P))) return st;
+  if (!valid_modes(n_modes)) return POLYPIC_EINVAL;
+  if (P == 0) return POLYPIC_OK;
+  if (!x || !coeff || !grid_mass_grad || !grid_mom_grad || !coeff_grad || !x_grad)
+    return POLYPIC_EINVAL;
+  if (!mass && !isfinite(uniform_mass)) return POLYPIC_EINVAL;
+  P2GBackArgs a;
+  a.g = to_dev(grid);
+  a.P = P;
+  a.x = x;
+  a.mass = mass;
+  a.uniform_mass = uniform_mass;
+  a.coeff = coeff;
+  a.perm = perm;
+  a.gmb = grid_mass_grad;
+  a.gpb = grid_mom_grad;
+  a.coeff_grad = coeff_grad;
+  a.x_grad = x_grad;
+  a.mass_grad = mass_grad;
+  a.status = status_dev;
+  discard_stale_error();
+  return from_hip(launch_p2g_backward(a, n_modes, (hipStream_t)stream));
 }
 
 }  // extern "C"

@@ -220,6 +220,154 @@ __device__ __forceinline__ void eval_modes(const float (&c)[27], const Basis1D& 
       }
 }
 
+// ---------------------------------------------------------------- adjoint building blocks
+// General 1-D row matrix r[k][j]: factor k (0, 1, 2) at stencil node j (0, 1, 2).
+struct Rows {
+  float r[3][3];
+};
+
+// P2G rows R[k][j] = w_j phi_k(j) (weight times mode factor) and dR = dR/dt.
+__device__ __forceinline__ void p2g_rows(float t, Rows& R, Rows& dR) {
+  const Basis1D B = basis_p2g(t);
+  const float h0 = 0.5f - t, h2 = 0.5f + t;
+  const float s3 = 2.0f + 4.0f * h0 * h2;  // 3 - 4 t^2
+  const float dw[3] = {-h0, -2.0f * t, h2};
+  const float dg[3] = {2.0f * h2 * s3 - 8.0f * t * h2 * h2, 16.0f * t * h0 * h2,
+                       -2.0f * h0 * s3 - 8.0f * t * h0 * h0};
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    R.r[0][j] = B.w[j];
+    R.r[1][j] = B.w[j] * B.z[j];
+    R.r[2][j] = B.w[j] * B.g[j];
+    dR.r[0][j] = dw[j];
+    dR.r[1][j] = dw[j] * B.z[j] - B.w[j];  // d zhat / dt = -1
+    dR.r[2][j] = dw[j] * B.g[j] + B.w[j] * dg[j];
+  }
+}
+
+// G2P projection rows (as proj_g2p) and their t-derivatives; the quadratic row
+// (1/2, -1, 1/2) does not depend on t.
+__device__ __forceinline__ void g2p_rows(float t, Rows& Pr, Rows& dP) {
+  const Proj1D P = proj_g2p(t);
+  const float h0 = 0.5f - t, h2 = 0.5f + t;
+  const float w[3] = {0.5f * h0 * h0, 0.5f + h0 * h2, 0.5f * h2 * h2};
+  const float z[3] = {-1.0f - t, -t, 1.0f - t};
+  const float dw[3] = {-h0, -2.0f * t, h2};
+#pragma unroll
+  for (int k = 0; k < 3; ++k)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) Pr.r[k][j] = P.pr[k][j];
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    dP.r[0][j] = dw[j];
+    dP.r[1][j] = 4.0f * (dw[j] * z[j] - w[j]);
+    dP.r[2][j] = 0.0f;
+  }
+}
+
+template <int NR>
+__device__ constexpr bool need_kx_any(int kx) {
+  return any_kykz<NR>(kx);
+}
+
+// out[r] = sum_j Rx[kx][jx] Ry[ky][jy] Rz[kz][jz] v[jx + 3 jy + 9 jz] for r < NR
+// (separable: contract x, then y, then z).
+template <int NR>
+__device__ __forceinline__ void contract_rows(const float (&v)[27], const Rows& Rx, const Rows& Ry,
+                                              const Rows& Rz, float (&out)[27]) {
+  float A[3][3][3];  // [kx][jy][jz]
+#pragma unroll
+  for (int kx = 0; kx < 3; ++kx) {
+    if (!any_kykz<NR>(kx)) continue;
+#pragma unroll
+    for (int jy = 0; jy < 3; ++jy)
+#pragma unroll
+      for (int jz = 0; jz < 3; ++jz) {
+        const float* vv = v + 3 * jy + 9 * jz;
+        A[kx][jy][jz] = fmaf(Rx.r[kx][2], vv[2], fmaf(Rx.r[kx][1], vv[1], Rx.r[kx][0] * vv[0]));
+      }
+  }
+  float B[3][3][3];  // [kx][ky][jz]
+#pragma unroll
+  for (int kx = 0; kx < 3; ++kx)
+#pragma unroll
+    for (int ky = 0; ky < 3; ++ky) {
+      if (!any_kz<NR>(kx, ky)) continue;
+#pragma unroll
+      for (int jz = 0; jz < 3; ++jz)
+        B[kx][ky][jz] = fmaf(Ry.r[ky][2], A[kx][2][jz],
+                             fmaf(Ry.r[ky][1], A[kx][1][jz], Ry.r[ky][0] * A[kx][0][jz]));
+    }
+#pragma unroll
+  for (int kx = 0; kx < 3; ++kx)
+#pragma unroll
+    for (int ky = 0; ky < 3; ++ky)
+#pragma unroll
+      for (int kz = 0; kz < 3; ++kz) {
+        if (!has_mode<NR>(kx, ky, kz)) continue;
+        out[mode_index(kx, ky, kz)] =
+            fmaf(Rz.r[kz][2], B[kx][ky][2], fmaf(Rz.r[kz][1], B[kx][ky][1], Rz.r[kz][0] * B[kx][ky][0]));
+      }
+}
+
+// V[jx + 3 jy + 9 jz] = sum_{r < NR} c[r] Rx[kx][jx] Ry[ky][jy] Rz[kz][jz]
+// (the transpose of contract_rows).
+template <int NR>
+__device__ __forceinline__ void expand_rows(const float (&c)[27], const Rows& Rx, const Rows& Ry,
+                                            const Rows& Rz, float (&V)[27]) {
+  float A[3][3][3];  // [kx][ky][jz]
+#pragma unroll
+  for (int kx = 0; kx < 3; ++kx)
+#pragma unroll
+    for (int ky = 0; ky < 3; ++ky) {
+      if (!any_kz<NR>(kx, ky)) continue;
+#pragma unroll
+      for (int jz = 0; jz < 3; ++jz) {
+        float s = 0.0f;
+#pragma unroll
+        for (int kz = 0; kz < 3; ++kz)
+          if (has_mode<NR>(kx, ky, kz)) s = fmaf(c[mode_index(kx, ky, kz)], Rz.r[kz][jz], s);
+        A[kx][ky][jz] = s;
+      }
+    }
+  float B[3][3][3];  // [kx][jy][jz]
+#pragma unroll
+  for (int kx = 0; kx < 3; ++kx) {
+    if (!any_kykz<NR>(kx)) continue;
+#pragma unroll
+    for (int jy = 0; jy < 3; ++jy)
+#pragma unroll
+      for (int jz = 0; jz < 3; ++jz) {
+        float s = 0.0f;
+#pragma unroll
+        for (int ky = 0; ky < 3; ++ky)
+          if (any_kz<NR>(kx, ky)) s = fmaf(A[kx][ky][jz], Ry.r[ky][jy], s);
+        B[kx][jy][jz] = s;
+      }
+  }
+#pragma unroll
+  for (int jx = 0; jx < 3; ++jx)
+#pragma unroll
+    for (int jy = 0; jy < 3; ++jy)
+#pragma unroll
+      for (int jz = 0; jz < 3; ++jz) {
+        float s = 0.0f;
+#pragma unroll
+        for (int kx = 0; kx < 3; ++kx)
+          if (any_kykz<NR>(kx)) s = fmaf(B[kx][jy][jz], Rx.r[kx][jx], s);
+        V[jx + 3 * jy + 9 * jz] = s;
+      }
+}
+
+// FP64 LDS brick of a 4^3-cell tile: 6^3 nodes stored with strides (1, 8, 68)
+// doubles.  With the lanes of a wavefront spread over the 64 cells of a tile,
+// the 32 cells handled by each half-wavefront fall on 32 distinct LDS bank
+// pairs for every stencil node.
+constexpr int kBrickT = 4;  // tile edge in cells
+constexpr int kBrickSY = 8;
+constexpr int kBrickSZ = 68;
+constexpr int kBrickV = 5 + 5 * kBrickSY + 5 * kBrickSZ + 1;  // 386 doubles per channel
+
 // ---------------------------------------------------------------- Morton key
 __device__ __forceinline__ uint32_t spread_bits3(uint32_t v) {
   v &= 0x3ffu;

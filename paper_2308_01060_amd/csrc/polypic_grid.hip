@@ -35,7 +35,20 @@ __global__ __launch_bounds__(256) void grid_update_kernel(GridUpdateArgs a) {
   a.gv[2 * N + n] = v2;
 }
 
+__global__ __launch_bounds__(256) void zero_kernel(float* __restrict__ p, int64_t n) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += stride) p[k] = 0.0f;
+}
+
 }  // namespace
+
+hipError_t launch_zero(float* p, int64_t n, hipStream_t stream) {
+  if (n <= 0) return hipSuccess;
+  int64_t blocks = (n + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  zero_kernel<<<(unsigned)blocks, 256, 0, stream>>>(p, n);
+  return hipGetLastError();
+}
 
 hipError_t launch_grid_update(const GridUpdateArgs& a, hipStream_t stream) {
   dim3 grid((unsigned)((a.nx + 255) / 256), (unsigned)a.ny, (unsigned)a.nz);

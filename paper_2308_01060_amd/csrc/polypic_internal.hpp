@@ -65,6 +65,8 @@ struct GridUpdateArgs {
   float* gv;        // [3][N]
 };
 hipError_t launch_grid_update(const GridUpdateArgs& a, hipStream_t stream);
+// zero-fills p[0 .. n) with a kernel (no hipMemsetAsync: safe under graph capture)
+hipError_t launch_zero(float* p, int64_t n, hipStream_t stream);
 
 // ---- G2P
 struct G2PArgs {
@@ -85,5 +87,52 @@ struct G2PArgs {
   int32_t* status;
 };
 hipError_t launch_g2p(const G2PArgs& a, int n_modes, hipStream_t stream);
+
+// ---- adjoint
+struct GridUpdateBackArgs {
+  int nx, ny, nz;
+  float dt;
+  float g0, g1, g2;
+  int bc_layers;
+  const float* gm;   // [N]
+  const float* gp;   // [3][N]
+  const float* gvb;  // [3][N] dL/d grid_vel
+  float* gmb;        // [N]   dL/d grid_mass (written)
+  float* gpb;        // [3][N] dL/d grid_mom (written)
+};
+hipError_t launch_grid_update_backward(const GridUpdateBackArgs& a, hipStream_t stream);
+
+struct P2GBackArgs {
+  GridDev g;
+  int64_t P;
+  const float* x;
+  const float* mass;
+  float uniform_mass;
+  const float* coeff;   // [3][NR][P]
+  const int32_t* perm;  // processing order or nullptr
+  const float* gmb;     // [N]
+  const float* gpb;     // [3][N]
+  float* coeff_grad;    // [3][NR][P] (written)
+  float* x_grad;        // [3][P] (accumulated)
+  float* mass_grad;     // [P] (written) or nullptr
+  int32_t* status;
+};
+hipError_t launch_p2g_backward(const P2GBackArgs& a, int n_modes, hipStream_t stream);
+
+struct G2PBackArgs {
+  GridDev g;
+  int64_t P;
+  float dt;
+  float lo[3], hi[3];
+  const float* gv;              // [3][N]
+  const float* x_in;            // [3][P]
+  const int32_t* perm;          // [P] or nullptr
+  const float* coeff_out_grad;  // [3][NR][P], slot order
+  const float* x_out_grad;      // [3][P], slot order, or nullptr
+  float* gvb;                   // [3][N] (accumulated)
+  float* x_in_grad;             // [3][P] (accumulated at perm[i])
+  int32_t* status;
+};
+hipError_t launch_g2p_backward(const G2PBackArgs& a, int n_modes, hipStream_t stream);
 
 }  // namespace polypic

@@ -35,14 +35,6 @@ namespace polypic {
 
 namespace {
 
-// FP64 brick of a 4^3-cell tile: 6^3 nodes stored with strides (1, 8, 68)
-// doubles.  With lanes spread over the 64 cells of a tile (see below), the 32
-// cells handled by each half-wavefront then fall on 32 distinct LDS bank pairs
-// for every stencil node.
-constexpr int kBrickT = 4;                       // tile edge in cells
-constexpr int kBrickSY = 8;
-constexpr int kBrickSZ = 68;
-constexpr int kBrickV = 5 + 5 * kBrickSY + 5 * kBrickSZ + 1;  // 386 doubles per channel
 constexpr int kBrickKMAX = 3;                    // bricks (tiles) per workgroup in LDS
 
 template <int NR, int BS>

@@ -176,3 +176,59 @@ def polypic_g2p(grid: polypic_grid, n_modes: int, dt: float, grid_vel: torch.Ten
         _ptr(F_in, torch.float32, 9 * P, "F_in"), _ptr(F_out, torch.float32, 9 * P, "F_out"),
         _ptr(mass_in, torch.float32, P, "mass_in"), _ptr(mass_out, torch.float32, P, "mass_out"),
         _ptr(status_dev, torch.int32, 1, "status_dev"), _stream()), "polypic_g2p")
+
+
+def polypic_g2p_backward(grid: polypic_grid, n_modes: int, dt: float, grid_vel: torch.Tensor,
+                         x_in: torch.Tensor, coeff_out_grad: torch.Tensor,
+                         grid_vel_grad: torch.Tensor, x_in_grad: torch.Tensor,
+                         perm: Optional[torch.Tensor] = None,
+                         x_out_grad: Optional[torch.Tensor] = None, accumulate: bool = False,
+                         status_dev: Optional[torch.Tensor] = None) -> None:
+    P = x_in.numel() // 3
+    N = n_nodes(grid)
+    check(_lib.load().polypic_g2p_backward(
+        ctypes.byref(grid), P, int(n_modes), float(dt),
+        _ptr(grid_vel, torch.float32, 3 * N, "grid_vel"),
+        _ptr(x_in, torch.float32, 3 * P, "x_in"), _ptr(perm, torch.int32, P, "perm"),
+        _ptr(coeff_out_grad, torch.float32, 3 * int(n_modes) * P, "coeff_out_grad"),
+        _ptr(x_out_grad, torch.float32, 3 * P, "x_out_grad"),
+        _ptr(grid_vel_grad, torch.float32, 3 * N, "grid_vel_grad"), int(bool(accumulate)),
+        _ptr(x_in_grad, torch.float32, 3 * P, "x_in_grad"),
+        _ptr(status_dev, torch.int32, 1, "status_dev"), _stream()), "polypic_g2p_backward")
+
+
+def polypic_grid_update_backward(grid: polypic_grid, dt: float, gravity: Sequence[float],
+                                 bc_layers: int, grid_mass: torch.Tensor, grid_mom: torch.Tensor,
+                                 grid_vel_grad: torch.Tensor, grid_mass_grad: torch.Tensor,
+                                 grid_mom_grad: torch.Tensor) -> None:
+    N = n_nodes(grid)
+    g3 = (ctypes.c_float * 3)(*[float(v) for v in gravity])
+    check(_lib.load().polypic_grid_update_backward(
+        ctypes.byref(grid), float(dt), g3, int(bc_layers),
+        _ptr(grid_mass, torch.float32, N, "grid_mass"),
+        _ptr(grid_mom, torch.float32, 3 * N, "grid_mom"),
+        _ptr(grid_vel_grad, torch.float32, 3 * N, "grid_vel_grad"),
+        _ptr(grid_mass_grad, torch.float32, N, "grid_mass_grad"),
+        _ptr(grid_mom_grad, torch.float32, 3 * N, "grid_mom_grad"), _stream()),
+        "polypic_grid_update_backward")
+
+
+def polypic_p2g_backward(grid: polypic_grid, n_modes: int, x: torch.Tensor, coeff: torch.Tensor,
+                         grid_mass_grad: torch.Tensor, grid_mom_grad: torch.Tensor,
+                         coeff_grad: torch.Tensor, x_grad: torch.Tensor,
+                         mass: Optional[torch.Tensor] = None, uniform_mass: float = 1.0,
+                         perm: Optional[torch.Tensor] = None,
+                         mass_grad: Optional[torch.Tensor] = None,
+                         status_dev: Optional[torch.Tensor] = None) -> None:
+    P = x.numel() // 3
+    N = n_nodes(grid)
+    check(_lib.load().polypic_p2g_backward(
+        ctypes.byref(grid), P, int(n_modes), _ptr(x, torch.float32, 3 * P, "x"),
+        _ptr(mass, torch.float32, P, "mass"), float(uniform_mass),
+        _ptr(coeff, torch.float32, 3 * int(n_modes) * P, "coeff"),
+        _ptr(perm, torch.int32, P, "perm"),
+        _ptr(grid_mass_grad, torch.float32, N, "grid_mass_grad"),
+        _ptr(grid_mom_grad, torch.float32, 3 * N, "grid_mom_grad"),
+        _ptr(coeff_grad, torch.float32, 3 * int(n_modes) * P, "coeff_grad"),
+        _ptr(x_grad, torch.float32, 3 * P, "x_grad"), _ptr(mass_grad, torch.float32, P, "mass_grad"),
+        _ptr(status_dev, torch.int32, 1, "status_dev"), _stream()), "polypic_p2g_backward")

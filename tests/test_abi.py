@@ -142,3 +142,47 @@ def test_p2g_config_table_validation():
     assert lib.polypic_set_p2g_config(8, _lib.POLYPIC_P2G_DEFAULT, 512) == 0
     assert lib.polypic_get_p2g_config(8, ctypes.byref(path), ctypes.byref(block)) == 0
     assert path.value == _lib.POLYPIC_P2G_DEFAULT
+
+
+def test_backward_entry_points_reject_bad_arguments():
+    lib = _lib.load()
+    g = grid()
+    grav = (ctypes.c_float * 3)(0.0, -9.8, 0.0)
+
+    def g2pb(P=10, nr=4, dt=1e-4, gv=FAKE, x=FAKE, perm=None, gco=FAKE, gxo=None, gvb=FAKE,
+             gxi=FAKE):
+        return lib.polypic_g2p_backward(ctypes.byref(g), P, nr, dt, gv, x, perm, gco, gxo, gvb, 0,
+                                        gxi, None, None)
+
+    assert g2pb(nr=5) == 1
+    assert g2pb(gv=None) == 1
+    assert g2pb(gco=None) == 1
+    assert g2pb(gvb=None) == 1
+    assert g2pb(gxi=None) == 1
+    assert g2pb(dt=float("nan")) == 1
+    assert g2pb(P=-1) == 1
+
+    def gub(gv=FAKE, gm=FAKE, gp=FAKE, gmb=FAKE, gpb=FAKE, bc=1, gr=grav):
+        return lib.polypic_grid_update_backward(ctypes.byref(g), 1e-4, gr, bc, gm, gp, gv, gmb,
+                                                gpb, None)
+
+    assert gub(gr=None) == 1
+    assert gub(bc=-2) == 1
+    assert gub(gm=None) == 1
+    assert gub(gv=None) == 1
+    assert gub(gpb=None) == 1
+    assert lib.polypic_grid_update_backward(None, 1e-4, grav, 1, FAKE, FAKE, FAKE, FAKE, FAKE,
+                                            None) == 1
+
+    def p2gb(P=10, nr=4, x=FAKE, mass=None, umass=1.0, c=FAKE, gmb=FAKE, gpb=FAKE, cg=FAKE,
+             xg=FAKE, mg=None):
+        return lib.polypic_p2g_backward(ctypes.byref(g), P, nr, x, mass, umass, c, None, gmb, gpb,
+                                        cg, xg, mg, None, None)
+
+    assert p2gb(nr=26) == 1
+    assert p2gb(x=None) == 1
+    assert p2gb(gmb=None) == 1
+    assert p2gb(cg=None) == 1
+    assert p2gb(xg=None) == 1
+    assert p2gb(umass=float("inf")) == 1
+    assert p2gb(P=0, x=None, c=None, cg=None, xg=None) == 0
