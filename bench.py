@@ -95,6 +95,8 @@ def parse_args():
                     help="particles in the oracle's timed sample")
     ap.add_argument("--no-apic", action="store_true", help="skip the 4-mode comparison run")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the bwd/fwd timing")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched-scenes timing")
+    ap.add_argument("--batch-steps", type=int, default=10, help="steps in the batched timing")
     ap.add_argument("--adjoint-steps", type=int, default=10,
                     help="differentiable steps in the bwd/fwd timing")
     ap.add_argument("--calib-copy", action="store_true",
@@ -239,6 +241,93 @@ def adjoint_timing(pp, torch, W, cells: int, n_modes: int, n_steps: int, reps: i
     }
 
 
+def batch_timing(pp, torch, W, n_modes: int, steps: int, warmup: int):
+    """64 independent scenes (grids of 64^3, 96^3 or 128^3 cells, log-uniform particle
+    counts in [1e4, 2e6] at 8 per cell): one graph-captured batched step versus one
+    ParticleSet step per scene.
+
+    Positions come from workloads.batched_scenes(0); the coefficients (mode 0 ~ N(0,1),
+    higher modes ~ N(0,0.1)) are drawn on the device from a seeded torch generator.
+    """
+    import numpy as np
+
+    scenes = W.batched_scenes(0, coefficients=False)
+    grids = [pp.grid_from_spec(s.grid) for s in scenes]
+    counts = [s.P for s in scenes]
+    P = int(sum(counts))
+    x = torch.from_numpy(np.ascontiguousarray(np.concatenate([s.x for s in scenes], axis=1)))
+    x = x.cuda()
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(20_000)
+    c = torch.randn(3, n_modes, P, generator=gen, device="cuda")
+    c[:, 1:] *= 0.1
+    s0 = scenes[0]
+    bs = pp.BatchedParticleSet(grids, counts, n_modes, x, c, dt=s0.dt, gravity=s0.gravity,
+                               bc_layers=s0.bc_layers)
+    for _ in range(warmup):
+        bs.step()
+    choice = bs.autotune()
+
+    def timed(fn, k):
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        t0 = time.perf_counter()
+        e0.record()
+        for _ in range(k):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / k, e0.elapsed_time(e1) / k
+
+    eager_wall, eager_ev = timed(bs.step, steps)
+    bs.capture()
+    bs.replay()
+    graph_wall, graph_ev = timed(bs.replay, steps)
+    if bs.status_flags() != 0:
+        raise RuntimeError(f"device status flags {bs.status_flags()} in the batched timing")
+
+    # the plain form: one ParticleSet per scene, stepped one after the other
+    sets = []
+    for k, sc in enumerate(scenes):
+        sl = bs.scene_slice(k)
+        sets.append(pp.ParticleSet(grids[k], n_modes, bs.x[:, sl].contiguous(),
+                                   bs.coeff[:, :, sl].contiguous(), dt=sc.dt,
+                                   gravity=sc.gravity, bc_layers=sc.bc_layers,
+                                   track_order=False))
+    del bs
+
+    def per_scene_step():
+        for ps in sets:
+            ps.step()
+
+    for _ in range(warmup):
+        per_scene_step()
+    single_wall, single_ev = timed(per_scene_step, steps)
+    for ps in sets:
+        if ps.status_flags() != 0:
+            raise RuntimeError("device status flags in the per-scene timing")
+    return {
+        "workload": f"batch_64scenes_{P}",
+        "scenes": len(scenes),
+        "particles": P,
+        "n_modes": n_modes,
+        "steps": steps,
+        "graph_ms_per_step": graph_wall * 1e3,
+        "graph_transfers_per_s": P / graph_wall,
+        "eager_batched_ms_per_step": eager_wall * 1e3,
+        "per_scene_ms_per_step": single_wall * 1e3,
+        "per_scene_transfers_per_s": P / single_wall,
+        "speedup_vs_per_scene": single_wall / graph_wall,
+        "event_ms_per_step": {"graph": round(graph_ev, 4), "eager_batched": round(eager_ev, 4),
+                              "per_scene": round(single_ev, 4)},
+        "p2g_config": {"block": choice.block, "schedule": choice.schedule,
+                       "per_cu": choice.per_cu, "chosen_by": "polypic_batch_autotune"},
+        "note": "whole steps (sort, P2G, grid update, G2P + advection) of every scene; "
+                "per-scene form = one ParticleSet.step per scene, launched in turn",
+    }
+
+
 def cpu_baseline(scene, n_modes: int, sample: int):
     """The FP64 oracle, as it is, timed on host cores over a bounded sample."""
     from oracle import polypic_oracle as O
@@ -315,8 +404,8 @@ def main():
         apic = {"n_modes": 4, "ms_per_step": w4 * 1e3 / args.steps,
                 "transfers_per_s": P * args.steps / w4,
                 "p2g_g2p_transfers_per_s": P / ((ph4["p2g"] + ph4["g2p"]) * 1e-3),
-                "p2g_config": {"path": "cells" if choice4[0] == 1 else "bricks",
-                               "block": choice4[1]},
+                "p2g_config": {"path": "cells" if choice4.path == 1 else "bricks",
+                               "block": choice4.block, "schedule": choice4.schedule},
                 "phase_ms": {k: round(v, 4) for k, v in ph4.items()}}
         del ps4, c4
 
@@ -334,6 +423,10 @@ def main():
     adj = None
     if not args.no_adjoint:
         adj = adjoint_timing(pp, torch, W, args.cells, n_modes, args.adjoint_steps)
+
+    batch = None
+    if not args.no_batch:
+        batch = batch_timing(pp, torch, W, n_modes, args.batch_steps, 2)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -356,12 +449,14 @@ def main():
                    "grid_nodes": list(scene.grid.nodes), "ppc": 8, "dt": scene.dt,
                    "step": "sort + p2g + grid_update + g2p(+advection)"},
         "p2g_g2p_transfers_per_s": P / (transfer_ms * 1e-3),
-        "p2g_config": {"path": "cells" if p2g_choice[0] == 1 else "bricks", "block": p2g_choice[1],
+        "p2g_config": {"path": "cells" if p2g_choice.path == 1 else "bricks",
+                       "block": p2g_choice.block, "schedule": p2g_choice.schedule,
                        "chosen_by": "polypic_autotune_p2g"},
         "phase_ms": {k: round(v, 4) for k, v in phase.items()},
         "apic_4mode": apic,
         "bwd_fwd_ratio": None if adj is None else round(adj["bwd_fwd_ratio"], 3),
         "adjoint": adj,
+        "batched": batch,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

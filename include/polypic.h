@@ -159,28 +159,48 @@ int32_t polypic_p2g(const polypic_grid* grid, int64_t P, int32_t n_modes, const 
  * path   POLYPIC_P2G_BRICKS: per-particle scatter into FP64 LDS bricks of 4^3
  *        cells (needs only perm); POLYPIC_P2G_CELLS: per-cell run sums (needs
  *        keys_sorted).  block: workgroup size of the brick path (256 or 512).
+ * schedule  how the brick path's workgroups take chunks of `block` slots:
+ *        POLYPIC_SCHED_LINEAR      one chunk per workgroup, in index order;
+ *        POLYPIC_SCHED_XCD         one chunk per workgroup, renumbered so that
+ *                                  the workgroups the dispatcher places on one
+ *                                  of the 8 XCDs take a contiguous eighth of
+ *                                  the chunks (sorted neighbours share an L2);
+ *        POLYPIC_SCHED_PERSISTENT  per_cu workgroups per compute unit (1..64),
+ *                                  each looping over a contiguous chunk range.
+ *        per_cu is ignored by the other schedules (pass 0).
  * The choice is kept per n_modes in a process-wide, mutex-guarded table.
  * Without an entry polypic_p2g uses the cell path when keys_sorted is given
- * and the brick path (block 512) otherwise; the cell path is never chosen
- * without keys_sorted.
+ * and the brick path (block 512, linear) otherwise; the cell path is never
+ * chosen without keys_sorted.
  *
  * polypic_autotune_p2g runs P2G once per candidate configuration on the given
  * inputs (same arguments as polypic_p2g, keys_sorted may be NULL), times each
- * with HIP events on `stream`, stores the fastest and returns it in
- * *path_out / *block_out (host pointers, may be NULL).  Unlike the other
- * entry points it SYNCHRONISES the stream.  On return grid_mass / grid_mom
- * hold a P2G result (accumulate = 0).
+ * with HIP events on `stream`, stores the fastest and returns it through the
+ * *_out host pointers (each may be NULL).  Unlike the other entry points it
+ * SYNCHRONISES the stream.  On return grid_mass / grid_mom hold a P2G result
+ * (accumulate = 0).
+ *
+ * polypic_set_g2p_schedule: process-wide chunk schedule of G2P (LINEAR or XCD;
+ * default LINEAR).
  * ------------------------------------------------------------------------ */
 #define POLYPIC_P2G_DEFAULT (-1)
 #define POLYPIC_P2G_BRICKS 0
 #define POLYPIC_P2G_CELLS 1
-int32_t polypic_set_p2g_config(int32_t n_modes, int32_t path, int32_t block);
-int32_t polypic_get_p2g_config(int32_t n_modes, int32_t* path, int32_t* block);
+#define POLYPIC_SCHED_LINEAR 0
+#define POLYPIC_SCHED_XCD 1
+#define POLYPIC_SCHED_PERSISTENT 2
+int32_t polypic_set_p2g_config(int32_t n_modes, int32_t path, int32_t block, int32_t schedule,
+                               int32_t per_cu);
+int32_t polypic_get_p2g_config(int32_t n_modes, int32_t* path, int32_t* block, int32_t* schedule,
+                               int32_t* per_cu);
 int32_t polypic_autotune_p2g(const polypic_grid* grid, int64_t P, int32_t n_modes, const float* x,
                              const float* mass, float uniform_mass, const float* coeff,
                              const int32_t* perm, const uint32_t* keys_sorted, void* ws,
                              size_t ws_bytes, float* grid_mass, float* grid_mom,
-                             int32_t* path_out, int32_t* block_out, void* stream);
+                             int32_t* path_out, int32_t* block_out, int32_t* schedule_out,
+                             int32_t* per_cu_out, void* stream);
+int32_t polypic_set_g2p_schedule(int32_t schedule);
+int32_t polypic_get_g2p_schedule(int32_t* schedule);
 
 /* ------------------------------------------------------------------------
  * Grid update.  Eq. 5 (v = (mv) / m) followed by an explicit update that the
@@ -265,6 +285,93 @@ int32_t polypic_p2g_backward(const polypic_grid* grid, int64_t P, int32_t n_mode
                              const int32_t* perm, const float* grid_mass_grad,
                              const float* grid_mom_grad, float* coeff_grad, float* x_grad,
                              float* mass_grad, int32_t* status_dev, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Batches of independent scenes (not in the paper: many small simulations
+ * stepped together).  Every scene has its own grid and particles; the
+ * particle arrays of all scenes are laid end to end (flattened index), and so
+ * are the grid arrays.  One call runs one step phase for every scene with a
+ * single launch (or a fixed sequence of launches for the sort), so a whole
+ * step can be captured once in a HIP graph and replayed.
+ *
+ * polypic_scene (host): scene s owns particles [p_offset, p_offset +
+ *   n_particles) of every particle array and nodes [node_offset, node_offset
+ *   + nx*ny*nz) of every grid channel.  Particle ranges must be contiguous
+ *   and in scene order starting at 0 (empty scenes allowed); node ranges in
+ *   scene order, not overlapping, inside [0, n_nodes_total).
+ * Layouts: x[3][P], coeff[3][n_modes][P], mass[P], F[9][P] with P the total
+ *   particle count; grid_mass[N], grid_mom[3][N], grid_vel[3][N] with
+ *   N = n_nodes_total.
+ *
+ * polypic_batch_plan validates the scenes, writes the device scene table
+ *   into table_dev (caller-owned device memory of polypic_batch_table_bytes()
+ *   bytes, which must outlive every call that uses the batch) and fills the
+ *   host descriptor *batch.  It copies synchronously (the scenes array may
+ *   be freed on return) and must not be called during graph capture.  The
+ *   descriptor is sealed: a batch call whose descriptor was modified after
+ *   planning returns POLYPIC_EINVAL.
+ * polypic_batch_sort: keys = scene << morton_bits | Morton(base node), sorted
+ *   stably over all P (so every particle stays inside its scene's range, in
+ *   cell order).  Workspace: polypic_batch_sort_workspace_bytes().
+ *   Returns POLYPIC_ENOTSUP if the scene index and the largest grid's Morton
+ *   code do not fit in 32 key bits.
+ * polypic_batch_p2g / _grid_update / _g2p: as polypic_p2g (brick path) /
+ *   polypic_grid_update / polypic_g2p, per scene, with the batch layouts.
+ *   perm (optional) must keep every particle inside its scene's range, as
+ *   the batched sort's does; slot i is processed with the grid of the scene
+ *   whose range holds i.
+ * polypic_batch_set_config / _get_config / _autotune: block, schedule and
+ *   per_cu of the batched P2G (same meaning as for polypic_p2g; default
+ *   block 256, POLYPIC_SCHED_XCD), per n_modes, process-wide.  The autotuner
+ *   times every candidate on the given inputs and SYNCHRONISES the stream.
+ * ------------------------------------------------------------------------ */
+typedef struct polypic_scene {
+  polypic_grid grid;
+  int64_t p_offset;
+  int64_t n_particles;
+  int64_t node_offset;
+} polypic_scene;
+
+typedef struct polypic_batch {
+  int32_t n_scenes;
+  int32_t key_bits;    /* bits of the batched sort keys */
+  int32_t morton_bits; /* Morton bits below the scene index */
+  int32_t max_nodes;   /* largest scene node count */
+  int64_t P;           /* total particles */
+  int64_t N;           /* total nodes per grid channel */
+  const void* table;   /* device scene table (in the caller's buffer) */
+  uint64_t seal;       /* written by polypic_batch_plan */
+} polypic_batch;
+
+int32_t polypic_batch_table_bytes(int32_t n_scenes, size_t* bytes);
+int32_t polypic_batch_plan(const polypic_scene* scenes, int32_t n_scenes, int64_t n_nodes_total,
+                           void* table_dev, size_t table_bytes, polypic_batch* batch,
+                           void* stream);
+int32_t polypic_batch_sort_workspace_bytes(const polypic_batch* batch, size_t* bytes);
+int32_t polypic_batch_sort(const polypic_batch* batch, const float* x, uint32_t* keys_out,
+                           int32_t* perm_out, void* ws, size_t ws_bytes, int32_t* status_dev,
+                           void* stream);
+int32_t polypic_batch_p2g(const polypic_batch* batch, int32_t n_modes, const float* x,
+                          const float* mass, float uniform_mass, const float* coeff,
+                          const int32_t* perm, float* grid_mass, float* grid_mom,
+                          int32_t accumulate, int32_t* status_dev, void* stream);
+int32_t polypic_batch_grid_update(const polypic_batch* batch, float dt, const float* gravity,
+                                  int32_t bc_layers, const float* grid_mass,
+                                  const float* grid_mom, float* grid_vel, void* stream);
+int32_t polypic_batch_g2p(const polypic_batch* batch, int32_t n_modes, float dt,
+                          const float* grid_vel, const float* x_in, const int32_t* perm,
+                          float* x_out, float* coeff_out, const float* F_in, float* F_out,
+                          const float* mass_in, float* mass_out, int32_t* status_dev,
+                          void* stream);
+int32_t polypic_batch_set_config(int32_t n_modes, int32_t block, int32_t schedule,
+                                 int32_t per_cu);
+int32_t polypic_batch_get_config(int32_t n_modes, int32_t* block, int32_t* schedule,
+                                 int32_t* per_cu);
+int32_t polypic_batch_autotune(const polypic_batch* batch, int32_t n_modes, const float* x,
+                               const float* mass, float uniform_mass, const float* coeff,
+                               const int32_t* perm, float* grid_mass, float* grid_mom,
+                               int32_t* block_out, int32_t* schedule_out, int32_t* per_cu_out,
+                               void* stream);
 
 #ifdef __cplusplus
 }

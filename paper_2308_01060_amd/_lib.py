@@ -22,6 +22,9 @@ POLYPIC_FLAG_RANGE = 1
 POLYPIC_P2G_DEFAULT = -1
 POLYPIC_P2G_BRICKS = 0
 POLYPIC_P2G_CELLS = 1
+POLYPIC_SCHED_LINEAR = 0
+POLYPIC_SCHED_XCD = 1
+POLYPIC_SCHED_PERSISTENT = 2
 
 EXPORTED = (
     "polypic_strerror",
@@ -34,11 +37,23 @@ EXPORTED = (
     "polypic_set_p2g_config",
     "polypic_get_p2g_config",
     "polypic_autotune_p2g",
+    "polypic_set_g2p_schedule",
+    "polypic_get_g2p_schedule",
     "polypic_grid_update",
     "polypic_g2p",
     "polypic_g2p_backward",
     "polypic_grid_update_backward",
     "polypic_p2g_backward",
+    "polypic_batch_table_bytes",
+    "polypic_batch_plan",
+    "polypic_batch_sort_workspace_bytes",
+    "polypic_batch_sort",
+    "polypic_batch_p2g",
+    "polypic_batch_grid_update",
+    "polypic_batch_g2p",
+    "polypic_batch_set_config",
+    "polypic_batch_get_config",
+    "polypic_batch_autotune",
 )
 
 
@@ -52,6 +67,32 @@ class polypic_grid(ctypes.Structure):
         ("dx", ctypes.c_float),
         ("inv_dx", ctypes.c_float),
         ("origin", ctypes.c_float * 3),
+    ]
+
+
+class polypic_scene(ctypes.Structure):
+    """Mirror of ``struct polypic_scene``."""
+
+    _fields_ = [
+        ("grid", polypic_grid),
+        ("p_offset", ctypes.c_int64),
+        ("n_particles", ctypes.c_int64),
+        ("node_offset", ctypes.c_int64),
+    ]
+
+
+class polypic_batch(ctypes.Structure):
+    """Mirror of ``struct polypic_batch`` (filled by polypic_batch_plan)."""
+
+    _fields_ = [
+        ("n_scenes", ctypes.c_int32),
+        ("key_bits", ctypes.c_int32),
+        ("morton_bits", ctypes.c_int32),
+        ("max_nodes", ctypes.c_int32),
+        ("P", ctypes.c_int64),
+        ("N", ctypes.c_int64),
+        ("table", ctypes.c_void_p),
+        ("seal", ctypes.c_uint64),
     ]
 
 
@@ -101,12 +142,17 @@ def load() -> ctypes.CDLL:
     lib.polypic_p2g.restype = i32
     lib.polypic_p2g.argtypes = [G, i64, i32, P, P, f32, P, P, P, P, sz, P, P, i32, P, P]
     lib.polypic_set_p2g_config.restype = i32
-    lib.polypic_set_p2g_config.argtypes = [i32, i32, i32]
+    lib.polypic_set_p2g_config.argtypes = [i32, i32, i32, i32, i32]
+    pi = ctypes.POINTER(i32)
     lib.polypic_get_p2g_config.restype = i32
-    lib.polypic_get_p2g_config.argtypes = [i32, ctypes.POINTER(i32), ctypes.POINTER(i32)]
+    lib.polypic_get_p2g_config.argtypes = [i32, pi, pi, pi, pi]
     lib.polypic_autotune_p2g.restype = i32
     lib.polypic_autotune_p2g.argtypes = [G, i64, i32, P, P, f32, P, P, P, P, sz, P, P,
-                                         ctypes.POINTER(i32), ctypes.POINTER(i32), P]
+                                         pi, pi, pi, pi, P]
+    lib.polypic_set_g2p_schedule.restype = i32
+    lib.polypic_set_g2p_schedule.argtypes = [i32]
+    lib.polypic_get_g2p_schedule.restype = i32
+    lib.polypic_get_g2p_schedule.argtypes = [pi]
     lib.polypic_grid_update.restype = i32
     lib.polypic_grid_update.argtypes = [G, f32, ctypes.POINTER(f32), i32, P, P, P, P]
     lib.polypic_g2p.restype = i32
@@ -118,6 +164,27 @@ def load() -> ctypes.CDLL:
                                                  P]
     lib.polypic_p2g_backward.restype = i32
     lib.polypic_p2g_backward.argtypes = [G, i64, i32, P, P, f32, P, P, P, P, P, P, P, P, P]
+    B = ctypes.POINTER(polypic_batch)
+    lib.polypic_batch_table_bytes.restype = i32
+    lib.polypic_batch_table_bytes.argtypes = [i32, ctypes.POINTER(sz)]
+    lib.polypic_batch_plan.restype = i32
+    lib.polypic_batch_plan.argtypes = [ctypes.POINTER(polypic_scene), i32, i64, P, sz, B, P]
+    lib.polypic_batch_sort_workspace_bytes.restype = i32
+    lib.polypic_batch_sort_workspace_bytes.argtypes = [B, ctypes.POINTER(sz)]
+    lib.polypic_batch_sort.restype = i32
+    lib.polypic_batch_sort.argtypes = [B, P, P, P, P, sz, P, P]
+    lib.polypic_batch_p2g.restype = i32
+    lib.polypic_batch_p2g.argtypes = [B, i32, P, P, f32, P, P, P, P, i32, P, P]
+    lib.polypic_batch_grid_update.restype = i32
+    lib.polypic_batch_grid_update.argtypes = [B, f32, ctypes.POINTER(f32), i32, P, P, P, P]
+    lib.polypic_batch_g2p.restype = i32
+    lib.polypic_batch_g2p.argtypes = [B, i32, f32, P, P, P, P, P, P, P, P, P, P, P]
+    lib.polypic_batch_set_config.restype = i32
+    lib.polypic_batch_set_config.argtypes = [i32, i32, i32, i32]
+    lib.polypic_batch_get_config.restype = i32
+    lib.polypic_batch_get_config.argtypes = [i32, pi, pi, pi]
+    lib.polypic_batch_autotune.restype = i32
+    lib.polypic_batch_autotune.argtypes = [B, i32, P, P, f32, P, P, P, P, pi, pi, pi, P]
     _lib = lib
     return lib
 

@@ -3,6 +3,7 @@
 #include <math.h>
 
 #include <algorithm>
+#include <atomic>
 #include <mutex>
 #include <vector>
 
@@ -79,7 +80,26 @@ void clamp_bounds(const polypic_grid* grid, float lo[3], float hi[3]) {
 struct P2GChoice {
   int path = POLYPIC_P2G_DEFAULT;
   int block = 512;
+  int sched = POLYPIC_SCHED_LINEAR;
+  int per_cu = 0;
 };
+
+bool valid_schedule(int32_t schedule, int32_t per_cu) {
+  if (schedule == POLYPIC_SCHED_LINEAR || schedule == POLYPIC_SCHED_XCD) return true;
+  return schedule == POLYPIC_SCHED_PERSISTENT && per_cu >= 1 && per_cu <= 64;
+}
+
+P2GConfig to_config(const P2GChoice& c) {
+  P2GConfig cfg = p2g_default_config();
+  cfg.block = c.block;
+  cfg.sched = c.sched == POLYPIC_SCHED_XCD          ? kSchedXcd
+              : c.sched == POLYPIC_SCHED_PERSISTENT ? kSchedPersistent
+                                                    : kSchedLinear;
+  cfg.persist_per_cu = c.sched == POLYPIC_SCHED_PERSISTENT ? c.per_cu : 0;
+  return cfg;
+}
+
+std::atomic<int> g_g2p_sched{POLYPIC_SCHED_LINEAR};
 std::mutex g_tune_mutex;
 P2GChoice g_tune[28];
 
@@ -122,10 +142,128 @@ int32_t run_p2g(const polypic_grid* grid, int64_t P, int32_t n_modes, const floa
   a.keys = keys_sorted;
   a.tile_list = nullptr;
   a.tile_count = nullptr;
+  a.sched = kSchedLinear;
   if (cells) return from_hip(launch_p2g_sorted(a, n_modes, ws, !accumulate, s));
-  P2GConfig cfg = p2g_default_config();
-  cfg.block = c.block;
-  return from_hip(launch_p2g(a, n_modes, cfg, s));
+  return from_hip(launch_p2g(a, n_modes, to_config(c), s));
+}
+
+
+// Times `run(k)` for every candidate k < n on stream s: one untimed run, then
+// the median of three timed ones (HIP events).  Synchronises s.  Writes the
+// fastest candidate to *best.
+template <class Run>
+int32_t time_candidates(int n, hipStream_t s, Run run, int* best) {
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess) return POLYPIC_EDEVICE;
+  if (hipEventCreate(&e1) != hipSuccess) {
+    hipEventDestroy(e0);
+    return POLYPIC_EDEVICE;
+  }
+  int32_t st = POLYPIC_OK;
+  float best_ms = -1.0f;
+  constexpr int kReps = 3;
+  for (int k = 0; k < n && st == POLYPIC_OK; ++k) {
+    float t[kReps];
+    for (int rep = -1; rep < kReps && st == POLYPIC_OK; ++rep) {
+      if (rep >= 0 && hipEventRecord(e0, s) != hipSuccess) st = POLYPIC_EDEVICE;
+      if (!st) st = run(k);
+      if (!st && rep >= 0) {
+        if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+            hipEventElapsedTime(&t[rep], e0, e1) != hipSuccess)
+          st = POLYPIC_EDEVICE;
+      }
+    }
+    if (st) break;
+    std::sort(t, t + kReps);
+    if (best_ms < 0.0f || t[kReps / 2] < best_ms) {
+      best_ms = t[kReps / 2];
+      *best = k;
+    }
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  if (st) return st;
+  if (hipStreamSynchronize(s) != hipSuccess) return POLYPIC_EDEVICE;
+  return POLYPIC_OK;
+}
+
+// ---- batches of scenes
+constexpr int32_t kMaxScenes = 65536;
+
+uint64_t batch_seal(const polypic_batch* b) {
+  uint64_t h = 1469598103934665603ull;  // FNV-1a over the descriptor's fields
+  auto mix = [&h](uint64_t v) {
+    for (int k = 0; k < 8; ++k) {
+      h ^= (v >> (8 * k)) & 0xffu;
+      h *= 1099511628211ull;
+    }
+  };
+  mix((uint32_t)b->n_scenes);
+  mix((uint32_t)b->key_bits);
+  mix((uint32_t)b->morton_bits);
+  mix((uint32_t)b->max_nodes);
+  mix((uint64_t)b->P);
+  mix((uint64_t)b->N);
+  mix((uint64_t)(uintptr_t)b->table);
+  return h;
+}
+
+int32_t check_batch(const polypic_batch* b) {
+  if (!b || !b->table || b->n_scenes < 1 || b->n_scenes > kMaxScenes) return POLYPIC_EINVAL;
+  if (b->seal != batch_seal(b)) return POLYPIC_EINVAL;
+  return POLYPIC_OK;
+}
+
+const SceneDev* batch_table(const polypic_batch* b) { return (const SceneDev*)b->table; }
+
+struct BatchChoice {
+  int block = 256;
+  int sched = POLYPIC_SCHED_XCD;
+  int per_cu = 0;
+};
+BatchChoice g_btune[28];
+
+BatchChoice get_bchoice(int n_modes) {
+  std::lock_guard<std::mutex> lock(g_tune_mutex);
+  return g_btune[n_modes];
+}
+
+void set_bchoice(int n_modes, BatchChoice c) {
+  std::lock_guard<std::mutex> lock(g_tune_mutex);
+  g_btune[n_modes] = c;
+}
+
+int32_t run_batch_p2g(const polypic_batch* b, int32_t n_modes, const float* x, const float* mass,
+                      float uniform_mass, const float* coeff, const int32_t* perm,
+                      float* grid_mass, float* grid_mom, int32_t accumulate, int32_t* status_dev,
+                      hipStream_t s, const BatchChoice& c) {
+  int32_t st;
+  if (!accumulate) {
+    if ((st = from_hip(launch_grid_clear(grid_mass, grid_mom, b->N, nullptr, s)))) return st;
+  }
+  P2GArgs a;
+  a.g = GridDev{3, 3, 3, 1.0f, 0.0f, 0.0f, 0.0f};  // unused: every slot reads its scene's grid
+  a.P = b->P;
+  a.x = x;
+  a.mass = mass;
+  a.uniform_mass = uniform_mass;
+  a.coeff = coeff;
+  a.perm = perm;
+  a.gm = grid_mass;
+  a.gp0 = grid_mom;
+  a.gp1 = grid_mom + b->N;
+  a.gp2 = grid_mom + 2 * b->N;
+  a.status = status_dev;
+  a.keys = nullptr;
+  a.tile_list = nullptr;
+  a.tile_count = nullptr;
+  a.sched = kSchedLinear;
+  P2GChoice pc;
+  pc.block = c.block;
+  pc.sched = c.sched;
+  pc.per_cu = c.per_cu;
+  return from_hip(
+      launch_p2g_batch(a, batch_table(b), b->n_scenes, n_modes, to_config(pc), s));
 }
 
 }  // namespace
@@ -201,23 +339,42 @@ int32_t polypic_p2g(const polypic_grid* grid, int64_t P, int32_t n_modes, const 
                  grid_mom, accumulate, status_dev, (hipStream_t)stream, get_choice(n_modes));
 }
 
-int32_t polypic_set_p2g_config(int32_t n_modes, int32_t path, int32_t block) {
+int32_t polypic_set_p2g_config(int32_t n_modes, int32_t path, int32_t block, int32_t schedule,
+                               int32_t per_cu) {
   if (!valid_modes(n_modes)) return POLYPIC_EINVAL;
   if (path != POLYPIC_P2G_DEFAULT && path != POLYPIC_P2G_BRICKS && path != POLYPIC_P2G_CELLS)
     return POLYPIC_EINVAL;
   if (block != 256 && block != 512) return POLYPIC_EINVAL;
+  if (!valid_schedule(schedule, per_cu)) return POLYPIC_EINVAL;
   P2GChoice c;
   c.path = path;
   c.block = block;
+  c.sched = schedule;
+  c.per_cu = schedule == POLYPIC_SCHED_PERSISTENT ? per_cu : 0;
   set_choice(n_modes, c);
   return POLYPIC_OK;
 }
 
-int32_t polypic_get_p2g_config(int32_t n_modes, int32_t* path, int32_t* block) {
+int32_t polypic_get_p2g_config(int32_t n_modes, int32_t* path, int32_t* block, int32_t* schedule,
+                               int32_t* per_cu) {
   if (!valid_modes(n_modes)) return POLYPIC_EINVAL;
   const P2GChoice c = get_choice(n_modes);
   if (path) *path = c.path;
   if (block) *block = c.block;
+  if (schedule) *schedule = c.sched;
+  if (per_cu) *per_cu = c.per_cu;
+  return POLYPIC_OK;
+}
+
+int32_t polypic_set_g2p_schedule(int32_t schedule) {
+  if (schedule != POLYPIC_SCHED_LINEAR && schedule != POLYPIC_SCHED_XCD) return POLYPIC_EINVAL;
+  g_g2p_sched.store(schedule);
+  return POLYPIC_OK;
+}
+
+int32_t polypic_get_g2p_schedule(int32_t* schedule) {
+  if (!schedule) return POLYPIC_EINVAL;
+  *schedule = g_g2p_sched.load();
   return POLYPIC_OK;
 }
 
@@ -225,7 +382,8 @@ int32_t polypic_autotune_p2g(const polypic_grid* grid, int64_t P, int32_t n_mode
                              const float* mass, float uniform_mass, const float* coeff,
                              const int32_t* perm, const uint32_t* keys_sorted, void* ws,
                              size_t ws_bytes, float* grid_mass, float* grid_mom,
-                             int32_t* path_out, int32_t* block_out, void* stream) {
+                             int32_t* path_out, int32_t* block_out, int32_t* schedule_out,
+                             int32_t* per_cu_out, void* stream) {
   int32_t st = check_grid(grid);
   if (st) return st;
   if ((st = check_P(P))) return st;
@@ -239,55 +397,35 @@ int32_t polypic_autotune_p2g(const polypic_grid* grid, int64_t P, int32_t n_mode
   }
   const hipStream_t s = (hipStream_t)stream;
   std::vector<P2GChoice> cand;
-  for (int block : {256, 512}) {
-    P2GChoice c;
-    c.path = POLYPIC_P2G_BRICKS;
-    c.block = block;
-    cand.push_back(c);
-  }
+  for (int block : {256, 512})
+    for (int sched : {POLYPIC_SCHED_LINEAR, POLYPIC_SCHED_XCD}) {
+      P2GChoice c;
+      c.path = POLYPIC_P2G_BRICKS;
+      c.block = block;
+      c.sched = sched;
+      cand.push_back(c);
+    }
   if (keys_sorted) {
     P2GChoice c;
     c.path = POLYPIC_P2G_CELLS;
     cand.push_back(c);
   }
   discard_stale_error();
-  hipEvent_t e0, e1;
-  if (hipEventCreate(&e0) != hipSuccess) return POLYPIC_EDEVICE;
-  if (hipEventCreate(&e1) != hipSuccess) {
-    hipEventDestroy(e0);
-    return POLYPIC_EDEVICE;
-  }
-  P2GChoice best;
-  float best_ms = -1.0f;
-  constexpr int kReps = 3;
-  for (const P2GChoice& c : cand) {
-    // one untimed run, then the median of kReps timed runs
-    float t[kReps];
-    for (int rep = -1; rep < kReps && st == POLYPIC_OK; ++rep) {
-      if (rep >= 0 && hipEventRecord(e0, s) != hipSuccess) st = POLYPIC_EDEVICE;
-      if (!st)
-        st = run_p2g(grid, P, n_modes, x, mass, uniform_mass, coeff, perm, keys_sorted, ws,
-                     grid_mass, grid_mom, 0, nullptr, s, c);
-      if (!st && rep >= 0) {
-        if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
-            hipEventElapsedTime(&t[rep], e0, e1) != hipSuccess)
-          st = POLYPIC_EDEVICE;
-      }
-    }
-    if (st) break;
-    std::sort(t, t + kReps);
-    if (best_ms < 0.0f || t[kReps / 2] < best_ms) {
-      best_ms = t[kReps / 2];
-      best = c;
-    }
-  }
-  hipEventDestroy(e0);
-  hipEventDestroy(e1);
+  int bi = 0;
+  st = time_candidates(
+      (int)cand.size(), s,
+      [&](int k) {
+        return run_p2g(grid, P, n_modes, x, mass, uniform_mass, coeff, perm, keys_sorted, ws,
+                       grid_mass, grid_mom, 0, nullptr, s, cand[k]);
+      },
+      &bi);
   if (st) return st;
-  if (hipStreamSynchronize(s) != hipSuccess) return POLYPIC_EDEVICE;
+  const P2GChoice best = cand[bi];
   set_choice(n_modes, best);
   if (path_out) *path_out = best.path;
   if (block_out) *block_out = best.block;
+  if (schedule_out) *schedule_out = best.sched;
+  if (per_cu_out) *per_cu_out = best.per_cu;
   return POLYPIC_OK;
 }
 
@@ -344,6 +482,8 @@ int32_t polypic_g2p(const polypic_grid* grid, int64_t P, int32_t n_modes, float 
   a.mass_in = mass_in;
   a.mass_out = mass_out;
   a.status = status_dev;
+  a.gstride = n_nodes(grid);
+  a.sched = g_g2p_sched.load() == POLYPIC_SCHED_XCD ? kSchedXcd : kSchedLinear;
   discard_stale_error();
   return from_hip(launch_g2p(a, n_modes, (hipStream_t)stream));
 }
@@ -439,6 +579,233 @@ int32_t polypic_p2g_backward(const polypic_grid* grid, int64_t P, int32_t n_mode
   a.status = status_dev;
   discard_stale_error();
   return from_hip(launch_p2g_backward(a, n_modes, (hipStream_t)stream));
+}
+
+
+// ---------------------------------------------------------------- batches
+int32_t polypic_batch_table_bytes(int32_t n_scenes, size_t* bytes) {
+  if (!bytes || n_scenes < 1 || n_scenes > kMaxScenes) return POLYPIC_EINVAL;
+  *bytes = align_up((size_t)n_scenes * sizeof(SceneDev));
+  return POLYPIC_OK;
+}
+
+int32_t polypic_batch_plan(const polypic_scene* scenes, int32_t n_scenes, int64_t n_nodes_total,
+                           void* table_dev, size_t table_bytes, polypic_batch* batch,
+                           void* stream) {
+  if (!scenes || !batch || !table_dev) return POLYPIC_EINVAL;
+  if (n_scenes < 1 || n_scenes > kMaxScenes || n_nodes_total < 1) return POLYPIC_EINVAL;
+  if (table_bytes < (size_t)n_scenes * sizeof(SceneDev)) return POLYPIC_ENOSPACE;
+  std::vector<SceneDev> host((size_t)n_scenes);
+  int64_t p_next = 0, node_end = 0, max_nodes = 0;
+  int mbits = 0;
+  for (int32_t k = 0; k < n_scenes; ++k) {
+    const polypic_scene& sc = scenes[k];
+    int32_t st = check_grid(&sc.grid);
+    if (st) return st;
+    if (sc.n_particles < 0 || sc.p_offset != p_next) return POLYPIC_EINVAL;
+    p_next += sc.n_particles;
+    if (p_next > (int64_t)INT32_MAX) return POLYPIC_EINVAL;
+    const int64_t nn = n_nodes(&sc.grid);
+    if (sc.node_offset < node_end || sc.node_offset > n_nodes_total - nn) return POLYPIC_EINVAL;
+    node_end = sc.node_offset + nn;
+    max_nodes = std::max(max_nodes, nn);
+    mbits = std::max(mbits, sort_key_bits(to_dev(&sc.grid)));
+    SceneDev& d = host[(size_t)k];
+    d.nx = sc.grid.nx;
+    d.ny = sc.grid.ny;
+    d.nz = sc.grid.nz;
+    d.inv_dx = sc.grid.inv_dx;
+    d.ox = sc.grid.origin[0];
+    d.oy = sc.grid.origin[1];
+    d.oz = sc.grid.origin[2];
+    d.dx = sc.grid.dx;
+    clamp_bounds(&sc.grid, d.lo, d.hi);
+    d.p_begin = sc.p_offset;
+    d.p_end = sc.p_offset + sc.n_particles;
+    d.node_off = sc.node_offset;
+  }
+  int sbits = 0;
+  while (((int64_t)1 << sbits) < (int64_t)n_scenes) ++sbits;
+  if (mbits + sbits > 32) return POLYPIC_ENOTSUP;
+  const hipStream_t s = (hipStream_t)stream;
+  discard_stale_error();
+  int32_t st = from_hip(hipMemcpyAsync(table_dev, host.data(), host.size() * sizeof(SceneDev),
+                                       hipMemcpyHostToDevice, s));
+  if (!st) st = from_hip(hipStreamSynchronize(s));
+  if (st) return st;
+  batch->n_scenes = n_scenes;
+  batch->key_bits = mbits + sbits;
+  batch->morton_bits = mbits;
+  batch->max_nodes = (int32_t)max_nodes;
+  batch->P = p_next;
+  batch->N = n_nodes_total;
+  batch->table = table_dev;
+  batch->seal = batch_seal(batch);
+  return POLYPIC_OK;
+}
+
+int32_t polypic_batch_sort_workspace_bytes(const polypic_batch* batch, size_t* bytes) {
+  int32_t st = check_batch(batch);
+  if (st) return st;
+  if (!bytes) return POLYPIC_EINVAL;
+  *bytes = sort_workspace_bytes(batch->P);
+  return POLYPIC_OK;
+}
+
+int32_t polypic_batch_sort(const polypic_batch* batch, const float* x, uint32_t* keys_out,
+                           int32_t* perm_out, void* ws, size_t ws_bytes, int32_t* status_dev,
+                           void* stream) {
+  int32_t st = check_batch(batch);
+  if (st) return st;
+  if (batch->P == 0) return POLYPIC_OK;
+  if (!x || !keys_out || !perm_out || !ws) return POLYPIC_EINVAL;
+  if (ws_bytes < sort_workspace_bytes(batch->P)) return POLYPIC_ENOSPACE;
+  discard_stale_error();
+  return from_hip(launch_sort_batch(batch_table(batch), batch->n_scenes, batch->morton_bits,
+                                    batch->key_bits, batch->P, x, keys_out, perm_out, ws,
+                                    status_dev, (hipStream_t)stream));
+}
+
+int32_t polypic_batch_p2g(const polypic_batch* batch, int32_t n_modes, const float* x,
+                          const float* mass, float uniform_mass, const float* coeff,
+                          const int32_t* perm, float* grid_mass, float* grid_mom,
+                          int32_t accumulate, int32_t* status_dev, void* stream) {
+  int32_t st = check_batch(batch);
+  if (st) return st;
+  if (!valid_modes(n_modes)) return POLYPIC_EINVAL;
+  if (!grid_mass || !grid_mom) return POLYPIC_EINVAL;
+  if (batch->P > 0 && (!x || !coeff)) return POLYPIC_EINVAL;
+  if (!mass && !isfinite(uniform_mass)) return POLYPIC_EINVAL;
+  discard_stale_error();
+  return run_batch_p2g(batch, n_modes, x, mass, uniform_mass, coeff, perm, grid_mass, grid_mom,
+                       accumulate, status_dev, (hipStream_t)stream, get_bchoice(n_modes));
+}
+
+int32_t polypic_batch_grid_update(const polypic_batch* batch, float dt, const float* gravity,
+                                  int32_t bc_layers, const float* grid_mass,
+                                  const float* grid_mom, float* grid_vel, void* stream) {
+  int32_t st = check_batch(batch);
+  if (st) return st;
+  if (!gravity || !grid_mass || !grid_mom || !grid_vel) return POLYPIC_EINVAL;
+  if (!isfinite(dt) || bc_layers < 0) return POLYPIC_EINVAL;
+  for (int a = 0; a < 3; ++a)
+    if (!isfinite(gravity[a])) return POLYPIC_EINVAL;
+  GridUpdateArgs a;
+  a.nx = a.ny = a.nz = 0;  // per scene, from the table
+  a.dt = dt;
+  a.g0 = gravity[0];
+  a.g1 = gravity[1];
+  a.g2 = gravity[2];
+  a.bc_layers = bc_layers;
+  a.gm = grid_mass;
+  a.gp = grid_mom;
+  a.gv = grid_vel;
+  discard_stale_error();
+  return from_hip(launch_grid_update_batch(a, batch_table(batch), batch->n_scenes,
+                                           batch->max_nodes, batch->N, (hipStream_t)stream));
+}
+
+int32_t polypic_batch_g2p(const polypic_batch* batch, int32_t n_modes, float dt,
+                          const float* grid_vel, const float* x_in, const int32_t* perm,
+                          float* x_out, float* coeff_out, const float* F_in, float* F_out,
+                          const float* mass_in, float* mass_out, int32_t* status_dev,
+                          void* stream) {
+  int32_t st = check_batch(batch);
+  if (st) return st;
+  if (!valid_modes(n_modes) || !isfinite(dt)) return POLYPIC_EINVAL;
+  if (batch->P == 0) return POLYPIC_OK;
+  if (!grid_vel || !x_in || !coeff_out) return POLYPIC_EINVAL;
+  if ((F_in == nullptr) != (F_out == nullptr)) return POLYPIC_EINVAL;
+  if ((mass_in == nullptr) != (mass_out == nullptr)) return POLYPIC_EINVAL;
+  G2PArgs a;
+  a.g = GridDev{3, 3, 3, 1.0f, 0.0f, 0.0f, 0.0f};  // unused: per scene, from the table
+  a.P = batch->P;
+  a.dt = dt;
+  a.dx = 1.0f;
+  for (int k = 0; k < 3; ++k) a.lo[k] = a.hi[k] = 0.0f;
+  a.gv = grid_vel;
+  a.x_in = x_in;
+  a.perm = perm;
+  a.x_out = x_out;
+  a.coeff_out = coeff_out;
+  a.F_in = F_in;
+  a.F_out = F_out;
+  a.mass_in = mass_in;
+  a.mass_out = mass_out;
+  a.status = status_dev;
+  a.gstride = batch->N;
+  a.sched = g_g2p_sched.load() == POLYPIC_SCHED_XCD ? kSchedXcd : kSchedLinear;
+  discard_stale_error();
+  return from_hip(
+      launch_g2p_batch(a, batch_table(batch), batch->n_scenes, n_modes, (hipStream_t)stream));
+}
+
+int32_t polypic_batch_set_config(int32_t n_modes, int32_t block, int32_t schedule,
+                                 int32_t per_cu) {
+  if (!valid_modes(n_modes)) return POLYPIC_EINVAL;
+  if (block != 256 && block != 512) return POLYPIC_EINVAL;
+  if (!valid_schedule(schedule, per_cu)) return POLYPIC_EINVAL;
+  BatchChoice c;
+  c.block = block;
+  c.sched = schedule;
+  c.per_cu = schedule == POLYPIC_SCHED_PERSISTENT ? per_cu : 0;
+  set_bchoice(n_modes, c);
+  return POLYPIC_OK;
+}
+
+int32_t polypic_batch_get_config(int32_t n_modes, int32_t* block, int32_t* schedule,
+                                 int32_t* per_cu) {
+  if (!valid_modes(n_modes)) return POLYPIC_EINVAL;
+  const BatchChoice c = get_bchoice(n_modes);
+  if (block) *block = c.block;
+  if (schedule) *schedule = c.sched;
+  if (per_cu) *per_cu = c.per_cu;
+  return POLYPIC_OK;
+}
+
+int32_t polypic_batch_autotune(const polypic_batch* batch, int32_t n_modes, const float* x,
+                               const float* mass, float uniform_mass, const float* coeff,
+                               const int32_t* perm, float* grid_mass, float* grid_mom,
+                               int32_t* block_out, int32_t* schedule_out, int32_t* per_cu_out,
+                               void* stream) {
+  int32_t st = check_batch(batch);
+  if (st) return st;
+  if (!valid_modes(n_modes)) return POLYPIC_EINVAL;
+  if (!grid_mass || !grid_mom) return POLYPIC_EINVAL;
+  if (batch->P > 0 && (!x || !coeff)) return POLYPIC_EINVAL;
+  if (!mass && !isfinite(uniform_mass)) return POLYPIC_EINVAL;
+  std::vector<BatchChoice> cand;
+  for (int block : {256, 512}) {
+    for (int sched : {POLYPIC_SCHED_LINEAR, POLYPIC_SCHED_XCD}) {
+      BatchChoice c;
+      c.block = block;
+      c.sched = sched;
+      cand.push_back(c);
+    }
+    for (int per_cu : {2, 4, 8}) {
+      BatchChoice c;
+      c.block = block;
+      c.sched = POLYPIC_SCHED_PERSISTENT;
+      c.per_cu = per_cu;
+      cand.push_back(c);
+    }
+  }
+  const hipStream_t s = (hipStream_t)stream;
+  discard_stale_error();
+  int bi = 0;
+  st = time_candidates(
+      (int)cand.size(), s,
+      [&](int k) {
+        return run_batch_p2g(batch, n_modes, x, mass, uniform_mass, coeff, perm, grid_mass,
+                             grid_mom, 0, nullptr, s, cand[k]);
+      },
+      &bi);
+  if (st) return st;
+  set_bchoice(n_modes, cand[bi]);
+  if (block_out) *block_out = cand[bi].block;
+  if (schedule_out) *schedule_out = cand[bi].sched;
+  if (per_cu_out) *per_cu_out = cand[bi].per_cu;
+  return POLYPIC_OK;
 }
 
 }  // extern "C"

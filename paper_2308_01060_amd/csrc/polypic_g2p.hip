@@ -77,28 +77,31 @@ __device__ __forceinline__ void project_modes(const float (&v)[27], const Proj1D
       }
 }
 
-template <int NR, int BS>
-__global__ __launch_bounds__(BS) void g2p_kernel(G2PArgs a) {
-  const int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x;
+template <int NR, int BS, class Scenes>
+__global__ __launch_bounds__(BS) void g2p_kernel(G2PArgs a, Scenes sc) {
+  const ChunkRange cr = block_chunks(a.sched, (a.P + BS - 1) / BS);  // one chunk
+  const int64_t i0 = cr.begin * BS;
+  const int64_t i = i0 + threadIdx.x;
   if (i >= a.P) return;
+  const SceneGrid sg = sc.grid(sc.of(i, sc.first(i0)));
   const size_t Ps = (size_t)a.P;
-  const int nx = a.g.nx, ny = a.g.ny, nz = a.g.nz;
+  const int nx = sg.nx, ny = sg.ny;
   // a caller permutation is clamped into [0, P): a bad one gives wrong results, never a fault
   const int p = a.perm ? min(max(a.perm[i], 0), (int)(a.P - 1)) : (int)i;
   const float xp[3] = {a.x_in[p], a.x_in[Ps + p], a.x_in[2 * Ps + p]};
   int b0, b1, b2;
   float t0, t1, t2;
-  bool ok = stencil_axis(xp[0], a.g.ox, a.g.inv_dx, nx, b0, t0);
-  ok &= stencil_axis(xp[1], a.g.oy, a.g.inv_dx, ny, b1, t1);
-  ok &= stencil_axis(xp[2], a.g.oz, a.g.inv_dx, nz, b2, t2);
+  bool ok = stencil_axis(xp[0], sg.ox, sg.inv_dx, nx, b0, t0);
+  ok &= stencil_axis(xp[1], sg.oy, sg.inv_dx, ny, b1, t1);
+  ok &= stencil_axis(xp[2], sg.oz, sg.inv_dx, sg.nz, b2, t2);
   if (!ok) raise_flag(a.status, kFlagRange);
 
   const Proj1D px = proj_g2p(t0);
   const Proj1D py = proj_g2p(t1);
   const Proj1D pz = proj_g2p(t2);
-  const size_t N = (size_t)nx * ny * nz;
+  const size_t N = (size_t)a.gstride;
   const int nxny = nx * ny;
-  const int gbase = (b2 * ny + b1) * nx + b0;
+  const int64_t gbase = sg.node_off + (int64_t)(b2 * ny + b1) * nx + b0;
 
   float lin[3][3];  // lin[a][b] = coefficient of mode 1 + b for component a
   float F[9];
@@ -128,8 +131,8 @@ __global__ __launch_bounds__(BS) void g2p_kernel(G2PArgs a) {
     for (int r = 0; r < NR; ++r) co[(size_t)r * Ps] = c[r];
     if (a.x_out) {
       float xn = fmaf(a.dt, c[0], xp[ax]);
-      xn = fmaxf(xn, a.lo[ax]);
-      xn = fminf(xn, a.hi[ax]);
+      xn = fmaxf(xn, sg.lo[ax]);
+      xn = fminf(xn, sg.hi[ax]);
       a.x_out[(size_t)ax * Ps + i] = xn;
     }
 #pragma unroll
@@ -137,7 +140,7 @@ __global__ __launch_bounds__(BS) void g2p_kernel(G2PArgs a) {
   }
   if (a.F_out) {
     // F' = F + dt C F with C_ab = lin[a][b] / dx
-    const float s = a.dt / a.dx;
+    const float s = a.dt / sg.dx;
 #pragma unroll
     for (int r = 0; r < 3; ++r)
 #pragma unroll
@@ -151,25 +154,53 @@ __global__ __launch_bounds__(BS) void g2p_kernel(G2PArgs a) {
   if (a.mass_out) a.mass_out[i] = a.mass_in[p];
 }
 
-template <int NR>
-hipError_t launch_nr(const G2PArgs& a, hipStream_t stream) {
+template <int NR, class Scenes>
+hipError_t launch_nr(const G2PArgs& a, const Scenes& sc, hipStream_t stream) {
   constexpr int BS = 256;
   const unsigned blocks = (unsigned)((a.P + BS - 1) / BS);
-  g2p_kernel<NR, BS><<<blocks, BS, 0, stream>>>(a);
+  g2p_kernel<NR, BS, Scenes><<<blocks, BS, 0, stream>>>(a, sc);
   return hipGetLastError();
+}
+
+template <class Scenes>
+hipError_t launch_modes(const G2PArgs& a, const Scenes& sc, int n_modes, hipStream_t stream) {
+  if (a.P == 0) return hipSuccess;
+  if (a.sched != kSchedLinear && a.sched != kSchedXcd) return hipErrorInvalidValue;
+  switch (n_modes) {
+    case 1: return launch_nr<1>(a, sc, stream);
+    case 4: return launch_nr<4>(a, sc, stream);
+    case 8: return launch_nr<8>(a, sc, stream);
+    case 27: return launch_nr<27>(a, sc, stream);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 }  // namespace
 
-hipError_t launch_g2p(const G2PArgs& a, int n_modes, hipStream_t stream) {
-  if (a.P == 0) return hipSuccess;
-  switch (n_modes) {
-    case 1: return launch_nr<1>(a, stream);
-    case 4: return launch_nr<4>(a, stream);
-    case 8: return launch_nr<8>(a, stream);
-    case 27: return launch_nr<27>(a, stream);
-    default: return hipErrorInvalidValue;
+hipError_t launch_g2p(const G2PArgs& a0, int n_modes, hipStream_t stream) {
+  G2PArgs a = a0;
+  a.gstride = (int64_t)a.g.nx * a.g.ny * a.g.nz;
+  OneScene one;
+  one.sg.nx = a.g.nx;
+  one.sg.ny = a.g.ny;
+  one.sg.nz = a.g.nz;
+  one.sg.inv_dx = a.g.inv_dx;
+  one.sg.ox = a.g.ox;
+  one.sg.oy = a.g.oy;
+  one.sg.oz = a.g.oz;
+  one.sg.dx = a.dx;
+  for (int k = 0; k < 3; ++k) {
+    one.sg.lo[k] = a.lo[k];
+    one.sg.hi[k] = a.hi[k];
   }
+  one.sg.node_off = 0;
+  return launch_modes(a, one, n_modes, stream);
+}
+
+hipError_t launch_g2p_batch(const G2PArgs& a, const SceneDev* table, int n_scenes, int n_modes,
+                            hipStream_t stream) {
+  SceneTable st{table, n_scenes};
+  return launch_modes(a, st, n_modes, stream);
 }
 
 }  // namespace polypic

@@ -6,16 +6,23 @@
 #include <stdint.h>
 
 #include "polypic_device.hpp"
+#include "polypic_scene.hpp"
 
 namespace polypic {
 
 inline size_t align_up(size_t n, size_t a = 256) { return (n + a - 1) / a * a; }
+
+constexpr int kComputeUnits = 256;  // MI355X
 
 // ---- sort
 size_t sort_workspace_bytes(int64_t P);
 int sort_key_bits(const GridDev& g);
 hipError_t launch_sort(const GridDev& g, int64_t P, const float* x, uint32_t* keys_out,
                        int32_t* perm_out, void* ws, int32_t* status, hipStream_t stream);
+// batch of scenes: key = scene << mbits | Morton(base node), key_bits in total
+hipError_t launch_sort_batch(const SceneDev* table, int n_scenes, int mbits, int key_bits,
+                             int64_t P, const float* x, uint32_t* keys_out, int32_t* perm_out,
+                             void* ws, int32_t* status, hipStream_t stream);
 
 // ---- P2G
 struct P2GArgs {
@@ -34,12 +41,15 @@ struct P2GArgs {
   const uint32_t* keys;        // sorted cell keys (cell-gather path) or nullptr
   const uint32_t* tile_list;   // set by the launcher
   const uint32_t* tile_count;
+  int sched;                   // chunk schedule (set by the launcher)
 };
 
 // Launch configuration chosen by the host (autotuned or default).
 struct P2GConfig {
-  int tile_log2;   // brick edge = 1 << tile_log2 cells
-  int block;       // threads per block = particles per block
+  int tile_log2;       // brick edge = 1 << tile_log2 cells
+  int block;           // threads per block = particles per block
+  int sched;           // kSchedLinear, kSchedXcd or kSchedPersistent
+  int persist_per_cu;  // persistent workgroups per compute unit (kSchedPersistent)
 };
 
 P2GConfig p2g_default_config();
@@ -48,6 +58,9 @@ bool p2g_config_supported(const P2GConfig& c);
 hipError_t launch_grid_clear(float* gm, float* gp, int64_t n_nodes, uint32_t* counter,
                              hipStream_t stream);
 hipError_t launch_p2g(const P2GArgs& a, int n_modes, const P2GConfig& cfg, hipStream_t stream);
+// brick path over a batch of scenes (flattened particles, a.g unused)
+hipError_t launch_p2g_batch(const P2GArgs& a, const SceneDev* table, int n_scenes, int n_modes,
+                            const P2GConfig& cfg, hipStream_t stream);
 int64_t p2g_max_tiles(const GridDev& g, int64_t P);
 size_t p2g_workspace_bytes(const GridDev& g, int64_t P);
 // sorted-input path; ws holds the tile counter and list (p2g_workspace_bytes)
@@ -65,6 +78,9 @@ struct GridUpdateArgs {
   float* gv;        // [3][N]
 };
 hipError_t launch_grid_update(const GridUpdateArgs& a, hipStream_t stream);
+// batch of scenes: a.nx/ny/nz unused; gm, gp, gv span `stride` nodes per channel
+hipError_t launch_grid_update_batch(const GridUpdateArgs& a, const SceneDev* table, int n_scenes,
+                                    int max_nodes, int64_t stride, hipStream_t stream);
 // zero-fills p[0 .. n) with a kernel (no hipMemsetAsync: safe under graph capture)
 hipError_t launch_zero(float* p, int64_t n, hipStream_t stream);
 
@@ -85,8 +101,13 @@ struct G2PArgs {
   const float* mass_in; // [P] or nullptr
   float* mass_out;
   int32_t* status;
+  int64_t gstride;      // channel stride of gv (set by the launcher for one scene)
+  int sched;            // kSchedLinear or kSchedXcd
 };
 hipError_t launch_g2p(const G2PArgs& a, int n_modes, hipStream_t stream);
+// over a batch of scenes (a.g, a.lo, a.hi, a.dx unused; a.gstride = total nodes)
+hipError_t launch_g2p_batch(const G2PArgs& a, const SceneDev* table, int n_scenes, int n_modes,
+                            hipStream_t stream);
 
 // ---- adjoint
 struct GridUpdateBackArgs {

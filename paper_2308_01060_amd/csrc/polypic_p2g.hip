@@ -37,16 +37,25 @@ namespace {
 
 constexpr int kBrickKMAX = 3;                    // bricks (tiles) per workgroup in LDS
 
-template <int NR, int BS>
-__global__ __launch_bounds__(BS) void p2g_brick_kernel(P2GArgs a) {
+// Tile id of a base node: 4^3-node tile coordinates, plus the scene relative
+// to the chunk's first scene in the high word (zero for one scene).
+__device__ __forceinline__ uint64_t brick_tile_id(int s_rel, int b0, int b1, int b2) {
+  return ((uint64_t)(uint32_t)s_rel << 32) | (uint64_t)((uint32_t)(b0 >> 2) |
+                                                       ((uint32_t)(b1 >> 2) << 10) |
+                                                       ((uint32_t)(b2 >> 2) << 20));
+}
+constexpr uint64_t kNoTile = ~0ull;
+
+template <int NR, int BS, class Scenes>
+__global__ __launch_bounds__(BS) void p2g_brick_kernel(P2GArgs a, Scenes sc) {
   constexpr int NW = BS / kWave;
   // LDS double atomics run at about 8 cycles per wavefront instruction on
   // gfx950 when their addresses avoid bank conflicts; float ones at about 190
   // whatever the addresses.
   __shared__ double brick[kBrickKMAX * 4 * kBrickV];  // [brick][channel][node]
-  __shared__ uint32_t tile_of[BS];  // by processing slot
+  __shared__ uint64_t tile_of[BS];  // by processing slot
   __shared__ int seg_of[BS];        // by processing slot
-  __shared__ uint32_t seg_tile[kBrickKMAX];
+  __shared__ uint64_t seg_tile[kBrickKMAX];
   __shared__ int wave_heads[NW];
 
   const int tid = threadIdx.x;
@@ -56,140 +65,151 @@ __global__ __launch_bounds__(BS) void p2g_brick_kernel(P2GArgs a) {
   // slot, so that in sorted order (about 8 particles per cell) they sit in
   // different cells and their brick atomics do not collide.
   const int slot = lane * NW + wv;
-  const int64_t i = (int64_t)blockIdx.x * BS + slot;
   const size_t Ps = (size_t)a.P;
-  const int nx = a.g.nx, ny = a.g.ny, nz = a.g.nz;
+  const int64_t n_chunks = (a.P + BS - 1) / BS;
+  const ChunkRange cr = block_chunks(a.sched, n_chunks);
 
-  bool valid = i < a.P;
-  int p = 0;
-  // a caller permutation is clamped into [0, P) so that a bad one cannot read
-  // out of bounds (results are then wrong, never a fault)
-  if (valid) p = a.perm ? min(max(a.perm[i], 0), (int)(a.P - 1)) : (int)i;
-  int b0 = 0, b1 = 0, b2 = 0;
-  float t0 = 0.f, t1 = 0.f, t2 = 0.f;
-  if (valid) {
-    bool ok = stencil_axis(a.x[p], a.g.ox, a.g.inv_dx, nx, b0, t0);
-    ok &= stencil_axis(a.x[Ps + p], a.g.oy, a.g.inv_dx, ny, b1, t1);
-    ok &= stencil_axis(a.x[2 * Ps + p], a.g.oz, a.g.inv_dx, nz, b2, t2);
-    if (!ok) {
-      raise_flag(a.status, kFlagRange);
-      valid = false;
+  for (int64_t chunk = cr.begin; chunk < cr.end; ++chunk) {
+    const int64_t i0 = chunk * BS;
+    const int s0 = sc.first(i0);  // uniform over the workgroup
+    const int64_t i = i0 + slot;
+    bool valid = i < a.P;
+    const int s = valid ? sc.of(i, s0) : s0;
+    const SceneGrid sg = sc.grid(s);
+    int p = 0;
+    // a caller permutation is clamped into [0, P) so that a bad one cannot read
+    // out of bounds (results are then wrong, never a fault)
+    if (valid) p = a.perm ? min(max(a.perm[i], 0), (int)(a.P - 1)) : (int)i;
+    int b0 = 0, b1 = 0, b2 = 0;
+    float t0 = 0.f, t1 = 0.f, t2 = 0.f;
+    if (valid) {
+      bool ok = stencil_axis(a.x[p], sg.ox, sg.inv_dx, sg.nx, b0, t0);
+      ok &= stencil_axis(a.x[Ps + p], sg.oy, sg.inv_dx, sg.ny, b1, t1);
+      ok &= stencil_axis(a.x[2 * Ps + p], sg.oz, sg.inv_dx, sg.nz, b2, t2);
+      if (!ok) {
+        raise_flag(a.status, kFlagRange);
+        valid = false;
+      }
     }
-  }
-  tile_of[slot] = valid ? ((uint32_t)(b0 >> 2) | ((uint32_t)(b1 >> 2) << 10) |
-                           ((uint32_t)(b2 >> 2) << 20))
-                        : 0xFFFFFFFFu;
-  for (int k = tid; k < kBrickKMAX * 4 * kBrickV; k += BS) brick[k] = 0.0;
-  __syncthreads();
-
-  // runs of equal tiles in slot order (thread t looks at slot t) -> segments
-  {
-    const uint32_t tt = tile_of[tid];
-    const bool head = tt != 0xFFFFFFFFu && (tid == 0 || tile_of[tid - 1] != tt);
-    const unsigned long long hb = __ballot(head);
-    if (lane == 0) wave_heads[wv] = __popcll(hb);
+    tile_of[slot] = valid ? brick_tile_id(s - s0, b0, b1, b2) : kNoTile;
+    for (int k = tid; k < kBrickKMAX * 4 * kBrickV; k += BS) brick[k] = 0.0;
     __syncthreads();
-    int pre = 0;
-#pragma unroll
-    for (int w = 0; w < NW; ++w) pre += (w < wv) ? wave_heads[w] : 0;
-    const int sg = pre + lanes_below(hb) + (head ? 1 : 0) - 1;
-    seg_of[tid] = sg;
-    if (head && sg < kBrickKMAX) seg_tile[sg] = tt;
-  }
-  __syncthreads();
-  int nseg = 0;
-#pragma unroll
-  for (int w = 0; w < NW; ++w) nseg += wave_heads[w];
-  const int seg = seg_of[slot];
 
-  if (valid) {
-    const Basis1D bx = basis_p2g(t0);
-    const Basis1D by = basis_p2g(t1);
-    const Basis1D bz = basis_p2g(t2);
-    const float m = a.mass ? a.mass[p] : a.uniform_mass;
-    const bool lds = seg < kBrickKMAX;
-    const int lbase = (b0 & 3) + kBrickSY * (b1 & 3) + kBrickSZ * (b2 & 3);
-    const int gbase = (b2 * ny + b1) * nx + b0;
-    double* const lb = brick + (lds ? seg : 0) * 4 * kBrickV + lbase;
-    float* const gch[4] = {a.gm + gbase, a.gp0 + gbase, a.gp1 + gbase, a.gp2 + gbase};
-    const int nxny = nx * ny;
-    float wyz[9];
+    // runs of equal tiles in slot order (thread t looks at slot t) -> segments
+    {
+      const uint64_t tt = tile_of[tid];
+      const bool head = tt != kNoTile && (tid == 0 || tile_of[tid - 1] != tt);
+      const unsigned long long hb = __ballot(head);
+      if (lane == 0) wave_heads[wv] = __popcll(hb);
+      __syncthreads();
+      int pre = 0;
 #pragma unroll
-    for (int jz = 0; jz < 3; ++jz)
+      for (int w = 0; w < NW; ++w) pre += (w < wv) ? wave_heads[w] : 0;
+      const int sgi = pre + lanes_below(hb) + (head ? 1 : 0) - 1;
+      seg_of[tid] = sgi;
+      if (head && sgi < kBrickKMAX) seg_tile[sgi] = tt;
+    }
+    __syncthreads();
+    int nseg = 0;
 #pragma unroll
-      for (int jy = 0; jy < 3; ++jy) wyz[jy + 3 * jz] = m * by.w[jy] * bz.w[jz];
+    for (int w = 0; w < NW; ++w) nseg += wave_heads[w];
+    const int seg = seg_of[slot];
+
+    if (valid) {
+      const Basis1D bx = basis_p2g(t0);
+      const Basis1D by = basis_p2g(t1);
+      const Basis1D bz = basis_p2g(t2);
+      const float m = a.mass ? a.mass[p] : a.uniform_mass;
+      const bool lds = seg < kBrickKMAX;
+      const int nx = sg.nx, ny = sg.ny;
+      const int lbase = (b0 & 3) + kBrickSY * (b1 & 3) + kBrickSZ * (b2 & 3);
+      const int64_t gbase = sg.node_off + (int64_t)(b2 * ny + b1) * nx + b0;
+      double* const lb = brick + (lds ? seg : 0) * 4 * kBrickV + lbase;
+      float* const gch[4] = {a.gm + gbase, a.gp0 + gbase, a.gp1 + gbase, a.gp2 + gbase};
+      const int nxny = nx * ny;
+      float wyz[9];
+#pragma unroll
+      for (int jz = 0; jz < 3; ++jz)
+#pragma unroll
+        for (int jy = 0; jy < 3; ++jy) wyz[jy + 3 * jz] = m * by.w[jy] * bz.w[jz];
 
 #pragma unroll
-    for (int ch = 0; ch < 4; ++ch) {
-      float val[27];
-      if (ch == 0) {
+      for (int ch = 0; ch < 4; ++ch) {
+        float val[27];
+        if (ch == 0) {
 #pragma unroll
-        for (int jz = 0; jz < 3; ++jz)
+          for (int jz = 0; jz < 3; ++jz)
 #pragma unroll
-          for (int jy = 0; jy < 3; ++jy)
+            for (int jy = 0; jy < 3; ++jy)
 #pragma unroll
-            for (int jx = 0; jx < 3; ++jx) val[jx + 3 * jy + 9 * jz] = wyz[jy + 3 * jz] * bx.w[jx];
-      } else {
-        float cf[27];
-        const float* cp = a.coeff + (size_t)(ch - 1) * NR * Ps + p;
+              for (int jx = 0; jx < 3; ++jx)
+                val[jx + 3 * jy + 9 * jz] = wyz[jy + 3 * jz] * bx.w[jx];
+        } else {
+          float cf[27];
+          const float* cp = a.coeff + (size_t)(ch - 1) * NR * Ps + p;
 #pragma unroll
-        for (int r = 0; r < 27; ++r) cf[r] = (r < NR) ? cp[(size_t)r * Ps] : 0.0f;
-        float V[27];
-        eval_modes<NR>(cf, bx, by, bz, V);
+          for (int r = 0; r < 27; ++r) cf[r] = (r < NR) ? cp[(size_t)r * Ps] : 0.0f;
+          float V[27];
+          eval_modes<NR>(cf, bx, by, bz, V);
 #pragma unroll
-        for (int jz = 0; jz < 3; ++jz)
+          for (int jz = 0; jz < 3; ++jz)
 #pragma unroll
-          for (int jy = 0; jy < 3; ++jy)
+            for (int jy = 0; jy < 3; ++jy)
 #pragma unroll
-            for (int jx = 0; jx < 3; ++jx) {
-              const int j = jx + 3 * jy + 9 * jz;
-              val[j] = (wyz[jy + 3 * jz] * bx.w[jx]) * V[j];
-            }
-      }
-      if (lds) {
-        double* const lbc = lb + ch * kBrickV;
+              for (int jx = 0; jx < 3; ++jx) {
+                const int j = jx + 3 * jy + 9 * jz;
+                val[j] = (wyz[jy + 3 * jz] * bx.w[jx]) * V[j];
+              }
+        }
+        if (lds) {
+          double* const lbc = lb + ch * kBrickV;
 #pragma unroll
-        for (int jz = 0; jz < 3; ++jz)
+          for (int jz = 0; jz < 3; ++jz)
 #pragma unroll
-          for (int jy = 0; jy < 3; ++jy)
+            for (int jy = 0; jy < 3; ++jy)
 #pragma unroll
-            for (int jx = 0; jx < 3; ++jx)
-              atomicAdd(lbc + jx + kBrickSY * jy + kBrickSZ * jz, (double)val[jx + 3 * jy + 9 * jz]);
-      } else {
+              for (int jx = 0; jx < 3; ++jx)
+                atomicAdd(lbc + jx + kBrickSY * jy + kBrickSZ * jz,
+                          (double)val[jx + 3 * jy + 9 * jz]);
+        } else {
 #pragma unroll
-        for (int jz = 0; jz < 3; ++jz)
+          for (int jz = 0; jz < 3; ++jz)
 #pragma unroll
-          for (int jy = 0; jy < 3; ++jy)
+            for (int jy = 0; jy < 3; ++jy)
 #pragma unroll
-            for (int jx = 0; jx < 3; ++jx)
-              atomicAdd(gch[ch] + jz * nxny + jy * nx + jx, val[jx + 3 * jy + 9 * jz]);
+              for (int jx = 0; jx < 3; ++jx)
+                atomicAdd(gch[ch] + jz * nxny + jy * nx + jx, val[jx + 3 * jy + 9 * jz]);
+        }
       }
     }
-  }
-  __syncthreads();
+    __syncthreads();
 
-  // flush: one global float atomic per channel per non-zero brick node
-  const int nb = nseg < kBrickKMAX ? nseg : kBrickKMAX;
-  for (int k = tid; k < nb * 4 * kBrickV; k += BS) {
-    const int sc = k / kBrickV;  // brick * 4 + channel
-    const int idx = k - sc * kBrickV;
-    const int s = sc >> 2;
-    const int ch = sc & 3;
-    const int lz = idx / kBrickSZ;
-    const int rem = idx - lz * kBrickSZ;
-    const int ly = rem / kBrickSY;
-    const int lx = rem - ly * kBrickSY;
-    if (lx > kBrickT + 1 || ly > kBrickT + 1) continue;  // padding
-    const float v = (float)brick[k];
-    if (v == 0.0f) continue;
-    const uint32_t tl = seg_tile[s];
-    const int gx = (int)(tl & 1023u) * kBrickT + lx;
-    const int gy = (int)((tl >> 10) & 1023u) * kBrickT + ly;
-    const int gz = (int)(tl >> 20) * kBrickT + lz;
-    if (gx < nx && gy < ny && gz < nz) {
-      float* const d = ch == 0 ? a.gm : ch == 1 ? a.gp0 : ch == 2 ? a.gp1 : a.gp2;
-      atomicAdd(d + ((gz * ny + gy) * nx + gx), v);
+    // flush: one global float atomic per channel per non-zero brick node
+    const int nb = nseg < kBrickKMAX ? nseg : kBrickKMAX;
+    for (int k = tid; k < nb * 4 * kBrickV; k += BS) {
+      const int sc4 = k / kBrickV;  // brick * 4 + channel
+      const int idx = k - sc4 * kBrickV;
+      const int sb = sc4 >> 2;
+      const int ch = sc4 & 3;
+      const int lz = idx / kBrickSZ;
+      const int rem = idx - lz * kBrickSZ;
+      const int ly = rem / kBrickSY;
+      const int lx = rem - ly * kBrickSY;
+      if (lx > kBrickT + 1 || ly > kBrickT + 1) continue;  // padding
+      const float v = (float)brick[k];
+      if (v == 0.0f) continue;
+      const uint64_t tl = seg_tile[sb];
+      const SceneGrid fg = sc.grid(s0 + (int)(tl >> 32));
+      const uint32_t tc = (uint32_t)tl;
+      const int gx = (int)(tc & 1023u) * kBrickT + lx;
+      const int gy = (int)((tc >> 10) & 1023u) * kBrickT + ly;
+      const int gz = (int)(tc >> 20) * kBrickT + lz;
+      if (gx < fg.nx && gy < fg.ny && gz < fg.nz) {
+        float* const d = ch == 0 ? a.gm : ch == 1 ? a.gp0 : ch == 2 ? a.gp1 : a.gp2;
+        atomicAdd(d + fg.node_off + ((int64_t)(gz * fg.ny + gy) * fg.nx + gx), v);
+      }
     }
+    __syncthreads();  // the next chunk reuses tile_of, seg_tile and the bricks
   }
 }
 
@@ -395,18 +415,39 @@ __global__ __launch_bounds__(kCellThreads) void p2g_cell_kernel(P2GArgs a) {
   }
 }
 
-template <int NR, int BS>
-hipError_t launch_cfg(const P2GArgs& a, hipStream_t stream) {
-  const unsigned blocks = (unsigned)((a.P + BS - 1) / BS);
-  p2g_brick_kernel<NR, BS><<<blocks, BS, 0, stream>>>(a);
+template <int NR, int BS, class Scenes>
+hipError_t launch_cfg(const P2GArgs& a0, const Scenes& sc, const P2GConfig& c, hipStream_t stream) {
+  P2GArgs a = a0;
+  const int64_t chunks = (a.P + BS - 1) / BS;
+  int64_t blocks = chunks;
+  a.sched = c.sched;
+  if (c.sched == kSchedPersistent) {
+    const int64_t cap = (int64_t)c.persist_per_cu * kComputeUnits;
+    if (cap < chunks) blocks = cap;
+    else a.sched = kSchedXcd;  // as many workgroups as chunks: one chunk each
+  }
+  p2g_brick_kernel<NR, BS, Scenes><<<(unsigned)blocks, BS, 0, stream>>>(a, sc);
   return hipGetLastError();
 }
 
-template <int NR>
-hipError_t launch_nr(const P2GArgs& a, const P2GConfig& c, hipStream_t stream) {
+template <int NR, class Scenes>
+hipError_t launch_nr(const P2GArgs& a, const Scenes& sc, const P2GConfig& c, hipStream_t stream) {
   switch (c.block) {
-    case 256: return launch_cfg<NR, 256>(a, stream);
-    case 512: return launch_cfg<NR, 512>(a, stream);
+    case 256: return launch_cfg<NR, 256>(a, sc, c, stream);
+    case 512: return launch_cfg<NR, 512>(a, sc, c, stream);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <class Scenes>
+hipError_t launch_modes(const P2GArgs& a, const Scenes& sc, int n_modes, const P2GConfig& cfg,
+                        hipStream_t stream) {
+  if (a.P == 0) return hipSuccess;
+  switch (n_modes) {
+    case 1: return launch_nr<1>(a, sc, cfg, stream);
+    case 4: return launch_nr<4>(a, sc, cfg, stream);
+    case 8: return launch_nr<8>(a, sc, cfg, stream);
+    case 27: return launch_nr<27>(a, sc, cfg, stream);
     default: return hipErrorInvalidValue;
   }
 }
@@ -419,10 +460,12 @@ hipError_t launch_cell_nr(const P2GArgs& a, int blocks, hipStream_t stream) {
 
 }  // namespace
 
-P2GConfig p2g_default_config() { return P2GConfig{2, 512}; }
+P2GConfig p2g_default_config() { return P2GConfig{2, 512, kSchedLinear, 0}; }
 
 bool p2g_config_supported(const P2GConfig& c) {
-  return c.tile_log2 == 2 && (c.block == 256 || c.block == 512);
+  if (c.tile_log2 != 2 || (c.block != 256 && c.block != 512)) return false;
+  if (c.sched == kSchedLinear || c.sched == kSchedXcd) return true;
+  return c.sched == kSchedPersistent && c.persist_per_cu >= 1 && c.persist_per_cu <= 64;
 }
 
 hipError_t launch_grid_clear(float* gm, float* gp, int64_t n_nodes, uint32_t* counter,
@@ -470,14 +513,24 @@ hipError_t launch_p2g_sorted(const P2GArgs& a0, int n_modes, void* ws, bool coun
 }
 
 hipError_t launch_p2g(const P2GArgs& a, int n_modes, const P2GConfig& cfg, hipStream_t stream) {
-  if (a.P == 0) return hipSuccess;
-  switch (n_modes) {
-    case 1: return launch_nr<1>(a, cfg, stream);
-    case 4: return launch_nr<4>(a, cfg, stream);
-    case 8: return launch_nr<8>(a, cfg, stream);
-    case 27: return launch_nr<27>(a, cfg, stream);
-    default: return hipErrorInvalidValue;
-  }
+  OneScene one;
+  one.sg.nx = a.g.nx;
+  one.sg.ny = a.g.ny;
+  one.sg.nz = a.g.nz;
+  one.sg.inv_dx = a.g.inv_dx;
+  one.sg.ox = a.g.ox;
+  one.sg.oy = a.g.oy;
+  one.sg.oz = a.g.oz;
+  one.sg.dx = 0.0f;  // unused by P2G
+  for (int k = 0; k < 3; ++k) one.sg.lo[k] = one.sg.hi[k] = 0.0f;
+  one.sg.node_off = 0;
+  return launch_modes(a, one, n_modes, cfg, stream);
+}
+
+hipError_t launch_p2g_batch(const P2GArgs& a, const SceneDev* table, int n_scenes, int n_modes,
+                            const P2GConfig& cfg, hipStream_t stream) {
+  SceneTable st{table, n_scenes};
+  return launch_modes(a, st, n_modes, cfg, stream);
 }
 
 }  // namespace polypic

@@ -17,12 +17,19 @@ constexpr int kSortTile = kSortBS * kSortIPT;
 constexpr int kRadix = 256;
 constexpr int kSortWaves = kSortBS / kWave;
 
-__global__ __launch_bounds__(256) void sort_keys_kernel(GridDev g, int64_t P, const float* __restrict__ x,
+// Cell key of every particle: Morton code of its base node, with the scene
+// index above bit `mbits` when the launch covers a batch of scenes.
+template <class Scenes>
+__global__ __launch_bounds__(256) void sort_keys_kernel(Scenes sc, int mbits, int64_t P,
+                                                        const float* __restrict__ x,
                                                         uint32_t* __restrict__ keys,
                                                         int32_t* __restrict__ vals,
                                                         int32_t* __restrict__ status) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t i0 = (int64_t)blockIdx.x * blockDim.x;
+  const int64_t i = i0 + threadIdx.x;
   if (i >= P) return;
+  const int s = sc.of(i, sc.first(i0));
+  const SceneGrid g = sc.grid(s);
   const size_t Ps = (size_t)P;
   int b0, b1, b2;
   float t0, t1, t2;
@@ -32,9 +39,9 @@ __global__ __launch_bounds__(256) void sort_keys_kernel(GridDev g, int64_t P, co
   if (!ok) {
     raise_flag(status, kFlagRange);
     // stencil_axis returns b = 0 for an out-of-range axis: the key stays in the
-    // configured bit range and the particle is ordered deterministically.
+    // configured bit range (and in its scene) and the order is deterministic.
   }
-  keys[i] = morton3(b0, b1, b2);
+  keys[i] = ((uint32_t)s << mbits) | morton3(b0, b1, b2);
   vals[i] = (int32_t)i;
 }
 
@@ -187,8 +194,14 @@ int sort_key_bits(const GridDev& g) {
   return 3 * bits;
 }
 
-hipError_t launch_sort(const GridDev& g, int64_t P, const float* x, uint32_t* keys_out,
-                       int32_t* perm_out, void* ws, int32_t* status, hipStream_t stream) {
+namespace {
+
+// Stable LSD radix sort of the keys the key kernel wrote to (ksrc, vsrc); the
+// last pass lands in (keys_out, perm_out).
+template <class Scenes>
+hipError_t sort_with(const Scenes& sc, int mbits, int key_bits, int64_t P, const float* x,
+                     uint32_t* keys_out, int32_t* perm_out, void* ws, int32_t* status,
+                     hipStream_t stream) {
   if (P == 0) return hipSuccess;
   const int n_tiles = (int)((P + kSortTile - 1) / kSortTile);
   char* w = (char*)ws;
@@ -200,7 +213,6 @@ hipError_t launch_sort(const GridDev& g, int64_t P, const float* x, uint32_t* ke
   w += align_up((size_t)kRadix * (size_t)n_tiles * sizeof(uint32_t));
   uint32_t* totals = (uint32_t*)w;
 
-  const int key_bits = sort_key_bits(g);
   const int passes = (key_bits + 7) / 8;
   // Ping-pong so that the last pass writes keys_out / perm_out.
   uint32_t* ksrc = (passes % 2) ? keys_alt : keys_out;
@@ -209,7 +221,8 @@ hipError_t launch_sort(const GridDev& g, int64_t P, const float* x, uint32_t* ke
   int32_t* vdst = (passes % 2) ? perm_out : vals_alt;
 
   const int kb = 256;
-  sort_keys_kernel<<<(unsigned)((P + kb - 1) / kb), kb, 0, stream>>>(g, P, x, ksrc, vsrc, status);
+  sort_keys_kernel<Scenes><<<(unsigned)((P + kb - 1) / kb), kb, 0, stream>>>(sc, mbits, P, x,
+                                                                            ksrc, vsrc, status);
   for (int pass = 0; pass < passes; ++pass) {
     const int shift = 8 * pass;
     sort_hist_kernel<<<n_tiles, kSortBS, 0, stream>>>(ksrc, P, shift, counts, n_tiles);
@@ -224,6 +237,32 @@ hipError_t launch_sort(const GridDev& g, int64_t P, const float* x, uint32_t* ke
     vdst = vt;
   }
   return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_sort(const GridDev& g, int64_t P, const float* x, uint32_t* keys_out,
+                       int32_t* perm_out, void* ws, int32_t* status, hipStream_t stream) {
+  OneScene one;
+  one.sg.nx = g.nx;
+  one.sg.ny = g.ny;
+  one.sg.nz = g.nz;
+  one.sg.inv_dx = g.inv_dx;
+  one.sg.ox = g.ox;
+  one.sg.oy = g.oy;
+  one.sg.oz = g.oz;
+  one.sg.dx = 0.0f;
+  for (int k = 0; k < 3; ++k) one.sg.lo[k] = one.sg.hi[k] = 0.0f;
+  one.sg.node_off = 0;
+  const int bits = sort_key_bits(g);
+  return sort_with(one, bits, bits, P, x, keys_out, perm_out, ws, status, stream);
+}
+
+hipError_t launch_sort_batch(const SceneDev* table, int n_scenes, int mbits, int key_bits,
+                             int64_t P, const float* x, uint32_t* keys_out, int32_t* perm_out,
+                             void* ws, int32_t* status, hipStream_t stream) {
+  SceneTable st{table, n_scenes};
+  return sort_with(st, mbits, key_bits, P, x, keys_out, perm_out, ws, status, stream);
 }
 
 }  // namespace polypic

@@ -7,7 +7,7 @@ nothing here computes any part of the transfers.
 from __future__ import annotations
 
 import ctypes
-from typing import Optional, Sequence, Tuple
+from typing import List, NamedTuple, Optional, Sequence, Tuple
 
 import torch
 
@@ -112,16 +112,26 @@ def polypic_p2g(grid: polypic_grid, n_modes: int, x: torch.Tensor, coeff: torch.
         _ptr(status_dev, torch.int32, 1, "status_dev"), _stream()), "polypic_p2g")
 
 
-def polypic_set_p2g_config(n_modes: int, path: int, block: int = 512) -> None:
-    check(_lib.load().polypic_set_p2g_config(int(n_modes), int(path), int(block)),
-          "polypic_set_p2g_config")
+class P2GChoice(NamedTuple):
+    """A P2G launch configuration (include/polypic.h): path, workgroup size, chunk schedule."""
+
+    path: int
+    block: int
+    schedule: int = _lib.POLYPIC_SCHED_LINEAR
+    per_cu: int = 0
 
 
-def polypic_get_p2g_config(n_modes: int) -> Tuple[int, int]:
-    path, block = ctypes.c_int32(0), ctypes.c_int32(0)
-    check(_lib.load().polypic_get_p2g_config(int(n_modes), ctypes.byref(path), ctypes.byref(block)),
+def polypic_set_p2g_config(n_modes: int, path: int, block: int = 512,
+                           schedule: int = _lib.POLYPIC_SCHED_LINEAR, per_cu: int = 0) -> None:
+    check(_lib.load().polypic_set_p2g_config(int(n_modes), int(path), int(block), int(schedule),
+                                             int(per_cu)), "polypic_set_p2g_config")
+
+
+def polypic_get_p2g_config(n_modes: int) -> P2GChoice:
+    v = [ctypes.c_int32(0) for _ in range(4)]
+    check(_lib.load().polypic_get_p2g_config(int(n_modes), *[ctypes.byref(t) for t in v]),
           "polypic_get_p2g_config")
-    return int(path.value), int(block.value)
+    return P2GChoice(*(int(t.value) for t in v))
 
 
 def polypic_autotune_p2g(grid: polypic_grid, n_modes: int, x: torch.Tensor, coeff: torch.Tensor,
@@ -129,11 +139,11 @@ def polypic_autotune_p2g(grid: polypic_grid, n_modes: int, x: torch.Tensor, coef
                          mass: Optional[torch.Tensor] = None, uniform_mass: float = 1.0,
                          perm: Optional[torch.Tensor] = None,
                          keys_sorted: Optional[torch.Tensor] = None,
-                         ws: Optional[torch.Tensor] = None) -> Tuple[int, int]:
-    """Times every P2G configuration on these inputs; returns the chosen (path, block)."""
+                         ws: Optional[torch.Tensor] = None) -> P2GChoice:
+    """Times every P2G configuration on these inputs; returns the chosen one."""
     P = x.numel() // 3
     N = n_nodes(grid)
-    path, block = ctypes.c_int32(0), ctypes.c_int32(0)
+    v = [ctypes.c_int32(0) for _ in range(4)]
     check(_lib.load().polypic_autotune_p2g(
         ctypes.byref(grid), P, int(n_modes), _ptr(x, torch.float32, 3 * P, "x"),
         _ptr(mass, torch.float32, P, "mass"), float(uniform_mass),
@@ -143,8 +153,18 @@ def polypic_autotune_p2g(grid: polypic_grid, n_modes: int, x: torch.Tensor, coef
         0 if ws is None else ws.numel(),
         _ptr(grid_mass, torch.float32, N, "grid_mass"),
         _ptr(grid_mom, torch.float32, 3 * N, "grid_mom"),
-        ctypes.byref(path), ctypes.byref(block), _stream()), "polypic_autotune_p2g")
-    return int(path.value), int(block.value)
+        *[ctypes.byref(t) for t in v], _stream()), "polypic_autotune_p2g")
+    return P2GChoice(*(int(t.value) for t in v))
+
+
+def polypic_set_g2p_schedule(schedule: int) -> None:
+    check(_lib.load().polypic_set_g2p_schedule(int(schedule)), "polypic_set_g2p_schedule")
+
+
+def polypic_get_g2p_schedule() -> int:
+    v = ctypes.c_int32(0)
+    check(_lib.load().polypic_get_g2p_schedule(ctypes.byref(v)), "polypic_get_g2p_schedule")
+    return int(v.value)
 
 
 def polypic_grid_update(grid: polypic_grid, dt: float, gravity: Sequence[float], bc_layers: int,
@@ -232,3 +252,146 @@ def polypic_p2g_backward(grid: polypic_grid, n_modes: int, x: torch.Tensor, coef
         _ptr(coeff_grad, torch.float32, 3 * int(n_modes) * P, "coeff_grad"),
         _ptr(x_grad, torch.float32, 3 * P, "x_grad"), _ptr(mass_grad, torch.float32, P, "mass_grad"),
         _ptr(status_dev, torch.int32, 1, "status_dev"), _stream()), "polypic_p2g_backward")
+
+
+# ---------------------------------------------------------------- batches
+class Batch:
+    """A planned batch of scenes: the sealed C descriptor plus the device table it points to.
+
+    scenes: list of (polypic_grid, n_particles).  Particles of scene k occupy the
+    flattened range [p_offset_k, p_offset_k + n_k) in scene order; its nodes the
+    range [node_offset_k, node_offset_k + nodes_k), scenes packed end to end.
+    """
+
+    def __init__(self, scenes: Sequence[Tuple[polypic_grid, int]], device="cuda"):
+        lib = _lib.load()
+        n = len(scenes)
+        arr = (_lib.polypic_scene * n)()
+        p = 0
+        node = 0
+        self.p_offsets: List[int] = []
+        self.node_offsets: List[int] = []
+        self.grids: List[polypic_grid] = []
+        for k, (g, count) in enumerate(scenes):
+            arr[k].grid = g
+            arr[k].p_offset = p
+            arr[k].n_particles = int(count)
+            arr[k].node_offset = node
+            self.p_offsets.append(p)
+            self.node_offsets.append(node)
+            self.grids.append(g)
+            p += int(count)
+            node += n_nodes(g)
+        self.p_offsets.append(p)
+        self.node_offsets.append(node)
+        nbytes = ctypes.c_size_t(0)
+        check(lib.polypic_batch_table_bytes(n, ctypes.byref(nbytes)), "polypic_batch_table_bytes")
+        self.table = torch.empty(max(1, nbytes.value), dtype=torch.uint8, device=device)
+        self.desc = _lib.polypic_batch()
+        check(lib.polypic_batch_plan(arr, n, node, ctypes.c_void_p(self.table.data_ptr()),
+                                     self.table.numel(), ctypes.byref(self.desc), _stream()),
+              "polypic_batch_plan")
+        self.P = int(self.desc.P)
+        self.N = int(self.desc.N)
+        self.n_scenes = n
+
+    def ref(self):
+        return ctypes.byref(self.desc)
+
+
+def polypic_batch_sort_workspace_bytes(batch: Batch) -> int:
+    out = ctypes.c_size_t(0)
+    check(_lib.load().polypic_batch_sort_workspace_bytes(batch.ref(), ctypes.byref(out)),
+          "polypic_batch_sort_workspace_bytes")
+    return int(out.value)
+
+
+def polypic_batch_sort(batch: Batch, x: torch.Tensor, keys_out: torch.Tensor,
+                       perm_out: torch.Tensor, ws: torch.Tensor,
+                       status_dev: Optional[torch.Tensor] = None) -> None:
+    P = batch.P
+    check(_lib.load().polypic_batch_sort(
+        batch.ref(), _ptr(x, torch.float32, 3 * P, "x"), _keys_ptr(keys_out, P),
+        _ptr(perm_out, torch.int32, P, "perm_out"), _ptr(ws, torch.uint8, ws.numel(), "ws"),
+        ws.numel(), _ptr(status_dev, torch.int32, 1, "status_dev"), _stream()), "polypic_batch_sort")
+
+
+def polypic_batch_p2g(batch: Batch, n_modes: int, x: torch.Tensor, coeff: torch.Tensor,
+                      grid_mass: torch.Tensor, grid_mom: torch.Tensor,
+                      mass: Optional[torch.Tensor] = None, uniform_mass: float = 1.0,
+                      perm: Optional[torch.Tensor] = None, accumulate: bool = False,
+                      status_dev: Optional[torch.Tensor] = None) -> None:
+    P, N = batch.P, batch.N
+    check(_lib.load().polypic_batch_p2g(
+        batch.ref(), int(n_modes), _ptr(x, torch.float32, 3 * P, "x"),
+        _ptr(mass, torch.float32, P, "mass"), float(uniform_mass),
+        _ptr(coeff, torch.float32, 3 * int(n_modes) * P, "coeff"),
+        _ptr(perm, torch.int32, P, "perm"), _ptr(grid_mass, torch.float32, N, "grid_mass"),
+        _ptr(grid_mom, torch.float32, 3 * N, "grid_mom"), int(bool(accumulate)),
+        _ptr(status_dev, torch.int32, 1, "status_dev"), _stream()), "polypic_batch_p2g")
+
+
+def polypic_batch_grid_update(batch: Batch, dt: float, gravity: Sequence[float], bc_layers: int,
+                              grid_mass: torch.Tensor, grid_mom: torch.Tensor,
+                              grid_vel: torch.Tensor) -> None:
+    N = batch.N
+    g3 = (ctypes.c_float * 3)(*[float(v) for v in gravity])
+    check(_lib.load().polypic_batch_grid_update(
+        batch.ref(), float(dt), g3, int(bc_layers),
+        _ptr(grid_mass, torch.float32, N, "grid_mass"),
+        _ptr(grid_mom, torch.float32, 3 * N, "grid_mom"),
+        _ptr(grid_vel, torch.float32, 3 * N, "grid_vel"), _stream()), "polypic_batch_grid_update")
+
+
+def polypic_batch_g2p(batch: Batch, n_modes: int, dt: float, grid_vel: torch.Tensor,
+                      x_in: torch.Tensor, coeff_out: torch.Tensor,
+                      perm: Optional[torch.Tensor] = None, x_out: Optional[torch.Tensor] = None,
+                      F_in: Optional[torch.Tensor] = None, F_out: Optional[torch.Tensor] = None,
+                      mass_in: Optional[torch.Tensor] = None,
+                      mass_out: Optional[torch.Tensor] = None,
+                      status_dev: Optional[torch.Tensor] = None) -> None:
+    P, N = batch.P, batch.N
+    check(_lib.load().polypic_batch_g2p(
+        batch.ref(), int(n_modes), float(dt), _ptr(grid_vel, torch.float32, 3 * N, "grid_vel"),
+        _ptr(x_in, torch.float32, 3 * P, "x_in"), _ptr(perm, torch.int32, P, "perm"),
+        _ptr(x_out, torch.float32, 3 * P, "x_out"),
+        _ptr(coeff_out, torch.float32, 3 * int(n_modes) * P, "coeff_out"),
+        _ptr(F_in, torch.float32, 9 * P, "F_in"), _ptr(F_out, torch.float32, 9 * P, "F_out"),
+        _ptr(mass_in, torch.float32, P, "mass_in"), _ptr(mass_out, torch.float32, P, "mass_out"),
+        _ptr(status_dev, torch.int32, 1, "status_dev"), _stream()), "polypic_batch_g2p")
+
+
+class BatchChoice(NamedTuple):
+    """Batched P2G launch configuration: workgroup size and chunk schedule."""
+
+    block: int
+    schedule: int
+    per_cu: int = 0
+
+
+def polypic_batch_set_config(n_modes: int, block: int, schedule: int, per_cu: int = 0) -> None:
+    check(_lib.load().polypic_batch_set_config(int(n_modes), int(block), int(schedule),
+                                               int(per_cu)), "polypic_batch_set_config")
+
+
+def polypic_batch_get_config(n_modes: int) -> BatchChoice:
+    v = [ctypes.c_int32(0) for _ in range(3)]
+    check(_lib.load().polypic_batch_get_config(int(n_modes), *[ctypes.byref(t) for t in v]),
+          "polypic_batch_get_config")
+    return BatchChoice(*(int(t.value) for t in v))
+
+
+def polypic_batch_autotune(batch: Batch, n_modes: int, x: torch.Tensor, coeff: torch.Tensor,
+                           grid_mass: torch.Tensor, grid_mom: torch.Tensor,
+                           mass: Optional[torch.Tensor] = None, uniform_mass: float = 1.0,
+                           perm: Optional[torch.Tensor] = None) -> BatchChoice:
+    P, N = batch.P, batch.N
+    v = [ctypes.c_int32(0) for _ in range(3)]
+    check(_lib.load().polypic_batch_autotune(
+        batch.ref(), int(n_modes), _ptr(x, torch.float32, 3 * P, "x"),
+        _ptr(mass, torch.float32, P, "mass"), float(uniform_mass),
+        _ptr(coeff, torch.float32, 3 * int(n_modes) * P, "coeff"),
+        _ptr(perm, torch.int32, P, "perm"), _ptr(grid_mass, torch.float32, N, "grid_mass"),
+        _ptr(grid_mom, torch.float32, 3 * N, "grid_mom"), *[ctypes.byref(t) for t in v],
+        _stream()), "polypic_batch_autotune")
+    return BatchChoice(*(int(t.value) for t in v))

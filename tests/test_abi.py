@@ -132,16 +132,96 @@ def test_grid_update_and_sort_reject_bad_arguments():
 
 def test_p2g_config_table_validation():
     lib = _lib.load()
-    path, block = ctypes.c_int32(0), ctypes.c_int32(0)
-    assert lib.polypic_set_p2g_config(5, 0, 512) == 1            # bad n_modes
-    assert lib.polypic_set_p2g_config(27, 7, 512) == 1           # bad path
-    assert lib.polypic_set_p2g_config(27, 0, 300) == 1           # bad block
-    assert lib.polypic_set_p2g_config(8, _lib.POLYPIC_P2G_BRICKS, 256) == 0
-    assert lib.polypic_get_p2g_config(8, ctypes.byref(path), ctypes.byref(block)) == 0
-    assert (path.value, block.value) == (_lib.POLYPIC_P2G_BRICKS, 256)
-    assert lib.polypic_set_p2g_config(8, _lib.POLYPIC_P2G_DEFAULT, 512) == 0
-    assert lib.polypic_get_p2g_config(8, ctypes.byref(path), ctypes.byref(block)) == 0
+    path, block, sched, per_cu = (ctypes.c_int32(0) for _ in range(4))
+    refs = [ctypes.byref(v) for v in (path, block, sched, per_cu)]
+    assert lib.polypic_set_p2g_config(5, 0, 512, 0, 0) == 1            # bad n_modes
+    assert lib.polypic_set_p2g_config(27, 7, 512, 0, 0) == 1           # bad path
+    assert lib.polypic_set_p2g_config(27, 0, 300, 0, 0) == 1           # bad block
+    assert lib.polypic_set_p2g_config(27, 0, 256, 3, 0) == 1           # bad schedule
+    assert lib.polypic_set_p2g_config(27, 0, 256, 2, 0) == 1           # persistent needs per_cu
+    assert lib.polypic_set_p2g_config(27, 0, 256, 2, 65) == 1
+    assert lib.polypic_set_p2g_config(8, _lib.POLYPIC_P2G_BRICKS, 256, _lib.POLYPIC_SCHED_XCD,
+                                      0) == 0
+    assert lib.polypic_get_p2g_config(8, *refs) == 0
+    assert (path.value, block.value, sched.value, per_cu.value) == (_lib.POLYPIC_P2G_BRICKS, 256,
+                                                                    _lib.POLYPIC_SCHED_XCD, 0)
+    assert lib.polypic_set_p2g_config(8, 0, 512, _lib.POLYPIC_SCHED_PERSISTENT, 4) == 0
+    assert lib.polypic_get_p2g_config(8, *refs) == 0
+    assert (sched.value, per_cu.value) == (_lib.POLYPIC_SCHED_PERSISTENT, 4)
+    assert lib.polypic_set_p2g_config(8, _lib.POLYPIC_P2G_DEFAULT, 512, 0, 0) == 0
+    assert lib.polypic_get_p2g_config(8, *refs) == 0
     assert path.value == _lib.POLYPIC_P2G_DEFAULT
+    # G2P schedule
+    assert lib.polypic_set_g2p_schedule(2) == 1
+    assert lib.polypic_set_g2p_schedule(_lib.POLYPIC_SCHED_XCD) == 0
+    assert lib.polypic_get_g2p_schedule(ctypes.byref(sched)) == 0 and sched.value == 1
+    assert lib.polypic_set_g2p_schedule(_lib.POLYPIC_SCHED_LINEAR) == 0
+    # batched P2G configuration
+    assert lib.polypic_batch_set_config(27, 384, 0, 0) == 1
+    assert lib.polypic_batch_set_config(27, 256, 2, 0) == 1
+    assert lib.polypic_batch_get_config(27, *refs[1:]) == 0
+    assert (block.value, sched.value) == (256, _lib.POLYPIC_SCHED_XCD)   # default
+    assert lib.polypic_batch_set_config(4, 512, _lib.POLYPIC_SCHED_PERSISTENT, 8) == 0
+    assert lib.polypic_batch_get_config(4, *refs[1:]) == 0
+    assert (block.value, sched.value, per_cu.value) == (512, 2, 8)
+    assert lib.polypic_batch_set_config(4, 256, _lib.POLYPIC_SCHED_XCD, 0) == 0
+
+
+def scene(g, p_off, n, node_off):
+    s = _lib.polypic_scene()
+    s.grid = g
+    s.p_offset, s.n_particles, s.node_offset = p_off, n, node_off
+    return s
+
+
+def test_batch_plan_validation():
+    """Every check that polypic_batch_plan makes before touching the device."""
+    lib = _lib.load()
+    g = grid(36, 36, 36)
+    nn = 36 ** 3
+    out = ctypes.c_size_t(0)
+    assert lib.polypic_batch_table_bytes(0, ctypes.byref(out)) == 1
+    assert lib.polypic_batch_table_bytes(65537, ctypes.byref(out)) == 1
+    assert lib.polypic_batch_table_bytes(3, ctypes.byref(out)) == 0 and out.value >= 3 * 64
+    table_bytes = out.value
+    b = _lib.polypic_batch()
+
+    def plan(scenes, n_total=3 * nn, tb=table_bytes, table=FAKE):
+        arr = (_lib.polypic_scene * len(scenes))(*scenes)
+        return lib.polypic_batch_plan(arr, len(scenes), n_total, table, tb, ctypes.byref(b), None)
+
+    ok = [scene(g, 0, 10, 0), scene(g, 10, 0, nn), scene(g, 10, 5, 2 * nn)]
+    assert plan(ok, table=None) == 1
+    assert plan(ok, tb=8) == _lib.POLYPIC_ENOSPACE
+    assert plan([scene(g, 0, 10, 0), scene(g, 11, 5, nn)]) == 1        # gap in particle ranges
+    assert plan([scene(g, 1, 10, 0)]) == 1                             # does not start at 0
+    assert plan([scene(g, 0, -1, 0)]) == 1                             # negative count
+    assert plan([scene(g, 0, 10, 0), scene(g, 10, 5, nn - 1)]) == 1    # overlapping nodes
+    assert plan([scene(g, 0, 10, 0), scene(g, 10, 5, 2 * nn + 1)]) == 1  # beyond n_nodes_total
+    assert plan([scene(grid(2, 36, 36), 0, 10, 0)]) == 1               # bad grid
+    # scene index bits + Morton bits above 32: 1026-node grids need 30 Morton bits
+    big = grid(1026, 1026, 1026)
+    nb = 1026 ** 3
+    many = [scene(big, 0, 0, k * nb) for k in range(8)]      # 3 scene bits + 30 Morton bits
+    assert plan(many, n_total=8 * nb, tb=1 << 20) == _lib.POLYPIC_ENOTSUP
+
+
+def test_batch_calls_reject_unplanned_descriptors():
+    lib = _lib.load()
+    b = _lib.polypic_batch()               # zeroed: no table, wrong seal
+    assert lib.polypic_batch_p2g(ctypes.byref(b), 27, FAKE, None, 1.0, FAKE, None, FAKE, FAKE, 0,
+                                 None, None) == 1
+    b.n_scenes, b.table, b.P, b.N = 1, 0x1000, 10, 100   # filled by hand: the seal does not match
+    assert lib.polypic_batch_p2g(ctypes.byref(b), 27, FAKE, None, 1.0, FAKE, None, FAKE, FAKE, 0,
+                                 None, None) == 1
+    grav = (ctypes.c_float * 3)(0.0, -9.8, 0.0)
+    assert lib.polypic_batch_grid_update(ctypes.byref(b), 1e-4, grav, 1, FAKE, FAKE, FAKE,
+                                         None) == 1
+    assert lib.polypic_batch_g2p(ctypes.byref(b), 27, 1e-4, FAKE, FAKE, None, None, FAKE, None,
+                                 None, None, None, None, None) == 1
+    out = ctypes.c_size_t(0)
+    assert lib.polypic_batch_sort_workspace_bytes(ctypes.byref(b), ctypes.byref(out)) == 1
+    assert lib.polypic_batch_sort(None, FAKE, FAKE, FAKE, FAKE, 1 << 20, None, None) == 1
 
 
 def test_backward_entry_points_reject_bad_arguments():

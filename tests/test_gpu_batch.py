@@ -1,0 +1,220 @@
+"""Batched scenes on the GPU: one launch per phase for many independent scenes.
+
+Every scene of a batch is checked against the oracle run on that scene alone
+(sort bit-exact; grid and coefficients at the normwise parity bar), and the
+batched G2P against the single-scene G2P of the library bit for bit (it is
+deterministic).  The graph-captured step is replayed several times with eager
+work between the replays, and every replay is checked against an eager step
+from the same state.
+"""
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+from oracle import polypic_oracle as O
+from tests.gpu_util import TOL_NORMWISE, dev, host, note, oracle_grid, rel, require_gpu, ulp_ok
+
+pytestmark = pytest.mark.gpu
+
+
+def small_batch(seed=0, n=6, empty_at=None):
+    scenes = W.batched_scenes(seed, n_scenes=n, sizes=(16, 24, 32), p_lo=500, p_hi=2e4)
+    if empty_at is not None:
+        s = scenes[empty_at]
+        s.x = s.x[:, :0].copy()
+        s.coeff = s.coeff[:, :, :0].copy()
+    return scenes
+
+
+def make_set(pp, scenes, n_modes, mass=None):
+    grids = [pp.grid_from_spec(s.grid) for s in scenes]
+    counts = [s.P for s in scenes]
+    x = np.concatenate([s.x for s in scenes], axis=1)
+    c = np.concatenate([s.coeff[:, :n_modes] for s in scenes], axis=2)
+    s0 = scenes[0]
+    return pp.BatchedParticleSet(grids, counts, n_modes, dev(x), dev(c),
+                                 mass=None if mass is None else dev(mass), dt=s0.dt,
+                                 gravity=s0.gravity, bc_layers=s0.bc_layers)
+
+
+def scene_grid_arrays(bs, k, gm, gp, shape):
+    ns = bs.node_slice(k)
+    N = bs.batch.N
+    return gm[ns].reshape(shape), gp.reshape(3, N)[:, ns].reshape((3,) + tuple(shape))
+
+
+def test_batched_sort_is_the_per_scene_stable_sort():
+    pp = require_gpu()
+    scenes = small_batch(0, n=7, empty_at=3)
+    note(f"batch sort: {[s.P for s in scenes]}")
+    bs = make_set(pp, scenes, 4)
+    bs.sort()
+    torch.cuda.synchronize()
+    assert bs.status_flags() == 0
+    perm = host(bs.perm).astype(np.int64)
+    keys = host(bs.keys).view(np.uint32)
+    mbits = bs.batch.desc.morton_bits
+    for k, s in enumerate(scenes):
+        sl = bs.scene_slice(k)
+        if s.P == 0:
+            assert sl.start == sl.stop
+            continue
+        kref, pref = O.sort_keys(O.grid_from_spec(s.grid), s.x)
+        assert np.array_equal(perm[sl] - sl.start, pref.astype(np.int64)), k
+        assert np.array_equal(keys[sl], (np.uint32(k) << np.uint32(mbits)) | kref), k
+
+
+@pytest.mark.parametrize("n_modes", [4, 27])
+def test_batched_p2g_every_configuration(n_modes):
+    pp = require_gpu()
+    scenes = small_batch(1, n=6)
+    rng = np.random.default_rng(5)
+    mass = (1.0 + 0.5 * rng.random(sum(s.P for s in scenes))).astype(np.float32)
+    note(f"batch p2g: n_modes={n_modes} {[s.P for s in scenes]}")
+    bs = make_set(pp, scenes, n_modes, mass=mass)
+    refs = []
+    off = 0
+    for s in scenes:
+        refs.append(O.p2g(O.grid_from_spec(s.grid), s.x, s.coeff, n_modes, mass[off:off + s.P]))
+        off += s.P
+    bs.sort()
+    configs = [(b, sc, pc) for b in (256, 512) for sc, pc in ((0, 0), (1, 0), (2, 1), (2, 4))]
+    try:
+        for cfg in configs:
+            pp.ops.polypic_batch_set_config(n_modes, *cfg)
+            for use_perm in (True, False):
+                bs.p2g(use_perm=use_perm)
+                torch.cuda.synchronize()
+                gm, gp = host(bs.grid_mass), host(bs.grid_mom)
+                for k, (M, Q) in enumerate(refs):
+                    m_k, q_k = scene_grid_arrays(bs, k, gm, gp, M.shape)
+                    assert rel(m_k, M) <= TOL_NORMWISE, (cfg, use_perm, k)
+                    assert rel(q_k, Q) <= TOL_NORMWISE, (cfg, use_perm, k)
+        choice = bs.autotune()
+        assert (choice.block, choice.schedule, choice.per_cu) in \
+            [(b, sc, pc) for b in (256, 512) for sc, pc in ((0, 0), (1, 0), (2, 2), (2, 4), (2, 8))]
+        gm, gp = host(bs.grid_mass), host(bs.grid_mom)
+        for k, (M, Q) in enumerate(refs):
+            assert rel(scene_grid_arrays(bs, k, gm, gp, M.shape)[1], Q) <= TOL_NORMWISE
+    finally:
+        pp.ops.polypic_batch_set_config(n_modes, 256, pp.POLYPIC_SCHED_XCD, 0)
+    assert bs.status_flags() == 0
+
+
+@pytest.mark.parametrize("n_modes", [1, 8, 27])
+def test_batched_step_matches_the_oracle_per_scene(n_modes):
+    pp = require_gpu()
+    scenes = small_batch(2, n=6, empty_at=0)
+    note(f"batch step: n_modes={n_modes} {[s.P for s in scenes]}")
+    bs = make_set(pp, scenes, n_modes)
+    bs.step()
+    torch.cuda.synchronize()
+    assert bs.status_flags() == 0
+    gm, gp = host(bs.grid_mass), host(bs.grid_mom)
+    xs, cs = host(bs.x), host(bs.coeff)
+    for k, s in enumerate(scenes):
+        if s.P == 0:
+            continue
+        ref = O.step(O.grid_from_spec(s.grid), s.x, s.coeff, n_modes, s.dt, s.gravity,
+                     s.bc_layers, sort=True)
+        m_k, q_k = scene_grid_arrays(bs, k, gm, gp, ref["grid_mass"].shape)
+        assert rel(m_k, ref["grid_mass"]) <= TOL_NORMWISE, k
+        assert rel(q_k, ref["grid_mom"]) <= TOL_NORMWISE, k
+        sl = bs.scene_slice(k)
+        assert rel(cs[:, :, sl], ref["coeff"]) <= TOL_NORMWISE, k
+        assert ulp_ok(xs[:, sl], ref["x"], 2, 1.0 + 4.0 / s.grid.cells[0]), k
+
+
+def test_batched_g2p_equals_single_scene_g2p_bitwise():
+    """Same grid velocities, same particles: the batched G2P (with F and mass) writes
+    exactly what the single-scene G2P writes, scene by scene."""
+    pp = require_gpu()
+    scenes = small_batch(3, n=5)
+    note(f"batch g2p vs single: {[s.P for s in scenes]}")
+    bs = make_set(pp, scenes, 27)
+    P, N = bs.P, bs.batch.N
+    rng = np.random.default_rng(9)
+    F = dev((np.eye(3).reshape(9, 1) + 0.01 * rng.standard_normal((9, P))).astype(np.float32))
+    m = dev((1.0 + rng.random(P)).astype(np.float32))
+    bs.sort()
+    bs.p2g()
+    bs.grid_update()
+    c_b = torch.empty(3, 27, P, device="cuda")
+    x_b = torch.empty(3, P, device="cuda")
+    F_b = torch.empty(9, P, device="cuda")
+    m_b = torch.empty(P, device="cuda")
+    pp.ops.polypic_batch_g2p(bs.batch, 27, bs.dt, bs.grid_vel, bs.x, c_b, perm=bs.perm, x_out=x_b,
+                             F_in=F, F_out=F_b, mass_in=m, mass_out=m_b, status_dev=bs.status)
+    gv = bs.grid_vel.reshape(3, N)
+    for k, s in enumerate(scenes):
+        sl, ns = bs.scene_slice(k), bs.node_slice(k)
+        Pk = sl.stop - sl.start
+        g = pp.grid_from_spec(s.grid)
+        perm_k = (bs.perm[sl] - sl.start).contiguous()
+        c_s = torch.empty(3, 27, Pk, device="cuda")
+        x_s = torch.empty(3, Pk, device="cuda")
+        F_s = torch.empty(9, Pk, device="cuda")
+        m_s = torch.empty(Pk, device="cuda")
+        pp.ops.polypic_g2p(g, 27, bs.dt, gv[:, ns].contiguous(), bs.x[:, sl].contiguous(), c_s,
+                           perm=perm_k, x_out=x_s, F_in=F[:, sl].contiguous(), F_out=F_s,
+                           mass_in=m[sl].contiguous(), mass_out=m_s, status_dev=bs.status)
+        torch.cuda.synchronize()
+        assert torch.equal(c_b[:, :, sl], c_s), k
+        assert torch.equal(x_b[:, sl], x_s), k
+        assert torch.equal(F_b[:, sl], F_s), k
+        assert torch.equal(m_b[sl], m_s), k
+    assert bs.status_flags() == 0
+
+
+def test_graph_replays_match_eager_steps():
+    """Capture the two step directions once; replay four steps, each checked against an
+    eager step from the same state on a second set, with eager work between replays."""
+    pp = require_gpu()
+    scenes = small_batch(4, n=6)
+    note(f"batch graph replay: {[s.P for s in scenes]}")
+    bs = make_set(pp, scenes, 27)
+    ref = make_set(pp, scenes, 27)
+    bs.step()                     # one eager step first: the capture starts mid-run
+    torch.cuda.synchronize()
+    bs.capture()
+    for it in range(4):
+        x0, c0 = bs.x.clone(), bs.coeff.clone()
+        ref.x.copy_(x0)
+        ref.coeff.copy_(c0)
+        torch.cuda.synchronize()
+        bs.replay()
+        torch.cuda.synchronize()
+        ref.step()
+        torch.cuda.synchronize()
+        assert rel(host(bs.coeff), host(ref.coeff)) <= TOL_NORMWISE, it
+        assert rel(host(bs.x), host(ref.x)) <= 1e-6, it
+        assert torch.equal(bs.perm, ref.perm), it
+        _ = (bs.x.sum() + bs.coeff.sum()).item()  # eager work between replays
+    assert bs.status_flags() == 0 and ref.status_flags() == 0
+
+
+def test_out_of_range_particle_flags_and_stays_in_its_scene():
+    pp = require_gpu()
+    scenes = small_batch(5, n=4)
+    s = scenes[1]
+    s.x = s.x.copy()
+    s.x[0, 0] = -5.0                              # far outside its grid
+    note("batch out-of-range particle")
+    bs = make_set(pp, scenes, 4)
+    bs.sort()
+    torch.cuda.synchronize()
+    assert bs.status_flags() & 1
+    perm = host(bs.perm)
+    for k in range(len(scenes)):
+        sl = bs.scene_slice(k)
+        assert np.array_equal(np.sort(perm[sl]), np.arange(sl.start, sl.stop)), k
+    # P2G of the other scenes is unaffected
+    bs.p2g()
+    torch.cuda.synchronize()
+    gm, gp = host(bs.grid_mass), host(bs.grid_mom)
+    for k in (0, 2, 3):
+        sc = scenes[k]
+        M, Q = O.p2g(O.grid_from_spec(sc.grid), sc.x, sc.coeff, 4)
+        m_k, q_k = scene_grid_arrays(bs, k, gm, gp, M.shape)
+        assert rel(m_k, M) <= TOL_NORMWISE and rel(q_k, Q) <= TOL_NORMWISE, k

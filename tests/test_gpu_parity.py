@@ -350,23 +350,27 @@ def test_cell_path_with_sparse_and_dense_cells():
 
 @pytest.mark.parametrize("n_modes", [4, 27])
 def test_every_p2g_configuration_and_the_autotuner(n_modes):
-    """Each P2G launch configuration (cell runs; FP64 bricks with 256 or 512 threads)
-    matches the oracle; the autotuner returns one of them and leaves a valid result."""
+    """Each P2G launch configuration (cell runs; FP64 bricks with 256 or 512 threads, in
+    index order, XCD order or persistent) matches the oracle; the autotuner returns one
+    of them and leaves a valid result."""
     pp = require_gpu()
     s = W.config0(4)
     pp_, g, ps = particle_set(s, n_modes)
     ps.sort()
     M_ref, Q_ref = O.p2g(oracle_grid(g), s.x, s.coeff, n_modes)
     try:
-        for path, block in [(1, 512), (0, 256), (0, 512)]:
-            pp.polypic_set_p2g_config(n_modes, path, block)
+        configs = [(1, 512, 0, 0)] + [(0, b, sc, pc) for b in (256, 512)
+                                      for sc, pc in ((0, 0), (1, 0), (2, 1), (2, 4))]
+        for cfg in configs:
+            pp.polypic_set_p2g_config(n_modes, *cfg)
             ps.p2g()
             torch.cuda.synchronize()
-            assert rel(host(ps.grid_mass).reshape(M_ref.shape), M_ref) <= TOL_NORMWISE, (path, block)
-            assert rel(host(ps.grid_mom).reshape(Q_ref.shape), Q_ref) <= TOL_NORMWISE, (path, block)
-        path, block = ps.autotune()
-        assert (path, block) in [(1, 512), (0, 256), (0, 512)]
-        assert pp.polypic_get_p2g_config(n_modes) == (path, block)
+            assert rel(host(ps.grid_mass).reshape(M_ref.shape), M_ref) <= TOL_NORMWISE, cfg
+            assert rel(host(ps.grid_mom).reshape(Q_ref.shape), Q_ref) <= TOL_NORMWISE, cfg
+        choice = ps.autotune()
+        assert (choice.path, choice.block) in [(1, 512), (0, 256), (0, 512)]
+        assert choice.schedule in (pp.POLYPIC_SCHED_LINEAR, pp.POLYPIC_SCHED_XCD)
+        assert pp.polypic_get_p2g_config(n_modes) == choice
         assert rel(host(ps.grid_mom).reshape(Q_ref.shape), Q_ref) <= TOL_NORMWISE
     finally:
         pp.polypic_set_p2g_config(n_modes, -1, 512)

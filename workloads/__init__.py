@@ -228,15 +228,19 @@ def random_scene(seed: int, n: int, P: int, n_lo: int = 2, ppc_hint: int = 8,
 
 
 def batched_scenes(seed: int = 0, n_scenes: int = 64,
-                   sizes=(64, 96, 128), p_lo: float = 1e4, p_hi: float = 2e6) -> List[Scene]:
+                   sizes=(64, 96, 128), p_lo: float = 1e4, p_hi: float = 2e6,
+                   coefficients: bool = True) -> List[Scene]:
     """Many independent scenes with log-uniform particle counts at 8 ppc in random blocks.
 
     For each scene: n from ``sizes``; target particle count log-uniform in
     [p_lo, p_hi]; a block of about count/8 cells with aspect ratios in [1/2, 2],
     placed uniformly at random inside the domain (n is redrawn if it does not fit).
-    The realised count is 8 * (block volume).
+    The realised count is 8 * (block volume).  With coefficients=False the
+    coefficient arrays are left empty (shape (3, 27, 0)) for callers that draw
+    them elsewhere; positions are the same either way.
     """
     rng = np.random.default_rng(seed)
+    crng = np.random.default_rng(20_000 + seed)   # coefficients: a stream of their own
     scenes = []
     for s in range(n_scenes):
         target = math.exp(rng.uniform(math.log(p_lo), math.log(p_hi)))
@@ -253,7 +257,8 @@ def batched_scenes(seed: int = 0, n_scenes: int = 64,
         g = cubic_grid(n)
         lo = [int(rng.integers(0, n - d + 1)) for d in dims]
         x = jittered_block(rng, g, lo, dims, (2, 2, 2))
-        c = _coefficients(rng, x.shape[1], 1.0, 0.1)
+        c = (_coefficients(crng, x.shape[1], 1.0, 0.1) if coefficients
+             else np.zeros((3, N_MODES_MAX, 0), np.float32))
         scenes.append(Scene(f"batch{s}_{n}cube_{x.shape[1]}", g, x, c, None, 1.0,
                             dt=1e-4, bc_layers=1, n_steps=10))
     return scenes
