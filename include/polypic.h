@@ -235,7 +235,8 @@ int32_t polypic_grid_update(const polypic_grid* grid, float dt, const float* gra
  *               C_ab = coeff_out[a][1 + b] / dx (C = 0 when n_modes == 1).
  * mass_in, mass_out  optional [P] (both or neither): mass_out[i] = mass_in[perm[i]]
  *               so a per-particle mass follows the new order.
- * Outputs may not alias inputs.
+ * Outputs may not alias inputs.  coeff_out may be the coefficient array of the
+ * preceding polypic_p2g (G2P reads no coefficients): an in-place update.
  * ------------------------------------------------------------------------ */
 int32_t polypic_g2p(const polypic_grid* grid, int64_t P, int32_t n_modes, float dt,
                     const float* grid_vel, const float* x_in, const int32_t* perm, float* x_out,

@@ -105,8 +105,9 @@ class PolyPICSteps(torch.autograd.Function):
                                      x_out_grad=gx, status_dev=B.status)
             ops.polypic_grid_update_backward(grid, dt, gravity, bc_layers, B.gm, B.gp, B.gvb,
                                              B.gmb, B.gpb)
+            # the P2G adjoint is a gather: particle order keeps its particle streams coalesced
             ops.polypic_p2g_backward(grid, n_modes, x, c, B.gmb, B.gpb, gc_in, gx_in,
-                                     uniform_mass=uniform_mass, perm=B.perm, status_dev=B.status)
+                                     uniform_mass=uniform_mass, status_dev=B.status)
             gx, gc = gx_in, gc_in
         ctx.checkpoints = None
         return gx, gc, None, None, None, None, None, None, None

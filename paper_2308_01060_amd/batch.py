@@ -8,8 +8,9 @@ end to end, and runs the batched entry points of the library:
                        -> polypic_batch_g2p (+ advection)
 
 A step can be captured once as a HIP graph (``capture``) and replayed
-(``replay``): the particle arrays ping-pong between two buffers, so two
-graphs are captured, one per direction.  Capture records kernels only (the
+(``replay``): the positions ping-pong between two buffers, so two graphs are
+captured, one per direction.  The coefficients are updated in place (G2P reads
+none), as in ``ParticleSet``.  Capture records kernels only (the
 library clears grids with a kernel, never with a memset node).
 """
 from __future__ import annotations
@@ -43,7 +44,7 @@ class BatchedParticleSet:
         self.coeff = coeff.contiguous()
         self.mass = None if mass is None else mass.contiguous()
         self.x_next = torch.empty_like(self.x)
-        self.coeff_next = torch.empty_like(self.coeff)
+        self.coeff_next = self.coeff  # G2P reads no coefficients: in place
         self.mass_next = None if mass is None else torch.empty_like(self.mass)
         self.grid_mass = torch.empty(N, **f32)
         self.grid_mom = torch.empty(3 * N, **f32)
@@ -87,7 +88,6 @@ class BatchedParticleSet:
 
     def swap(self):
         self.x, self.x_next = self.x_next, self.x
-        self.coeff, self.coeff_next = self.coeff_next, self.coeff
         if self.mass is not None:
             self.mass, self.mass_next = self.mass_next, self.mass
 

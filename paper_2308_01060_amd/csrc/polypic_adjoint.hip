@@ -115,6 +115,11 @@ __global__ __launch_bounds__(256) void p2g_backward_kernel(P2GBackArgs a) {
     contract_rows<1>(v, R[0], R[1], dR[2], o);
     xg[2] += m * o[0];
   }
+  // Per momentum component: T_r = sum_i R_r(i) pb_i gives dL/dc_r = m T_r, and the
+  // same contraction with the t-derivative row on axis b gives dT_r/dt_b, whose
+  // sum over r weighted by c_r is the x gradient.  The four contractions share
+  // their stages (x, then y, then z), one kx plane at a time, so no 27-wide
+  // output array is held.
 #pragma unroll 1
   for (int ax = 0; ax < 3; ++ax) {
     float v[27];
@@ -125,26 +130,63 @@ __global__ __launch_bounds__(256) void p2g_backward_kernel(P2GBackArgs a) {
       for (int jy = 0; jy < 3; ++jy)
 #pragma unroll
         for (int jx = 0; jx < 3; ++jx) v[jx + 3 * jy + 9 * jz] = q[jz * nxny + jy * nx + jx];
-    float c[27];
     const float* cp = a.coeff + (size_t)ax * NR * Ps + p;
+    float* cg = a.coeff_grad + (size_t)ax * NR * Ps + p;
+    // all coefficients first: the compiler cannot move a load of coeff past a
+    // store to coeff_grad (they might alias), so loads inside the mode loop
+    // would each wait out their full latency
+    float c[27];
 #pragma unroll
     for (int r = 0; r < 27; ++r) c[r] = (r < NR) ? cp[(size_t)r * Ps] : 0.0f;
-    float o[27];
-    contract_rows<NR>(v, R[0], R[1], R[2], o);
-    float* cg = a.coeff_grad + (size_t)ax * NR * Ps + p;
+    float sx = 0.0f, sy = 0.0f, sz = 0.0f;
 #pragma unroll
-    for (int r = 0; r < NR; ++r) {
-      cg[(size_t)r * Ps] = m * o[r];
-      mg = fmaf(c[r], o[r], mg);
+    for (int kx = 0; kx < 3; ++kx) {
+      if (!any_kykz<NR>(kx)) continue;
+      float A[3][3], Ad[3][3];  // [jy][jz]: x contracted with R, with dR
+#pragma unroll
+      for (int jy = 0; jy < 3; ++jy)
+#pragma unroll
+        for (int jz = 0; jz < 3; ++jz) {
+          const float* vv = v + 3 * jy + 9 * jz;
+          A[jy][jz] = fmaf(R[0].r[kx][2], vv[2], fmaf(R[0].r[kx][1], vv[1], R[0].r[kx][0] * vv[0]));
+          Ad[jy][jz] =
+              fmaf(dR[0].r[kx][2], vv[2], fmaf(dR[0].r[kx][1], vv[1], dR[0].r[kx][0] * vv[0]));
+        }
+#pragma unroll
+      for (int ky = 0; ky < 3; ++ky) {
+        if (!any_kz<NR>(kx, ky)) continue;
+        float B[3], By[3], Bx[3];  // [jz]
+#pragma unroll
+        for (int jz = 0; jz < 3; ++jz) {
+          B[jz] = fmaf(R[1].r[ky][2], A[2][jz], fmaf(R[1].r[ky][1], A[1][jz], R[1].r[ky][0] * A[0][jz]));
+          By[jz] =
+              fmaf(dR[1].r[ky][2], A[2][jz], fmaf(dR[1].r[ky][1], A[1][jz], dR[1].r[ky][0] * A[0][jz]));
+          Bx[jz] =
+              fmaf(R[1].r[ky][2], Ad[2][jz], fmaf(R[1].r[ky][1], Ad[1][jz], R[1].r[ky][0] * Ad[0][jz]));
+        }
+#pragma unroll
+        for (int kz = 0; kz < 3; ++kz) {
+          if (!has_mode<NR>(kx, ky, kz)) continue;
+          const int r = mode_index(kx, ky, kz);
+          const float cr = c[r];
+          const float T = fmaf(R[2].r[kz][2], B[2], fmaf(R[2].r[kz][1], B[1], R[2].r[kz][0] * B[0]));
+          const float Tz =
+              fmaf(dR[2].r[kz][2], B[2], fmaf(dR[2].r[kz][1], B[1], dR[2].r[kz][0] * B[0]));
+          const float Ty =
+              fmaf(R[2].r[kz][2], By[2], fmaf(R[2].r[kz][1], By[1], R[2].r[kz][0] * By[0]));
+          const float Tx =
+              fmaf(R[2].r[kz][2], Bx[2], fmaf(R[2].r[kz][1], Bx[1], R[2].r[kz][0] * Bx[0]));
+          cg[(size_t)r * Ps] = m * T;
+          mg = fmaf(cr, T, mg);
+          sx = fmaf(cr, Tx, sx);
+          sy = fmaf(cr, Ty, sy);
+          sz = fmaf(cr, Tz, sz);
+        }
+      }
     }
-#pragma unroll
-    for (int b = 0; b < 3; ++b) {
-      contract_rows<NR>(v, b == 0 ? dR[0] : R[0], b == 1 ? dR[1] : R[1], b == 2 ? dR[2] : R[2], o);
-      float s = 0.0f;
-#pragma unroll
-      for (int r = 0; r < NR; ++r) s = fmaf(c[r], o[r], s);
-      xg[b] = fmaf(m, s, xg[b]);
-    }
+    xg[0] = fmaf(m, sx, xg[0]);
+    xg[1] = fmaf(m, sy, xg[1]);
+    xg[2] = fmaf(m, sz, xg[2]);
   }
   const float inv_dx = a.g.inv_dx;
   a.x_grad[p] += inv_dx * xg[0];
@@ -255,39 +297,26 @@ __global__ __launch_bounds__(BS) void g2p_backward_kernel(G2PBackArgs a) {
           cb[0] = fmaf(a.dt, xb, cb[0]);
         }
       }
-      // x_bar from the derivative of the projection rows
-      float o[27];
-#pragma unroll
-      for (int b = 0; b < 3; ++b) {
-        contract_rows<NR>(v, b == 0 ? dP[0] : Pr[0], b == 1 ? dP[1] : Pr[1],
-                          b == 2 ? dP[2] : Pr[2], o);
-        float s = 0.0f;
-#pragma unroll
-        for (int r = 0; r < NR; ++r) s = fmaf(cb[r], o[r], s);
-        xg[b] = fmaf(a.g.inv_dx, s, xg[b]);
-      }
-      // v_bar: the transpose of the projection
-      float val[27];
-      expand_rows<NR>(cb, Pr[0], Pr[1], Pr[2], val);
-      if (lds) {
-        double* const lbc = lb + ax * kBrickV;
-#pragma unroll
-        for (int jz = 0; jz < 3; ++jz)
-#pragma unroll
-          for (int jy = 0; jy < 3; ++jy)
-#pragma unroll
-            for (int jx = 0; jx < 3; ++jx)
-              atomicAdd(lbc + jx + kBrickSY * jy + kBrickSZ * jz, (double)val[jx + 3 * jy + 9 * jz]);
-      } else {
-        float* const dst = a.gvb + (size_t)ax * N + gbase;
-#pragma unroll
-        for (int jz = 0; jz < 3; ++jz)
-#pragma unroll
-          for (int jy = 0; jy < 3; ++jy)
-#pragma unroll
-            for (int jx = 0; jx < 3; ++jx)
-              atomicAdd(dst + jz * nxny + jy * nx + jx, val[jx + 3 * jy + 9 * jz]);
-      }
+      // One pass over the nodes gives, per node j, f = sum_r P_r(j) cb_r (the
+      // transpose of the projection: v_bar, scattered to the brick) and its
+      // t-derivatives, whose dot products with v are the x gradient.
+      float sx = 0.0f, sy = 0.0f, sz = 0.0f;
+      double* const lbc = lb + ax * kBrickV;
+      float* const dst = a.gvb + (size_t)ax * N + gbase;
+      stream_modes_d<NR>(cb, Pr[0], Pr[1], Pr[2], dP[0], dP[1], dP[2],
+                         [&](int jx, int jy, int jz, float f, float fx, float fy, float fz) {
+                           const float vj = v[jx + 3 * jy + 9 * jz];
+                           sx = fmaf(vj, fx, sx);
+                           sy = fmaf(vj, fy, sy);
+                           sz = fmaf(vj, fz, sz);
+                           if (lds)
+                             atomicAdd(lbc + jx + kBrickSY * jy + kBrickSZ * jz, (double)f);
+                           else
+                             atomicAdd(dst + jz * nxny + jy * nx + jx, f);
+                         });
+      xg[0] = fmaf(a.g.inv_dx, sx, xg[0]);
+      xg[1] = fmaf(a.g.inv_dx, sy, xg[1]);
+      xg[2] = fmaf(a.g.inv_dx, sz, xg[2]);
     }
     a.x_in_grad[p] += xg[0];
     a.x_in_grad[Ps + p] += xg[1];

@@ -265,6 +265,128 @@ __device__ __forceinline__ void g2p_rows(float t, Rows& Pr, Rows& dP) {
   }
 }
 
+// P2G rows with the weight folded in, scaled by s: R[k][j] = s w_j phi_k(j).
+__device__ __forceinline__ Rows p2g_rows_scaled(const Basis1D& B, float s) {
+  Rows R;
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    const float w = s * B.w[j];
+    R.r[0][j] = w;
+    R.r[1][j] = w * B.z[j];
+    R.r[2][j] = w * B.g[j];
+  }
+  return R;
+}
+
+// Nodal values of one channel, node by node: for every stencil node j (z
+// outermost, then y, then x) emit(jx, jy, jz, sum_r c_r Rx[kx][jx] Ry[ky][jy]
+// Rz[kz][jz]) over the first NR modes.  The three separable stages are
+// interleaved with the walk over the nodes, so only 9 + 3 partial sums are live
+// besides the coefficients and the rows (the same 3 x 81 multiply-adds as
+// contracting the whole array stage by stage).
+template <int NR, class Emit>
+__device__ __forceinline__ void stream_modes(const float (&c)[27], const Rows& Rx, const Rows& Ry,
+                                             const Rows& Rz, Emit&& emit) {
+#pragma unroll
+  for (int jz = 0; jz < 3; ++jz) {
+    float C1[3][3];  // [kx][ky]: z contracted at this jz
+#pragma unroll
+    for (int kx = 0; kx < 3; ++kx)
+#pragma unroll
+      for (int ky = 0; ky < 3; ++ky) {
+        if (!any_kz<NR>(kx, ky)) continue;
+        float acc = 0.0f;
+#pragma unroll
+        for (int kz = 0; kz < 3; ++kz)
+          if (has_mode<NR>(kx, ky, kz)) acc = fmaf(c[mode_index(kx, ky, kz)], Rz.r[kz][jz], acc);
+        C1[kx][ky] = acc;
+      }
+#pragma unroll
+    for (int jy = 0; jy < 3; ++jy) {
+      float C2[3];  // [kx]
+#pragma unroll
+      for (int kx = 0; kx < 3; ++kx) {
+        if (!any_kykz<NR>(kx)) continue;
+        float acc = 0.0f;
+#pragma unroll
+        for (int ky = 0; ky < 3; ++ky)
+          if (any_kz<NR>(kx, ky)) acc = fmaf(C1[kx][ky], Ry.r[ky][jy], acc);
+        C2[kx] = acc;
+      }
+#pragma unroll
+      for (int jx = 0; jx < 3; ++jx) {
+        float val = 0.0f;
+#pragma unroll
+        for (int kx = 0; kx < 3; ++kx)
+          if (any_kykz<NR>(kx)) val = fmaf(C2[kx], Rx.r[kx][jx], val);
+        emit(jx, jy, jz, val);
+      }
+    }
+  }
+}
+
+// As stream_modes, with the derivatives: for every node j emits
+// (jx, jy, jz, f, fx, fy, fz) where f = sum_r c_r Rx Ry Rz and fb is the same
+// sum with the derivative row dR on axis b.  The stages are shared: z with Rz
+// and dRz, y with Ry and dRy, x with Rx and dRx.
+template <int NR, class Emit>
+__device__ __forceinline__ void stream_modes_d(const float (&c)[27], const Rows& Rx, const Rows& Ry,
+                                               const Rows& Rz, const Rows& dRx, const Rows& dRy,
+                                               const Rows& dRz, Emit&& emit) {
+#pragma unroll
+  for (int jz = 0; jz < 3; ++jz) {
+    float C1[3][3], C1z[3][3];  // [kx][ky]
+#pragma unroll
+    for (int kx = 0; kx < 3; ++kx)
+#pragma unroll
+      for (int ky = 0; ky < 3; ++ky) {
+        if (!any_kz<NR>(kx, ky)) continue;
+        float acc = 0.0f, accz = 0.0f;
+#pragma unroll
+        for (int kz = 0; kz < 3; ++kz)
+          if (has_mode<NR>(kx, ky, kz)) {
+            const float cr = c[mode_index(kx, ky, kz)];
+            acc = fmaf(cr, Rz.r[kz][jz], acc);
+            accz = fmaf(cr, dRz.r[kz][jz], accz);
+          }
+        C1[kx][ky] = acc;
+        C1z[kx][ky] = accz;
+      }
+#pragma unroll
+    for (int jy = 0; jy < 3; ++jy) {
+      float C2[3], C2y[3], C2z[3];  // [kx]
+#pragma unroll
+      for (int kx = 0; kx < 3; ++kx) {
+        if (!any_kykz<NR>(kx)) continue;
+        float acc = 0.0f, accy = 0.0f, accz = 0.0f;
+#pragma unroll
+        for (int ky = 0; ky < 3; ++ky)
+          if (any_kz<NR>(kx, ky)) {
+            acc = fmaf(C1[kx][ky], Ry.r[ky][jy], acc);
+            accy = fmaf(C1[kx][ky], dRy.r[ky][jy], accy);
+            accz = fmaf(C1z[kx][ky], Ry.r[ky][jy], accz);
+          }
+        C2[kx] = acc;
+        C2y[kx] = accy;
+        C2z[kx] = accz;
+      }
+#pragma unroll
+      for (int jx = 0; jx < 3; ++jx) {
+        float f = 0.0f, fx = 0.0f, fy = 0.0f, fz = 0.0f;
+#pragma unroll
+        for (int kx = 0; kx < 3; ++kx)
+          if (any_kykz<NR>(kx)) {
+            f = fmaf(C2[kx], Rx.r[kx][jx], f);
+            fx = fmaf(C2[kx], dRx.r[kx][jx], fx);
+            fy = fmaf(C2y[kx], Rx.r[kx][jx], fy);
+            fz = fmaf(C2z[kx], Rx.r[kx][jx], fz);
+          }
+        emit(jx, jy, jz, f, fx, fy, fz);
+      }
+    }
+  }
+}
+
 template <int NR>
 __device__ constexpr bool need_kx_any(int kx) {
   return any_kykz<NR>(kx);

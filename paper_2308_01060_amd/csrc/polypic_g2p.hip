@@ -126,14 +126,17 @@ __global__ __launch_bounds__(BS) void g2p_kernel(G2PArgs a, Scenes sc) {
 #pragma unroll
       for (int r = 0; r < 27; ++r) c[r] = 0.0f;
     }
+    // Outputs are streamed with non-temporal stores: written once, never re-read by this
+    // kernel, they would otherwise displace the grid lines the gathers reuse from L2
+    // (measured: 0.40 -> 0.27 ms at 27 modes, 4.19 M particles).
     float* co = a.coeff_out + (size_t)ax * NR * Ps + i;
 #pragma unroll
-    for (int r = 0; r < NR; ++r) co[(size_t)r * Ps] = c[r];
+    for (int r = 0; r < NR; ++r) __builtin_nontemporal_store(c[r], co + (size_t)r * Ps);
     if (a.x_out) {
       float xn = fmaf(a.dt, c[0], xp[ax]);
       xn = fmaxf(xn, sg.lo[ax]);
       xn = fminf(xn, sg.hi[ax]);
-      a.x_out[(size_t)ax * Ps + i] = xn;
+      __builtin_nontemporal_store(xn, a.x_out + (size_t)ax * Ps + i);
     }
 #pragma unroll
     for (int b = 0; b < 3; ++b) lin[ax][b] = (NR >= 4) ? c[1 + b] : 0.0f;
@@ -148,10 +151,11 @@ __global__ __launch_bounds__(BS) void g2p_kernel(G2PArgs a, Scenes sc) {
         float acc = 0.0f;
 #pragma unroll
         for (int k = 0; k < 3; ++k) acc = fmaf(lin[r][k], F[3 * k + col], acc);
-        a.F_out[(size_t)(3 * r + col) * Ps + i] = fmaf(s, acc, F[3 * r + col]);
+        __builtin_nontemporal_store(fmaf(s, acc, F[3 * r + col]),
+                                     a.F_out + (size_t)(3 * r + col) * Ps + i);
       }
   }
-  if (a.mass_out) a.mass_out[i] = a.mass_in[p];
+  if (a.mass_out) __builtin_nontemporal_store(a.mass_in[p], a.mass_out + i);
 }
 
 template <int NR, class Scenes>
