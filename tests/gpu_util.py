@@ -60,12 +60,21 @@ def sample_nodes(gm: np.ndarray, k: int, seed: int) -> np.ndarray:
 
 
 def particles_touching(g: O.Grid, x: np.ndarray, nodes_flat: np.ndarray) -> np.ndarray:
-    """Indices of the particles whose 3x3x3 stencil contains any of the given nodes."""
+    """Indices of the particles whose 3x3x3 stencil contains any of the given nodes.
+
+    A node n is in the stencil of base node b iff n - 2 <= b <= n per axis, so the
+    candidate base nodes of the sample are enumerated and matched in one pass.
+    """
     b, _ = O.stencil_base(g, x)
-    iz, rem = np.divmod(nodes_flat, g.nx * g.ny)
+    iz, rem = np.divmod(np.asarray(nodes_flat, np.int64), g.nx * g.ny)
     iy, ix = np.divmod(rem, g.nx)
-    keep = np.zeros(x.shape[1], bool)
-    for nx_, ny_, nz_ in zip(ix, iy, iz):
-        keep |= ((b[0] >= nx_ - 2) & (b[0] <= nx_) & (b[1] >= ny_ - 2) & (b[1] <= ny_)
-                 & (b[2] >= nz_ - 2) & (b[2] <= nz_))
-    return np.flatnonzero(keep)
+    cand = []
+    for dz in range(3):
+        for dy in range(3):
+            for dx in range(3):
+                bx, by, bz = ix - dx, iy - dy, iz - dz
+                ok = (bx >= 0) & (by >= 0) & (bz >= 0)
+                cand.append((bz[ok] * g.ny + by[ok]) * g.nx + bx[ok])
+    cand = np.unique(np.concatenate(cand))
+    flat_b = (b[2].astype(np.int64) * g.ny + b[1]) * g.nx + b[0]
+    return np.flatnonzero(np.isin(flat_b, cand))
