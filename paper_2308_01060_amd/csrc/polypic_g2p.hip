@@ -83,7 +83,13 @@ __global__ __launch_bounds__(BS) void g2p_kernel(G2PArgs a, Scenes sc) {
   const int64_t i0 = cr.begin * BS;
   const int64_t i = i0 + threadIdx.x;
   if (i >= a.P) return;
-  const SceneGrid sg = sc.grid(sc.of(i, sc.first(i0)));
+  const int s0 = sc.first(i0);  // uniform over the workgroup
+  const int s = sc.of(i, s0);
+  // one wave-uniform lookup unless the wavefront straddles a scene boundary
+  SceneGrid sg = sc.grid(s0);
+  if constexpr (Scenes::kMany) {
+    if (__ballot(s != s0) != 0ull) sg = sc.grid(s);
+  }
   const size_t Ps = (size_t)a.P;
   const int nx = sg.nx, ny = sg.ny;
   // a caller permutation is clamped into [0, P): a bad one gives wrong results, never a fault

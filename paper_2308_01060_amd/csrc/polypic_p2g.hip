@@ -59,6 +59,9 @@ __global__ __launch_bounds__(BS, BS == 256 ? 4 : 2) void p2g_brick_kernel(P2GArg
   __shared__ int seg_of[BS];        // by processing slot
   __shared__ uint64_t seg_tile[kBrickKMAX];
   __shared__ int wave_heads[NW];
+  // grid of each brick's scene (batches only; one scene folds to constants)
+  __shared__ int seg_dims[kBrickKMAX][3];
+  __shared__ int64_t seg_node_off[kBrickKMAX];
 
   const int tid = threadIdx.x;
   const int lane = tid & (kWave - 1);
@@ -77,7 +80,11 @@ __global__ __launch_bounds__(BS, BS == 256 ? 4 : 2) void p2g_brick_kernel(P2GArg
     const int64_t i = i0 + slot;
     bool valid = i < a.P;
     const int s = valid ? sc.of(i, s0) : s0;
-    const SceneGrid sg = sc.grid(s);
+    // one wave-uniform lookup unless the wavefront straddles a scene boundary
+    SceneGrid sg = sc.grid(s0);
+    if constexpr (Scenes::kMany) {
+      if (__ballot(s != s0) != 0ull) sg = sc.grid(s);
+    }
     int p = 0;
     // a caller permutation is clamped into [0, P) so that a bad one cannot read
     // out of bounds (results are then wrong, never a fault)
@@ -119,7 +126,16 @@ __global__ __launch_bounds__(BS, BS == 256 ? 4 : 2) void p2g_brick_kernel(P2GArg
       for (int w = 0; w < NW; ++w) pre += (w < wv) ? wave_heads[w] : 0;
       const int sgi = pre + lanes_below(hb) + (head ? 1 : 0) - 1;
       seg_of[tid] = sgi;
-      if (head && sgi < kBrickKMAX) seg_tile[sgi] = tt;
+      if (head && sgi < kBrickKMAX) {
+        seg_tile[sgi] = tt;
+        if constexpr (Scenes::kMany) {
+          const SceneGrid fg = sc.grid(s0 + (int)(tt >> 32));
+          seg_dims[sgi][0] = fg.nx;
+          seg_dims[sgi][1] = fg.ny;
+          seg_dims[sgi][2] = fg.nz;
+          seg_node_off[sgi] = fg.node_off;
+        }
+      }
     }
     __syncthreads();
     int nseg = 0;
@@ -182,15 +198,21 @@ __global__ __launch_bounds__(BS, BS == 256 ? 4 : 2) void p2g_brick_kernel(P2GArg
       if (lx > kBrickT + 1 || ly > kBrickT + 1) continue;  // padding
       const float v = (float)brick[k];
       if (v == 0.0f) continue;
-      const uint64_t tl = seg_tile[sb];
-      const SceneGrid fg = sc.grid(s0 + (int)(tl >> 32));
-      const uint32_t tc = (uint32_t)tl;
+      const uint32_t tc = (uint32_t)seg_tile[sb];
+      int fnx = sg.nx, fny = sg.ny, fnz = sg.nz;  // one scene: constants
+      int64_t foff = 0;
+      if constexpr (Scenes::kMany) {
+        fnx = seg_dims[sb][0];
+        fny = seg_dims[sb][1];
+        fnz = seg_dims[sb][2];
+        foff = seg_node_off[sb];
+      }
       const int gx = (int)(tc & 1023u) * kBrickT + lx;
       const int gy = (int)((tc >> 10) & 1023u) * kBrickT + ly;
       const int gz = (int)(tc >> 20) * kBrickT + lz;
-      if (gx < fg.nx && gy < fg.ny && gz < fg.nz) {
+      if (gx < fnx && gy < fny && gz < fnz) {
         float* const d = ch == 0 ? a.gm : ch == 1 ? a.gp0 : ch == 2 ? a.gp1 : a.gp2;
-        atomicAdd(d + fg.node_off + ((int64_t)(gz * fg.ny + gy) * fg.nx + gx), v);
+        atomicAdd(d + foff + ((int64_t)(gz * fny + gy) * fnx + gx), v);
       }
     }
     __syncthreads();  // the next chunk reuses tile_of, seg_tile and the bricks

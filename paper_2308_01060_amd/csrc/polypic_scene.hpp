@@ -41,6 +41,7 @@ struct SceneGrid {
 };
 
 struct OneScene {
+  static constexpr bool kMany = false;
   SceneGrid sg;
   __device__ __forceinline__ int first(int64_t) const { return 0; }
   __device__ __forceinline__ int of(int64_t, int) const { return 0; }
@@ -48,6 +49,7 @@ struct OneScene {
 };
 
 struct SceneTable {
+  static constexpr bool kMany = true;
   const SceneDev* t;
   int n;
   // Scene holding slot i (0 <= i < total particles): the last scene whose

@@ -28,8 +28,12 @@ __global__ __launch_bounds__(256) void sort_keys_kernel(Scenes sc, int mbits, in
   const int64_t i0 = (int64_t)blockIdx.x * blockDim.x;
   const int64_t i = i0 + threadIdx.x;
   if (i >= P) return;
-  const int s = sc.of(i, sc.first(i0));
-  const SceneGrid g = sc.grid(s);
+  const int s0 = sc.first(i0);  // uniform over the workgroup
+  const int s = sc.of(i, s0);
+  SceneGrid g = sc.grid(s0);
+  if constexpr (Scenes::kMany) {
+    if (__ballot(s != s0) != 0ull) g = sc.grid(s);
+  }
   const size_t Ps = (size_t)P;
   int b0, b1, b2;
   float t0, t1, t2;
