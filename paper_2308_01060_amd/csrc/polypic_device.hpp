@@ -514,6 +514,14 @@ __device__ __forceinline__ uint32_t morton3(int bx, int by, int bz) {
          (spread_bits3((uint32_t)bz) << 2);
 }
 
+// DPP exchanges within a quad of lanes: with lane ^ 1, and with lane ^ 2
+__device__ __forceinline__ int pair_swap_i(int v) {
+  return __builtin_amdgcn_mov_dpp(v, 0xB1, 0xF, 0xF, false);  // quad_perm [1, 0, 3, 2]
+}
+__device__ __forceinline__ int quad_swap_i(int v) {
+  return __builtin_amdgcn_mov_dpp(v, 0x4E, 0xF, 0xF, false);  // quad_perm [2, 3, 0, 1]
+}
+
 // popcount of the bits of `mask` below this lane
 __device__ __forceinline__ int lanes_below(unsigned long long mask) {
   return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),

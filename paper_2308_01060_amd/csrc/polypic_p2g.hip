@@ -66,10 +66,14 @@ __global__ __launch_bounds__(BS, BS == 256 ? 4 : 2) void p2g_brick_kernel(P2GArg
   const int tid = threadIdx.x;
   const int lane = tid & (kWave - 1);
   const int wv = tid / kWave;
-  // Slot of this thread's particle: the lanes of a wavefront take every NW-th
-  // slot, so that in sorted order (about 8 particles per cell) they sit in
-  // different cells and their brick atomics do not collide.
-  const int slot = lane * NW + wv;
+  // Slot of this thread's particle.  Lane groups of G (4 at 8 or more modes,
+  // else 2) take G consecutive slots, which in sorted order (about 8 particles
+  // per cell) usually share a cell, hence a base node: the group adds its nodal
+  // values across lanes (DPP) and one lane does the atomic.  Groups of a
+  // wavefront take every NW-th group of slots, so that they sit in different
+  // cells and their brick atomics do not collide.
+  constexpr int LG = NR >= 8 ? 2 : 1;  // log2 G
+  const int slot = (((lane >> LG) * NW + wv) << LG) | (lane & ((1 << LG) - 1));
   const size_t Ps = (size_t)a.P;
   const int64_t n_chunks = (a.P + BS - 1) / BS;
   const ChunkRange cr = block_chunks(a.sched, n_chunks);
@@ -143,8 +147,23 @@ __global__ __launch_bounds__(BS, BS == 256 ? 4 : 2) void p2g_brick_kernel(P2GArg
     for (int w = 0; w < NW; ++w) nseg += wave_heads[w];
     const int seg = seg_of[slot];
 
-    if (valid) {
-      const float m = a.mass ? a.mass[p] : a.uniform_mass;
+    // Lanes that share this lane's segment and base node: the pair (lane ^ 1)
+    // and, with G = 4, the whole quad.  Every lane runs the evaluation below
+    // (an invalid one with zero mass), since the DPP exchanges need them all.
+    // (All exchanges run unconditionally: a DPP read from a lane that did not
+    // execute it would return an undefined value.)
+    const int mykey = valid ? ((b2 * 1024 + b1) * 1024 + b0) : -1 - lane;
+    const int pair_key = pair_swap_i(mykey), pair_seg = pair_swap_i(seg);
+    const bool pair = mykey == pair_key && seg == pair_seg;
+    bool quad = false;
+    if constexpr (LG == 2) {
+      const int quad_pair = quad_swap_i((int)pair), quad_key = quad_swap_i(mykey);
+      const int quad_seg = quad_swap_i(seg);
+      quad = pair && quad_pair != 0 && mykey == quad_key && seg == quad_seg;
+    }
+    const bool emit = valid && (quad ? (lane & 3) == 0 : (!pair || (lane & 1) == 0));
+    {
+      const float m = valid ? (a.mass ? a.mass[p] : a.uniform_mass) : 0.0f;
       // rows s w_j phi_k(j) per axis; the particle mass rides on the x rows
       const Rows Rx = p2g_rows_scaled(basis_p2g(t0), m);
       const Rows Ry = p2g_rows_scaled(basis_p2g(t1), 1.0f);
@@ -153,7 +172,7 @@ __global__ __launch_bounds__(BS, BS == 256 ? 4 : 2) void p2g_brick_kernel(P2GArg
       const int nx = sg.nx, ny = sg.ny;
       const int lbase = (b0 & 3) + kBrickSY * (b1 & 3) + kBrickSZ * (b2 & 3);
       const int64_t gbase = sg.node_off + (int64_t)(b2 * ny + b1) * nx + b0;
-      double* const lb = brick + (lds ? seg : 0) * 4 * kBrickV + lbase;
+      double* const lb = brick + (lds ? max(seg, 0) : 0) * 4 * kBrickV + lbase;
       float* const gch[4] = {a.gm + gbase, a.gp0 + gbase, a.gp1 + gbase, a.gp2 + gbase};
       const int nxny = nx * ny;
       // each nodal value goes straight to its brick (or, past the LDS budget, to HBM)
@@ -161,10 +180,17 @@ __global__ __launch_bounds__(BS, BS == 256 ? 4 : 2) void p2g_brick_kernel(P2GArg
         double* const lbc = lb + ch * kBrickV;
         float* const gc = gch[ch];
         return [=](int jx, int jy, int jz, float v) {
+          const float v2 = v + __int_as_float(pair_swap_i(__float_as_int(v)));
+          float w = pair ? v2 : v;
+          if constexpr (LG == 2) {
+            const float v4 = v2 + __int_as_float(quad_swap_i(__float_as_int(v2)));
+            w = quad ? v4 : w;
+          }
+          if (!emit) return;
           if (lds)
-            atomicAdd(lbc + jx + kBrickSY * jy + kBrickSZ * jz, (double)v);
+            atomicAdd(lbc + jx + kBrickSY * jy + kBrickSZ * jz, (double)w);
           else
-            atomicAdd(gc + jz * nxny + jy * nx + jx, v);
+            atomicAdd(gc + jz * nxny + jy * nx + jx, w);
         };
       };
       {  // mass: m W_ip

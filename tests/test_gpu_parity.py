@@ -374,3 +374,46 @@ def test_every_p2g_configuration_and_the_autotuner(n_modes):
         assert rel(host(ps.grid_mom).reshape(Q_ref.shape), Q_ref) <= TOL_NORMWISE
     finally:
         pp.polypic_set_p2g_config(n_modes, -1, 512)
+
+
+@pytest.mark.parametrize("n_modes", [4, 27])
+def test_p2g_lane_groups_with_every_cell_size(n_modes):
+    """Cells holding 1 .. 9 particles in turn (so that in sorted order the runs of one cell
+    start at every offset of the lane pairs and quads that pre-add their nodal values), with
+    out-of-range particles among them: every particle is counted exactly once."""
+    pp = require_gpu()
+    rng = np.random.default_rng(11)
+    gs = W.cubic_grid(32)
+    cells = [(cx, cy, cz) for cz in range(4, 28, 2) for cy in range(4, 28, 3) for cx in range(4, 28)]
+    xs = []
+    for k, (cx, cy, cz) in enumerate(cells):
+        n = 1 + k % 9
+        u = rng.random((3, n))
+        xs.append(np.stack([(2 + cx + u[0]) * gs.dx, (2 + cy + u[1]) * gs.dx,
+                            (2 + cz + u[2]) * gs.dx]))
+    x = np.concatenate(xs, axis=1).astype(np.float32)
+    P = x.shape[1]
+    bad = rng.choice(P, size=37, replace=False)
+    x[0, bad] = -1.0                                  # outside the grid: skipped and flagged
+    c = np.zeros((3, 27, P), np.float32)
+    c[:, 0] = rng.standard_normal((3, P))
+    c[:, 1:] = 0.1 * rng.standard_normal((3, 26, P))
+    m = (0.5 + rng.random(P)).astype(np.float32)
+    note(f"p2g lane groups: P={P} n_modes={n_modes}")
+    g = pp.grid_from_spec(gs)
+    ps = pp.ParticleSet(g, n_modes, dev(x), dev(c[:, :n_modes]), mass=dev(m))
+    good = np.setdiff1d(np.arange(P), bad)
+    M_ref, Q_ref = O.p2g(oracle_grid(g), x[:, good], c[:, :, good], n_modes, m[good])
+    ps.sort()
+    configs = [(0, 256, 0, 0), (0, 512, 0, 0), (0, 256, 1, 0), (0, 256, 2, 2), (1, 512, 0, 0)]
+    try:
+        for cfg in configs:
+            pp.polypic_set_p2g_config(n_modes, *cfg)
+            ps.status.zero_()
+            ps.p2g()
+            torch.cuda.synchronize()
+            assert ps.status_flags() & 1
+            assert rel(host(ps.grid_mass).reshape(M_ref.shape), M_ref) <= TOL_NORMWISE, cfg
+            assert rel(host(ps.grid_mom).reshape(Q_ref.shape), Q_ref) <= TOL_NORMWISE, cfg
+    finally:
+        pp.polypic_set_p2g_config(n_modes, -1, 512)
