@@ -166,7 +166,10 @@ __global__ __launch_bounds__(BS) void g2p_kernel(G2PArgs a, Scenes sc) {
 
 template <int NR, class Scenes>
 hipError_t launch_nr(const G2PArgs& a, const Scenes& sc, hipStream_t stream) {
-  constexpr int BS = 256;
+  // 512 particles per workgroup: each output row is then written in 2 KB runs per
+  // workgroup (measured in the step, 27 modes, 4.19 M particles: 0.37 ms at 256
+  // threads, 0.27 ms at 512, 0.32 ms at 1024)
+  constexpr int BS = 512;
   const unsigned blocks = (unsigned)((a.P + BS - 1) / BS);
   g2p_kernel<NR, BS, Scenes><<<blocks, BS, 0, stream>>>(a, sc);
   return hipGetLastError();
