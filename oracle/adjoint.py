@@ -53,28 +53,46 @@ def _flat(grid: Grid, b, j):
     return ((b[2] + j[2]) * grid.ny + (b[1] + j[1])) * grid.nx + (b[0] + j[0])
 
 
+def _mode_index(n_modes: int):
+    """Per-axis indices (kx_r, ky_r, kz_r) of the first n_modes modes."""
+    return (torch.tensor([MODES[r][0] for r in range(n_modes)]),
+            torch.tensor([MODES[r][1] for r in range(n_modes)]),
+            torch.tensor([MODES[r][2] for r in range(n_modes)]))
+
+
 def step(grid: Grid, x: torch.Tensor, c: torch.Tensor, n_modes: int, dt: float,
          gravity: Sequence[float] = (0.0, -9.8, 0.0), bc_layers: int = 1,
          mass: torch.Tensor = None, uniform_mass: float = 1.0):
-    """One differentiable step: (x (3, P), c (3, n_modes, P)) -> (x', c', grid dict)."""
+    """One differentiable step: (x (3, P), c (3, n_modes, P)) -> (x', c', grid dict).
+
+    A loop over the 27 stencil nodes; at each node all modes at once.
+    """
     P = x.shape[1]
     m = mass if mass is not None else torch.full((P,), float(uniform_mass), dtype=torch.float64)
     b, t = _stencil(grid, x)
-    fac = [_factors(t[a]) for a in range(3)]
-    phi = [[[torch.ones_like(t[a])] * 3, fac[a][1], fac[a][2]] for a in range(3)]
+    KX, KY, KZ = _mode_index(n_modes)
     nn = grid.n_nodes
-    # P2G (Eq. 1, 4, 13)
+    # per-axis tables over (factor k, node j, particle p)
+    wt, phit, qt = [], [], []
+    for a in range(3):
+        w, z, g = (torch.stack(f) for f in _factors(t[a]))  # (3 j, P): w_j, zhat_j, ghat_j
+        one = torch.ones_like(w)
+        wt.append(w)
+        phit.append(torch.stack([one, z, g]))             # phi_k(j): 1, zhat, ghat (Eq. 11, 14)
+        # G2P projection rows (K(t) cancelled on quadratic axes): w, w zhat, (1, -2, 1)
+        qt.append(torch.stack([w, w * z, torch.stack([one[0], -2.0 * one[1], one[2]])]))
+
+    def mode_rows(f, j):
+        """(n_modes, P): f_x[kx_r, jx] f_y[ky_r, jy] f_z[kz_r, jz] at stencil node j."""
+        return f[0][KX, j[0]] * f[1][KY, j[1]] * f[2][KZ, j[2]]
+
+    # P2G (Eq. 1, 4, 13): m_i = sum_p m_p W_ip;  p_i = sum_p m_p W_ip sum_r c_pr s_r(i)
     M = torch.zeros(nn, dtype=torch.float64)
     Q = torch.zeros(3, nn, dtype=torch.float64)
     for j in STENCIL:
         node = _flat(grid, b, j)
-        W = fac[0][0][j[0]] * fac[1][0][j[1]] * fac[2][0][j[2]]
-        mW = m * W
-        V = torch.zeros(3, P, dtype=torch.float64)
-        for r in range(n_modes):
-            kx, ky, kz = MODES[r]
-            s = phi[0][kx][j[0]] * phi[1][ky][j[1]] * phi[2][kz][j[2]]
-            V = V + c[:, r, :] * s
+        mW = m * wt[0][j[0]] * wt[1][j[1]] * wt[2][j[2]]    # m_p W_ip
+        V = (c * mode_rows(phit, j)).sum(dim=1)             # sum_r c_par s_r(j): (3, P)
         M = M.index_add(0, node, mW)
         Q = Q.index_add(1, node, mW * V)
     # grid update (Eq. 5 + gravity + separating slip walls)
@@ -98,24 +116,13 @@ def step(grid: Grid, x: torch.Tensor, c: torch.Tensor, n_modes: int, dt: float,
             rows.append(va)
         v = torch.stack(rows)
     # G2P: c'_r = <v, s_r>_W / <s_r, s_r>_W with K(t) cancelled on quadratic axes
-    q = []
-    for a in range(3):
-        w, z, _ = fac[a]
-        q.append([w, [w[k] * z[k] for k in range(3)],
-                  [torch.ones_like(t[a]), -2.0 * torch.ones_like(t[a]), torch.ones_like(t[a])]])
-    cols = []
-    gathered = {j: v[:, _flat(grid, b, j)] for j in STENCIL}
-    for r in range(n_modes):
-        kx, ky, kz = MODES[r]
-        num = torch.zeros(3, P, dtype=torch.float64)
-        den = torch.zeros(P, dtype=torch.float64)
-        for j in STENCIL:
-            qq = q[0][kx][j[0]] * q[1][ky][j[1]] * q[2][kz][j[2]]
-            s = phi[0][kx][j[0]] * phi[1][ky][j[1]] * phi[2][kz][j[2]]
-            num = num + qq * gathered[j]
-            den = den + qq * s
-        cols.append(num / den)
-    c_out = torch.stack(cols, dim=1)
+    num = torch.zeros(3, n_modes, P, dtype=torch.float64)
+    den = torch.zeros(n_modes, P, dtype=torch.float64)
+    for j in STENCIL:
+        qq = mode_rows(qt, j)                               # projection weight: (n_modes, P)
+        num = num + qq * v[:, _flat(grid, b, j)].unsqueeze(1)
+        den = den + qq * mode_rows(phit, j)
+    c_out = num / den
     # advection, kept inside [o + 2 dx, o + (N - 2) dx]
     lo = torch.tensor([grid.origin[a] + 2 * grid.dx for a in range(3)],
                       dtype=torch.float64).reshape(3, 1)
