@@ -132,11 +132,13 @@ int32_t polypic_sort(const polypic_grid* grid, int64_t P, const float* x, uint32
  *               handles particle perm[i].
  * keys_sorted   NULL, or the sorted cell keys of that order (keys_sorted and
  *               perm as returned together by polypic_sort for this x and grid).
- *               With them P2G takes its fast path: particles of one cell are
- *               reduced in registers, cells of a 4^3 tile in LDS, and every
- *               grid node is written with one atomic per tile.  Without them
- *               every particle adds its 27 nodes through LDS/HBM float atomics
- *               (correct for any order, much slower).
+ *               They enable the cell-run path (per-cell sums, one workgroup
+ *               per 4^3-cell tile), used when the configuration table selects
+ *               it.  The default brick path needs only perm: in sorted order,
+ *               lane groups of particles sharing a cell add their nodal values
+ *               across lanes, bricks of 4^3 tiles accumulate in LDS and reach
+ *               HBM with one atomic per node and channel.  Any order is
+ *               correct; unsorted input is slower.
  * ws, ws_bytes  device workspace, at least polypic_p2g_workspace_bytes(); used
  *               only with keys_sorted (may be NULL otherwise).
  * grid_mass[N], grid_mom[3][N]   outputs (device).
@@ -169,9 +171,8 @@ int32_t polypic_p2g(const polypic_grid* grid, int64_t P, int32_t n_modes, const 
  *                                  each looping over a contiguous chunk range.
  *        per_cu is ignored by the other schedules (pass 0).
  * The choice is kept per n_modes in a process-wide, mutex-guarded table.
- * Without an entry polypic_p2g uses the cell path when keys_sorted is given
- * and the brick path (block 512, linear) otherwise; the cell path is never
- * chosen without keys_sorted.
+ * Without an entry polypic_p2g uses the brick path (block 256, linear); the
+ * cell path runs only when chosen and keys_sorted is given.
  *
  * polypic_autotune_p2g runs P2G once per candidate configuration on the given
  * inputs (same arguments as polypic_p2g, keys_sorted may be NULL), times each

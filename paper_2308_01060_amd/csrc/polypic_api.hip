@@ -79,7 +79,7 @@ void clamp_bounds(const polypic_grid* grid, float lo[3], float hi[3]) {
 // ---- P2G launch-configuration table (per n_modes), shared by the process
 struct P2GChoice {
   int path = POLYPIC_P2G_DEFAULT;
-  int block = 512;
+  int block = 256;
   int sched = POLYPIC_SCHED_LINEAR;
   int per_cu = 0;
 };
@@ -120,8 +120,7 @@ int32_t run_p2g(const polypic_grid* grid, int64_t P, int32_t n_modes, const floa
                 int32_t accumulate, int32_t* status_dev, hipStream_t s, P2GChoice c) {
   int32_t st;
   const int64_t N = n_nodes(grid);
-  const bool cells = keys_sorted != nullptr &&
-                     (c.path == POLYPIC_P2G_CELLS || c.path == POLYPIC_P2G_DEFAULT);
+  const bool cells = keys_sorted != nullptr && c.path == POLYPIC_P2G_CELLS;
   uint32_t* counter = cells ? (uint32_t*)ws : nullptr;
   if (!accumulate) {
     if ((st = from_hip(launch_grid_clear(grid_mass, grid_mom, N, counter, s)))) return st;

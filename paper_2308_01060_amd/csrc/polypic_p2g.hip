@@ -492,7 +492,7 @@ hipError_t launch_cell_nr(const P2GArgs& a, int blocks, hipStream_t stream) {
 
 }  // namespace
 
-P2GConfig p2g_default_config() { return P2GConfig{2, 512, kSchedLinear, 0}; }
+P2GConfig p2g_default_config() { return P2GConfig{2, 256, kSchedLinear, 0}; }
 
 bool p2g_config_supported(const P2GConfig& c) {
   if (c.tile_log2 != 2 || (c.block != 256 && c.block != 512)) return false;

@@ -74,7 +74,8 @@ class ParticleSet:
         ops.polypic_sort(self.grid, self.x, self.keys, self.perm, self.ws, self.status)
 
     def p2g(self, use_perm: bool = True, use_keys: bool = True):
-        """P2G; with use_perm and use_keys (after sort()) it takes the cell-gather path."""
+        """P2G in sort order (use_perm); use_keys hands the sorted keys over as well, which the
+        cell-run path needs when the configuration table selects it."""
         sorted_ = use_perm and use_keys
         ops.polypic_p2g(self.grid, self.n_modes, self.x, self.coeff, self.grid_mass,
                         self.grid_mom, mass=self.mass, uniform_mass=self.uniform_mass,

@@ -2,6 +2,7 @@
 library through the C ABI, and compare with the FP64 oracle."""
 from __future__ import annotations
 
+import contextlib
 import sys
 
 import numpy as np
@@ -20,6 +21,16 @@ def require_gpu():
         pytest.fail("GPU test run without a visible GPU")
     import paper_2308_01060_amd as pp  # noqa: F401  (fails loudly without the HIP library)
     return pp
+
+
+@contextlib.contextmanager
+def p2g_config(pp, n_modes: int, path: int, block: int = 256, schedule: int = 0, per_cu: int = 0):
+    """Select a P2G configuration for the block, then restore the default."""
+    pp.polypic_set_p2g_config(n_modes, path, block, schedule, per_cu)
+    try:
+        yield
+    finally:
+        pp.polypic_set_p2g_config(n_modes, -1, 256)
 
 
 def note(msg: str) -> None:

@@ -15,6 +15,7 @@ import torch
 
 import workloads as W
 from oracle import polypic_oracle as O
+from tests.gpu_util import p2g_config
 from tests.gpu_util import (TOL_NORMWISE, dev, host, note, oracle_grid, rel, require_gpu,
                             ulp_ok)
 
@@ -87,8 +88,9 @@ def test_p2g_parity(n_modes, path):
     pp, g, ps = particle_set(s, n_modes)
     if path != "unsorted":
         ps.sort()
-    ps.p2g(use_perm=(path != "unsorted"), use_keys=(path == "cells"))
-    torch.cuda.synchronize()
+    with p2g_config(pp, n_modes, pp.POLYPIC_P2G_CELLS if path == "cells" else pp.POLYPIC_P2G_BRICKS):
+        ps.p2g(use_perm=(path != "unsorted"), use_keys=(path == "cells"))
+        torch.cuda.synchronize()
     M_ref, Q_ref = O.p2g(oracle_grid(g), s.x, s.coeff, n_modes)
     M = host(ps.grid_mass).reshape(M_ref.shape)
     Q = host(ps.grid_mom).reshape(Q_ref.shape)
@@ -309,15 +311,17 @@ def test_invalid_permutation_never_faults():
 
 
 def test_stale_keys_are_flagged_not_trusted():
-    """Keys that no longer match the positions: those particles are skipped and flagged."""
+    """Cell path: keys that no longer match the positions: those particles are skipped and
+    flagged (the brick path recomputes every stencil from the positions)."""
     pp = require_gpu()
     s = W.config0(5)
     pp_, g, ps = particle_set(s, 8)
     ps.sort()
     moved = ps.perm[:100].long()
     ps.x[0, moved] += 1.5 / 32   # moves 100 particles by 1.5 cells along x
-    ps.p2g()
-    torch.cuda.synchronize()
+    with p2g_config(pp, 8, pp.POLYPIC_P2G_CELLS, 512):
+        ps.p2g()
+        torch.cuda.synchronize()
     assert ps.status_flags() & 1
     total = float(ps.grid_mass.double().sum())
     assert abs(total - (s.P - 100)) < 1e-3
@@ -340,11 +344,13 @@ def test_cell_path_with_sparse_and_dense_cells():
     g = pp.make_grid((n + 4,) * 3, 1 / n)
     ps = pp.ParticleSet(g, 27, dev(x), dev(c), mass=dev(mass))
     ps.sort()
-    ps.p2g()
-    torch.cuda.synchronize()
     M_ref, Q_ref = O.p2g(oracle_grid(g), x, c, 27, mass)
-    assert rel(host(ps.grid_mass).reshape(M_ref.shape), M_ref) <= TOL_NORMWISE
-    assert rel(host(ps.grid_mom).reshape(Q_ref.shape), Q_ref) <= TOL_NORMWISE
+    for path in (pp.POLYPIC_P2G_CELLS, pp.POLYPIC_P2G_BRICKS):
+        with p2g_config(pp, 27, path, 512 if path == pp.POLYPIC_P2G_CELLS else 256):
+            ps.p2g()
+            torch.cuda.synchronize()
+        assert rel(host(ps.grid_mass).reshape(M_ref.shape), M_ref) <= TOL_NORMWISE, path
+        assert rel(host(ps.grid_mom).reshape(Q_ref.shape), Q_ref) <= TOL_NORMWISE, path
     assert ps.status_flags() == 0
 
 
@@ -373,7 +379,7 @@ def test_every_p2g_configuration_and_the_autotuner(n_modes):
         assert pp.polypic_get_p2g_config(n_modes) == choice
         assert rel(host(ps.grid_mom).reshape(Q_ref.shape), Q_ref) <= TOL_NORMWISE
     finally:
-        pp.polypic_set_p2g_config(n_modes, -1, 512)
+        pp.polypic_set_p2g_config(n_modes, -1, 256)
 
 
 @pytest.mark.parametrize("n_modes", [4, 27])
@@ -416,4 +422,4 @@ def test_p2g_lane_groups_with_every_cell_size(n_modes):
             assert rel(host(ps.grid_mass).reshape(M_ref.shape), M_ref) <= TOL_NORMWISE, cfg
             assert rel(host(ps.grid_mom).reshape(Q_ref.shape), Q_ref) <= TOL_NORMWISE, cfg
     finally:
-        pp.polypic_set_p2g_config(n_modes, -1, 512)
+        pp.polypic_set_p2g_config(n_modes, -1, 256)
