@@ -79,6 +79,9 @@ extern "C" {
 
 /* ---- device status flags, OR-ed into *status_dev ---- */
 #define POLYPIC_FLAG_RANGE 1 /* a particle's stencil left the grid; it was skipped */
+#define POLYPIC_FLAG_ORDER 2 /* polypic_sort_update was given keys_prev out of order */
+#define POLYPIC_FLAG_STALL 4 /* a re-sort pass gave up waiting on an earlier tile (a tile that
+                              * waits far longer than any run takes); outputs unspecified */
 
 /* Collocated grid description (host struct, passed by pointer). */
 typedef struct polypic_grid {
@@ -115,6 +118,30 @@ int32_t polypic_sort_workspace_bytes(const polypic_grid* grid, int64_t P, size_t
 int32_t polypic_sort(const polypic_grid* grid, int64_t P, const float* x, uint32_t* keys_out,
                      int32_t* perm_out, void* ws, size_t ws_bytes, int32_t* status_dev,
                      void* stream);
+
+/* ------------------------------------------------------------------------
+ * Re-sort after a step: the same result as polypic_sort, bit for bit, faster
+ * when few particles changed cell.
+ *
+ * keys_prev[P] (device, read only): the keys_out of the previous sort, the
+ * particle arrays having been permuted by its perm_out since (as polypic_g2p
+ * does with perm), so that keys_prev[i] is the key slot i was sorted under
+ * and keys_prev is ascending.  Particles whose key is unchanged already form
+ * an ordered subsequence; only the changed ones are sorted (radix), and the
+ * two are merged by (key, index).  keys_prev must not alias keys_out.  If
+ * keys_prev is not ascending, POLYPIC_FLAG_ORDER is raised and the outputs
+ * are unspecified (every written index stays in [0, P)).  The sort of the
+ * changed particles chains its tiles' digit prefixes through device memory;
+ * a tile that waits on its predecessor far longer than any run takes (which
+ * does not happen when the launches run in order on one stream) stops
+ * waiting and raises POLYPIC_FLAG_STALL, the outputs then unspecified.
+ * ws: at least polypic_sort_update_workspace_bytes() bytes (about 19 B per
+ * particle), contents scratch.
+ * ------------------------------------------------------------------------ */
+int32_t polypic_sort_update_workspace_bytes(const polypic_grid* grid, int64_t P, size_t* bytes);
+int32_t polypic_sort_update(const polypic_grid* grid, int64_t P, const float* x,
+                            const uint32_t* keys_prev, uint32_t* keys_out, int32_t* perm_out,
+                            void* ws, size_t ws_bytes, int32_t* status_dev, void* stream);
 
 /* ------------------------------------------------------------------------
  * P2G scatter.  Section 3.1 Eq. 1 and 4 (mass), Eq. 13 (momentum), summed over

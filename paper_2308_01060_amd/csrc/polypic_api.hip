@@ -308,6 +308,30 @@ int32_t polypic_sort(const polypic_grid* grid, int64_t P, const float* x, uint32
                               (hipStream_t)stream));
 }
 
+int32_t polypic_sort_update_workspace_bytes(const polypic_grid* grid, int64_t P, size_t* bytes) {
+  int32_t st = check_grid(grid);
+  if (st) return st;
+  if ((st = check_P(P))) return st;
+  if (!bytes) return POLYPIC_EINVAL;
+  *bytes = sort_update_workspace_bytes(P);
+  return POLYPIC_OK;
+}
+
+int32_t polypic_sort_update(const polypic_grid* grid, int64_t P, const float* x,
+                            const uint32_t* keys_prev, uint32_t* keys_out, int32_t* perm_out,
+                            void* ws, size_t ws_bytes, int32_t* status_dev, void* stream) {
+  int32_t st = check_grid(grid);
+  if (st) return st;
+  if ((st = check_P(P))) return st;
+  if (P == 0) return POLYPIC_OK;
+  if (!x || !keys_prev || !keys_out || !perm_out || !ws) return POLYPIC_EINVAL;
+  if ((const void*)keys_prev == (const void*)keys_out) return POLYPIC_EINVAL;
+  if (ws_bytes < sort_update_workspace_bytes(P)) return POLYPIC_ENOSPACE;
+  discard_stale_error();
+  return from_hip(launch_sort_update(to_dev(grid), P, x, keys_prev, keys_out, perm_out, ws,
+                                     status_dev, (hipStream_t)stream));
+}
+
 int32_t polypic_p2g_workspace_bytes(const polypic_grid* grid, int64_t P, size_t* bytes) {
   int32_t st = check_grid(grid);
   if (st) return st;

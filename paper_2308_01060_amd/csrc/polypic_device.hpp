@@ -15,6 +15,8 @@ constexpr int kWave = 64;
 
 // Device flags (mirrors POLYPIC_FLAG_* of the public header).
 constexpr int kFlagRange = 1;
+constexpr int kFlagOrder = 2;  // a re-sort was given previous keys out of order
+constexpr int kFlagStall = 4;  // a sort's chained tile prefixes did not complete
 
 struct GridDev {
   int nx, ny, nz;

@@ -19,6 +19,11 @@ size_t sort_workspace_bytes(int64_t P);
 int sort_key_bits(const GridDev& g);
 hipError_t launch_sort(const GridDev& g, int64_t P, const float* x, uint32_t* keys_out,
                        int32_t* perm_out, void* ws, int32_t* status, hipStream_t stream);
+// re-sort after a step (keys_prev: the previous sort's keys, in the current slot order)
+size_t sort_update_workspace_bytes(int64_t P);
+hipError_t launch_sort_update(const GridDev& g, int64_t P, const float* x,
+                              const uint32_t* keys_prev, uint32_t* keys_out, int32_t* perm_out,
+                              void* ws, int32_t* status, hipStream_t stream);
 // batch of scenes: key = scene << mbits | Morton(base node), key_bits in total
 hipError_t launch_sort_batch(const SceneDev* table, int n_scenes, int mbits, int key_bits,
                              int64_t P, const float* x, uint32_t* keys_out, int32_t* perm_out,

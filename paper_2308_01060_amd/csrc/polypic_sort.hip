@@ -1,10 +1,15 @@
-// Cell-key computation and stable LSD radix sort (8-bit digits) for gfx950.
+// Cell keys, the stable LSD radix sort (8-bit digits) and the re-sort, for gfx950.
 //
-// Each pass: (1) per-tile digit histograms, (2) per-digit exclusive scan over
-// tiles, (3) a stable scatter in which every tile ranks its keys in input
-// order -- within a wavefront by ballot matching of equal digits, across the
-// wavefronts of the block through small LDS histograms.  Ties keep input
+// Full sort, per pass: (1) per-tile digit histograms, (2) per-digit exclusive
+// scan over tiles, (3) a stable scatter in which every tile ranks its keys in
+// input order -- within a wavefront by ballot matching of equal digits, across
+// the wavefronts of the block through small LDS histograms.  Ties keep input
 // order, so the result equals a stable argsort of the keys.
+//
+// Re-sort: after a step whose particle arrays were permuted by the previous
+// sort, only the particles whose cell changed are out of place.  They are
+// compacted and sorted on their own (a radix sort whose length only the device
+// knows), then merged with the unchanged ones by (key, index).
 #include "polypic_internal.hpp"
 
 namespace polypic {
@@ -267,6 +272,593 @@ hipError_t launch_sort_batch(const SceneDev* table, int n_scenes, int mbits, int
                              void* ws, int32_t* status, hipStream_t stream) {
   SceneTable st{table, n_scenes};
   return sort_with(st, mbits, key_bits, P, x, keys_out, perm_out, ws, status, stream);
+}
+
+
+// ------------------------------------------------ sort of a device-counted list
+// Sorts the first *count (key, value) pairs of a buffer sized for `cap` pairs
+// when the host does not know the count.  Launches: one histogram of every
+// pass over the active tiles (digit totals straight into device memory), then
+// one stable scatter per pass.  A scatter tile learns how many keys of each digit precede it from its
+// predecessors' published counts (decoupled look-back): each tile publishes
+// its own digit counts as soon as it has them, then reads its predecessors'
+// words, nearest first and kLookWindow per round trip, until an inclusive
+// prefix, and publishes its own inclusive prefix.  Tiles are numbered in the
+// order workgroups claim them (an atomic counter), so a tile only waits on
+// tiles whose workgroups already run and publish before they wait.  The polls
+// must be coherent across the chip's L2 caches, so a chain over thousands of
+// tiles is slow; the lists sorted here are short (the changed particles).
+//
+// Inside a tile, wave w ranks the contiguous keys [w * 512, (w + 1) * 512) in
+// rounds of 64 by ballot matching of equal digits, keeping a wave-private
+// running count per digit; the per-digit counts are then prefixed over the
+// waves.  Order inside a tile is (wave, round, lane) = input order: stable.
+namespace {
+
+constexpr int kMaxPasses = 4;
+constexpr int kWaveKeys = kSortTile / kSortWaves;
+constexpr uint32_t kInclusive = 0x80000000u;
+// look-back word: 0 = not yet published; 1 + n = the tile's own count n;
+// kInclusive | n = keys with this digit in this tile and all tiles before it
+constexpr int kSpinLimit = 1 << 20;  // polls without progress before giving up
+constexpr int kLookWindow = 16;      // predecessors read per round trip
+constexpr int kCountedGrid = 512;    // workgroups of the device-counted sort's launches
+static_assert(kSortBS == kRadix, "one thread per digit");
+static_assert(kWaveKeys == kSortIPT * kWave, "a wave's keys are kSortIPT rounds of a wave");
+
+__device__ __forceinline__ uint32_t load_agent(const uint32_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void store_agent(uint32_t* p, uint32_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// lanes of the wave whose (valid) digit equals this lane's; every lane calls it
+__device__ __forceinline__ unsigned long long match_digit(uint32_t d, bool valid) {
+  unsigned long long same = __ballot(valid);
+#pragma unroll
+  for (int bit = 0; bit < 8; ++bit) {
+    const unsigned long long bal = __ballot((d >> bit) & 1u);
+    same &= ((d >> bit) & 1u) ? bal : ~bal;
+  }
+  return same;
+}
+
+// Digit totals of every pass over the first *count keys (added to `totals`,
+// cleared beforehand), and the look-back words of every active tile cleared.
+// Workgroups loop over the active tiles.
+__global__ __launch_bounds__(kSortBS) void counted_hist_kernel(const uint32_t* __restrict__ keys,
+                                                              const uint32_t* __restrict__ count,
+                                                              int passes, int cap_tiles,
+                                                              uint32_t* __restrict__ look,
+                                                              uint32_t* __restrict__ totals) {
+  __shared__ uint32_t whist[kSortWaves][kMaxPasses * kRadix];
+  const int64_t M = (int64_t)*count;
+  const int tid = threadIdx.x;
+  const int lane = tid & (kWave - 1);
+  const int wv = tid / kWave;
+  for (int64_t t = blockIdx.x; t * kSortTile < M; t += gridDim.x) {
+    const int64_t base = t * kSortTile + (int64_t)wv * kWaveKeys;
+    uint32_t key[kSortIPT];
+#pragma unroll
+    for (int j = 0; j < kSortIPT; ++j) {
+      const int64_t i = base + (int64_t)j * kWave + lane;
+      key[j] = i < M ? keys[i] : 0u;
+    }
+#pragma unroll
+    for (int w = 0; w < kSortWaves; ++w)
+#pragma unroll
+      for (int q = 0; q < kMaxPasses; ++q) whist[w][q * kRadix + tid] = 0u;
+    for (int q = 0; q < passes; ++q) look[((size_t)q * cap_tiles + t) * kRadix + tid] = 0u;
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < kSortIPT; ++j) {
+      const bool valid = base + (int64_t)j * kWave + lane < M;
+      for (int q = 0; q < passes; ++q) {
+        const uint32_t d = (key[j] >> (8 * q)) & (kRadix - 1);
+        const unsigned long long same = match_digit(d, valid);
+        if (valid && lanes_below(same) == 0)
+          atomicAdd(&whist[wv][q * kRadix + d], (uint32_t)__popcll(same));
+      }
+    }
+    __syncthreads();
+    for (int q = 0; q < passes; ++q) {
+      uint32_t c = 0;
+#pragma unroll
+      for (int w = 0; w < kSortWaves; ++w) c += whist[w][q * kRadix + tid];
+      if (c) atomicAdd(&totals[q * kRadix + tid], c);
+    }
+    __syncthreads();  // whist is cleared again for the next tile
+  }
+}
+
+// One stable scatter pass (digit at `shift`) over the first *count pairs;
+// workgroups claim tiles until none is left.
+__global__ __launch_bounds__(kSortBS) void counted_scatter_kernel(
+    const uint32_t* __restrict__ keys_in, const int32_t* __restrict__ vals_in,
+    uint32_t* __restrict__ keys_out, int32_t* __restrict__ vals_out,
+    const uint32_t* __restrict__ count, int shift, const uint32_t* __restrict__ totals,
+    uint32_t* __restrict__ look, uint32_t* __restrict__ tile_ctr, int32_t* __restrict__ status) {
+  __shared__ uint32_t whist[kSortWaves][kRadix];  // per wave: running digit counts
+  __shared__ uint32_t offset[kRadix];
+  __shared__ uint32_t wsum[kSortWaves];
+  __shared__ uint32_t tile_sh;
+  const int64_t M = (int64_t)*count;
+  const int tid = threadIdx.x;
+  const int lane = tid & (kWave - 1);
+  const int wv = tid / kWave;
+  // Workgroups with no tile to start on leave without touching the counter
+  // (a counter that every workgroup of a large grid bumps serialises them).
+  if ((int64_t)blockIdx.x * kSortTile >= M) return;
+  while (true) {
+#pragma unroll
+  for (int w = 0; w < kSortWaves; ++w) whist[w][tid] = 0u;
+  if (tid == 0) tile_sh = atomicAdd(tile_ctr, 1u);
+  __syncthreads();
+  const int64_t tile = (int64_t)tile_sh;
+  if (tile * kSortTile >= M) return;  // uniform: every tile is taken
+
+  const int64_t base = tile * kSortTile + (int64_t)wv * kWaveKeys;
+  uint32_t key[kSortIPT];
+  int32_t val[kSortIPT];
+  uint32_t rank[kSortIPT];
+#pragma unroll
+  for (int j = 0; j < kSortIPT; ++j) {
+    const int64_t i = base + (int64_t)j * kWave + lane;
+    key[j] = i < M ? keys_in[i] : 0u;
+    val[j] = i < M ? vals_in[i] : 0;
+  }
+#pragma unroll
+  for (int j = 0; j < kSortIPT; ++j) {
+    const bool valid = base + (int64_t)j * kWave + lane < M;
+    const uint32_t d = (key[j] >> shift) & (kRadix - 1);
+    const unsigned long long same = match_digit(d, valid);
+    const int r = lanes_below(same);
+    const uint32_t before = whist[wv][d];  // this wave's keys with digit d so far
+    if (valid && r == 0) whist[wv][d] = before + (uint32_t)__popcll(same);
+    rank[j] = before + (uint32_t)r;
+  }
+  __syncthreads();
+
+  // digit tid: prefix over the waves, this tile's count, published at once
+  uint32_t cnt = 0;
+#pragma unroll
+  for (int w = 0; w < kSortWaves; ++w) {
+    const uint32_t c = whist[w][tid];
+    whist[w][tid] = cnt;
+    cnt += c;
+  }
+  uint32_t* mine = look + tile * kRadix + tid;
+  store_agent(mine, tile == 0 ? (kInclusive | cnt) : cnt + 1u);
+
+  // keys with a smaller digit, all tiles: exclusive scan of the totals
+  uint32_t digit_base;
+  {
+    const uint32_t v = totals[tid];
+    uint32_t sc = v;
+#pragma unroll
+    for (int off = 1; off < kWave; off <<= 1) {
+      const uint32_t o = __shfl_up(sc, off, kWave);
+      if (lane >= off) sc += o;
+    }
+    if (lane == kWave - 1) wsum[wv] = sc;
+    __syncthreads();
+    uint32_t pre = 0;
+#pragma unroll
+    for (int w = 0; w < kSortWaves; ++w) pre += (w < wv) ? wsum[w] : 0u;
+    digit_base = pre + sc - v;
+  }
+
+  // keys with digit tid in earlier tiles
+  uint32_t excl = 0;
+  if (tile > 0) {
+    int64_t j = tile - 1;  // nearest predecessor not yet accounted for
+    int spins = 0;
+    bool done = false;
+    while (!done) {
+      uint32_t w[kLookWindow];
+#pragma unroll
+      for (int k = 0; k < kLookWindow; ++k)
+        w[k] = j - k >= 0 ? load_agent(look + (j - k) * kRadix + tid) : kInclusive;
+      int advanced = 0;
+#pragma unroll
+      for (int k = 0; k < kLookWindow; ++k) {
+        if (done || advanced < k) continue;  // stopped at a tile not yet published
+        if (w[k] & kInclusive) {
+          excl += w[k] & ~kInclusive;  // (tile 0 is inclusive: the walk ends there)
+          done = true;
+        } else if (w[k] != 0u) {
+          excl += w[k] - 1u;
+          advanced = k + 1;
+        }
+      }
+      if (done) break;
+      if (advanced > 0) {
+        j -= advanced;
+        spins = 0;
+        continue;
+      }
+      if (++spins > kSpinLimit) {
+        raise_flag(status, kFlagStall);
+        break;
+      }
+      __builtin_amdgcn_s_sleep(1);
+    }
+    store_agent(mine, kInclusive | (excl + cnt));
+  }
+  offset[tid] = digit_base + excl;
+  __syncthreads();
+
+#pragma unroll
+  for (int j = 0; j < kSortIPT; ++j) {
+    const int64_t i = base + (int64_t)j * kWave + lane;
+    if (i < M) {
+      const uint32_t d = (key[j] >> shift) & (kRadix - 1);
+      int64_t pos = (int64_t)offset[d] + whist[wv][d] + rank[j];
+      pos = pos < M ? pos : M - 1;  // only after a stall (flagged) can it be out of range
+      keys_out[pos] = key[j];
+      vals_out[pos] = val[j];
+    }
+  }
+  __syncthreads();  // LDS is reused by the next tile
+  }
+}
+
+// ---------------------------------------------------------------- re-sort
+// Slots are taken in groups of 64 (one wavefront's round); a workgroup covers
+// kUpdTile slots = 32 groups.  Per group: a 64-bit mask of the changed slots
+// and the number of changed slots before the group.
+constexpr int kUpdTile = kSortTile;
+constexpr int kGroupsPerTile = kUpdTile / kWave;
+constexpr int kWindowCap = 2048;  // changed pairs a workgroup stages in LDS
+
+__device__ __forceinline__ uint32_t cell_key(const GridDev& g, const float* __restrict__ x,
+                                             size_t Ps, int64_t i, bool& ok) {
+  int b0, b1, b2;
+  float t0, t1, t2;
+  ok = stencil_axis(x[i], g.ox, g.inv_dx, g.nx, b0, t0);
+  ok &= stencil_axis(x[Ps + i], g.oy, g.inv_dx, g.ny, b1, t1);
+  ok &= stencil_axis(x[2 * Ps + i], g.oz, g.inv_dx, g.nz, b2, t2);
+  return morton3(b0, b1, b2);  // of the clamped base node when !ok, as the full sort
+}
+
+// changed-slot masks, per-workgroup counts, and the order check of keys_prev
+__global__ __launch_bounds__(kSortBS) void upd_mask_kernel(GridDev g, int64_t P,
+                                                         const float* __restrict__ x,
+                                                         const uint32_t* __restrict__ keys_prev,
+                                                         unsigned long long* __restrict__ mask,
+                                                         uint32_t* __restrict__ blk_count,
+                                                         int32_t* __restrict__ status) {
+  __shared__ uint32_t wcount[kSortWaves];
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wv = threadIdx.x / kWave;
+  const size_t Ps = (size_t)P;
+  uint32_t c = 0;
+#pragma unroll 2
+  for (int j = 0; j < kSortIPT; ++j) {
+    const int64_t grp = (int64_t)blockIdx.x * kGroupsPerTile + j * kSortWaves + wv;
+    const int64_t i = grp * kWave + lane;
+    bool changed = false;
+    if (i < P) {
+      bool ok;
+      const uint32_t key = cell_key(g, x, Ps, i, ok);
+      if (!ok) raise_flag(status, kFlagRange);
+      const uint32_t prev = keys_prev[i];
+      if (i > 0 && keys_prev[i - 1] > prev) raise_flag(status, kFlagOrder);
+      changed = key != prev;
+    }
+    const unsigned long long m = __ballot(changed);
+    if (lane == 0 && grp * kWave < P) mask[grp] = m;
+    c += (uint32_t)__popcll(m);
+  }
+  if (lane == 0) wcount[wv] = c;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t t = 0;
+#pragma unroll
+    for (int w = 0; w < kSortWaves; ++w) t += wcount[w];
+    blk_count[blockIdx.x] = t;
+  }
+}
+
+// one workgroup: exclusive scan of the per-workgroup counts, total to *count;
+// also clears the digit totals and tile counters of the changed-list sort
+__global__ __launch_bounds__(1024) void upd_scan_kernel(uint32_t* __restrict__ blk, int n,
+                                                        uint32_t* __restrict__ count,
+                                                        uint32_t* __restrict__ totals,
+                                                        uint32_t* __restrict__ tile_ctr) {
+  __shared__ uint32_t wsum[1024 / kWave];
+  const int tid = threadIdx.x;
+  const int lane = tid & (kWave - 1);
+  const int wv = tid / kWave;
+  if (tid < kMaxPasses * kRadix) totals[tid] = 0u;
+  if (tid < kMaxPasses) tile_ctr[tid] = 0u;
+  uint32_t running = 0;
+  for (int base = 0; base < n; base += 1024) {
+    const int k = base + tid;
+    const uint32_t v = k < n ? blk[k] : 0u;
+    uint32_t s = v;
+#pragma unroll
+    for (int off = 1; off < kWave; off <<= 1) {
+      const uint32_t o = __shfl_up(s, off, kWave);
+      if (lane >= off) s += o;
+    }
+    if (lane == kWave - 1) wsum[wv] = s;
+    __syncthreads();
+    uint32_t pre = 0, tot = 0;
+#pragma unroll
+    for (int w = 0; w < 1024 / kWave; ++w) {
+      pre += (w < wv) ? wsum[w] : 0u;
+      tot += wsum[w];
+    }
+    if (k < n) blk[k] = running + pre + s - v;
+    running += tot;
+    __syncthreads();
+  }
+  if (tid == 0) *count = running;
+}
+
+// changed (key, index) pairs in index order; gpre[grp] = changed slots before
+// the group
+__global__ __launch_bounds__(kSortBS) void upd_compact_kernel(
+    GridDev g, int64_t P, const float* __restrict__ x,
+    const unsigned long long* __restrict__ mask, const uint32_t* __restrict__ blk_off,
+    uint32_t* __restrict__ gpre, uint32_t* __restrict__ ck, int32_t* __restrict__ cv) {
+  __shared__ uint32_t pre_sh[kGroupsPerTile];
+  __shared__ int any_sh;
+  const int tid = threadIdx.x;
+  const int lane = tid & (kWave - 1);
+  const int wv = tid / kWave;
+  const int64_t n_groups = (P + kWave - 1) / kWave;
+  const int64_t g0 = (int64_t)blockIdx.x * kGroupsPerTile;
+  if (wv == 0) {
+    const bool in = lane < kGroupsPerTile && g0 + lane < n_groups;
+    const uint32_t c = in ? (uint32_t)__popcll(mask[g0 + lane]) : 0u;
+    const bool any = __ballot(c != 0u) != 0ull;  // every lane of wave 0 takes part
+    if (lane == 0) any_sh = any;
+    uint32_t s = c;
+#pragma unroll
+    for (int off = 1; off < kGroupsPerTile; off <<= 1) {
+      const uint32_t o = __shfl_up(s, off, kWave);
+      if (lane >= off) s += o;
+    }
+    const uint32_t p = blk_off[blockIdx.x] + s - c;
+    if (lane < kGroupsPerTile) pre_sh[lane] = p;
+    if (in) gpre[g0 + lane] = p;
+  }
+  __syncthreads();
+  if (!any_sh) return;  // uniform: no changed slot in this workgroup
+  const size_t Ps = (size_t)P;
+  unsigned long long m[kSortIPT];
+#pragma unroll
+  for (int j = 0; j < kSortIPT; ++j) {
+    const int64_t grp = g0 + j * kSortWaves + wv;
+    m[j] = grp < n_groups ? mask[grp] : 0ull;
+  }
+#pragma unroll
+  for (int j = 0; j < kSortIPT; ++j) {
+    if ((m[j] >> lane) & 1ull) {
+      const int k = j * kSortWaves + wv;
+      const int64_t i = (g0 + k) * kWave + lane;
+      bool ok;
+      const uint32_t pos = pre_sh[k] + (uint32_t)lanes_below(m[j]);
+      ck[pos] = cell_key(g, x, Ps, i, ok);
+      cv[pos] = (int32_t)i;
+    }
+  }
+}
+
+// changed slots before slot s (0 <= s <= P)
+__device__ __forceinline__ int64_t changed_before(int64_t s, int64_t P, uint32_t M,
+                                                  const unsigned long long* __restrict__ mask,
+                                                  const uint32_t* __restrict__ gpre) {
+  if (s >= P) return M;
+  const int64_t grp = s / kWave;
+  const int bit = (int)(s % kWave);
+  const unsigned long long below = bit ? (mask[grp] & ((1ull << bit) - 1ull)) : 0ull;
+  return (int64_t)gpre[grp] + __popcll(below);
+}
+
+// first changed pair in [lo, hi) not below (key, idx)
+template <class KeyAt, class IdxAt>
+__device__ __forceinline__ int lower_pair(KeyAt kat, IdxAt iat, int lo, int hi, uint32_t key,
+                                          int64_t idx) {
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    const uint32_t k = kat(mid);
+    if (k < key || (k == key && iat(mid) < idx))
+      lo = mid + 1;
+    else
+      hi = mid;
+  }
+  return lo;
+}
+
+// The same found by a whole wavefront (every lane calls it with the same
+// arguments): each round samples 64 evenly spaced positions of the range and
+// keeps the stretch between the last sample below (key, idx) and the next one,
+// so a range of n shrinks to n / 64 per round trip.
+template <class KeyAt, class IdxAt>
+__device__ __forceinline__ int64_t wave_lower_pair(KeyAt kat, IdxAt iat, int64_t lo, int64_t hi,
+                                                   uint32_t key, int64_t idx) {
+  const int lane = threadIdx.x & (kWave - 1);
+  while (lo < hi) {
+    const int64_t stride = (hi - lo + kWave - 1) / kWave;
+    const int64_t p = lo + (int64_t)lane * stride;
+    bool below = false;
+    if (p < hi) {
+      const uint32_t k = kat(p);
+      below = k < key || (k == key && (int64_t)iat(p) < idx);
+    }
+    const int c = __popcll(__ballot(below));  // a prefix of the samples when sorted
+    if (stride == 1) return lo + c;
+    if (c == 0) return lo;
+    const int64_t nhi = lo + (int64_t)c * stride;
+    lo = lo + (int64_t)(c - 1) * stride + 1;
+    hi = nhi < hi ? nhi : hi;
+  }
+  return lo;
+}
+
+// Final place of every changed pair j (sorted): j changed pairs precede it,
+// and so do the unchanged slots before `lo`, the first slot s whose
+// (keys_prev[s], s) is not below the pair's (key, index).
+__global__ __launch_bounds__(kSortBS) void upd_place_changed_kernel(
+    int64_t P, const uint32_t* __restrict__ keys_prev, const unsigned long long* __restrict__ mask,
+    const uint32_t* __restrict__ gpre, const uint32_t* __restrict__ cks,
+    const int32_t* __restrict__ cvs, const uint32_t* __restrict__ count,
+    uint32_t* __restrict__ keys_out, int32_t* __restrict__ perm_out) {
+  const uint32_t M = *count;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int64_t waves = (int64_t)gridDim.x * kSortWaves;
+  auto pk = [&](int64_t s) { return keys_prev[s]; };
+  auto ps = [&](int64_t s) { return s; };
+  for (int64_t j = (int64_t)blockIdx.x * kSortWaves + threadIdx.x / kWave; j < (int64_t)M;
+       j += waves) {  // one pair per wavefront
+    const uint32_t key = cks[j];
+    const int32_t idx = cvs[j];
+    const int64_t lo = wave_lower_pair(pk, ps, 0, P, key, idx);
+    if (lane == 0) {
+      int64_t pos = j + (lo - changed_before(lo, P, M, mask, gpre));
+      pos = pos < 0 ? 0 : (pos >= P ? P - 1 : pos);  // in range even for unsorted keys_prev
+      keys_out[pos] = key;
+      perm_out[pos] = idx;
+    }
+  }
+}
+
+// Final place of every unchanged slot i: its rank among the unchanged plus the
+// changed pairs below (keys_prev[i], i).  The unchanged slots of a workgroup
+// lie between (keys_prev[i0], i0) and (keys_prev[i1 - 1], i1), which bound the
+// window of the changed list they can fall into; it is staged in LDS when it
+// fits.
+__global__ __launch_bounds__(kSortBS) void upd_place_unchanged_kernel(
+    int64_t P, const uint32_t* __restrict__ keys_prev, const unsigned long long* __restrict__ mask,
+    const uint32_t* __restrict__ gpre, const uint32_t* __restrict__ cks,
+    const int32_t* __restrict__ cvs, const uint32_t* __restrict__ count,
+    uint32_t* __restrict__ keys_out, int32_t* __restrict__ perm_out) {
+  __shared__ int window[2];
+  __shared__ uint32_t wk[kWindowCap];
+  __shared__ int32_t wi[kWindowCap];
+  const int tid = threadIdx.x;
+  const int lane = tid & (kWave - 1);
+  const int wv = tid / kWave;
+  const int64_t i0 = (int64_t)blockIdx.x * kUpdTile;
+  const int64_t i1 = min(i0 + (int64_t)kUpdTile, P);
+  const int M = (int)*count;
+  auto gk = [&](int64_t m) { return cks[m]; };
+  auto gi = [&](int64_t m) { return cvs[m]; };
+  if (wv < 2) {  // waves 0 and 1: the two ends of the window
+    const int64_t at = wv == 0 ? i0 : i1 - 1;
+    const int64_t w = wave_lower_pair(gk, gi, 0, M, keys_prev[at], wv == 0 ? i0 : i1);
+    if (lane == 0) window[wv] = (int)w;
+  }
+  __syncthreads();
+  const int wlo = window[0];
+  const int whi = max(window[0], window[1]);  // (reversed only for unsorted keys_prev)
+  const int wn = whi - wlo;
+  const bool staged = wn <= kWindowCap;
+  if (staged) {
+    for (int m = tid; m < wn; m += kSortBS) {
+      wk[m] = cks[wlo + m];
+      wi[m] = cvs[wlo + m];
+    }
+  }
+  __syncthreads();
+  auto sk = [&](int m) { return wk[m]; };
+  auto si = [&](int m) { return wi[m]; };
+  const int64_t g0 = (int64_t)blockIdx.x * kGroupsPerTile;
+#pragma unroll 2
+  for (int j = 0; j < kSortIPT; ++j) {
+    const int64_t grp = g0 + j * kSortWaves + wv;
+    const int64_t i = grp * kWave + lane;
+    if (i >= P) break;  // the last group of the last workgroup only
+    const unsigned long long m = mask[grp];
+    if ((m >> lane) & 1ull) continue;
+    const uint32_t key = keys_prev[i];
+    const int below = staged ? wlo + lower_pair(sk, si, 0, wn, key, i)
+                             : lower_pair(gk, gi, wlo, whi, key, i);
+    const int64_t unchanged_before = i - ((int64_t)gpre[grp] + lanes_below(m));
+    int64_t pos = unchanged_before + below;
+    pos = pos < 0 ? 0 : (pos >= P ? P - 1 : pos);  // in range even for unsorted keys_prev
+    keys_out[pos] = key;
+    perm_out[pos] = (int32_t)i;
+  }
+}
+
+struct UpdLayout {
+  unsigned long long* mask;
+  uint32_t *blk, *gpre, *count, *ck0, *ck1, *look, *totals, *tile_ctr;
+  int32_t *cv0, *cv1;
+  size_t bytes;
+};
+
+UpdLayout upd_layout(void* ws, int64_t P) {
+  const int64_t n_tiles = (P + kSortTile - 1) / kSortTile;
+  const int64_t n_groups = (P + kWave - 1) / kWave;
+  char* w = (char*)ws;
+  UpdLayout L;
+  size_t off = 0;
+  auto take = [&](size_t n) {
+    char* q = w ? w + off : nullptr;
+    off += align_up(n);
+    return q;
+  };
+  L.mask = (unsigned long long*)take((size_t)n_groups * 8);
+  L.blk = (uint32_t*)take((size_t)n_tiles * 4);
+  L.gpre = (uint32_t*)take((size_t)n_groups * 4);
+  L.count = (uint32_t*)take(4);
+  L.ck0 = (uint32_t*)take((size_t)P * 4);
+  L.cv0 = (int32_t*)take((size_t)P * 4);
+  L.ck1 = (uint32_t*)take((size_t)P * 4);
+  L.cv1 = (int32_t*)take((size_t)P * 4);
+  L.look = (uint32_t*)take((size_t)kMaxPasses * n_tiles * kRadix * 4);
+  L.totals = (uint32_t*)take((size_t)kMaxPasses * kRadix * 4);
+  L.tile_ctr = (uint32_t*)take((size_t)kMaxPasses * 4);
+  L.bytes = off;
+  return L;
+}
+
+}  // namespace
+
+size_t sort_update_workspace_bytes(int64_t P) { return upd_layout(nullptr, P).bytes; }
+
+hipError_t launch_sort_update(const GridDev& g, int64_t P, const float* x,
+                              const uint32_t* keys_prev, uint32_t* keys_out, int32_t* perm_out,
+                              void* ws, int32_t* status, hipStream_t stream) {
+  if (P == 0) return hipSuccess;
+  const UpdLayout L = upd_layout(ws, P);
+  const int n_tiles = (int)((P + kSortTile - 1) / kSortTile);
+  const int passes = (sort_key_bits(g) + 7) / 8;
+  if (passes > kMaxPasses) return hipErrorInvalidValue;
+  upd_mask_kernel<<<n_tiles, kSortBS, 0, stream>>>(g, P, x, keys_prev, L.mask, L.blk, status);
+  upd_scan_kernel<<<1, 1024, 0, stream>>>(L.blk, n_tiles, L.count, L.totals, L.tile_ctr);
+  upd_compact_kernel<<<n_tiles, kSortBS, 0, stream>>>(g, P, x, L.mask, L.blk, L.gpre, L.ck0,
+                                                      L.cv0);
+  // stable radix sort of the changed pairs (their number known on the device only)
+  const int counted_grid = n_tiles < kCountedGrid ? n_tiles : kCountedGrid;
+  counted_hist_kernel<<<counted_grid, kSortBS, 0, stream>>>(L.ck0, L.count, passes, n_tiles,
+                                                            L.look, L.totals);
+  uint32_t* ks = L.ck0;
+  int32_t* vs = L.cv0;
+  uint32_t* kd = L.ck1;
+  int32_t* vd = L.cv1;
+  for (int pass = 0; pass < passes; ++pass) {
+    counted_scatter_kernel<<<counted_grid, kSortBS, 0, stream>>>(
+        ks, vs, kd, vd, L.count, 8 * pass, L.totals + pass * kRadix,
+        L.look + (size_t)pass * n_tiles * kRadix, L.tile_ctr + pass, status);
+    uint32_t* kt = ks;
+    ks = kd;
+    kd = kt;
+    int32_t* vt = vs;
+    vs = vd;
+    vd = vt;
+  }
+  upd_place_unchanged_kernel<<<n_tiles, kSortBS, 0, stream>>>(P, keys_prev, L.mask, L.gpre, ks, vs,
+                                                              L.count, keys_out, perm_out);
+  upd_place_changed_kernel<<<1024, kSortBS, 0, stream>>>(P, keys_prev, L.mask, L.gpre, ks, vs,
+                                                         L.count, keys_out, perm_out);
+  return hipGetLastError();
 }
 
 }  // namespace polypic

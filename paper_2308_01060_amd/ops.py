@@ -85,6 +85,26 @@ def polypic_sort(grid: polypic_grid, x: torch.Tensor, keys_out: torch.Tensor,
         _ptr(status_dev, torch.int32, 1, "status_dev"), _stream()), "polypic_sort")
 
 
+def polypic_sort_update_workspace_bytes(grid: polypic_grid, P: int) -> int:
+    out = ctypes.c_size_t(0)
+    check(_lib.load().polypic_sort_update_workspace_bytes(ctypes.byref(grid), int(P),
+                                                          ctypes.byref(out)),
+          "polypic_sort_update_workspace_bytes")
+    return int(out.value)
+
+
+def polypic_sort_update(grid: polypic_grid, x: torch.Tensor, keys_prev: torch.Tensor,
+                        keys_out: torch.Tensor, perm_out: torch.Tensor, ws: torch.Tensor,
+                        status_dev: Optional[torch.Tensor] = None) -> None:
+    """Re-sort after a step (keys_prev: the previous sort's keys, in the current slot order)."""
+    P = x.numel() // 3
+    check(_lib.load().polypic_sort_update(
+        ctypes.byref(grid), P, _ptr(x, torch.float32, 3 * P, "x"), _keys_ptr(keys_prev, P),
+        _keys_ptr(keys_out, P), _ptr(perm_out, torch.int32, P, "perm_out"),
+        _ptr(ws, torch.uint8, ws.numel(), "ws"), ws.numel(),
+        _ptr(status_dev, torch.int32, 1, "status_dev"), _stream()), "polypic_sort_update")
+
+
 def polypic_p2g_workspace_bytes(grid: polypic_grid, P: int) -> int:
     out = ctypes.c_size_t(0)
     check(_lib.load().polypic_p2g_workspace_bytes(ctypes.byref(grid), int(P), ctypes.byref(out)),

@@ -8,7 +8,9 @@ stream:
     polypic_sort -> polypic_p2g -> polypic_grid_update -> polypic_g2p
 
 G2P writes the new state in sorted order, so after a step the arrays are in
-cell order and the next sort is close to the identity.  G2P reads no
+cell order and the next sort is close to the identity: from the second step on,
+``sort`` re-sorts incrementally (``polypic_sort_update``: only the particles
+whose cell changed are sorted, then merged; same result as a full sort).  G2P reads no
 coefficients, so by default it writes the new ones over the array P2G read
 (``coeff_in_place``): one coefficient array instead of two (1.4 GB saved at
 27 modes and 4.19 M particles).  The set takes ownership of the tensors it is
@@ -30,7 +32,8 @@ class ParticleSet:
                  mass: Optional[torch.Tensor] = None, uniform_mass: float = 1.0,
                  F: Optional[torch.Tensor] = None, dt: float = 1e-4,
                  gravity: Sequence[float] = (0.0, -9.8, 0.0), bc_layers: int = 1,
-                 device: str = "cuda", track_order: bool = True, coeff_in_place: bool = True):
+                 device: str = "cuda", track_order: bool = True, coeff_in_place: bool = True,
+                 incremental_sort: bool = True):
         if n_modes not in ops.ALLOWED_N_MODES:
             raise ValueError("n_modes must be one of 1, 4, 8, 27")
         self.grid = grid
@@ -63,6 +66,13 @@ class ParticleSet:
         self.perm = torch.empty(P, dtype=torch.int32, device=dev)
         self.ws = torch.empty(max(1, ops.polypic_sort_workspace_bytes(grid, P)),
                               dtype=torch.uint8, device=dev)
+        # incremental re-sort: the previous keys (in the current slot order) and its workspace
+        self.incremental_sort = bool(incremental_sort)
+        self.keys_prev = torch.empty_like(self.keys) if self.incremental_sort else None
+        self.resort_ws = (torch.empty(max(1, ops.polypic_sort_update_workspace_bytes(grid, P)),
+                                      dtype=torch.uint8, device=dev)
+                          if self.incremental_sort else None)
+        self.resort_ready = False  # the keys describe the current slot order
         self.p2g_ws = torch.empty(max(1, ops.polypic_p2g_workspace_bytes(grid, P)),
                                   dtype=torch.uint8, device=dev)
         self.status = torch.zeros(1, dtype=torch.int32, device=dev)
@@ -70,8 +80,14 @@ class ParticleSet:
         self.order = torch.arange(P, dtype=torch.int64, device=dev)
 
     # -- the four calls of one step
-    def sort(self):
-        ops.polypic_sort(self.grid, self.x, self.keys, self.perm, self.ws, self.status)
+    def sort(self, full: bool = False):
+        """Cell-key sort of the current positions; incremental after a step in sort order."""
+        if self.resort_ready and not full:
+            self.keys, self.keys_prev = self.keys_prev, self.keys
+            ops.polypic_sort_update(self.grid, self.x, self.keys_prev, self.keys, self.perm,
+                                    self.resort_ws, self.status)
+        else:
+            ops.polypic_sort(self.grid, self.x, self.keys, self.perm, self.ws, self.status)
 
     def p2g(self, use_perm: bool = True, use_keys: bool = True):
         """P2G in sort order (use_perm); use_keys hands the sorted keys over as well, which the
@@ -112,6 +128,8 @@ class ParticleSet:
             self.F, self.F_next = self.F_next, self.F
         if use_perm and self.track_order:
             self.order = self.order[self.perm.long()]
+        # after an advected step in sort order, slot i was sorted under keys[i]
+        self.resort_ready = self.incremental_sort and use_perm
 
     def step(self):
         """One full step: sort, P2G, grid update, G2P + advection, then swap buffers."""

@@ -266,3 +266,21 @@ def test_backward_entry_points_reject_bad_arguments():
     assert p2gb(xg=None) == 1
     assert p2gb(umass=float("inf")) == 1
     assert p2gb(P=0, x=None, c=None, cg=None, xg=None) == 0
+
+
+def test_sort_update_rejects_bad_arguments():
+    lib = _lib.load()
+    g = grid()
+    out = ctypes.c_size_t(0)
+    assert lib.polypic_sort_update_workspace_bytes(ctypes.byref(g), 1000, ctypes.byref(out)) == 0
+    need = out.value
+    assert need >= 24 * 1000
+    other = ctypes.c_void_p(0x2000)
+    call = lambda x=FAKE, kp=FAKE, ko=other, pm=FAKE, ws=FAKE, wsb=need: lib.polypic_sort_update(  # noqa
+        ctypes.byref(g), 1000, x, kp, ko, pm, ws, wsb, None, None)
+    assert call(kp=None) == 1
+    assert call(x=None) == 1
+    assert call(ko=FAKE) == 1                 # keys_prev aliases keys_out
+    assert call(wsb=need - 1) == _lib.POLYPIC_ENOSPACE
+    assert lib.polypic_sort_update(ctypes.byref(g), 0, None, None, None, None, None, 0, None,
+                                   None) == 0

@@ -423,3 +423,98 @@ def test_p2g_lane_groups_with_every_cell_size(n_modes):
             assert rel(host(ps.grid_mom).reshape(Q_ref.shape), Q_ref) <= TOL_NORMWISE, cfg
     finally:
         pp.polypic_set_p2g_config(n_modes, -1, 256)
+
+
+# ---------------------------------------------------------------- incremental re-sort
+
+def _resort(pp, g, x, keys_prev, P):
+    keys = torch.zeros(P, dtype=torch.int32, device="cuda")
+    perm = torch.zeros(P, dtype=torch.int32, device="cuda")
+    ws = torch.empty(pp.ops.polypic_sort_update_workspace_bytes(g, P), dtype=torch.uint8,
+                     device="cuda")
+    status = torch.zeros(1, dtype=torch.int32, device="cuda")
+    pp.ops.polypic_sort_update(g, x, keys_prev, keys, perm, ws, status)
+    torch.cuda.synchronize()
+    return keys, perm, int(status.item())
+
+
+def _full_sort(pp, g, x, P):
+    keys = torch.empty(P, dtype=torch.int32, device="cuda")
+    perm = torch.empty(P, dtype=torch.int32, device="cuda")
+    ws = torch.empty(pp.ops.polypic_sort_workspace_bytes(g, P), dtype=torch.uint8, device="cuda")
+    pp.ops.polypic_sort(g, x, keys, perm, ws)
+    torch.cuda.synchronize()
+    return keys, perm
+
+
+def test_resort_over_steps_equals_full_sort_and_oracle():
+    """Ten steps of a moving set: every step's incremental re-sort gives exactly the full
+    sort's and the oracle's stable argsort."""
+    pp = require_gpu()
+    s = W.config0(6)
+    pp_, g, ps = particle_set(s, 8, dt=2e-3)          # larger dt: more cell changes per step
+    og = oracle_grid(g)
+    changed_total = 0
+    for k in range(10):
+        x_before = host(ps.x).copy()
+        ps.sort()
+        torch.cuda.synchronize()
+        keys_ref, perm_ref = O.sort_keys(og, x_before)
+        assert np.array_equal(host(ps.keys).view(np.uint32), keys_ref), k
+        assert np.array_equal(host(ps.perm), perm_ref), k
+        if k > 0:
+            changed_total += int((host(ps.keys_prev).view(np.uint32) !=
+                                  O.morton_key(O.stencil_base(og, x_before)[0])).sum())
+        ps.p2g()
+        ps.grid_update()
+        ps.g2p()
+        ps.swap()
+    assert changed_total > 0                 # the incremental path did reorder something
+    assert ps.status_flags() == 0
+
+
+@pytest.mark.parametrize("case", ["half", "all", "none", "out_of_range"])
+def test_resort_cases(case):
+    pp = require_gpu()
+    s = W.random_scene(9, 32, 50000)
+    g = pp.grid_from_spec(s.grid)
+    og = oracle_grid(g)
+    P = s.P
+    x0 = dev(s.x)
+    keys0, perm0 = _full_sort(pp, g, x0, P)
+    xs = x0[:, perm0.long()].contiguous()            # the particle arrays in sort order
+    rng = np.random.default_rng(3)
+    xh = host(xs).copy()
+    if case == "half":
+        pick = rng.random(P) < 0.5
+        xh[:, pick] += (rng.integers(-2, 3, size=(3, int(pick.sum()))) / 32.0).astype(np.float32)
+        xh = np.clip(xh, 2.5 / 32, 1 + 1.5 / 32).astype(np.float32)
+    elif case == "all":
+        xh[0] += np.float32(1.0 / 32)
+    elif case == "out_of_range":
+        pick = rng.choice(P, size=50, replace=False)
+        xh[1, pick] = -3.0
+    xn = dev(xh)
+    note(f"resort case {case}: P={P}")
+    keys, perm, status = _resort(pp, g, xn, keys0, P)
+    keys_f, perm_f = _full_sort(pp, g, xn, P)
+    assert torch.equal(keys, keys_f) and torch.equal(perm, perm_f)
+    if case != "out_of_range":
+        keys_ref, perm_ref = O.sort_keys(og, xh)
+        assert np.array_equal(host(perm), perm_ref)
+        assert status == 0
+    else:
+        assert status & 1
+
+
+def test_resort_with_unordered_previous_keys_is_flagged_and_in_range():
+    pp = require_gpu()
+    s = W.random_scene(10, 24, 20000)
+    g = pp.grid_from_spec(s.grid)
+    P = s.P
+    x = dev(s.x)
+    bogus = torch.randint(0, 1 << 20, (P,), dtype=torch.int32, device="cuda")  # not ascending
+    keys, perm, status = _resort(pp, g, x, bogus, P)
+    assert status & 2
+    p = host(perm)
+    assert p.min() >= 0 and p.max() < P
