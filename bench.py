@@ -8,6 +8,9 @@ Synthetic seeded inputs (workloads.config1); no dataset is involved.
 
 A step is one pass of the whole transfer path on device-resident data:
     cell-key radix sort -> P2G (27 modes) -> grid update -> G2P + advection
+From the second step on, the sort is the exact re-sort from the previous step's
+keys (polypic_sort_update, bit-identical to a full sort); the full sort's time on
+the same state is reported beside it.
 The timed region is K consecutive steps between two device synchronisations;
 per-phase times come from HIP events recorded on the stream the kernels run on.
 
@@ -389,6 +392,16 @@ def main():
     ms_per_step = wall * 1e3 / args.steps
     value = P * args.steps / wall
     transfer_ms = phase["p2g"] + phase["g2p"]
+    # The timed steps sort with polypic_sort_update (the previous step's keys; same
+    # result as a full sort).  For reference, the full sort of the same state:
+    full_sort_ms = []
+    for _ in range(10):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        ps.sort(full=True)
+        e1.record()
+        torch.cuda.synchronize()
+        full_sort_ms.append(e0.elapsed_time(e1))
 
     # 4-mode (APIC) comparison at the same size
     apic = None
@@ -447,12 +460,14 @@ def main():
         "data": "synthetic (seeded jittered dam-break block, workloads.config1)",
         "config": {"workload": workload, "n_modes": n_modes, "particles": P,
                    "grid_nodes": list(scene.grid.nodes), "ppc": 8, "dt": scene.dt,
-                   "step": "sort + p2g + grid_update + g2p(+advection)"},
+                   "step": "sort (re-sort) + p2g + grid_update + g2p(+advection)"},
         "p2g_g2p_transfers_per_s": P / (transfer_ms * 1e-3),
         "p2g_config": {"path": "cells" if p2g_choice.path == 1 else "bricks",
                        "block": p2g_choice.block, "schedule": p2g_choice.schedule,
                        "chosen_by": "polypic_autotune_p2g"},
         "phase_ms": {k: round(v, 4) for k, v in phase.items()},
+        "sort": {"timed": "polypic_sort_update (exact re-sort from the previous step's keys)",
+                 "full_sort_ms": round(float(np.median(full_sort_ms)), 4)},
         "apic_4mode": apic,
         "bwd_fwd_ratio": None if adj is None else round(adj["bwd_fwd_ratio"], 3),
         "adjoint": adj,

@@ -66,13 +66,15 @@ class ParticleSet:
         self.perm = torch.empty(P, dtype=torch.int32, device=dev)
         self.ws = torch.empty(max(1, ops.polypic_sort_workspace_bytes(grid, P)),
                               dtype=torch.uint8, device=dev)
-        # incremental re-sort: the previous keys (in the current slot order) and its workspace
+        # incremental re-sort: slot_keys[i] = the key slot i of the particle arrays was sorted
+        # under (valid once a step has permuted the arrays by a sort), and its workspace
         self.incremental_sort = bool(incremental_sort)
-        self.keys_prev = torch.empty_like(self.keys) if self.incremental_sort else None
+        self.slot_keys = torch.empty_like(self.keys) if self.incremental_sort else None
+        self.slot_keys_valid = False
+        self._keys_are_slot_keys = False  # set by swap(): `keys` now describes the slot order
         self.resort_ws = (torch.empty(max(1, ops.polypic_sort_update_workspace_bytes(grid, P)),
                                       dtype=torch.uint8, device=dev)
                           if self.incremental_sort else None)
-        self.resort_ready = False  # the keys describe the current slot order
         self.p2g_ws = torch.empty(max(1, ops.polypic_p2g_workspace_bytes(grid, P)),
                                   dtype=torch.uint8, device=dev)
         self.status = torch.zeros(1, dtype=torch.int32, device=dev)
@@ -81,10 +83,15 @@ class ParticleSet:
 
     # -- the four calls of one step
     def sort(self, full: bool = False):
-        """Cell-key sort of the current positions; incremental after a step in sort order."""
-        if self.resort_ready and not full:
-            self.keys, self.keys_prev = self.keys_prev, self.keys
-            ops.polypic_sort_update(self.grid, self.x, self.keys_prev, self.keys, self.perm,
+        """Cell-key sort of the current positions into keys / perm: the exact re-sort from
+        the keys the current slot order was sorted under when they are known, else (or with
+        full=True) the full sort.  Both give the same result."""
+        if self._keys_are_slot_keys:
+            self.keys, self.slot_keys = self.slot_keys, self.keys
+            self._keys_are_slot_keys = False
+            self.slot_keys_valid = True
+        if self.slot_keys_valid and not full:
+            ops.polypic_sort_update(self.grid, self.x, self.slot_keys, self.keys, self.perm,
                                     self.resort_ws, self.status)
         else:
             ops.polypic_sort(self.grid, self.x, self.keys, self.perm, self.ws, self.status)
@@ -128,8 +135,10 @@ class ParticleSet:
             self.F, self.F_next = self.F_next, self.F
         if use_perm and self.track_order:
             self.order = self.order[self.perm.long()]
-        # after an advected step in sort order, slot i was sorted under keys[i]
-        self.resort_ready = self.incremental_sort and use_perm
+        # G2P wrote slot i from particle perm[i]: slot i was sorted under keys[i].  (Without
+        # the permutation the slot order is unchanged, and so is what describes it.)
+        if self.incremental_sort and use_perm:
+            self._keys_are_slot_keys = True
 
     def step(self):
         """One full step: sort, P2G, grid update, G2P + advection, then swap buffers."""

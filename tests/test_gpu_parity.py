@@ -463,13 +463,42 @@ def test_resort_over_steps_equals_full_sort_and_oracle():
         assert np.array_equal(host(ps.keys).view(np.uint32), keys_ref), k
         assert np.array_equal(host(ps.perm), perm_ref), k
         if k > 0:
-            changed_total += int((host(ps.keys_prev).view(np.uint32) !=
+            changed_total += int((host(ps.slot_keys).view(np.uint32) !=
                                   O.morton_key(O.stencil_base(og, x_before)[0])).sum())
         ps.p2g()
         ps.grid_update()
         ps.g2p()
         ps.swap()
     assert changed_total > 0                 # the incremental path did reorder something
+    assert ps.status_flags() == 0
+
+
+def test_resort_after_a_sort_without_a_step_keeps_its_reference():
+    """A sort that no step follows (the autotuner's) leaves the particle arrays in place, so
+    the next re-sort still starts from the keys the slot order was sorted under: few slots
+    count as changed, and the result is still the exact stable sort."""
+    pp = require_gpu()
+    s = W.config0(7)
+    _, g, ps = particle_set(s, 8, dt=2e-3)
+    og = oracle_grid(g)
+    for _ in range(2):
+        ps.step()
+    ps.sort()                                        # no step after this one
+    for k in range(2):
+        x_before = host(ps.x).copy()
+        ps.sort()
+        torch.cuda.synchronize()
+        keys_ref, perm_ref = O.sort_keys(og, x_before)
+        assert np.array_equal(host(ps.keys).view(np.uint32), keys_ref), k
+        assert np.array_equal(host(ps.perm), perm_ref), k
+        slot_ref = O.morton_key(O.stencil_base(og, x_before)[0])
+        changed = float((host(ps.slot_keys).view(np.uint32) != slot_ref).mean())
+        note(f"  step {k}: fraction of slots changed {changed:.4f}")
+        assert changed < 0.1, changed
+        ps.p2g()
+        ps.grid_update()
+        ps.g2p()
+        ps.swap()
     assert ps.status_flags() == 0
 
 
