@@ -8,9 +8,13 @@ Synthetic seeded inputs (workloads.config1); no dataset is involved.
 
 A step is one pass of the whole transfer path on device-resident data:
     cell-key radix sort -> P2G (27 modes) -> grid update -> G2P + advection
-From the second step on, the sort is the exact re-sort from the previous step's
-keys (polypic_sort_update, bit-identical to a full sort); the full sort's time on
-the same state is reported beside it.
+run as sort -> grid update -> G2P2G: the G2P of a step and the P2G of the next
+are one kernel (polypic_g2p2g), which scatters the new state into the grid while
+its coefficients are in registers (they are still written, not read back).  A
+run with separate P2G and G2P calls is reported beside it ("unfused").  From the
+second step on, the sort is the exact re-sort from the previous step's keys
+(polypic_sort_update, bit-identical to a full sort); the full sort's time on the
+same state is reported beside it.
 The timed region is K consecutive steps between two device synchronisations;
 per-phase times come from HIP events recorded on the stream the kernels run on.
 
@@ -51,9 +55,16 @@ def g2p_bytes_per_particle(n_modes: int) -> int:
     return 12 + 12 * n_modes + 12
 
 
+#   G2P fused with the next P2G reads x (12 B) and the permutation (4 B), writes x (12 B)
+#   and 3 * n_modes coefficients; the coefficients are not read back.
+def g2p2g_bytes_per_particle(n_modes: int) -> int:
+    return 12 + 4 + 12 + 12 * n_modes
+
+
 KERNEL_SOURCES = {
     "p2g": "paper_2308_01060_amd/csrc/polypic_p2g.hip",
     "g2p": "paper_2308_01060_amd/csrc/polypic_g2p.hip",
+    "g2p2g": "paper_2308_01060_amd/csrc/polypic_g2p2g.hip",
 }
 
 
@@ -99,6 +110,10 @@ def parse_args():
     ap.add_argument("--no-apic", action="store_true", help="skip the 4-mode comparison run")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the bwd/fwd timing")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-scenes timing")
+    ap.add_argument("--no-unfused", action="store_true",
+                    help="skip the reference run with separate P2G and G2P calls")
+    ap.add_argument("--unfused-steps", type=int, default=30,
+                    help="timed steps of the unfused reference run")
     ap.add_argument("--batch-steps", type=int, default=10, help="steps in the batched timing")
     ap.add_argument("--adjoint-steps", type=int, default=10,
                     help="differentiable steps in the bwd/fwd timing")
@@ -121,30 +136,42 @@ def calib_copy():
 
 
 def time_steps(ps, steps: int, torch):
-    """Run `steps` full steps; returns (wall_s, per-phase mean ms dict)."""
-    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(5)] for _ in range(steps)]
+    """Run `steps` full steps; returns (wall_s, per-phase mean ms dict).
+
+    Fused sets (the default) step as sort -> grid update -> G2P2G, the P2G of each
+    step having been done by the G2P2G of the step before; unfused sets as
+    sort -> P2G -> grid update -> G2P."""
+    if ps.fused:
+        if not ps.grid_current:
+            raise RuntimeError("a fused set needs its grid current before the timed steps")
+        names = ("sort", "grid_update", "g2p2g")
+        calls = (ps.sort, ps.grid_update, ps.g2p2g)
+    else:
+        names = ("sort", "p2g", "grid_update", "g2p")
+        calls = (ps.sort, ps.p2g, ps.grid_update, ps.g2p)
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(len(names) + 1)]
+          for _ in range(steps)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(steps):
         e = ev[k]
         e[0].record()
-        ps.sort()
-        e[1].record()
-        ps.p2g()
-        e[2].record()
-        ps.grid_update()
-        e[3].record()
-        ps.g2p()
-        e[4].record()
+        for j, call in enumerate(calls):
+            call()
+            e[j + 1].record()
         ps.swap()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    names = ("sort", "p2g", "grid_update", "g2p")
     phase = {n: 0.0 for n in names}
     for e in ev:
         for j, n in enumerate(names):
             phase[n] += e[j].elapsed_time(e[j + 1])
     return wall, {n: v / steps for n, v in phase.items()}
+
+
+def transfer_ms(phase) -> float:
+    """Time of the two transfers of a step: P2G + G2P, or the fused G2P2G."""
+    return phase["g2p2g"] if "g2p2g" in phase else phase["p2g"] + phase["g2p"]
 
 
 def adjoint_timing(pp, torch, W, cells: int, n_modes: int, n_steps: int, reps: int = 3):
@@ -297,7 +324,7 @@ def batch_timing(pp, torch, W, n_modes: int, steps: int, warmup: int):
         sets.append(pp.ParticleSet(grids[k], n_modes, bs.x[:, sl].contiguous(),
                                    bs.coeff[:, :, sl].contiguous(), dt=sc.dt,
                                    gravity=sc.gravity, bc_layers=sc.bc_layers,
-                                   track_order=False))
+                                   track_order=False, fused=False))  # as the batched calls
     del bs
 
     def per_scene_step():
@@ -391,7 +418,7 @@ def main():
         raise RuntimeError(f"device status flags {ps.status_flags()} during the benchmark")
     ms_per_step = wall * 1e3 / args.steps
     value = P * args.steps / wall
-    transfer_ms = phase["p2g"] + phase["g2p"]
+    t_transfer = transfer_ms(phase)
     # The timed steps sort with polypic_sort_update (the previous step's keys; same
     # result as a full sort).  For reference, the full sort of the same state:
     full_sort_ms = []
@@ -416,22 +443,47 @@ def main():
         w4, ph4 = time_steps(ps4, args.steps, torch)
         apic = {"n_modes": 4, "ms_per_step": w4 * 1e3 / args.steps,
                 "transfers_per_s": P * args.steps / w4,
-                "p2g_g2p_transfers_per_s": P / ((ph4["p2g"] + ph4["g2p"]) * 1e-3),
+                "p2g_g2p_transfers_per_s": P / (transfer_ms(ph4) * 1e-3),
                 "p2g_config": {"path": "cells" if choice4.path == 1 else "bricks",
                                "block": choice4.block, "schedule": choice4.schedule},
                 "phase_ms": {k: round(v, 4) for k, v in ph4.items()}}
         del ps4, c4
 
+    # The same workload stepped unfused (separate P2G and G2P), for reference
+    unfused = None
+    if not args.no_unfused:
+        psu = pp.ParticleSet(g, n_modes, torch.from_numpy(scene.x).cuda(),
+                             torch.from_numpy(np.ascontiguousarray(scene.coeff[:, :n_modes])).cuda(),
+                             dt=scene.dt, gravity=scene.gravity, bc_layers=scene.bc_layers,
+                             track_order=False, fused=False)
+        for _ in range(args.warmup):
+            psu.step()
+        psu.autotune()
+        wu, phu = time_steps(psu, args.unfused_steps, torch)
+        unfused = {"ms_per_step": wu * 1e3 / args.unfused_steps,
+                   "transfers_per_s": P * args.unfused_steps / wu,
+                   "p2g_g2p_transfers_per_s": P / (transfer_ms(phu) * 1e-3),
+                   "steps": args.unfused_steps,
+                   "phase_ms": {k: round(v, 4) for k, v in phu.items()}}
+        del psu
+
     # roofline of the dominant kernel (HIP-event durations of its launches)
-    dom = "p2g" if phase["p2g"] >= phase["g2p"] else "g2p"
-    bpp = p2g_bytes_per_particle(n_modes) if dom == "p2g" else g2p_bytes_per_particle(n_modes)
+    if ps.fused:
+        dom = "g2p2g"
+        bpp = g2p2g_bytes_per_particle(n_modes)
+        note = ("event time of the polypic_g2p2g call (grid clear and the fused kernel); bytes: "
+                "x read, permutation, x and coefficients written")
+    elif phase["p2g"] >= phase["g2p"]:
+        dom, bpp = "p2g", p2g_bytes_per_particle(n_modes)
+        note = "event time of the polypic_p2g call (grid clear, tile list and P2G kernels)"
+    else:
+        dom, bpp = "g2p", g2p_bytes_per_particle(n_modes)
+        note = "event time of the polypic_g2p call (one kernel)"
     achieved = bpp * P / (phase[dom] * 1e-3) / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": measured_traffic(dom, workload), "kernel": dom,
-                "bytes_per_particle": bpp,
-                "note": ("event time of the polypic_p2g call (grid clear, tile list and P2G kernels)"
-                         if dom == "p2g" else "event time of the polypic_g2p call (one kernel)")}
+                "bytes_per_particle": bpp, "note": note}
 
     adj = None
     if not args.no_adjoint:
@@ -460,12 +512,14 @@ def main():
         "data": "synthetic (seeded jittered dam-break block, workloads.config1)",
         "config": {"workload": workload, "n_modes": n_modes, "particles": P,
                    "grid_nodes": list(scene.grid.nodes), "ppc": 8, "dt": scene.dt,
-                   "step": "sort (re-sort) + p2g + grid_update + g2p(+advection)"},
-        "p2g_g2p_transfers_per_s": P / (transfer_ms * 1e-3),
+                   "step": "sort (re-sort) + grid_update + g2p2g (G2P + advection fused with the "
+                           "next step's P2G)"},
+        "p2g_g2p_transfers_per_s": P / (t_transfer * 1e-3),
         "p2g_config": {"path": "cells" if p2g_choice.path == 1 else "bricks",
                        "block": p2g_choice.block, "schedule": p2g_choice.schedule,
                        "chosen_by": "polypic_autotune_p2g"},
         "phase_ms": {k: round(v, 4) for k, v in phase.items()},
+        "unfused": unfused,
         "sort": {"timed": "polypic_sort_update (exact re-sort from the previous step's keys)",
                  "full_sort_ms": round(float(np.median(full_sort_ms)), 4)},
         "apic_4mode": apic,

@@ -272,6 +272,31 @@ int32_t polypic_g2p(const polypic_grid* grid, int64_t P, int32_t n_modes, float 
                     float* mass_out, int32_t* status_dev, void* stream);
 
 /* ------------------------------------------------------------------------
+ * G2P of a step fused with the P2G of the next.  Equal, up to the order of the
+ * floating-point sums, to
+ *     polypic_g2p(grid, P, n_modes, dt, grid_vel, x_in, perm, x_out, coeff_out,
+ *                 F_in, F_out, mass_in, mass_out, ...)
+ *     polypic_p2g(grid, P, n_modes, x_out, mass_out (or uniform_mass), uniform_mass,
+ *                 coeff_out, perm = NULL, ..., grid_mass, grid_mom, accumulate = 0, ...)
+ * i.e. the new state's mass and momentum (Eq. 1, 4, 13) are scattered from the
+ * coefficients while they are still in registers: the coefficient array is
+ * written but not read back (28 + 12 n_modes instead of 40 + 24 n_modes bytes
+ * per particle).  Not in the paper: a reordering of its transfers.
+ *
+ * x_out[3][P] is required (the scatter is at the advected positions);
+ * F_in/F_out and mass_in/mass_out are optional pairs as in polypic_g2p; without
+ * mass_in every particle has mass uniform_mass.  grid_mass[N] and grid_mom[3][N]
+ * are overwritten (cleared first).  They, x_out, F_out and mass_out may not
+ * overlap grid_vel, x_in, perm, F_in or mass_in; coeff_out may be the
+ * coefficient array of the preceding P2G (nothing reads coefficients here).
+ * ------------------------------------------------------------------------ */
+int32_t polypic_g2p2g(const polypic_grid* grid, int64_t P, int32_t n_modes, float dt,
+                      const float* grid_vel, const float* x_in, const int32_t* perm,
+                      float* x_out, float* coeff_out, const float* F_in, float* F_out,
+                      const float* mass_in, float* mass_out, float uniform_mass,
+                      float* grid_mass, float* grid_mom, int32_t* status_dev, void* stream);
+
+/* ------------------------------------------------------------------------
  * Adjoint (reverse mode) of one step.  For a scalar loss L of the step's
  * outputs, these propagate dL/d(output) to dL/d(input) through the same
  * operations as above, in reverse order:

@@ -36,9 +36,12 @@ from .ops import (  # noqa: E402
     grid_from_spec,
     make_grid,
     polypic_g2p,
+    polypic_g2p2g,
     polypic_grid_update,
     polypic_p2g,
     polypic_sort,
+    polypic_sort_update,
+    polypic_sort_update_workspace_bytes,
     polypic_sort_workspace_bytes,
 )
 from .stepper import ParticleSet  # noqa: E402
@@ -48,7 +51,8 @@ from .autograd import PolyPICSteps, polypic_steps  # noqa: E402
 __all__ = [
     "LIB_PATH", "PolyPICError", "polypic_grid", "ops", "make_grid", "grid_from_spec",
     "polypic_sort", "polypic_sort_workspace_bytes", "polypic_p2g", "polypic_grid_update",
-    "polypic_g2p", "polypic_autotune_p2g", "polypic_get_p2g_config", "polypic_set_p2g_config",
+    "polypic_g2p", "polypic_g2p2g", "polypic_sort_update",
+    "polypic_sort_update_workspace_bytes", "polypic_autotune_p2g", "polypic_get_p2g_config", "polypic_set_p2g_config",
     "polypic_get_g2p_schedule", "polypic_set_g2p_schedule", "P2GChoice", "Batch",
     "POLYPIC_P2G_BRICKS", "POLYPIC_P2G_CELLS", "POLYPIC_P2G_DEFAULT", "POLYPIC_SCHED_LINEAR",
     "POLYPIC_SCHED_PERSISTENT", "POLYPIC_SCHED_XCD",

@@ -45,6 +45,7 @@ EXPORTED = (
     "polypic_get_g2p_schedule",
     "polypic_grid_update",
     "polypic_g2p",
+    "polypic_g2p2g",
     "polypic_g2p_backward",
     "polypic_grid_update_backward",
     "polypic_p2g_backward",
@@ -165,6 +166,8 @@ def load() -> ctypes.CDLL:
     lib.polypic_grid_update.argtypes = [G, f32, ctypes.POINTER(f32), i32, P, P, P, P]
     lib.polypic_g2p.restype = i32
     lib.polypic_g2p.argtypes = [G, i64, i32, f32, P, P, P, P, P, P, P, P, P, P, P]
+    lib.polypic_g2p2g.restype = i32
+    lib.polypic_g2p2g.argtypes = [G, i64, i32, f32, P, P, P, P, P, P, P, P, P, f32, P, P, P, P]
     lib.polypic_g2p_backward.restype = i32
     lib.polypic_g2p_backward.argtypes = [G, i64, i32, f32, P, P, P, P, P, P, i32, P, P, P]
     lib.polypic_grid_update_backward.restype = i32

@@ -511,6 +511,66 @@ int32_t polypic_g2p(const polypic_grid* grid, int64_t P, int32_t n_modes, float 
   return from_hip(launch_g2p(a, n_modes, (hipStream_t)stream));
 }
 
+namespace {
+// [a, a + na) and [b, b + nb) floats overlap (either may be null)
+bool overlaps(const void* a, int64_t na, const void* b, int64_t nb) {
+  if (!a || !b) return false;
+  const char* pa = (const char*)a;
+  const char* pb = (const char*)b;
+  return pa < pb + nb * 4 && pb < pa + na * 4;
+}
+}  // namespace
+
+int32_t polypic_g2p2g(const polypic_grid* grid, int64_t P, int32_t n_modes, float dt,
+                      const float* grid_vel, const float* x_in, const int32_t* perm,
+                      float* x_out, float* coeff_out, const float* F_in, float* F_out,
+                      const float* mass_in, float* mass_out, float uniform_mass,
+                      float* grid_mass, float* grid_mom, int32_t* status_dev, void* stream) {
+  int32_t st = check_grid(grid);
+  if (st) return st;
+  if ((st = check_P(P))) return st;
+  if (!valid_modes(n_modes) || !isfinite(dt)) return POLYPIC_EINVAL;
+  if (!grid_mass || !grid_mom) return POLYPIC_EINVAL;
+  if (!mass_in && !isfinite(uniform_mass)) return POLYPIC_EINVAL;
+  if (P > 0 && (!grid_vel || !x_in || !x_out || !coeff_out)) return POLYPIC_EINVAL;
+  if ((F_in == nullptr) != (F_out == nullptr)) return POLYPIC_EINVAL;
+  if (mass_out && !mass_in) return POLYPIC_EINVAL;
+  const int64_t N = n_nodes(grid);
+  // outputs written while other threads still read the inputs
+  const void* ins[5] = {grid_vel, x_in, perm, F_in, mass_in};
+  const int64_t nin[5] = {3 * N, 3 * P, P, 9 * P, P};
+  const void* outs[5] = {grid_mass, grid_mom, x_out, F_out, mass_out};
+  const int64_t nout[5] = {N, 3 * N, 3 * P, 9 * P, P};
+  for (int o = 0; o < 5; ++o)
+    for (int k = 0; k < 5; ++k)
+      if (overlaps(outs[o], nout[o], ins[k], nin[k])) return POLYPIC_EINVAL;
+  if (overlaps(grid_mass, N, grid_mom, 3 * N)) return POLYPIC_EINVAL;
+  G2P2GArgs a;
+  a.g = to_dev(grid);
+  a.P = P;
+  a.dt = dt;
+  a.dx = grid->dx;
+  clamp_bounds(grid, a.lo, a.hi);
+  a.gv = grid_vel;
+  a.x_in = x_in;
+  a.perm = perm;
+  a.x_out = x_out;
+  a.coeff_out = coeff_out;
+  a.F_in = F_in;
+  a.F_out = F_out;
+  a.mass_in = mass_in;
+  a.mass_out = mass_out;
+  a.uniform_mass = uniform_mass;
+  a.gm = grid_mass;
+  a.gp0 = grid_mom;
+  a.gp1 = grid_mom + N;
+  a.gp2 = grid_mom + 2 * N;
+  a.status = status_dev;
+  a.gstride = N;
+  discard_stale_error();
+  return from_hip(launch_g2p2g(a, n_modes, (hipStream_t)stream));
+}
+
 int32_t polypic_g2p_backward(const polypic_grid* grid, int64_t P, int32_t n_modes, float dt,
                              const float* grid_vel, const float* x_in, const int32_t* perm,
                              const float* coeff_out_grad, const float* x_out_grad,

@@ -141,6 +141,72 @@ __device__ __forceinline__ Proj1D proj_g2p(float t) {
   return P;
 }
 
+// ---------------------------------------------------------------- G2P projection
+template <int NR>
+__device__ constexpr bool need_kx(int kx) {
+  return has_mode<NR>(kx, 0, 0) || has_mode<NR>(kx, 0, 1) || has_mode<NR>(kx, 0, 2) ||
+         has_mode<NR>(kx, 1, 0) || has_mode<NR>(kx, 1, 1) || has_mode<NR>(kx, 1, 2) ||
+         has_mode<NR>(kx, 2, 0) || has_mode<NR>(kx, 2, 1) || has_mode<NR>(kx, 2, 2);
+}
+
+template <int NR>
+__device__ constexpr bool need_kxky(int kx, int ky) {
+  return has_mode<NR>(kx, ky, 0) || has_mode<NR>(kx, ky, 1) || has_mode<NR>(kx, ky, 2);
+}
+
+// c[r] = sum_j Px[kx][jx] Py[ky][jy] Pz[kz][jz] v[jx + 3 jy + 9 jz] for r < NR
+template <int NR>
+__device__ __forceinline__ void project_modes(const float (&v)[27], const Proj1D& px,
+                                              const Proj1D& py, const Proj1D& pz,
+                                              float (&c)[27]) {
+  float A[3][3][3];  // [kx][jy][jz]
+#pragma unroll
+  for (int kx = 0; kx < 3; ++kx) {
+    if (!need_kx<NR>(kx)) continue;
+#pragma unroll
+    for (int jy = 0; jy < 3; ++jy)
+#pragma unroll
+      for (int jz = 0; jz < 3; ++jz) {
+        const float* vv = v + 3 * jy + 9 * jz;
+        if (kx == 2)  // (1/2, -1, 1/2): additions only
+          A[kx][jy][jz] = 0.5f * (vv[0] + vv[2]) - vv[1];
+        else
+          A[kx][jy][jz] = fmaf(px.pr[kx][2], vv[2], fmaf(px.pr[kx][1], vv[1], px.pr[kx][0] * vv[0]));
+      }
+  }
+  float B[3][3][3];  // [kx][ky][jz]
+#pragma unroll
+  for (int kx = 0; kx < 3; ++kx)
+#pragma unroll
+    for (int ky = 0; ky < 3; ++ky) {
+      if (!need_kxky<NR>(kx, ky)) continue;
+#pragma unroll
+      for (int jz = 0; jz < 3; ++jz) {
+        if (ky == 2)
+          B[kx][ky][jz] = 0.5f * (A[kx][0][jz] + A[kx][2][jz]) - A[kx][1][jz];
+        else
+          B[kx][ky][jz] = fmaf(py.pr[ky][2], A[kx][2][jz],
+                               fmaf(py.pr[ky][1], A[kx][1][jz], py.pr[ky][0] * A[kx][0][jz]));
+      }
+    }
+#pragma unroll
+  for (int kx = 0; kx < 3; ++kx)
+#pragma unroll
+    for (int ky = 0; ky < 3; ++ky)
+#pragma unroll
+      for (int kz = 0; kz < 3; ++kz) {
+        if (!has_mode<NR>(kx, ky, kz)) continue;
+        float s;
+        if (kz == 2)
+          s = 0.5f * (B[kx][ky][0] + B[kx][ky][2]) - B[kx][ky][1];
+        else
+          s = fmaf(pz.pr[kz][2], B[kx][ky][2],
+                   fmaf(pz.pr[kz][1], B[kx][ky][1], pz.pr[kz][0] * B[kx][ky][0]));
+        c[mode_index(kx, ky, kz)] = s;
+      }
+}
+
+
 // ---------------------------------------------------------------- P2G mode evaluation
 template <int NR>
 __device__ constexpr bool any_kz(int kx, int ky) {
@@ -487,6 +553,17 @@ __device__ __forceinline__ void expand_rows(const float (&c)[27], const Rows& Rx
 // doubles.  With the lanes of a wavefront spread over the 64 cells of a tile,
 // the 32 cells handled by each half-wavefront fall on 32 distinct LDS bank
 // pairs for every stencil node.
+constexpr int kBrickKMAX = 3;  // bricks (tiles) per workgroup in LDS
+
+// Tile id of a base node: 4^3-node tile coordinates, plus the scene relative
+// to the chunk's first scene in the high word (zero for one scene).
+__device__ __forceinline__ uint64_t brick_tile_id(int s_rel, int b0, int b1, int b2) {
+  return ((uint64_t)(uint32_t)s_rel << 32) | (uint64_t)((uint32_t)(b0 >> 2) |
+                                                       ((uint32_t)(b1 >> 2) << 10) |
+                                                       ((uint32_t)(b2 >> 2) << 20));
+}
+constexpr uint64_t kNoTile = ~0ull;
+
 constexpr int kBrickT = 4;  // tile edge in cells
 constexpr int kBrickSY = 8;
 constexpr int kBrickSZ = 68;

@@ -1,0 +1,334 @@
+// G2P of one step fused with the P2G of the next, for gfx950.
+//
+// G2P reads no coefficients: the new ones come from the grid velocity alone
+// (Eq. 6-8, section 3.3), and the next step's P2G (Eq. 1, 4, 13) is their only
+// reader.  One thread per output slot i (particle perm[i]) therefore does:
+//
+//   * G2P at the particle's position: gather the 27 node velocities per
+//     component, project them onto the first n_modes modes, write the new
+//     coefficients, the advected position x' (and F', mass) at slot i;
+//   * P2G at x' with the coefficients still in registers: the stencil of x',
+//     the weighted mode rows, and the nodal mass and momentum streamed node by
+//     node into FP64 LDS bricks of 4^3-node tiles (lane groups that share a
+//     base node add across lanes first), then one float atomic per brick node
+//     and channel into the next grid.
+//
+// The coefficient array is written once and never read back, instead of being
+// written by G2P and read again by the next step's P2G: the particle stream
+// drops from 40 + 24 n_modes to 28 + 12 n_modes bytes per particle.  The result
+// is the G2P call followed by the P2G call on its outputs, up to the order of
+// the floating-point sums.
+#include "polypic_internal.hpp"
+
+namespace polypic {
+
+namespace {
+
+// Slot of a thread: lane groups of G = 2^LG consecutive slots (which in cell
+// order usually share a cell, hence a base node), the groups of a wavefront
+// spread over the workgroup's chunk so that they sit in different cells and
+// their brick atomics do not collide.
+template <int LG, int NW>
+__device__ __forceinline__ int fused_slot(int tid) {
+  const int lane = tid & (kWave - 1);
+  const int wv = tid / kWave;
+  return (((lane >> LG) * NW + wv) << LG) | (lane & ((1 << LG) - 1));
+}
+
+template <int NR, int BS>
+__global__ __launch_bounds__(BS) void g2p2g_kernel(G2P2GArgs a) {
+  constexpr int NW = BS / kWave;
+  constexpr int LG = NR >= 8 ? 2 : 1;  // log2 of the lane-group size
+  __shared__ double brick[kBrickKMAX * 4 * kBrickV];  // [brick][channel][node]
+  __shared__ uint64_t tile_of[BS];                    // by processing slot
+  __shared__ int seg_of[BS];
+  __shared__ uint64_t seg_tile[kBrickKMAX];
+  __shared__ int wave_heads[NW];
+  __shared__ uint64_t run_tile[kWave];  // tile of each of the first 64 runs
+  __shared__ int run_brick[kWave];      // brick (distinct-tile index) of each run
+  __shared__ int n_bricks;
+
+  const int tid = threadIdx.x;
+  const int lane = tid & (kWave - 1);
+  const int wv = tid / kWave;
+  const int slot = fused_slot<LG, NW>(tid);
+  const size_t Ps = (size_t)a.P;
+  const GridDev& g = a.g;
+  const int nx = g.nx, ny = g.ny, nz = g.nz;
+  const int nxny = nx * ny;
+  const int64_t i = (int64_t)blockIdx.x * BS + slot;
+  const bool in = i < a.P;
+  // a caller permutation is clamped into [0, P): a bad one gives wrong results, never a fault
+  const int p = in ? (a.perm ? min(max(a.perm[i], 0), (int)(a.P - 1)) : (int)i) : 0;
+
+  // ---------------------------------------------------------------- G2P
+  float xp[3] = {0.f, 0.f, 0.f};
+  if (in) {
+    xp[0] = a.x_in[p];
+    xp[1] = a.x_in[Ps + p];
+    xp[2] = a.x_in[2 * Ps + p];
+  }
+  int b0, b1, b2;
+  float t0, t1, t2;
+  bool ok = stencil_axis(xp[0], g.ox, g.inv_dx, nx, b0, t0);
+  ok &= stencil_axis(xp[1], g.oy, g.inv_dx, ny, b1, t1);
+  ok &= stencil_axis(xp[2], g.oz, g.inv_dx, nz, b2, t2);
+  if (in && !ok) raise_flag(a.status, kFlagRange);
+  const bool gather = in && ok;
+
+  float c[3][27];  // the new coefficients, kept for the P2G half
+  float xn[3];     // the advected position
+  // Output rows go through LDS (the bricks are not in use yet) so that every
+  // wavefront writes 64 consecutive slots (measured, 27 modes, 4.19 M particles:
+  // 2.0 ms with the rows written from the spread slots, 0.47 ms staged): row k of
+  // a round is stage[k * BS + slot], read back as stage[k * BS + tid].
+  float* const stage = reinterpret_cast<float*>(brick);
+  static_assert(28 * BS * sizeof(float) <= sizeof(brick), "staging fits in the bricks");
+  const int64_t i_out = (int64_t)blockIdx.x * BS + tid;  // slot this thread writes out
+  const bool out_ok = i_out < a.P;
+  {
+    const Proj1D px = proj_g2p(t0);
+    const Proj1D py = proj_g2p(t1);
+    const Proj1D pz = proj_g2p(t2);
+    const int64_t gbase = (int64_t)(b2 * ny + b1) * nx + b0;
+#pragma unroll
+    for (int ax = 0; ax < 3; ++ax) {
+      if (gather) {
+        const float* vg = a.gv + (size_t)ax * a.gstride + gbase;
+        float v[27];
+#pragma unroll
+        for (int jz = 0; jz < 3; ++jz)
+#pragma unroll
+          for (int jy = 0; jy < 3; ++jy)
+#pragma unroll
+            for (int jx = 0; jx < 3; ++jx) v[jx + 3 * jy + 9 * jz] = vg[jz * nxny + jy * nx + jx];
+        project_modes<NR>(v, px, py, pz, c[ax]);
+      } else {
+#pragma unroll
+        for (int r = 0; r < 27; ++r) c[ax][r] = 0.0f;
+      }
+#pragma unroll
+      for (int r = NR; r < 27; ++r) c[ax][r] = 0.0f;
+      float x1 = fmaf(a.dt, c[ax][0], xp[ax]);
+      x1 = fmaxf(x1, a.lo[ax]);
+      xn[ax] = fminf(x1, a.hi[ax]);
+      // rows of this component: the NR coefficients and x'; written once, never
+      // re-read here, so streamed past the caches the gathers use
+      float* const co = a.coeff_out + (size_t)ax * NR * Ps;
+      float* const xo = a.x_out + (size_t)ax * Ps;
+#pragma unroll
+      for (int r = 0; r < NR; ++r) stage[r * BS + slot] = c[ax][r];
+      stage[NR * BS + slot] = xn[ax];
+      __syncthreads();
+      if (out_ok) {
+#pragma unroll
+        for (int r = 0; r < NR; ++r)
+          __builtin_nontemporal_store(stage[r * BS + tid], co + (size_t)r * Ps + i_out);
+        __builtin_nontemporal_store(stage[NR * BS + tid], xo + i_out);
+      }
+      __syncthreads();  // the next component overwrites the stage
+    }
+  }
+  float m = 0.0f;
+  if (in) m = a.mass_in ? a.mass_in[p] : a.uniform_mass;
+  if (a.F_in || a.mass_out) {  // (uniform: kernel arguments)
+    // F' = F + dt C F with C_ab = c[a][1 + b] / dx; rows 0-8 F', row 9 the mass
+    float Fn[9];
+    if (in && a.F_in) {
+      float F[9];
+#pragma unroll
+      for (int e = 0; e < 9; ++e) F[e] = a.F_in[(size_t)e * Ps + p];
+      const float sdt = a.dt / a.dx;
+#pragma unroll
+      for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int col = 0; col < 3; ++col) {
+          float acc = 0.0f;
+          if constexpr (NR >= 4) {
+#pragma unroll
+            for (int k = 0; k < 3; ++k) acc = fmaf(c[r][1 + k], F[3 * k + col], acc);
+          }
+          Fn[3 * r + col] = fmaf(sdt, acc, F[3 * r + col]);
+        }
+    } else {
+#pragma unroll
+      for (int e = 0; e < 9; ++e) Fn[e] = 0.0f;
+    }
+#pragma unroll
+    for (int e = 0; e < 9; ++e) stage[e * BS + slot] = Fn[e];
+    stage[9 * BS + slot] = m;
+    __syncthreads();
+    if (out_ok) {
+      if (a.F_out) {
+#pragma unroll
+        for (int e = 0; e < 9; ++e)
+          __builtin_nontemporal_store(stage[e * BS + tid], a.F_out + (size_t)e * Ps + i_out);
+      }
+      if (a.mass_out) __builtin_nontemporal_store(stage[9 * BS + tid], a.mass_out + i_out);
+    }
+    __syncthreads();  // the bricks are cleared next
+  }
+
+  // ---------------------------------------------------------------- P2G of x'
+  bool valid = in;
+  int c0 = 0, c1 = 0, c2 = 0;
+  float u0 = 0.f, u1 = 0.f, u2 = 0.f;
+  if (valid) {
+    bool ok2 = stencil_axis(xn[0], g.ox, g.inv_dx, nx, c0, u0);
+    ok2 &= stencil_axis(xn[1], g.oy, g.inv_dx, ny, c1, u1);
+    ok2 &= stencil_axis(xn[2], g.oz, g.inv_dx, nz, c2, u2);
+    if (!ok2) {  // (x' is clamped into the grid: only for a grid too small for a stencil)
+      raise_flag(a.status, kFlagRange);
+      valid = false;
+    }
+  }
+  if (!valid) m = 0.0f;
+  tile_of[slot] = valid ? brick_tile_id(0, c0, c1, c2) : kNoTile;
+  for (int k = tid; k < kBrickKMAX * 4 * kBrickV; k += BS) brick[k] = 0.0;
+  __syncthreads();
+
+  // Bricks are given per distinct tile, not per run: the chunk is in the order of
+  // the previous positions, so a particle that changed cell can split a run of
+  // equal tiles, and per-run segments would then spill the rest of the chunk to
+  // HBM.  Runs of equal tiles in slot order (thread t looks at slot t), then the
+  // first kRuns runs' tiles deduplicated in order of appearance by wavefront 0.
+  constexpr int kRuns = kWave;
+  {
+    const uint64_t tt = tile_of[tid];
+    const bool head = tt != kNoTile && (tid == 0 || tile_of[tid - 1] != tt);
+    const unsigned long long hb = __ballot(head);
+    if (lane == 0) wave_heads[wv] = __popcll(hb);
+    __syncthreads();
+    int pre = 0;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) pre += (w < wv) ? wave_heads[w] : 0;
+    const int run = pre + lanes_below(hb) + (head ? 1 : 0) - 1;
+    seg_of[tid] = run;  // run index for now (-1 before the first valid slot)
+    if (head && run < kRuns) run_tile[run] = tt;
+  }
+  __syncthreads();
+  int nruns = 0;
+#pragma unroll
+  for (int w = 0; w < NW; ++w) nruns += wave_heads[w];
+  const int nr = nruns < kRuns ? nruns : kRuns;
+  if (wv == 0) {
+    const uint64_t mine = lane < nr ? run_tile[lane] : kNoTile;
+    int first_same = lane;  // first run with this run's tile
+    for (int q = nr - 1; q >= 0; --q)
+      if (q < lane && run_tile[q] == mine) first_same = q;
+    const bool first = lane < nr && first_same == lane;
+    const unsigned long long fb = __ballot(first);
+    // distinct index of a first run = first runs before it; a later run takes its
+    // first run's index (all lanes hold a value, so the shuffle is well defined)
+    const int d_first = lanes_below(fb);
+    const int d = __shfl(d_first, first_same, kWave);
+    if (lane < nr) run_brick[lane] = d;
+    if (first && d < kBrickKMAX) seg_tile[d] = mine;
+    if (lane == 0) n_bricks = __popcll(fb);
+  }
+  __syncthreads();
+  const int run_slot = seg_of[slot];
+  // brick of this slot's run; runs past kRuns, and tiles past the brick budget, go to HBM
+  const int seg = run_slot < 0 ? -1 : (run_slot < kRuns ? run_brick[run_slot] : kBrickKMAX);
+  const int nseg = n_bricks;
+
+  // lanes that share this lane's segment and base node: the pair (lane ^ 1) and,
+  // with groups of 4, the quad; every lane runs the exchanges (an invalid one with
+  // zero mass), since a DPP read from a lane that did not execute it is undefined
+  const int mykey = valid ? ((c2 * 1024 + c1) * 1024 + c0) : -1 - lane;
+  const int pair_key = pair_swap_i(mykey), pair_seg = pair_swap_i(seg);
+  const bool pair = mykey == pair_key && seg == pair_seg;
+  bool quad = false;
+  if constexpr (LG == 2) {
+    const int quad_pair = quad_swap_i((int)pair), quad_key = quad_swap_i(mykey);
+    const int quad_seg = quad_swap_i(seg);
+    quad = pair && quad_pair != 0 && mykey == quad_key && seg == quad_seg;
+  }
+  const bool emit = valid && (quad ? (lane & 3) == 0 : (!pair || (lane & 1) == 0));
+  {
+    const Rows Rx = p2g_rows_scaled(basis_p2g(u0), m);
+    const Rows Ry = p2g_rows_scaled(basis_p2g(u1), 1.0f);
+    const Rows Rz = p2g_rows_scaled(basis_p2g(u2), 1.0f);
+    const bool lds = seg < kBrickKMAX;
+    const int lbase = (c0 & 3) + kBrickSY * (c1 & 3) + kBrickSZ * (c2 & 3);
+    const int64_t gbase = (int64_t)(c2 * ny + c1) * nx + c0;
+    double* const lb = brick + (lds ? max(seg, 0) : 0) * 4 * kBrickV + lbase;
+    float* const gch[4] = {a.gm + gbase, a.gp0 + gbase, a.gp1 + gbase, a.gp2 + gbase};
+    auto emitter = [&](int ch) {
+      double* const lbc = lb + ch * kBrickV;
+      float* const gc = gch[ch];
+      return [=](int jx, int jy, int jz, float v) {
+        const float v2 = v + __int_as_float(pair_swap_i(__float_as_int(v)));
+        float w = pair ? v2 : v;
+        if constexpr (LG == 2) {
+          const float v4 = v2 + __int_as_float(quad_swap_i(__float_as_int(v2)));
+          w = quad ? v4 : w;
+        }
+        if (!emit) return;
+        if (lds)
+          atomicAdd(lbc + jx + kBrickSY * jy + kBrickSZ * jz, (double)w);
+        else
+          atomicAdd(gc + jz * nxny + jy * nx + jx, w);
+      };
+    };
+    {  // mass: m W_ip
+      float one[27];
+#pragma unroll
+      for (int r = 0; r < 27; ++r) one[r] = r == 0 ? 1.0f : 0.0f;
+      stream_modes<1>(one, Rx, Ry, Rz, emitter(0));
+    }
+    stream_modes<NR>(c[0], Rx, Ry, Rz, emitter(1));
+    stream_modes<NR>(c[1], Rx, Ry, Rz, emitter(2));
+    stream_modes<NR>(c[2], Rx, Ry, Rz, emitter(3));
+  }
+  __syncthreads();
+
+  // flush: one global float atomic per channel per non-zero brick node
+  const int nb = nseg < kBrickKMAX ? nseg : kBrickKMAX;
+  for (int k = tid; k < nb * 4 * kBrickV; k += BS) {
+    const int sc4 = k / kBrickV;  // brick * 4 + channel
+    const int idx = k - sc4 * kBrickV;
+    const int sb = sc4 >> 2;
+    const int ch = sc4 & 3;
+    const int lz = idx / kBrickSZ;
+    const int rem = idx - lz * kBrickSZ;
+    const int ly = rem / kBrickSY;
+    const int lx = rem - ly * kBrickSY;
+    if (lx > kBrickT + 1 || ly > kBrickT + 1) continue;  // padding
+    const float v = (float)brick[k];
+    if (v == 0.0f) continue;
+    const uint32_t tc = (uint32_t)seg_tile[sb];
+    const int gx = (int)(tc & 1023u) * kBrickT + lx;
+    const int gy = (int)((tc >> 10) & 1023u) * kBrickT + ly;
+    const int gz = (int)(tc >> 20) * kBrickT + lz;
+    if (gx < nx && gy < ny && gz < nz) {
+      float* const d = ch == 0 ? a.gm : ch == 1 ? a.gp0 : ch == 2 ? a.gp1 : a.gp2;
+      atomicAdd(d + ((int64_t)(gz * ny + gy) * nx + gx), v);
+    }
+  }
+}
+
+template <int NR>
+hipError_t launch_nr(const G2P2GArgs& a, hipStream_t stream) {
+  constexpr int BS = 256;
+  const unsigned blocks = (unsigned)((a.P + BS - 1) / BS);
+  g2p2g_kernel<NR, BS><<<blocks, BS, 0, stream>>>(a);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_g2p2g(const G2P2GArgs& a, int n_modes, hipStream_t stream) {
+  hipError_t e = launch_grid_clear(a.gm, a.gp0, (int64_t)a.g.nx * a.g.ny * a.g.nz, nullptr,
+                                   stream);
+  if (e != hipSuccess || a.P == 0) return e;
+  switch (n_modes) {
+    case 1: return launch_nr<1>(a, stream);
+    case 4: return launch_nr<4>(a, stream);
+    case 8: return launch_nr<8>(a, stream);
+    case 27: return launch_nr<27>(a, stream);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace polypic

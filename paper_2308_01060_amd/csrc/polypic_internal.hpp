@@ -114,6 +114,32 @@ hipError_t launch_g2p(const G2PArgs& a, int n_modes, hipStream_t stream);
 hipError_t launch_g2p_batch(const G2PArgs& a, const SceneDev* table, int n_scenes, int n_modes,
                             hipStream_t stream);
 
+// ---- G2P fused with the next step's P2G
+struct G2P2GArgs {
+  GridDev g;
+  int64_t P;
+  float dt;
+  float dx;
+  float lo[3], hi[3];    // clamp bounds for advection
+  const float* gv;       // [3][N] grid velocity of this step
+  const float* x_in;     // [3][P]
+  const int32_t* perm;   // [P] or nullptr
+  float* x_out;          // [3][P]
+  float* coeff_out;      // [3][NR][P]
+  const float* F_in;     // [9][P] or nullptr
+  float* F_out;
+  const float* mass_in;  // [P] or nullptr (then uniform_mass)
+  float* mass_out;       // [P] or nullptr
+  float uniform_mass;
+  float* gm;             // next grid mass [N] (cleared by the launcher)
+  float* gp0;            // next grid momentum, [3][N] contiguous from gp0
+  float* gp1;
+  float* gp2;
+  int32_t* status;
+  int64_t gstride;       // channel stride of gv
+};
+hipError_t launch_g2p2g(const G2P2GArgs& a, int n_modes, hipStream_t stream);
+
 // ---- adjoint
 struct GridUpdateBackArgs {
   int nx, ny, nz;

@@ -35,17 +35,6 @@ namespace polypic {
 
 namespace {
 
-constexpr int kBrickKMAX = 3;                    // bricks (tiles) per workgroup in LDS
-
-// Tile id of a base node: 4^3-node tile coordinates, plus the scene relative
-// to the chunk's first scene in the high word (zero for one scene).
-__device__ __forceinline__ uint64_t brick_tile_id(int s_rel, int b0, int b1, int b2) {
-  return ((uint64_t)(uint32_t)s_rel << 32) | (uint64_t)((uint32_t)(b0 >> 2) |
-                                                       ((uint32_t)(b1 >> 2) << 10) |
-                                                       ((uint32_t)(b2 >> 2) << 20));
-}
-constexpr uint64_t kNoTile = ~0ull;
-
 // Occupancy is bounded by LDS to 4 waves per SIMD (about 40 KB per 256-thread
 // workgroup); the launch bound holds the registers to the 128 that allow it.
 template <int NR, int BS, class Scenes>

@@ -218,6 +218,30 @@ def polypic_g2p(grid: polypic_grid, n_modes: int, dt: float, grid_vel: torch.Ten
         _ptr(status_dev, torch.int32, 1, "status_dev"), _stream()), "polypic_g2p")
 
 
+def polypic_g2p2g(grid: polypic_grid, n_modes: int, dt: float, grid_vel: torch.Tensor,
+                  x_in: torch.Tensor, x_out: torch.Tensor, coeff_out: torch.Tensor,
+                  grid_mass: torch.Tensor, grid_mom: torch.Tensor,
+                  perm: Optional[torch.Tensor] = None,
+                  F_in: Optional[torch.Tensor] = None, F_out: Optional[torch.Tensor] = None,
+                  mass_in: Optional[torch.Tensor] = None, mass_out: Optional[torch.Tensor] = None,
+                  uniform_mass: float = 1.0,
+                  status_dev: Optional[torch.Tensor] = None) -> None:
+    P = x_in.numel() // 3
+    N = n_nodes(grid)
+    check(_lib.load().polypic_g2p2g(
+        ctypes.byref(grid), P, int(n_modes), float(dt),
+        _ptr(grid_vel, torch.float32, 3 * N, "grid_vel"),
+        _ptr(x_in, torch.float32, 3 * P, "x_in"), _ptr(perm, torch.int32, P, "perm"),
+        _ptr(x_out, torch.float32, 3 * P, "x_out"),
+        _ptr(coeff_out, torch.float32, 3 * int(n_modes) * P, "coeff_out"),
+        _ptr(F_in, torch.float32, 9 * P, "F_in"), _ptr(F_out, torch.float32, 9 * P, "F_out"),
+        _ptr(mass_in, torch.float32, P, "mass_in"), _ptr(mass_out, torch.float32, P, "mass_out"),
+        float(uniform_mass),
+        _ptr(grid_mass, torch.float32, N, "grid_mass"),
+        _ptr(grid_mom, torch.float32, 3 * N, "grid_mom"),
+        _ptr(status_dev, torch.int32, 1, "status_dev"), _stream()), "polypic_g2p2g")
+
+
 def polypic_g2p_backward(grid: polypic_grid, n_modes: int, dt: float, grid_vel: torch.Tensor,
                          x_in: torch.Tensor, coeff_out_grad: torch.Tensor,
                          grid_vel_grad: torch.Tensor, x_in_grad: torch.Tensor,

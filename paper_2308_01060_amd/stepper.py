@@ -7,6 +7,11 @@ stream:
 
     polypic_sort -> polypic_p2g -> polypic_grid_update -> polypic_g2p
 
+or, fused (the default), ``polypic_g2p2g`` in place of the G2P of one step and the
+P2G of the next: G2P reads no coefficients, and the next P2G is their only reader,
+so the new state is scattered into the grid while its coefficients are still in
+registers (a step is then sort -> grid update -> G2P2G).
+
 G2P writes the new state in sorted order, so after a step the arrays are in
 cell order and the next sort is close to the identity: from the second step on,
 ``sort`` re-sorts incrementally (``polypic_sort_update``: only the particles
@@ -33,7 +38,7 @@ class ParticleSet:
                  F: Optional[torch.Tensor] = None, dt: float = 1e-4,
                  gravity: Sequence[float] = (0.0, -9.8, 0.0), bc_layers: int = 1,
                  device: str = "cuda", track_order: bool = True, coeff_in_place: bool = True,
-                 incremental_sort: bool = True):
+                 incremental_sort: bool = True, fused: bool = True):
         if n_modes not in ops.ALLOWED_N_MODES:
             raise ValueError("n_modes must be one of 1, 4, 8, 27")
         self.grid = grid
@@ -80,6 +85,11 @@ class ParticleSet:
         self.status = torch.zeros(1, dtype=torch.int32, device=dev)
         self.track_order = bool(track_order)
         self.order = torch.arange(P, dtype=torch.int64, device=dev)
+        # fused stepping: G2P scatters the new state into the grid at once (polypic_g2p2g);
+        # grid_current says grid_mass / grid_mom hold the P2G of the current state
+        self.fused = bool(fused)
+        self.grid_current = False
+        self._next_grid_current = False
 
     # -- the four calls of one step
     def sort(self, full: bool = False):
@@ -105,6 +115,7 @@ class ParticleSet:
                         perm=self.perm if use_perm else None,
                         keys_sorted=self.keys if sorted_ else None,
                         ws=self.p2g_ws if sorted_ else None, status_dev=self.status)
+        self.grid_current = True
 
     def autotune(self):
         """Sort, then let the library time its P2G configurations on this set (synchronises)."""
@@ -124,6 +135,21 @@ class ParticleSet:
                         x_out=self.x_next if advect else None,
                         F_in=self.F, F_out=self.F_next,
                         mass_in=self.mass, mass_out=self.mass_next, status_dev=self.status)
+        self._next_grid_current = False
+
+    def g2p2g(self, use_perm: bool = True):
+        """G2P + advection, and the P2G of the new state into grid_mass / grid_mom (the grid
+        velocity has been computed from them already)."""
+        ops.polypic_g2p2g(self.grid, self.n_modes, self.dt, self.grid_vel, self.x, self.x_next,
+                          self.coeff_next, self.grid_mass, self.grid_mom,
+                          perm=self.perm if use_perm else None, F_in=self.F, F_out=self.F_next,
+                          mass_in=self.mass, mass_out=self.mass_next,
+                          uniform_mass=self.uniform_mass, status_dev=self.status)
+        self._next_grid_current = True
+
+    def invalidate_grid(self):
+        """Call after changing x, coeff or mass directly: the next fused step redoes P2G."""
+        self.grid_current = False
 
     def swap(self, use_perm: bool = True):
         self.x, self.x_next = self.x_next, self.x
@@ -139,13 +165,24 @@ class ParticleSet:
         # the permutation the slot order is unchanged, and so is what describes it.)
         if self.incremental_sort and use_perm:
             self._keys_are_slot_keys = True
+        self.grid_current = self._next_grid_current
+        self._next_grid_current = False
 
     def step(self):
-        """One full step: sort, P2G, grid update, G2P + advection, then swap buffers."""
+        """One full step: sort, P2G, grid update, G2P + advection, then swap buffers.  Fused
+        (default), the P2G of a step was done by the G2P of the step before (polypic_g2p2g),
+        so a step is sort, grid update, G2P2G -- with a P2G first when the grid is not
+        current (the first step)."""
         self.sort()
-        self.p2g()
-        self.grid_update()
-        self.g2p()
+        if self.fused:
+            if not self.grid_current:
+                self.p2g()
+            self.grid_update()
+            self.g2p2g()
+        else:
+            self.p2g()
+            self.grid_update()
+            self.g2p()
         self.swap()
 
     def status_flags(self) -> int:

@@ -284,3 +284,27 @@ def test_sort_update_rejects_bad_arguments():
     assert call(wsb=need - 1) == _lib.POLYPIC_ENOSPACE
     assert lib.polypic_sort_update(ctypes.byref(g), 0, None, None, None, None, None, 0, None,
                                    None) == 0
+
+
+def test_g2p2g_rejects_bad_arguments():
+    lib = _lib.load()
+    g = grid()
+    far = lambda k: ctypes.c_void_p(0x10000000 + k * 0x1000000)  # noqa: E731  disjoint, fake
+    gv, x, xo, co, gm, gp = (far(k) for k in range(6))
+
+    def call(n_modes=27, dt=1e-4, gv=gv, x=x, perm=None, xo=xo, co=co, fi=None, fo=None,
+             mi=None, mo=None, um=1.0, gm=gm, gp=gp):
+        return lib.polypic_g2p2g(ctypes.byref(g), 10, n_modes, dt, gv, x, perm, xo, co, fi, fo,
+                                 mi, mo, um, gm, gp, None, None)
+    assert call(n_modes=5) == 1
+    assert call(dt=float("nan")) == 1
+    assert call(xo=None) == 1                   # the scatter needs the advected positions
+    assert call(co=None) == 1
+    assert call(gm=None) == 1 and call(gp=None) == 1
+    assert call(fi=far(7)) == 1                 # F_in without F_out
+    assert call(mo=far(8)) == 1                 # mass_out without mass_in
+    assert call(um=float("inf")) == 1
+    assert call(xo=x) == 1                      # x_out overlaps x_in
+    assert call(gm=gv) == 1                     # the next grid overlaps grid_vel
+    assert call(gp=ctypes.c_void_p(0x10000000 + 4 * 0x1000000 + 4)) == 1  # grid_mom over grid_mass
+    assert call(fi=far(7), fo=far(7)) == 1      # F_out overlaps F_in

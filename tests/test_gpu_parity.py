@@ -24,7 +24,8 @@ pytestmark = pytest.mark.gpu
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "tiny_exact.json")
 
 
-def particle_set(scene, n_modes, dt=None, gravity=None, bc_layers=None, with_mass=True):
+def particle_set(scene, n_modes, dt=None, gravity=None, bc_layers=None, with_mass=True,
+                 **kw):
     pp = require_gpu()
     g = pp.grid_from_spec(scene.grid)
     ps = pp.ParticleSet(
@@ -34,8 +35,18 @@ def particle_set(scene, n_modes, dt=None, gravity=None, bc_layers=None, with_mas
         F=dev(scene.F) if scene.F is not None else None,
         dt=scene.dt if dt is None else dt,
         gravity=scene.gravity if gravity is None else gravity,
-        bc_layers=scene.bc_layers if bc_layers is None else bc_layers)
+        bc_layers=scene.bc_layers if bc_layers is None else bc_layers, **kw)
     return pp, g, ps
+
+
+def check_grid_of_state(ps, og, n_modes, mass=None, uniform_mass=1.0):
+    """After a fused step the grid holds the P2G of the new state: compare it with the
+    oracle's P2G of the state the device wrote (teacher-forced positions and coefficients)."""
+    P = ps.P
+    M_ref, Q_ref = O.p2g(og, host(ps.x), host(ps.coeff).reshape(3, n_modes, P), n_modes,
+                         None if mass is None else host(mass), uniform_mass)
+    assert rel(host(ps.grid_mass).reshape(M_ref.shape), M_ref) <= TOL_NORMWISE
+    assert rel(host(ps.grid_mom).reshape(Q_ref.shape), Q_ref) <= TOL_NORMWISE
 
 
 # ---------------------------------------------------------------- sort
@@ -167,38 +178,138 @@ def test_g2p_parity(n_modes):
 
 @pytest.mark.parametrize("n_modes", O.ALLOWED_N_MODES)
 @pytest.mark.parametrize("variant", ["dt0_nowalls", "gravity_walls"])
-def test_full_step_parity(n_modes, variant):
+@pytest.mark.parametrize("fused", [False, True])
+def test_full_step_parity(n_modes, variant, fused):
     """Single-step parity case: sort -> P2G -> update -> G2P + advection on 32,768
-    particles, against the oracle's own step (its own sort, P2G, update, G2P)."""
+    particles, against the oracle's own step (its own sort, P2G, update, G2P).  Fused, the
+    G2P is polypic_g2p2g, after which the grid holds the P2G of the new state."""
     s = W.config0(0)
     dt, grav, bc = (0.0, (0.0, 0.0, 0.0), 0) if variant == "dt0_nowalls" else \
         (1e-4, (0.0, -9.8, 0.0), 1)
-    note(f"step parity: config0 n_modes={n_modes} {variant}")
-    pp, g, ps = particle_set(s, n_modes, dt=dt, gravity=grav, bc_layers=bc)
+    note(f"step parity: config0 n_modes={n_modes} {variant} fused={fused}")
+    pp, g, ps = particle_set(s, n_modes, dt=dt, gravity=grav, bc_layers=bc, fused=fused)
     ps.step()
     torch.cuda.synchronize()
+    assert ps.status_flags() == 0
     ref = O.step(oracle_grid(g), s.x, s.coeff, n_modes, dt, grav, bc, sort=True)
     assert np.array_equal(host(ps.order), ref["perm"].astype(np.int64))
-    assert rel(host(ps.grid_mass).reshape(ref["grid_mass"].shape), ref["grid_mass"]) <= TOL_NORMWISE
-    assert rel(host(ps.grid_mom).reshape(ref["grid_mom"].shape), ref["grid_mom"]) <= TOL_NORMWISE
+    if fused:
+        check_grid_of_state(ps, oracle_grid(g), n_modes)
+    else:
+        assert rel(host(ps.grid_mass).reshape(ref["grid_mass"].shape),
+                   ref["grid_mass"]) <= TOL_NORMWISE
+        assert rel(host(ps.grid_mom).reshape(ref["grid_mom"].shape),
+                   ref["grid_mom"]) <= TOL_NORMWISE
     c = host(ps.coeff).reshape(3, n_modes, s.P)
     assert rel(c, ref["coeff"]) <= TOL_NORMWISE
     assert ulp_ok(host(ps.x), ref["x"], 2, 1.0 + 4 / 32)
 
 
-def test_f_and_mass_follow_the_permutation():
+@pytest.mark.parametrize("fused", [False, True])
+def test_f_and_mass_follow_the_permutation(fused):
     """Fabric-style set: per-point masses and deformation gradients (F' = (I + dt C) F)."""
     s = W.config2_fabric(0, n=64, side=120)
-    note(f"fabric F update: P={s.P}")
-    pp, g, ps = particle_set(s, 27)
+    note(f"fabric F update: P={s.P} fused={fused}")
+    pp, g, ps = particle_set(s, 27, fused=fused)
     ps.step()
     torch.cuda.synchronize()
+    assert ps.status_flags() == 0
     ref = O.step(oracle_grid(g), s.x, s.coeff, 27, s.dt, s.gravity, s.bc_layers, mass=s.mass,
                  F=s.F, sort=True)
     assert np.array_equal(host(ps.mass), s.mass[ref["perm"]])
     assert rel(host(ps.coeff).reshape(3, 27, s.P), ref["coeff"]) <= TOL_NORMWISE
     assert rel(host(ps.F), ref["F"]) <= 1e-6
-    assert rel(host(ps.grid_mass).reshape(ref["grid_mass"].shape), ref["grid_mass"]) <= TOL_NORMWISE
+    if fused:
+        check_grid_of_state(ps, oracle_grid(g), 27, mass=ps.mass)
+    else:
+        assert rel(host(ps.grid_mass).reshape(ref["grid_mass"].shape),
+                   ref["grid_mass"]) <= TOL_NORMWISE
+
+
+# ---------------------------------------------------------------- G2P fused with the next P2G
+
+@pytest.mark.parametrize("n_modes", O.ALLOWED_N_MODES)
+def test_g2p2g_halves_against_the_oracle(n_modes):
+    """One polypic_g2p2g call: its G2P half against the oracle's G2P of the same grid
+    velocity (teacher-forced), its P2G half against the oracle's P2G of the state it wrote."""
+    pp = require_gpu()
+    s = W.config0(3)
+    _, g, ps = particle_set(s, n_modes, dt=1e-3)
+    og = oracle_grid(g)
+    note(f"g2p2g: n_modes={n_modes} P={s.P}")
+    ps.sort()
+    ps.p2g()
+    ps.grid_update()
+    torch.cuda.synchronize()
+    gv = host(ps.grid_vel).reshape(3, og.nz, og.ny, og.nx).astype(np.float64)
+    src = host(ps.perm)
+    ps.g2p2g()
+    torch.cuda.synchronize()
+    assert ps.status_flags() == 0
+    c_ref, x_ref, _ = O.g2p(og, gv, s.x[:, src], n_modes, ps.dt)
+    assert rel(host(ps.coeff_next).reshape(3, n_modes, s.P), c_ref) <= TOL_NORMWISE
+    assert ulp_ok(host(ps.x_next), x_ref, 2, 1.0 + 4 / 32)
+    M_ref, Q_ref = O.p2g(og, host(ps.x_next), host(ps.coeff_next).reshape(3, n_modes, s.P),
+                         n_modes)
+    assert rel(host(ps.grid_mass).reshape(M_ref.shape), M_ref) <= TOL_NORMWISE
+    assert rel(host(ps.grid_mom).reshape(Q_ref.shape), Q_ref) <= TOL_NORMWISE
+
+
+def test_g2p2g_with_mass_and_f_unsorted_ragged():
+    """Per-particle mass and F, no permutation (input order), a ragged particle count."""
+    pp = require_gpu()
+    s = W.config2_fabric(1, n=64, side=97)        # 9,409 points: not a multiple of 256
+    _, g, ps = particle_set(s, 27)
+    og = oracle_grid(g)
+    note(f"g2p2g with mass and F: P={s.P}")
+    ps.p2g(use_perm=False)
+    ps.grid_update()
+    torch.cuda.synchronize()
+    gv = host(ps.grid_vel).reshape(3, og.nz, og.ny, og.nx).astype(np.float64)
+    ps.g2p2g(use_perm=False)
+    torch.cuda.synchronize()
+    assert ps.status_flags() == 0
+    c_ref, x_ref, F_ref = O.g2p(og, gv, s.x, 27, ps.dt, s.F)
+    assert rel(host(ps.coeff_next).reshape(3, 27, s.P), c_ref) <= TOL_NORMWISE
+    assert rel(host(ps.F_next), F_ref) <= 1e-6
+    assert np.array_equal(host(ps.mass_next), s.mass)
+    M_ref, Q_ref = O.p2g(og, host(ps.x_next), host(ps.coeff_next).reshape(3, 27, s.P), 27,
+                         s.mass)
+    assert rel(host(ps.grid_mass).reshape(M_ref.shape), M_ref) <= TOL_NORMWISE
+    assert rel(host(ps.grid_mom).reshape(Q_ref.shape), Q_ref) <= TOL_NORMWISE
+
+
+def test_fused_steps_track_unfused_steps():
+    """Eight steps of a moving scene, fused and unfused, from the same state: the same
+    trajectory up to the order of the sums (and the permutations are identical)."""
+    pp = require_gpu()
+    s = W.config0(6)
+    _, g, a = particle_set(s, 8, dt=2e-3, fused=True)
+    _, _, b = particle_set(s, 8, dt=2e-3, fused=False)
+    for k in range(8):
+        a.step()
+        b.step()
+    torch.cuda.synchronize()
+    assert a.status_flags() == 0 and b.status_flags() == 0
+
+    def by_particle(ps, t):  # back to the original particle order
+        out = torch.empty_like(t)
+        out[..., ps.order] = t
+        return host(out)
+    assert rel(by_particle(a, a.x), by_particle(b, b.x)) <= 1e-6
+    assert rel(by_particle(a, a.coeff), by_particle(b, b.coeff)) <= 1e-5
+
+
+def test_g2p2g_empty_clears_the_grid():
+    pp = require_gpu()
+    g = pp.make_grid((12, 12, 12), 1 / 8)
+    gm = torch.full((12 ** 3,), 7.0, device="cuda")
+    gp = torch.full((3 * 12 ** 3,), 7.0, device="cuda")
+    gv = torch.zeros(3 * 12 ** 3, device="cuda")
+    e = torch.empty(0, device="cuda")
+    pp.polypic_g2p2g(g, 27, 1e-4, gv, e, e.clone(), e.clone(), gm, gp)
+    torch.cuda.synchronize()
+    assert float(gm.abs().max()) == 0.0 and float(gp.abs().max()) == 0.0
 
 
 # ---------------------------------------------------------------- exact fixture and edges
@@ -270,7 +381,7 @@ def test_degenerate_offsets_t_minus_half():
     u[0, P // 2:] = np.floor(u[0, P // 2:]) + 0.5        # t = -1/2 on x only
     x = (u / n).astype(np.float32)
     c = (rng.standard_normal((3, 27, P)) * 0.3).astype(np.float32)
-    ps = pp.ParticleSet(g, 27, dev(x), dev(c), dt=1e-4, bc_layers=1)
+    ps = pp.ParticleSet(g, 27, dev(x), dev(c), dt=1e-4, bc_layers=1, fused=False)
     ps.step()
     torch.cuda.synchronize()
     og = oracle_grid(g)
