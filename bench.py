@@ -324,7 +324,7 @@ def batch_timing(pp, torch, W, n_modes: int, steps: int, warmup: int):
         sets.append(pp.ParticleSet(grids[k], n_modes, bs.x[:, sl].contiguous(),
                                    bs.coeff[:, :, sl].contiguous(), dt=sc.dt,
                                    gravity=sc.gravity, bc_layers=sc.bc_layers,
-                                   track_order=False, fused=False))  # as the batched calls
+                                   track_order=False))  # fused, as the batched set
     del bs
 
     def per_scene_step():
@@ -353,8 +353,9 @@ def batch_timing(pp, torch, W, n_modes: int, steps: int, warmup: int):
                               "per_scene": round(single_ev, 4)},
         "p2g_config": {"block": choice.block, "schedule": choice.schedule,
                        "per_cu": choice.per_cu, "chosen_by": "polypic_batch_autotune"},
-        "note": "whole steps (sort, P2G, grid update, G2P + advection) of every scene; "
-                "per-scene form = one ParticleSet.step per scene, launched in turn",
+        "note": "whole fused steps (sort, grid update, G2P2G: G2P + advection + the next "
+                "P2G) of every scene; per-scene form = one ParticleSet.step per scene, "
+                "launched in turn",
     }
 
 

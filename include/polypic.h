@@ -405,6 +405,15 @@ int32_t polypic_batch_sort_workspace_bytes(const polypic_batch* batch, size_t* b
 int32_t polypic_batch_sort(const polypic_batch* batch, const float* x, uint32_t* keys_out,
                            int32_t* perm_out, void* ws, size_t ws_bytes, int32_t* status_dev,
                            void* stream);
+/* polypic_batch_sort_update: polypic_sort_update over the batch -- the same keys and
+ * permutation as polypic_batch_sort, bit for bit, from the previous batched sort's
+ * keys (keys_prev[i]: the key slot i was sorted under; ascending).  Flags, aliasing
+ * and workspace rules as polypic_sort_update. */
+int32_t polypic_batch_sort_update_workspace_bytes(const polypic_batch* batch, size_t* bytes);
+int32_t polypic_batch_sort_update(const polypic_batch* batch, const float* x,
+                                  const uint32_t* keys_prev, uint32_t* keys_out,
+                                  int32_t* perm_out, void* ws, size_t ws_bytes,
+                                  int32_t* status_dev, void* stream);
 int32_t polypic_batch_p2g(const polypic_batch* batch, int32_t n_modes, const float* x,
                           const float* mass, float uniform_mass, const float* coeff,
                           const int32_t* perm, float* grid_mass, float* grid_mom,
@@ -417,6 +426,16 @@ int32_t polypic_batch_g2p(const polypic_batch* batch, int32_t n_modes, float dt,
                           float* x_out, float* coeff_out, const float* F_in, float* F_out,
                           const float* mass_in, float* mass_out, int32_t* status_dev,
                           void* stream);
+/* polypic_batch_g2p2g: polypic_g2p2g over every scene of the batch (each scene's
+ * G2P, advection and next P2G on its own grid; grid_mass / grid_mom span batch->N
+ * nodes and are cleared first).  Arguments as polypic_batch_g2p plus uniform_mass,
+ * grid_mass and grid_mom, with the aliasing rules of polypic_g2p2g. */
+int32_t polypic_batch_g2p2g(const polypic_batch* batch, int32_t n_modes, float dt,
+                            const float* grid_vel, const float* x_in, const int32_t* perm,
+                            float* x_out, float* coeff_out, const float* F_in, float* F_out,
+                            const float* mass_in, float* mass_out, float uniform_mass,
+                            float* grid_mass, float* grid_mom, int32_t* status_dev,
+                            void* stream);
 int32_t polypic_batch_set_config(int32_t n_modes, int32_t block, int32_t schedule,
                                  int32_t per_cu);
 int32_t polypic_batch_get_config(int32_t n_modes, int32_t* block, int32_t* schedule,

@@ -53,9 +53,12 @@ EXPORTED = (
     "polypic_batch_plan",
     "polypic_batch_sort_workspace_bytes",
     "polypic_batch_sort",
+    "polypic_batch_sort_update_workspace_bytes",
+    "polypic_batch_sort_update",
     "polypic_batch_p2g",
     "polypic_batch_grid_update",
     "polypic_batch_g2p",
+    "polypic_batch_g2p2g",
     "polypic_batch_set_config",
     "polypic_batch_get_config",
     "polypic_batch_autotune",
@@ -184,12 +187,18 @@ def load() -> ctypes.CDLL:
     lib.polypic_batch_sort_workspace_bytes.argtypes = [B, ctypes.POINTER(sz)]
     lib.polypic_batch_sort.restype = i32
     lib.polypic_batch_sort.argtypes = [B, P, P, P, P, sz, P, P]
+    lib.polypic_batch_sort_update_workspace_bytes.restype = i32
+    lib.polypic_batch_sort_update_workspace_bytes.argtypes = [B, ctypes.POINTER(sz)]
+    lib.polypic_batch_sort_update.restype = i32
+    lib.polypic_batch_sort_update.argtypes = [B, P, P, P, P, P, sz, P, P]
     lib.polypic_batch_p2g.restype = i32
     lib.polypic_batch_p2g.argtypes = [B, i32, P, P, f32, P, P, P, P, i32, P, P]
     lib.polypic_batch_grid_update.restype = i32
     lib.polypic_batch_grid_update.argtypes = [B, f32, ctypes.POINTER(f32), i32, P, P, P, P]
     lib.polypic_batch_g2p.restype = i32
     lib.polypic_batch_g2p.argtypes = [B, i32, f32, P, P, P, P, P, P, P, P, P, P, P]
+    lib.polypic_batch_g2p2g.restype = i32
+    lib.polypic_batch_g2p2g.argtypes = [B, i32, f32, P, P, P, P, P, P, P, P, P, f32, P, P, P, P]
     lib.polypic_batch_set_config.restype = i32
     lib.polypic_batch_set_config.argtypes = [i32, i32, i32, i32]
     lib.polypic_batch_get_config.restype = i32

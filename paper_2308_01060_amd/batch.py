@@ -7,6 +7,12 @@ end to end, and runs the batched entry points of the library:
     polypic_batch_sort -> polypic_batch_p2g -> polypic_batch_grid_update
                        -> polypic_batch_g2p (+ advection)
 
+From the second step on the sort is the exact re-sort from the previous step's
+keys (``polypic_batch_sort_update``), as in ``ParticleSet``.  Fused (the default),
+the G2P of a step and the P2G of the next are one call,
+``polypic_batch_g2p2g``, as in ``ParticleSet``: a step is sort -> grid update ->
+G2P2G, with a P2G first when the grid does not hold the current state.
+
 A step can be captured once as a HIP graph (``capture``) and replayed
 (``replay``): the positions ping-pong between two buffers, so two graphs are
 captured, one per direction.  The coefficients are updated in place (G2P reads
@@ -27,7 +33,7 @@ class BatchedParticleSet:
                  coeff: torch.Tensor, mass: Optional[torch.Tensor] = None,
                  uniform_mass: float = 1.0, dt: float = 1e-4,
                  gravity: Sequence[float] = (0.0, -9.8, 0.0), bc_layers: int = 1,
-                 device: str = "cuda"):
+                 device: str = "cuda", fused: bool = True, incremental_sort: bool = True):
         if n_modes not in ops.ALLOWED_N_MODES:
             raise ValueError(f"n_modes must be one of {ops.ALLOWED_N_MODES}")
         self.batch = ops.Batch(list(zip(grids, counts)), device=device)
@@ -53,9 +59,19 @@ class BatchedParticleSet:
         self.perm = torch.empty(P, dtype=torch.int32, device=device)
         self.sort_ws = torch.empty(max(1, ops.polypic_batch_sort_workspace_bytes(self.batch)),
                                    dtype=torch.uint8, device=device)
+        # incremental re-sort, as in ParticleSet: slot_keys[i] = the key slot i was sorted under
+        self.incremental_sort = bool(incremental_sort)
+        self.slot_keys = torch.empty_like(self.keys) if self.incremental_sort else None
+        self.slot_keys_valid = False
+        self._keys_are_slot_keys = False
+        self.resort_ws = (torch.empty(max(1, ops.polypic_batch_sort_update_workspace_bytes(
+            self.batch)), dtype=torch.uint8, device=device) if self.incremental_sort else None)
         self.status = torch.zeros(1, dtype=torch.int32, device=device)
         self.graphs = None
         self.phase = 0
+        self.fused = bool(fused)
+        self.grid_current = False  # grid_mass / grid_mom hold the P2G of the current state
+        self._next_grid_current = False
 
     @property
     def P(self) -> int:
@@ -68,13 +84,29 @@ class BatchedParticleSet:
         return slice(self.batch.node_offsets[k], self.batch.node_offsets[k + 1])
 
     # ---- phases
-    def sort(self):
-        ops.polypic_batch_sort(self.batch, self.x, self.keys, self.perm, self.sort_ws, self.status)
+    def _take_slot_keys(self):
+        """After a step in sort order, `keys` describes the slot order: make it slot_keys."""
+        if self._keys_are_slot_keys:
+            self.keys, self.slot_keys = self.slot_keys, self.keys
+            self._keys_are_slot_keys = False
+            self.slot_keys_valid = True
+
+    def sort(self, full: bool = False):
+        """Every scene's cell-key sort: the exact re-sort from the keys the slot order was
+        sorted under when they are known, else (or with full=True) the full sort."""
+        self._take_slot_keys()
+        if self.slot_keys_valid and not full:
+            ops.polypic_batch_sort_update(self.batch, self.x, self.slot_keys, self.keys,
+                                          self.perm, self.resort_ws, self.status)
+        else:
+            ops.polypic_batch_sort(self.batch, self.x, self.keys, self.perm, self.sort_ws,
+                                   self.status)
 
     def p2g(self, use_perm: bool = True):
         ops.polypic_batch_p2g(self.batch, self.n_modes, self.x, self.coeff, self.grid_mass,
                               self.grid_mom, mass=self.mass, uniform_mass=self.uniform_mass,
                               perm=self.perm if use_perm else None, status_dev=self.status)
+        self.grid_current = True
 
     def grid_update(self):
         ops.polypic_batch_grid_update(self.batch, self.dt, self.gravity, self.bc_layers,
@@ -85,20 +117,49 @@ class BatchedParticleSet:
                               self.coeff_next, perm=self.perm if use_perm else None,
                               x_out=self.x_next, mass_in=self.mass, mass_out=self.mass_next,
                               status_dev=self.status)
+        self._next_grid_current = False
+
+    def g2p2g(self, use_perm: bool = True):
+        """G2P + advection of every scene, and the P2G of the new state into the grid."""
+        ops.polypic_batch_g2p2g(self.batch, self.n_modes, self.dt, self.grid_vel, self.x,
+                                self.x_next, self.coeff_next, self.grid_mass, self.grid_mom,
+                                perm=self.perm if use_perm else None, mass_in=self.mass,
+                                mass_out=self.mass_next, uniform_mass=self.uniform_mass,
+                                status_dev=self.status)
+        self._next_grid_current = True
 
     def swap(self):
         self.x, self.x_next = self.x_next, self.x
         if self.mass is not None:
             self.mass, self.mass_next = self.mass_next, self.mass
+        self.grid_current = self._next_grid_current
+        self._next_grid_current = False
+        # G2P wrote slot i from particle perm[i]: slot i was sorted under keys[i]
+        if self.incremental_sort:
+            self._keys_are_slot_keys = True
+
+    def _step_calls(self):
+        """One step after the sort, the grid holding the current state's P2G when fused."""
+        if self.fused:
+            self.grid_update()
+            self.g2p2g()
+        else:
+            self.p2g()
+            self.grid_update()
+            self.g2p()
 
     def step(self):
         """One eager step for every scene (outputs come out in each scene's cell order)."""
         self.sort()
-        self.p2g()
-        self.grid_update()
-        self.g2p()
+        if self.fused and not self.grid_current:
+            self.p2g()  # the first step's P2G; later ones come from the G2P2G before them
+        self._step_calls()
         self.swap()
         self.phase ^= 1
+
+    def invalidate_grid(self):
+        """Call after changing x, coeff or mass directly: the next fused step redoes P2G."""
+        self.grid_current = False
 
     def autotune(self):
         """Sort, then let the library time its batched P2G configurations (synchronises)."""
@@ -109,16 +170,19 @@ class BatchedParticleSet:
 
     # ---- graph capture
     def capture(self):
-        """Capture one step in each buffer direction as a HIP graph (no work is run)."""
+        """Capture one step in each buffer direction as a HIP graph (no work is run).
+
+        Fused, the graphs hold sort -> grid update -> G2P2G, so the grid must hold the
+        current state's P2G before the first replay (one eager step does that)."""
+        if self.fused and not self.grid_current:
+            raise RuntimeError("fused capture needs the grid current: run one step() first")
         torch.cuda.synchronize()
         graphs = []
         for _ in range(2):
             g = torch.cuda.CUDAGraph()
             with torch.cuda.graph(g):
                 self.sort()
-                self.p2g()
-                self.grid_update()
-                self.g2p()
+                self._step_calls()
             graphs.append(g)
             self.swap()       # the second graph reads what the first one writes
         # two swaps: the buffers are back where they started, and graphs[0]
@@ -131,6 +195,9 @@ class BatchedParticleSet:
         if self.graphs is None:
             raise RuntimeError("capture() first")
         self.graphs[self.phase].replay()
+        # the bookkeeping of what the graph ran: its sort (key roles) and its last call
+        self._take_slot_keys()
+        self._next_grid_current = self.fused  # the graph ends with G2P2G (fused) or G2P
         self.swap()
         self.phase ^= 1
 

@@ -519,6 +519,21 @@ bool overlaps(const void* a, int64_t na, const void* b, int64_t nb) {
   const char* pb = (const char*)b;
   return pa < pb + nb * 4 && pb < pa + na * 4;
 }
+
+// an output of the fused call overlaps an input it reads, or the two grid outputs overlap
+bool g2p2g_overlap(int64_t P, int64_t N, const float* grid_vel, const float* x_in,
+                   const int32_t* perm, const float* F_in, const float* mass_in,
+                   const float* grid_mass, const float* grid_mom, const float* x_out,
+                   const float* F_out, const float* mass_out) {
+  const void* ins[5] = {grid_vel, x_in, perm, F_in, mass_in};
+  const int64_t nin[5] = {3 * N, 3 * P, P, 9 * P, P};
+  const void* outs[5] = {grid_mass, grid_mom, x_out, F_out, mass_out};
+  const int64_t nout[5] = {N, 3 * N, 3 * P, 9 * P, P};
+  for (int o = 0; o < 5; ++o)
+    for (int k = 0; k < 5; ++k)
+      if (overlaps(outs[o], nout[o], ins[k], nin[k])) return true;
+  return overlaps(grid_mass, N, grid_mom, 3 * N);
+}
 }  // namespace
 
 int32_t polypic_g2p2g(const polypic_grid* grid, int64_t P, int32_t n_modes, float dt,
@@ -536,15 +551,9 @@ int32_t polypic_g2p2g(const polypic_grid* grid, int64_t P, int32_t n_modes, floa
   if ((F_in == nullptr) != (F_out == nullptr)) return POLYPIC_EINVAL;
   if (mass_out && !mass_in) return POLYPIC_EINVAL;
   const int64_t N = n_nodes(grid);
-  // outputs written while other threads still read the inputs
-  const void* ins[5] = {grid_vel, x_in, perm, F_in, mass_in};
-  const int64_t nin[5] = {3 * N, 3 * P, P, 9 * P, P};
-  const void* outs[5] = {grid_mass, grid_mom, x_out, F_out, mass_out};
-  const int64_t nout[5] = {N, 3 * N, 3 * P, 9 * P, P};
-  for (int o = 0; o < 5; ++o)
-    for (int k = 0; k < 5; ++k)
-      if (overlaps(outs[o], nout[o], ins[k], nin[k])) return POLYPIC_EINVAL;
-  if (overlaps(grid_mass, N, grid_mom, 3 * N)) return POLYPIC_EINVAL;
+  if (g2p2g_overlap(P, N, grid_vel, x_in, perm, F_in, mass_in, grid_mass, grid_mom, x_out, F_out,
+                    mass_out))
+    return POLYPIC_EINVAL;
   G2P2GArgs a;
   a.g = to_dev(grid);
   a.P = P;
@@ -749,6 +758,31 @@ int32_t polypic_batch_sort(const polypic_batch* batch, const float* x, uint32_t*
                                     status_dev, (hipStream_t)stream));
 }
 
+int32_t polypic_batch_sort_update_workspace_bytes(const polypic_batch* batch, size_t* bytes) {
+  int32_t st = check_batch(batch);
+  if (st) return st;
+  if (!bytes) return POLYPIC_EINVAL;
+  *bytes = sort_update_workspace_bytes(batch->P);
+  return POLYPIC_OK;
+}
+
+int32_t polypic_batch_sort_update(const polypic_batch* batch, const float* x,
+                                  const uint32_t* keys_prev, uint32_t* keys_out,
+                                  int32_t* perm_out, void* ws, size_t ws_bytes,
+                                  int32_t* status_dev, void* stream) {
+  int32_t st = check_batch(batch);
+  if (st) return st;
+  if (batch->P == 0) return POLYPIC_OK;
+  if (!x || !keys_prev || !keys_out || !perm_out || !ws) return POLYPIC_EINVAL;
+  if ((const void*)keys_prev == (const void*)keys_out) return POLYPIC_EINVAL;
+  if (ws_bytes < sort_update_workspace_bytes(batch->P)) return POLYPIC_ENOSPACE;
+  discard_stale_error();
+  return from_hip(launch_sort_update_batch(batch_table(batch), batch->n_scenes,
+                                           batch->morton_bits, batch->key_bits, batch->P, x,
+                                           keys_prev, keys_out, perm_out, ws, status_dev,
+                                           (hipStream_t)stream));
+}
+
 int32_t polypic_batch_p2g(const polypic_batch* batch, int32_t n_modes, const float* x,
                           const float* mass, float uniform_mass, const float* coeff,
                           const int32_t* perm, float* grid_mass, float* grid_mom,
@@ -821,6 +855,51 @@ int32_t polypic_batch_g2p(const polypic_batch* batch, int32_t n_modes, float dt,
   discard_stale_error();
   return from_hip(
       launch_g2p_batch(a, batch_table(batch), batch->n_scenes, n_modes, (hipStream_t)stream));
+}
+
+int32_t polypic_batch_g2p2g(const polypic_batch* batch, int32_t n_modes, float dt,
+                            const float* grid_vel, const float* x_in, const int32_t* perm,
+                            float* x_out, float* coeff_out, const float* F_in, float* F_out,
+                            const float* mass_in, float* mass_out, float uniform_mass,
+                            float* grid_mass, float* grid_mom, int32_t* status_dev,
+                            void* stream) {
+  int32_t st = check_batch(batch);
+  if (st) return st;
+  if (!valid_modes(n_modes) || !isfinite(dt)) return POLYPIC_EINVAL;
+  if (!grid_mass || !grid_mom) return POLYPIC_EINVAL;
+  if (!mass_in && !isfinite(uniform_mass)) return POLYPIC_EINVAL;
+  const int64_t P = batch->P, N = batch->N;
+  if (P > 0 && (!grid_vel || !x_in || !x_out || !coeff_out)) return POLYPIC_EINVAL;
+  if ((F_in == nullptr) != (F_out == nullptr)) return POLYPIC_EINVAL;
+  if (mass_out && !mass_in) return POLYPIC_EINVAL;
+  if (g2p2g_overlap(P, N, grid_vel, x_in, perm, F_in, mass_in, grid_mass, grid_mom, x_out, F_out,
+                    mass_out))
+    return POLYPIC_EINVAL;
+  G2P2GArgs a;
+  a.g = GridDev{3, 3, 3, 1.0f, 0.0f, 0.0f, 0.0f};  // unused: per scene, from the table
+  a.P = P;
+  a.dt = dt;
+  a.dx = 1.0f;
+  for (int k = 0; k < 3; ++k) a.lo[k] = a.hi[k] = 0.0f;
+  a.gv = grid_vel;
+  a.x_in = x_in;
+  a.perm = perm;
+  a.x_out = x_out;
+  a.coeff_out = coeff_out;
+  a.F_in = F_in;
+  a.F_out = F_out;
+  a.mass_in = mass_in;
+  a.mass_out = mass_out;
+  a.uniform_mass = uniform_mass;
+  a.gm = grid_mass;
+  a.gp0 = grid_mom;
+  a.gp1 = grid_mom + N;
+  a.gp2 = grid_mom + 2 * N;
+  a.status = status_dev;
+  a.gstride = N;
+  discard_stale_error();
+  return from_hip(launch_g2p2g_batch(a, batch_table(batch), batch->n_scenes, n_modes,
+                                     (hipStream_t)stream));
 }
 
 int32_t polypic_batch_set_config(int32_t n_modes, int32_t block, int32_t schedule,

@@ -38,8 +38,8 @@ __device__ __forceinline__ int fused_slot(int tid) {
 // LDS (about 41 KB per 256-thread workgroup) allows 4 waves per SIMD; the launch
 // bound holds the registers to the 128 that allow them too.  At 27 modes that
 // spills 9 registers and still wins (measured, 4.19 M particles: 0.48 -> 0.44 ms).
-template <int NR, int BS>
-__global__ __launch_bounds__(BS, 4) void g2p2g_kernel(G2P2GArgs a) {
+template <int NR, int BS, class Scenes>
+__global__ __launch_bounds__(BS, Scenes::kMany ? 3 : 4) void g2p2g_kernel(G2P2GArgs a, Scenes sc) {
   constexpr int NW = BS / kWave;
   constexpr int LG = NR >= 8 ? 2 : 1;  // log2 of the lane-group size
   __shared__ double brick[kBrickKMAX * 4 * kBrickV];  // [brick][channel][node]
@@ -47,20 +47,32 @@ __global__ __launch_bounds__(BS, 4) void g2p2g_kernel(G2P2GArgs a) {
   __shared__ int seg_of[BS];
   __shared__ uint64_t seg_tile[kBrickKMAX];
   __shared__ int wave_heads[NW];
-  __shared__ uint64_t run_tile[kWave];  // tile of each of the first 64 runs
+  // tile of each of the first 64 runs: in tile_of's storage, written only after the
+  // last read of tile_of (the run index needs the barrier that follows those reads)
+  uint64_t* const run_tile = tile_of;
   __shared__ int run_brick[kWave];      // brick (distinct-tile index) of each run
   __shared__ int n_bricks;
+  // grid of each brick's scene (batches only; one scene folds to constants)
+  __shared__ int seg_dims[kBrickKMAX][3];
+  __shared__ int64_t seg_node_off[kBrickKMAX];
 
   const int tid = threadIdx.x;
   const int lane = tid & (kWave - 1);
   const int wv = tid / kWave;
   const int slot = fused_slot<LG, NW>(tid);
   const size_t Ps = (size_t)a.P;
-  const GridDev& g = a.g;
+  const int64_t i0 = (int64_t)blockIdx.x * BS;
+  const int64_t i = i0 + slot;
+  const bool in = i < a.P;
+  // scene of the slot; one wave-uniform lookup unless the wavefront straddles scenes
+  const int s0 = sc.first(i0);
+  const int s = in ? sc.of(i, s0) : s0;
+  SceneGrid g = sc.grid(s0);
+  if constexpr (Scenes::kMany) {
+    if (__ballot(s != s0) != 0ull) g = sc.grid(s);
+  }
   const int nx = g.nx, ny = g.ny, nz = g.nz;
   const int nxny = nx * ny;
-  const int64_t i = (int64_t)blockIdx.x * BS + slot;
-  const bool in = i < a.P;
   // a caller permutation is clamped into [0, P): a bad one gives wrong results, never a fault
   const int p = in ? (a.perm ? min(max(a.perm[i], 0), (int)(a.P - 1)) : (int)i) : 0;
 
@@ -93,7 +105,7 @@ __global__ __launch_bounds__(BS, 4) void g2p2g_kernel(G2P2GArgs a) {
     const Proj1D px = proj_g2p(t0);
     const Proj1D py = proj_g2p(t1);
     const Proj1D pz = proj_g2p(t2);
-    const int64_t gbase = (int64_t)(b2 * ny + b1) * nx + b0;
+    const int64_t gbase = g.node_off + (int64_t)(b2 * ny + b1) * nx + b0;
 #pragma unroll
     for (int ax = 0; ax < 3; ++ax) {
       if (gather) {
@@ -113,8 +125,8 @@ __global__ __launch_bounds__(BS, 4) void g2p2g_kernel(G2P2GArgs a) {
 #pragma unroll
       for (int r = NR; r < 27; ++r) c[ax][r] = 0.0f;
       float x1 = fmaf(a.dt, c[ax][0], xp[ax]);
-      x1 = fmaxf(x1, a.lo[ax]);
-      xn[ax] = fminf(x1, a.hi[ax]);
+      x1 = fmaxf(x1, g.lo[ax]);
+      xn[ax] = fminf(x1, g.hi[ax]);
       // rows of this component: the NR coefficients and x'; written once, never
       // re-read here, so streamed past the caches the gathers use
       float* const co = a.coeff_out + (size_t)ax * NR * Ps;
@@ -141,7 +153,7 @@ __global__ __launch_bounds__(BS, 4) void g2p2g_kernel(G2P2GArgs a) {
       float F[9];
 #pragma unroll
       for (int e = 0; e < 9; ++e) F[e] = a.F_in[(size_t)e * Ps + p];
-      const float sdt = a.dt / a.dx;
+      const float sdt = a.dt / g.dx;
 #pragma unroll
       for (int r = 0; r < 3; ++r)
 #pragma unroll
@@ -186,7 +198,7 @@ __global__ __launch_bounds__(BS, 4) void g2p2g_kernel(G2P2GArgs a) {
     }
   }
   if (!valid) m = 0.0f;
-  tile_of[slot] = valid ? brick_tile_id(0, c0, c1, c2) : kNoTile;
+  tile_of[slot] = valid ? brick_tile_id(s - s0, c0, c1, c2) : kNoTile;
   for (int k = tid; k < kBrickKMAX * 4 * kBrickV; k += BS) brick[k] = 0.0;
   __syncthreads();
 
@@ -226,7 +238,16 @@ __global__ __launch_bounds__(BS, 4) void g2p2g_kernel(G2P2GArgs a) {
     const int d_first = lanes_below(fb);
     const int d = __shfl(d_first, first_same, kWave);
     if (lane < nr) run_brick[lane] = d;
-    if (first && d < kBrickKMAX) seg_tile[d] = mine;
+    if (first && d < kBrickKMAX) {
+      seg_tile[d] = mine;
+      if constexpr (Scenes::kMany) {
+        const SceneGrid fg = sc.grid(s0 + (int)(mine >> 32));
+        seg_dims[d][0] = fg.nx;
+        seg_dims[d][1] = fg.ny;
+        seg_dims[d][2] = fg.nz;
+        seg_node_off[d] = fg.node_off;
+      }
+    }
     if (lane == 0) n_bricks = __popcll(fb);
   }
   __syncthreads();
@@ -254,7 +275,7 @@ __global__ __launch_bounds__(BS, 4) void g2p2g_kernel(G2P2GArgs a) {
     const Rows Rz = p2g_rows_scaled(basis_p2g(u2), 1.0f);
     const bool lds = seg < kBrickKMAX;
     const int lbase = (c0 & 3) + kBrickSY * (c1 & 3) + kBrickSZ * (c2 & 3);
-    const int64_t gbase = (int64_t)(c2 * ny + c1) * nx + c0;
+    const int64_t gbase = g.node_off + (int64_t)(c2 * ny + c1) * nx + c0;
     double* const lb = brick + (lds ? max(seg, 0) : 0) * 4 * kBrickV + lbase;
     float* const gch[4] = {a.gm + gbase, a.gp0 + gbase, a.gp1 + gbase, a.gp2 + gbase};
     auto emitter = [&](int ch) {
@@ -301,37 +322,70 @@ __global__ __launch_bounds__(BS, 4) void g2p2g_kernel(G2P2GArgs a) {
     const float v = (float)brick[k];
     if (v == 0.0f) continue;
     const uint32_t tc = (uint32_t)seg_tile[sb];
+    int fnx = nx, fny = ny, fnz = nz;  // one scene: constants
+    int64_t foff = 0;
+    if constexpr (Scenes::kMany) {
+      fnx = seg_dims[sb][0];
+      fny = seg_dims[sb][1];
+      fnz = seg_dims[sb][2];
+      foff = seg_node_off[sb];
+    }
     const int gx = (int)(tc & 1023u) * kBrickT + lx;
     const int gy = (int)((tc >> 10) & 1023u) * kBrickT + ly;
     const int gz = (int)(tc >> 20) * kBrickT + lz;
-    if (gx < nx && gy < ny && gz < nz) {
+    if (gx < fnx && gy < fny && gz < fnz) {
       float* const d = ch == 0 ? a.gm : ch == 1 ? a.gp0 : ch == 2 ? a.gp1 : a.gp2;
-      atomicAdd(d + ((int64_t)(gz * ny + gy) * nx + gx), v);
+      atomicAdd(d + foff + ((int64_t)(gz * fny + gy) * fnx + gx), v);
     }
   }
 }
 
-template <int NR>
-hipError_t launch_nr(const G2P2GArgs& a, hipStream_t stream) {
+template <int NR, class Scenes>
+hipError_t launch_nr(const G2P2GArgs& a, const Scenes& sc, hipStream_t stream) {
   constexpr int BS = 256;
   const unsigned blocks = (unsigned)((a.P + BS - 1) / BS);
-  g2p2g_kernel<NR, BS><<<blocks, BS, 0, stream>>>(a);
+  g2p2g_kernel<NR, BS, Scenes><<<blocks, BS, 0, stream>>>(a, sc);
   return hipGetLastError();
+}
+
+template <class Scenes>
+hipError_t launch_modes(const G2P2GArgs& a, const Scenes& sc, int n_modes, int64_t n_nodes,
+                        hipStream_t stream) {
+  hipError_t e = launch_grid_clear(a.gm, a.gp0, n_nodes, nullptr, stream);
+  if (e != hipSuccess || a.P == 0) return e;
+  switch (n_modes) {
+    case 1: return launch_nr<1>(a, sc, stream);
+    case 4: return launch_nr<4>(a, sc, stream);
+    case 8: return launch_nr<8>(a, sc, stream);
+    case 27: return launch_nr<27>(a, sc, stream);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 }  // namespace
 
 hipError_t launch_g2p2g(const G2P2GArgs& a, int n_modes, hipStream_t stream) {
-  hipError_t e = launch_grid_clear(a.gm, a.gp0, (int64_t)a.g.nx * a.g.ny * a.g.nz, nullptr,
-                                   stream);
-  if (e != hipSuccess || a.P == 0) return e;
-  switch (n_modes) {
-    case 1: return launch_nr<1>(a, stream);
-    case 4: return launch_nr<4>(a, stream);
-    case 8: return launch_nr<8>(a, stream);
-    case 27: return launch_nr<27>(a, stream);
-    default: return hipErrorInvalidValue;
+  OneScene one;
+  one.sg.nx = a.g.nx;
+  one.sg.ny = a.g.ny;
+  one.sg.nz = a.g.nz;
+  one.sg.inv_dx = a.g.inv_dx;
+  one.sg.ox = a.g.ox;
+  one.sg.oy = a.g.oy;
+  one.sg.oz = a.g.oz;
+  one.sg.dx = a.dx;
+  for (int k = 0; k < 3; ++k) {
+    one.sg.lo[k] = a.lo[k];
+    one.sg.hi[k] = a.hi[k];
   }
+  one.sg.node_off = 0;
+  return launch_modes(a, one, n_modes, (int64_t)a.g.nx * a.g.ny * a.g.nz, stream);
+}
+
+hipError_t launch_g2p2g_batch(const G2P2GArgs& a, const SceneDev* table, int n_scenes,
+                              int n_modes, hipStream_t stream) {
+  SceneTable st{table, n_scenes};
+  return launch_modes(a, st, n_modes, a.gstride, stream);
 }
 
 }  // namespace polypic

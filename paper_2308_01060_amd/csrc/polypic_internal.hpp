@@ -24,6 +24,10 @@ size_t sort_update_workspace_bytes(int64_t P);
 hipError_t launch_sort_update(const GridDev& g, int64_t P, const float* x,
                               const uint32_t* keys_prev, uint32_t* keys_out, int32_t* perm_out,
                               void* ws, int32_t* status, hipStream_t stream);
+hipError_t launch_sort_update_batch(const SceneDev* table, int n_scenes, int mbits, int key_bits,
+                                    int64_t P, const float* x, const uint32_t* keys_prev,
+                                    uint32_t* keys_out, int32_t* perm_out, void* ws,
+                                    int32_t* status, hipStream_t stream);
 // batch of scenes: key = scene << mbits | Morton(base node), key_bits in total
 hipError_t launch_sort_batch(const SceneDev* table, int n_scenes, int mbits, int key_bits,
                              int64_t P, const float* x, uint32_t* keys_out, int32_t* perm_out,
@@ -139,6 +143,9 @@ struct G2P2GArgs {
   int64_t gstride;       // channel stride of gv
 };
 hipError_t launch_g2p2g(const G2P2GArgs& a, int n_modes, hipStream_t stream);
+// over a batch of scenes (a.g, a.lo, a.hi, a.dx unused; a.gstride = total nodes)
+hipError_t launch_g2p2g_batch(const G2P2GArgs& a, const SceneDev* table, int n_scenes,
+                              int n_modes, hipStream_t stream);
 
 // ---- adjoint
 struct GridUpdateBackArgs {

@@ -512,18 +512,26 @@ constexpr int kUpdTile = kSortTile;
 constexpr int kGroupsPerTile = kUpdTile / kWave;
 constexpr int kWindowCap = 2048;  // changed pairs a workgroup stages in LDS
 
-__device__ __forceinline__ uint32_t cell_key(const GridDev& g, const float* __restrict__ x,
-                                             size_t Ps, int64_t i, bool& ok) {
+// Key of the particle at slot i, as the full sort computes it: the Morton code
+// of its base node (of the clamped base node when !ok), with the scene index
+// above bit mbits in a batch.  s: a scene at or before slot i's (advanced here).
+template <class Scenes>
+__device__ __forceinline__ uint32_t cell_key(const Scenes& sc, int mbits,
+                                             const float* __restrict__ x, size_t Ps, int64_t i,
+                                             int& s, bool& ok) {
+  s = sc.of(i, s);
+  const SceneGrid g = sc.grid(s);
   int b0, b1, b2;
   float t0, t1, t2;
   ok = stencil_axis(x[i], g.ox, g.inv_dx, g.nx, b0, t0);
   ok &= stencil_axis(x[Ps + i], g.oy, g.inv_dx, g.ny, b1, t1);
   ok &= stencil_axis(x[2 * Ps + i], g.oz, g.inv_dx, g.nz, b2, t2);
-  return morton3(b0, b1, b2);  // of the clamped base node when !ok, as the full sort
+  return ((uint32_t)s << mbits) | morton3(b0, b1, b2);
 }
 
 // changed-slot masks, per-workgroup counts, and the order check of keys_prev
-__global__ __launch_bounds__(kSortBS) void upd_mask_kernel(GridDev g, int64_t P,
+template <class Scenes>
+__global__ __launch_bounds__(kSortBS) void upd_mask_kernel(Scenes sc, int mbits, int64_t P,
                                                          const float* __restrict__ x,
                                                          const uint32_t* __restrict__ keys_prev,
                                                          unsigned long long* __restrict__ mask,
@@ -533,6 +541,7 @@ __global__ __launch_bounds__(kSortBS) void upd_mask_kernel(GridDev g, int64_t P,
   const int lane = threadIdx.x & (kWave - 1);
   const int wv = threadIdx.x / kWave;
   const size_t Ps = (size_t)P;
+  int s = sc.first((int64_t)blockIdx.x * kUpdTile);  // slots only grow along the rounds
   uint32_t c = 0;
 #pragma unroll 2
   for (int j = 0; j < kSortIPT; ++j) {
@@ -541,7 +550,7 @@ __global__ __launch_bounds__(kSortBS) void upd_mask_kernel(GridDev g, int64_t P,
     bool changed = false;
     if (i < P) {
       bool ok;
-      const uint32_t key = cell_key(g, x, Ps, i, ok);
+      const uint32_t key = cell_key(sc, mbits, x, Ps, i, s, ok);
       if (!ok) raise_flag(status, kFlagRange);
       const uint32_t prev = keys_prev[i];
       if (i > 0 && keys_prev[i - 1] > prev) raise_flag(status, kFlagOrder);
@@ -600,8 +609,9 @@ __global__ __launch_bounds__(1024) void upd_scan_kernel(uint32_t* __restrict__ b
 
 // changed (key, index) pairs in index order; gpre[grp] = changed slots before
 // the group
+template <class Scenes>
 __global__ __launch_bounds__(kSortBS) void upd_compact_kernel(
-    GridDev g, int64_t P, const float* __restrict__ x,
+    Scenes sc, int mbits, int64_t P, const float* __restrict__ x,
     const unsigned long long* __restrict__ mask, const uint32_t* __restrict__ blk_off,
     uint32_t* __restrict__ gpre, uint32_t* __restrict__ ck, int32_t* __restrict__ cv) {
   __shared__ uint32_t pre_sh[kGroupsPerTile];
@@ -629,6 +639,7 @@ __global__ __launch_bounds__(kSortBS) void upd_compact_kernel(
   __syncthreads();
   if (!any_sh) return;  // uniform: no changed slot in this workgroup
   const size_t Ps = (size_t)P;
+  int s = sc.first(g0 * kWave);
   unsigned long long m[kSortIPT];
 #pragma unroll
   for (int j = 0; j < kSortIPT; ++j) {
@@ -642,7 +653,7 @@ __global__ __launch_bounds__(kSortBS) void upd_compact_kernel(
       const int64_t i = (g0 + k) * kWave + lane;
       bool ok;
       const uint32_t pos = pre_sh[k] + (uint32_t)lanes_below(m[j]);
-      ck[pos] = cell_key(g, x, Ps, i, ok);
+      ck[pos] = cell_key(sc, mbits, x, Ps, i, s, ok);
       cv[pos] = (int32_t)i;
     }
   }
@@ -823,18 +834,22 @@ UpdLayout upd_layout(void* ws, int64_t P) {
 
 size_t sort_update_workspace_bytes(int64_t P) { return upd_layout(nullptr, P).bytes; }
 
-hipError_t launch_sort_update(const GridDev& g, int64_t P, const float* x,
-                              const uint32_t* keys_prev, uint32_t* keys_out, int32_t* perm_out,
-                              void* ws, int32_t* status, hipStream_t stream) {
+namespace {
+
+template <class Scenes>
+hipError_t sort_update_with(const Scenes& sc, int mbits, int key_bits, int64_t P,
+                            const float* x, const uint32_t* keys_prev, uint32_t* keys_out,
+                            int32_t* perm_out, void* ws, int32_t* status, hipStream_t stream) {
   if (P == 0) return hipSuccess;
   const UpdLayout L = upd_layout(ws, P);
   const int n_tiles = (int)((P + kSortTile - 1) / kSortTile);
-  const int passes = (sort_key_bits(g) + 7) / 8;
-  if (passes > kMaxPasses) return hipErrorInvalidValue;
-  upd_mask_kernel<<<n_tiles, kSortBS, 0, stream>>>(g, P, x, keys_prev, L.mask, L.blk, status);
+  const int passes = (key_bits + 7) / 8;
+  if (passes < 1 || passes > kMaxPasses) return hipErrorInvalidValue;
+  upd_mask_kernel<Scenes><<<n_tiles, kSortBS, 0, stream>>>(sc, mbits, P, x, keys_prev, L.mask,
+                                                           L.blk, status);
   upd_scan_kernel<<<1, 1024, 0, stream>>>(L.blk, n_tiles, L.count, L.totals, L.tile_ctr);
-  upd_compact_kernel<<<n_tiles, kSortBS, 0, stream>>>(g, P, x, L.mask, L.blk, L.gpre, L.ck0,
-                                                      L.cv0);
+  upd_compact_kernel<Scenes><<<n_tiles, kSortBS, 0, stream>>>(sc, mbits, P, x, L.mask, L.blk,
+                                                              L.gpre, L.ck0, L.cv0);
   // stable radix sort of the changed pairs (their number known on the device only)
   const int counted_grid = n_tiles < kCountedGrid ? n_tiles : kCountedGrid;
   counted_hist_kernel<<<counted_grid, kSortBS, 0, stream>>>(L.ck0, L.count, passes, n_tiles,
@@ -859,6 +874,36 @@ hipError_t launch_sort_update(const GridDev& g, int64_t P, const float* x,
   upd_place_changed_kernel<<<1024, kSortBS, 0, stream>>>(P, keys_prev, L.mask, L.gpre, ks, vs,
                                                          L.count, keys_out, perm_out);
   return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_sort_update(const GridDev& g, int64_t P, const float* x,
+                              const uint32_t* keys_prev, uint32_t* keys_out, int32_t* perm_out,
+                              void* ws, int32_t* status, hipStream_t stream) {
+  OneScene one;
+  one.sg.nx = g.nx;
+  one.sg.ny = g.ny;
+  one.sg.nz = g.nz;
+  one.sg.inv_dx = g.inv_dx;
+  one.sg.ox = g.ox;
+  one.sg.oy = g.oy;
+  one.sg.oz = g.oz;
+  one.sg.dx = 0.0f;
+  for (int k = 0; k < 3; ++k) one.sg.lo[k] = one.sg.hi[k] = 0.0f;
+  one.sg.node_off = 0;
+  const int bits = sort_key_bits(g);
+  return sort_update_with(one, bits, bits, P, x, keys_prev, keys_out, perm_out, ws, status,
+                          stream);
+}
+
+hipError_t launch_sort_update_batch(const SceneDev* table, int n_scenes, int mbits, int key_bits,
+                                    int64_t P, const float* x, const uint32_t* keys_prev,
+                                    uint32_t* keys_out, int32_t* perm_out, void* ws,
+                                    int32_t* status, hipStream_t stream) {
+  SceneTable st{table, n_scenes};
+  return sort_update_with(st, mbits, key_bits, P, x, keys_prev, keys_out, perm_out, ws, status,
+                          stream);
 }
 
 }  // namespace polypic

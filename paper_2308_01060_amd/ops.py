@@ -360,6 +360,24 @@ def polypic_batch_sort(batch: Batch, x: torch.Tensor, keys_out: torch.Tensor,
         ws.numel(), _ptr(status_dev, torch.int32, 1, "status_dev"), _stream()), "polypic_batch_sort")
 
 
+def polypic_batch_sort_update_workspace_bytes(batch: Batch) -> int:
+    out = ctypes.c_size_t(0)
+    check(_lib.load().polypic_batch_sort_update_workspace_bytes(batch.ref(), ctypes.byref(out)),
+          "polypic_batch_sort_update_workspace_bytes")
+    return int(out.value)
+
+
+def polypic_batch_sort_update(batch: Batch, x: torch.Tensor, keys_prev: torch.Tensor,
+                              keys_out: torch.Tensor, perm_out: torch.Tensor, ws: torch.Tensor,
+                              status_dev: Optional[torch.Tensor] = None) -> None:
+    P = batch.P
+    check(_lib.load().polypic_batch_sort_update(
+        batch.ref(), _ptr(x, torch.float32, 3 * P, "x"), _keys_ptr(keys_prev, P),
+        _keys_ptr(keys_out, P), _ptr(perm_out, torch.int32, P, "perm_out"),
+        _ptr(ws, torch.uint8, ws.numel(), "ws"), ws.numel(),
+        _ptr(status_dev, torch.int32, 1, "status_dev"), _stream()), "polypic_batch_sort_update")
+
+
 def polypic_batch_p2g(batch: Batch, n_modes: int, x: torch.Tensor, coeff: torch.Tensor,
                       grid_mass: torch.Tensor, grid_mom: torch.Tensor,
                       mass: Optional[torch.Tensor] = None, uniform_mass: float = 1.0,
@@ -403,6 +421,27 @@ def polypic_batch_g2p(batch: Batch, n_modes: int, dt: float, grid_vel: torch.Ten
         _ptr(F_in, torch.float32, 9 * P, "F_in"), _ptr(F_out, torch.float32, 9 * P, "F_out"),
         _ptr(mass_in, torch.float32, P, "mass_in"), _ptr(mass_out, torch.float32, P, "mass_out"),
         _ptr(status_dev, torch.int32, 1, "status_dev"), _stream()), "polypic_batch_g2p")
+
+
+def polypic_batch_g2p2g(batch: Batch, n_modes: int, dt: float, grid_vel: torch.Tensor,
+                        x_in: torch.Tensor, x_out: torch.Tensor, coeff_out: torch.Tensor,
+                        grid_mass: torch.Tensor, grid_mom: torch.Tensor,
+                        perm: Optional[torch.Tensor] = None,
+                        F_in: Optional[torch.Tensor] = None, F_out: Optional[torch.Tensor] = None,
+                        mass_in: Optional[torch.Tensor] = None,
+                        mass_out: Optional[torch.Tensor] = None, uniform_mass: float = 1.0,
+                        status_dev: Optional[torch.Tensor] = None) -> None:
+    P, N = batch.P, batch.N
+    check(_lib.load().polypic_batch_g2p2g(
+        batch.ref(), int(n_modes), float(dt), _ptr(grid_vel, torch.float32, 3 * N, "grid_vel"),
+        _ptr(x_in, torch.float32, 3 * P, "x_in"), _ptr(perm, torch.int32, P, "perm"),
+        _ptr(x_out, torch.float32, 3 * P, "x_out"),
+        _ptr(coeff_out, torch.float32, 3 * int(n_modes) * P, "coeff_out"),
+        _ptr(F_in, torch.float32, 9 * P, "F_in"), _ptr(F_out, torch.float32, 9 * P, "F_out"),
+        _ptr(mass_in, torch.float32, P, "mass_in"), _ptr(mass_out, torch.float32, P, "mass_out"),
+        float(uniform_mass), _ptr(grid_mass, torch.float32, N, "grid_mass"),
+        _ptr(grid_mom, torch.float32, 3 * N, "grid_mom"),
+        _ptr(status_dev, torch.int32, 1, "status_dev"), _stream()), "polypic_batch_g2p2g")
 
 
 class BatchChoice(NamedTuple):

@@ -219,9 +219,14 @@ def test_batch_calls_reject_unplanned_descriptors():
                                          None) == 1
     assert lib.polypic_batch_g2p(ctypes.byref(b), 27, 1e-4, FAKE, FAKE, None, None, FAKE, None,
                                  None, None, None, None, None) == 1
+    assert lib.polypic_batch_g2p2g(ctypes.byref(b), 27, 1e-4, FAKE, FAKE, None, FAKE, FAKE,
+                                   None, None, None, None, 1.0, FAKE, FAKE, None, None) == 1
     out = ctypes.c_size_t(0)
     assert lib.polypic_batch_sort_workspace_bytes(ctypes.byref(b), ctypes.byref(out)) == 1
     assert lib.polypic_batch_sort(None, FAKE, FAKE, FAKE, FAKE, 1 << 20, None, None) == 1
+    assert lib.polypic_batch_sort_update(ctypes.byref(b), FAKE, FAKE, ctypes.c_void_p(0x2000),
+                                         FAKE, FAKE, 1 << 30, None, None) == 1
+    assert lib.polypic_batch_sort_update_workspace_bytes(ctypes.byref(b), ctypes.byref(out)) == 1
 
 
 def test_backward_entry_points_reject_bad_arguments():

@@ -27,7 +27,7 @@ def small_batch(seed=0, n=6, empty_at=None):
     return scenes
 
 
-def make_set(pp, scenes, n_modes, mass=None):
+def make_set(pp, scenes, n_modes, mass=None, fused=True):
     grids = [pp.grid_from_spec(s.grid) for s in scenes]
     counts = [s.P for s in scenes]
     x = np.concatenate([s.x for s in scenes], axis=1)
@@ -35,7 +35,7 @@ def make_set(pp, scenes, n_modes, mass=None):
     s0 = scenes[0]
     return pp.BatchedParticleSet(grids, counts, n_modes, dev(x), dev(c),
                                  mass=None if mass is None else dev(mass), dt=s0.dt,
-                                 gravity=s0.gravity, bc_layers=s0.bc_layers)
+                                 gravity=s0.gravity, bc_layers=s0.bc_layers, fused=fused)
 
 
 def scene_grid_arrays(bs, k, gm, gp, shape):
@@ -63,6 +63,49 @@ def test_batched_sort_is_the_per_scene_stable_sort():
         kref, pref = O.sort_keys(O.grid_from_spec(s.grid), s.x)
         assert np.array_equal(perm[sl] - sl.start, pref.astype(np.int64)), k
         assert np.array_equal(keys[sl], (np.uint32(k) << np.uint32(mbits)) | kref), k
+
+
+def test_batched_resort_over_steps_equals_full_sort():
+    """Five fused steps with a larger dt (particles change cell): every step's batched
+    re-sort gives exactly the full batched sort of the same positions, and each scene's
+    part is the oracle's stable argsort of that scene."""
+    pp = require_gpu()
+    scenes = small_batch(8, n=5, empty_at=2)
+    note(f"batch re-sort: {[s.P for s in scenes]}")
+    bs = make_set(pp, scenes, 8)
+    bs.dt = 2e-3
+    P = bs.P
+    keys_f = torch.empty(P, dtype=torch.int32, device="cuda")
+    perm_f = torch.empty(P, dtype=torch.int32, device="cuda")
+    ws = torch.empty(pp.ops.polypic_batch_sort_workspace_bytes(bs.batch), dtype=torch.uint8,
+                     device="cuda")
+    mbits = bs.batch.desc.morton_bits
+    changed = 0
+    for k in range(5):
+        x_before = host(bs.x).copy()
+        bs.sort()
+        pp.ops.polypic_batch_sort(bs.batch, bs.x, keys_f, perm_f, ws, bs.status)
+        torch.cuda.synchronize()
+        assert torch.equal(bs.keys, keys_f), k
+        assert torch.equal(bs.perm, perm_f), k
+        if k > 0:
+            changed += int((bs.slot_keys != keys_f[torch.argsort(perm_f.long())]).sum())
+        perm = host(bs.perm).astype(np.int64)
+        keys = host(bs.keys).view(np.uint32)
+        for j, s in enumerate(scenes):
+            sl = bs.scene_slice(j)
+            if sl.start == sl.stop:
+                continue
+            kref, pref = O.sort_keys(O.grid_from_spec(s.grid), x_before[:, sl])
+            assert np.array_equal(perm[sl] - sl.start, pref.astype(np.int64)), (k, j)
+            assert np.array_equal(keys[sl], (np.uint32(j) << np.uint32(mbits)) | kref), (k, j)
+        if k == 0:
+            bs.p2g()
+        bs.grid_update()
+        bs.g2p2g()
+        bs.swap()
+    assert changed > 0
+    assert bs.status_flags() == 0
 
 
 @pytest.mark.parametrize("n_modes", [4, 27])
@@ -103,25 +146,34 @@ def test_batched_p2g_every_configuration(n_modes):
 
 
 @pytest.mark.parametrize("n_modes", [1, 8, 27])
-def test_batched_step_matches_the_oracle_per_scene(n_modes):
+@pytest.mark.parametrize("fused", [False, True])
+def test_batched_step_matches_the_oracle_per_scene(n_modes, fused):
+    """One step of every scene against the oracle's step of that scene alone.  Fused
+    (polypic_batch_g2p2g), the grid then holds the P2G of the new state: it is compared with
+    the oracle's P2G of the state the device wrote, scene by scene."""
     pp = require_gpu()
     scenes = small_batch(2, n=6, empty_at=0)
-    note(f"batch step: n_modes={n_modes} {[s.P for s in scenes]}")
-    bs = make_set(pp, scenes, n_modes)
+    note(f"batch step: n_modes={n_modes} fused={fused} {[s.P for s in scenes]}")
+    bs = make_set(pp, scenes, n_modes, fused=fused)
     bs.step()
     torch.cuda.synchronize()
     assert bs.status_flags() == 0
     gm, gp = host(bs.grid_mass), host(bs.grid_mom)
     xs, cs = host(bs.x), host(bs.coeff)
     for k, s in enumerate(scenes):
+        sl = bs.scene_slice(k)
+        og = O.grid_from_spec(s.grid)
+        if fused:
+            M, Q = O.p2g(og, xs[:, sl], cs[:, :, sl], n_modes)
+            m_k, q_k = scene_grid_arrays(bs, k, gm, gp, M.shape)
+            assert rel(m_k, M) <= TOL_NORMWISE and rel(q_k, Q) <= TOL_NORMWISE, k
         if s.P == 0:
             continue
-        ref = O.step(O.grid_from_spec(s.grid), s.x, s.coeff, n_modes, s.dt, s.gravity,
-                     s.bc_layers, sort=True)
-        m_k, q_k = scene_grid_arrays(bs, k, gm, gp, ref["grid_mass"].shape)
-        assert rel(m_k, ref["grid_mass"]) <= TOL_NORMWISE, k
-        assert rel(q_k, ref["grid_mom"]) <= TOL_NORMWISE, k
-        sl = bs.scene_slice(k)
+        ref = O.step(og, s.x, s.coeff, n_modes, s.dt, s.gravity, s.bc_layers, sort=True)
+        if not fused:
+            m_k, q_k = scene_grid_arrays(bs, k, gm, gp, ref["grid_mass"].shape)
+            assert rel(m_k, ref["grid_mass"]) <= TOL_NORMWISE, k
+            assert rel(q_k, ref["grid_mom"]) <= TOL_NORMWISE, k
         assert rel(cs[:, :, sl], ref["coeff"]) <= TOL_NORMWISE, k
         assert ulp_ok(xs[:, sl], ref["x"], 2, 1.0 + 4.0 / s.grid.cells[0]), k
 
@@ -167,14 +219,63 @@ def test_batched_g2p_equals_single_scene_g2p_bitwise():
     assert bs.status_flags() == 0
 
 
-def test_graph_replays_match_eager_steps():
+def test_batched_g2p2g_with_mass_matches_single_scene_calls():
+    """Same grid velocities, same particles, per-particle masses: the batched fused call writes
+    what the single-scene fused call writes, scene by scene (outputs bit for bit; grids at
+    the parity bar, the atomic sums being unordered)."""
+    pp = require_gpu()
+    scenes = small_batch(6, n=5)
+    rng = np.random.default_rng(11)
+    P_all = sum(s.P for s in scenes)
+    mass = (1.0 + rng.random(P_all)).astype(np.float32)
+    note(f"batch g2p2g vs single: {[s.P for s in scenes]}")
+    bs = make_set(pp, scenes, 27, mass=mass)
+    P, N = bs.P, bs.batch.N
+    bs.sort()
+    bs.p2g()
+    bs.grid_update()
+    c_b = torch.empty(3, 27, P, device="cuda")
+    x_b = torch.empty(3, P, device="cuda")
+    m_b = torch.empty(P, device="cuda")
+    gm_b = torch.empty(N, device="cuda")
+    gp_b = torch.empty(3 * N, device="cuda")
+    pp.ops.polypic_batch_g2p2g(bs.batch, 27, bs.dt, bs.grid_vel, bs.x, x_b, c_b, gm_b, gp_b,
+                               perm=bs.perm, mass_in=bs.mass, mass_out=m_b,
+                               status_dev=bs.status)
+    gv = bs.grid_vel.reshape(3, N)
+    for k, s in enumerate(scenes):
+        sl, ns = bs.scene_slice(k), bs.node_slice(k)
+        Pk = sl.stop - sl.start
+        g = pp.grid_from_spec(s.grid)
+        Nk = ns.stop - ns.start
+        perm_k = (bs.perm[sl] - sl.start).contiguous()
+        c_s = torch.empty(3, 27, Pk, device="cuda")
+        x_s = torch.empty(3, Pk, device="cuda")
+        m_s = torch.empty(Pk, device="cuda")
+        gm_s = torch.empty(Nk, device="cuda")
+        gp_s = torch.empty(3 * Nk, device="cuda")
+        pp.ops.polypic_g2p2g(g, 27, bs.dt, gv[:, ns].contiguous(), bs.x[:, sl].contiguous(),
+                             x_s, c_s, gm_s, gp_s, perm=perm_k,
+                             mass_in=bs.mass[sl].contiguous(), mass_out=m_s,
+                             status_dev=bs.status)
+        torch.cuda.synchronize()
+        assert torch.equal(c_b[:, :, sl], c_s), k
+        assert torch.equal(x_b[:, sl], x_s), k
+        assert torch.equal(m_b[sl], m_s), k
+        assert rel(host(gm_b[ns]), host(gm_s)) <= TOL_NORMWISE, k
+        assert rel(host(gp_b.reshape(3, N)[:, ns]), host(gp_s.reshape(3, Nk))) <= TOL_NORMWISE, k
+    assert bs.status_flags() == 0
+
+
+@pytest.mark.parametrize("fused", [False, True])
+def test_graph_replays_match_eager_steps(fused):
     """Capture the two step directions once; replay four steps, each checked against an
     eager step from the same state on a second set, with eager work between replays."""
     pp = require_gpu()
     scenes = small_batch(4, n=6)
-    note(f"batch graph replay: {[s.P for s in scenes]}")
-    bs = make_set(pp, scenes, 27)
-    ref = make_set(pp, scenes, 27)
+    note(f"batch graph replay: fused={fused} {[s.P for s in scenes]}")
+    bs = make_set(pp, scenes, 27, fused=fused)
+    ref = make_set(pp, scenes, 27, fused=fused)
     bs.step()                     # one eager step first: the capture starts mid-run
     torch.cuda.synchronize()
     bs.capture()
@@ -182,6 +283,7 @@ def test_graph_replays_match_eager_steps():
         x0, c0 = bs.x.clone(), bs.coeff.clone()
         ref.x.copy_(x0)
         ref.coeff.copy_(c0)
+        ref.invalidate_grid()     # its grid is not of this state: the eager step redoes P2G
         torch.cuda.synchronize()
         bs.replay()
         torch.cuda.synchronize()
