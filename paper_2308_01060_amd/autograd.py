@@ -1,15 +1,20 @@
 """Differentiable multi-step transfers: ``PolyPICSteps`` (a torch.autograd.Function).
 
-Forward: S steps of sort -> P2G -> grid update -> G2P + advection through the
-library, keeping one checkpoint (x_s, c_s) per step.  Backward: for
-s = S-1 .. 0 the step's sort, P2G and grid update are recomputed from the
-checkpoint (the stencil weights are never stored), then
+Forward: S steps run as the library steps a ParticleSet -- the sort (the exact
+re-sort from the previous step's keys after the first), the grid update, and
+G2P + advection fused with the next step's P2G (``polypic_g2p2g``; the first
+step's P2G and the last step's G2P are separate calls).  Per step it keeps a
+checkpoint: the particle state (x_s, c_s), the sort permutation and the grid
+fields (mass, momentum, velocity) -- 81 MB per step at 132^3 nodes and 4.19 M
+particles, beside the 1.4 GB of particle state.  The stencil weights are never
+stored.  Backward, for s = S-1 .. 0:
 
     polypic_g2p_backward -> polypic_grid_update_backward -> polypic_p2g_backward
 
-carry dL/d(x_{s+1}, c_{s+1}) to dL/d(x_s, c_s).  Each step's outputs come out
-in its sort order; the function returns (x_S, c_S) in the caller's particle
-order and its gradients in that order too.
+carry dL/d(x_{s+1}, c_{s+1}) to dL/d(x_s, c_s), each kernel recomputing the
+weights from x_s.  Each step's outputs come out in its sort order; the function
+returns (x_S, c_S) in the caller's particle order and its gradients in that
+order too.
 """
 from __future__ import annotations
 
@@ -26,27 +31,18 @@ class _Buffers:
     def __init__(self, grid, P: int, n_modes: int, device):
         f32 = dict(dtype=torch.float32, device=device)
         N = ops.n_nodes(grid)
-        self.gm = torch.empty(N, **f32)
-        self.gp = torch.empty(3 * N, **f32)
-        self.gv = torch.empty(3 * N, **f32)
+        self.N = N
         self.gvb = torch.empty(3 * N, **f32)
         self.gmb = torch.empty(N, **f32)
         self.gpb = torch.empty(3 * N, **f32)
-        self.keys = torch.empty(P, dtype=torch.int32, device=device)
-        self.perm = torch.empty(P, dtype=torch.int32, device=device)
+        self.keys = [torch.empty(P, dtype=torch.int32, device=device) for _ in range(2)]
         self.sort_ws = torch.empty(max(1, ops.polypic_sort_workspace_bytes(grid, P)),
                                    dtype=torch.uint8, device=device)
+        self.resort_ws = torch.empty(max(1, ops.polypic_sort_update_workspace_bytes(grid, P)),
+                                     dtype=torch.uint8, device=device)
         self.p2g_ws = torch.empty(max(1, ops.polypic_p2g_workspace_bytes(grid, P)),
                                   dtype=torch.uint8, device=device)
         self.status = torch.zeros(1, dtype=torch.int32, device=device)
-
-
-def _forward_grid(grid, n_modes, dt, gravity, bc_layers, uniform_mass, x, c, B: _Buffers):
-    """sort + P2G + grid update for the step whose inputs are (x, c)."""
-    ops.polypic_sort(grid, x, B.keys, B.perm, B.sort_ws, B.status)
-    ops.polypic_p2g(grid, n_modes, x, c, B.gm, B.gp, uniform_mass=uniform_mass, perm=B.perm,
-                    keys_sorted=B.keys, ws=B.p2g_ws, status_dev=B.status)
-    ops.polypic_grid_update(grid, dt, gravity, bc_layers, B.gm, B.gp, B.gv)
 
 
 class PolyPICSteps(torch.autograd.Function):
@@ -58,18 +54,38 @@ class PolyPICSteps(torch.autograd.Function):
         P = x0.shape[-1]
         dev = x0.device
         B = _Buffers(grid, P, n_modes, dev)
+        N = B.N
+        f32 = dict(dtype=torch.float32, device=dev)
         x = x0.detach().contiguous().reshape(3, P)
         c = c0.detach().contiguous().reshape(3, n_modes, P)
         order = torch.arange(P, dtype=torch.int64, device=dev)
         checkpoints = []
-        for _ in range(n_steps):
-            checkpoints.append((x, c))
-            _forward_grid(grid, n_modes, dt, gravity, bc_layers, uniform_mass, x, c, B)
+        gm = torch.empty(N, **f32)
+        gp = torch.empty(3 * N, **f32)
+        for s in range(n_steps):
+            keys, keys_prev = B.keys[s % 2], B.keys[(s + 1) % 2]
+            perm = torch.empty(P, dtype=torch.int32, device=dev)
+            if s == 0:
+                ops.polypic_sort(grid, x, keys, perm, B.sort_ws, B.status)
+                ops.polypic_p2g(grid, n_modes, x, c, gm, gp, uniform_mass=uniform_mass,
+                                perm=perm, keys_sorted=keys, ws=B.p2g_ws, status_dev=B.status)
+            else:
+                # slot i of x was written from the previous sort's slot i: sorted under
+                # keys_prev[i]
+                ops.polypic_sort_update(grid, x, keys_prev, keys, perm, B.resort_ws, B.status)
+            gv = torch.empty(3 * N, **f32)
+            ops.polypic_grid_update(grid, dt, gravity, bc_layers, gm, gp, gv)
+            checkpoints.append((x, c, perm, gm, gp, gv))
             x_next = torch.empty_like(x)
             c_next = torch.empty_like(c)
-            ops.polypic_g2p(grid, n_modes, dt, B.gv, x, c_next, perm=B.perm, x_out=x_next,
-                            status_dev=B.status)
-            order = order[B.perm.long()]
+            if s + 1 < n_steps:
+                gm, gp = torch.empty(N, **f32), torch.empty(3 * N, **f32)
+                ops.polypic_g2p2g(grid, n_modes, dt, gv, x, x_next, c_next, gm, gp, perm=perm,
+                                  uniform_mass=uniform_mass, status_dev=B.status)
+            else:
+                ops.polypic_g2p(grid, n_modes, dt, gv, x, c_next, perm=perm, x_out=x_next,
+                                status_dev=B.status)
+            order = order[perm.long()]
             x, c = x_next, c_next
         ctx.grid = grid
         ctx.params = (n_modes, n_steps, float(dt), tuple(float(g) for g in gravity),
@@ -97,18 +113,18 @@ class PolyPICSteps(torch.autograd.Function):
         gx = gx_out.float()[:, order].contiguous()
         gc = gc_out.float()[:, :, order].contiguous()
         for s in range(n_steps - 1, -1, -1):
-            x, c = ctx.checkpoints[s]
-            _forward_grid(grid, n_modes, dt, gravity, bc_layers, uniform_mass, x, c, B)
+            x, c, perm, gm, gp, gv = ctx.checkpoints[s]
             gx_in = torch.zeros_like(gx)
             gc_in = torch.empty_like(gc)
-            ops.polypic_g2p_backward(grid, n_modes, dt, B.gv, x, gc, B.gvb, gx_in, perm=B.perm,
+            ops.polypic_g2p_backward(grid, n_modes, dt, gv, x, gc, B.gvb, gx_in, perm=perm,
                                      x_out_grad=gx, status_dev=B.status)
-            ops.polypic_grid_update_backward(grid, dt, gravity, bc_layers, B.gm, B.gp, B.gvb,
+            ops.polypic_grid_update_backward(grid, dt, gravity, bc_layers, gm, gp, B.gvb,
                                              B.gmb, B.gpb)
             # the P2G adjoint is a gather: particle order keeps its particle streams coalesced
             ops.polypic_p2g_backward(grid, n_modes, x, c, B.gmb, B.gpb, gc_in, gx_in,
                                      uniform_mass=uniform_mass, status_dev=B.status)
             gx, gc = gx_in, gc_in
+            ctx.checkpoints[s] = None  # released as soon as its step is done
         ctx.checkpoints = None
         return gx, gc, None, None, None, None, None, None, None
 
