@@ -568,6 +568,23 @@ constexpr int kBrickT = 4;  // tile edge in cells
 constexpr int kBrickSY = 8;
 constexpr int kBrickSZ = 68;
 constexpr int kBrickV = 5 + 5 * kBrickSY + 5 * kBrickSZ + 1;  // 386 doubles per channel
+constexpr int kBrickN = kBrickT + 2;                           // nodes per brick edge
+constexpr int kBrickNodes = kBrickN * kBrickN * kBrickN;       // 216
+
+// Brick node owned by thread t < kBrickNodes (x fastest): the thread clears it in
+// every brick and channel and flushes it, so the padding is never touched.
+struct BrickNode {
+  int lx, ly, lz;
+  int lds;  // offset in a channel, in doubles
+};
+__device__ __forceinline__ BrickNode brick_node(int t) {
+  BrickNode n;
+  n.lz = t / (kBrickN * kBrickN);
+  n.ly = (t / kBrickN) % kBrickN;
+  n.lx = t % kBrickN;
+  n.lds = n.lx + kBrickSY * n.ly + kBrickSZ * n.lz;
+  return n;
+}
 
 // ---------------------------------------------------------------- Morton key
 __device__ __forceinline__ uint32_t spread_bits3(uint32_t v) {
@@ -599,6 +616,25 @@ __device__ __forceinline__ int pair_swap_i(int v) {
 }
 __device__ __forceinline__ int quad_swap_i(int v) {
   return __builtin_amdgcn_mov_dpp(v, 0x4E, 0xF, 0xF, false);  // quad_perm [2, 3, 0, 1]
+}
+
+// v + f * (v of lane ^ 1), and v + f * (v of lane ^ 2), each one v_fmac_f32 with a
+// DPP source (the compiler emits a DPP move and a separate multiply-add instead).
+// With f 1 or 0 per lane, a lane adds its partner's value only where both belong
+// together; a non-finite partner value still reaches a lane with f = 0, as NaN.
+// Every lane of the quad must execute the call.  The s_nop gives the two wait
+// states a DPP read needs after a VALU write of its source.
+__device__ __forceinline__ float pair_fold(float v, float f) {
+  asm volatile("s_nop 1\n\tv_fmac_f32_dpp %0, %0, %1 quad_perm:[1,0,3,2] row_mask:0xf bank_mask:0xf"
+               : "+v"(v)
+               : "v"(f));
+  return v;
+}
+__device__ __forceinline__ float quad_fold(float v, float f) {
+  asm volatile("s_nop 1\n\tv_fmac_f32_dpp %0, %0, %1 quad_perm:[2,3,0,1] row_mask:0xf bank_mask:0xf"
+               : "+v"(v)
+               : "v"(f));
+  return v;
 }
 
 // popcount of the bits of `mask` below this lane

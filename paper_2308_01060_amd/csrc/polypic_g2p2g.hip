@@ -35,6 +35,18 @@ __device__ __forceinline__ int fused_slot(int tid) {
   return (((lane >> LG) * NW + wv) << LG) | (lane & ((1 << LG) - 1));
 }
 
+// Position of slot s in a staging row (a permutation of each 32 slots).  The 64
+// slots one wavefront writes agree in their wavefront-index bits (LG, LG + 1) and
+// differ in bits 5-7, which a plain index drops from the bank number.  XORing bit 6,
+// and bits 5 ^ 7, into the wavefront-index bits puts the writes of each half
+// wavefront on 32 distinct banks and those of the whole wavefront on 64, while a
+// read of 64 consecutive slots only permutes each half.  (Written for 256-thread
+// workgroups; any size stays a bijection.)
+template <int LG>
+__device__ __forceinline__ int stage_pos(int s) {
+  return s ^ (((s >> 6) & 1) << LG) ^ ((((s >> 7) ^ (s >> 5)) & 1) << (LG + 1));
+}
+
 // LDS (about 41 KB per 256-thread workgroup) allows 4 waves per SIMD; the launch
 // bound holds the registers to the 128 that allow them too.  At 27 modes that
 // spills 9 registers and still wins (measured, 4.19 M particles: 0.48 -> 0.44 ms).
@@ -96,10 +108,11 @@ __global__ __launch_bounds__(BS, Scenes::kMany ? 3 : 4) void g2p2g_kernel(G2P2GA
   // Output rows go through LDS (the bricks are not in use yet) so that every
   // wavefront writes 64 consecutive slots (measured, 27 modes, 4.19 M particles:
   // 2.0 ms with the rows written from the spread slots, 0.47 ms staged): row k of
-  // a round is stage[k * BS + slot], read back as stage[k * BS + tid].
+  // a round is stage[k * BS + stage_pos(slot)], read back at stage_pos(tid).
   float* const stage = reinterpret_cast<float*>(brick);
   static_assert(28 * BS * sizeof(float) <= sizeof(brick), "staging fits in the bricks");
   const int64_t i_out = (int64_t)blockIdx.x * BS + tid;  // slot this thread writes out
+  const int put = stage_pos<LG>(slot), get = stage_pos<LG>(tid);
   const bool out_ok = i_out < a.P;
   {
     const Proj1D px = proj_g2p(t0);
@@ -132,14 +145,14 @@ __global__ __launch_bounds__(BS, Scenes::kMany ? 3 : 4) void g2p2g_kernel(G2P2GA
       float* const co = a.coeff_out + (size_t)ax * NR * Ps;
       float* const xo = a.x_out + (size_t)ax * Ps;
 #pragma unroll
-      for (int r = 0; r < NR; ++r) stage[r * BS + slot] = c[ax][r];
-      stage[NR * BS + slot] = xn[ax];
+      for (int r = 0; r < NR; ++r) stage[r * BS + put] = c[ax][r];
+      stage[NR * BS + put] = xn[ax];
       __syncthreads();
       if (out_ok) {
 #pragma unroll
         for (int r = 0; r < NR; ++r)
-          __builtin_nontemporal_store(stage[r * BS + tid], co + (size_t)r * Ps + i_out);
-        __builtin_nontemporal_store(stage[NR * BS + tid], xo + i_out);
+          __builtin_nontemporal_store(stage[r * BS + get], co + (size_t)r * Ps + i_out);
+        __builtin_nontemporal_store(stage[NR * BS + get], xo + i_out);
       }
       __syncthreads();  // the next component overwrites the stage
     }
@@ -170,16 +183,16 @@ __global__ __launch_bounds__(BS, Scenes::kMany ? 3 : 4) void g2p2g_kernel(G2P2GA
       for (int e = 0; e < 9; ++e) Fn[e] = 0.0f;
     }
 #pragma unroll
-    for (int e = 0; e < 9; ++e) stage[e * BS + slot] = Fn[e];
-    stage[9 * BS + slot] = m;
+    for (int e = 0; e < 9; ++e) stage[e * BS + put] = Fn[e];
+    stage[9 * BS + put] = m;
     __syncthreads();
     if (out_ok) {
       if (a.F_out) {
 #pragma unroll
         for (int e = 0; e < 9; ++e)
-          __builtin_nontemporal_store(stage[e * BS + tid], a.F_out + (size_t)e * Ps + i_out);
+          __builtin_nontemporal_store(stage[e * BS + get], a.F_out + (size_t)e * Ps + i_out);
       }
-      if (a.mass_out) __builtin_nontemporal_store(stage[9 * BS + tid], a.mass_out + i_out);
+      if (a.mass_out) __builtin_nontemporal_store(stage[9 * BS + get], a.mass_out + i_out);
     }
     __syncthreads();  // the bricks are cleared next
   }
@@ -199,7 +212,12 @@ __global__ __launch_bounds__(BS, Scenes::kMany ? 3 : 4) void g2p2g_kernel(G2P2GA
   }
   if (!valid) m = 0.0f;
   tile_of[slot] = valid ? brick_tile_id(s - s0, c0, c1, c2) : kNoTile;
-  for (int k = tid; k < kBrickKMAX * 4 * kBrickV; k += BS) brick[k] = 0.0;
+  static_assert(kBrickNodes <= BS, "one brick node per thread");
+  const BrickNode bn = brick_node(tid);
+  if (tid < kBrickNodes) {
+#pragma unroll
+    for (int k = 0; k < kBrickKMAX * 4; ++k) brick[k * kBrickV + bn.lds] = 0.0;
+  }
   __syncthreads();
 
   // Bricks are given per distinct tile, not per run: the chunk is in the order of
@@ -269,6 +287,7 @@ __global__ __launch_bounds__(BS, Scenes::kMany ? 3 : 4) void g2p2g_kernel(G2P2GA
     quad = pair && quad_pair != 0 && mykey == quad_key && seg == quad_seg;
   }
   const bool emit = valid && (quad ? (lane & 3) == 0 : (!pair || (lane & 1) == 0));
+  const float pair_f = pair ? 1.0f : 0.0f, quad_f = quad ? 1.0f : 0.0f;
   {
     const Rows Rx = p2g_rows_scaled(basis_p2g(u0), m);
     const Rows Ry = p2g_rows_scaled(basis_p2g(u1), 1.0f);
@@ -282,12 +301,8 @@ __global__ __launch_bounds__(BS, Scenes::kMany ? 3 : 4) void g2p2g_kernel(G2P2GA
       double* const lbc = lb + ch * kBrickV;
       float* const gc = gch[ch];
       return [=](int jx, int jy, int jz, float v) {
-        const float v2 = v + __int_as_float(pair_swap_i(__float_as_int(v)));
-        float w = pair ? v2 : v;
-        if constexpr (LG == 2) {
-          const float v4 = v2 + __int_as_float(quad_swap_i(__float_as_int(v2)));
-          w = quad ? v4 : w;
-        }
+        float w = pair_fold(v, pair_f);
+        if constexpr (LG == 2) w = quad_fold(w, quad_f);
         if (!emit) return;
         if (lds)
           atomicAdd(lbc + jx + kBrickSY * jy + kBrickSZ * jz, (double)w);
@@ -307,35 +322,32 @@ __global__ __launch_bounds__(BS, Scenes::kMany ? 3 : 4) void g2p2g_kernel(G2P2GA
   }
   __syncthreads();
 
-  // flush: one global float atomic per channel per non-zero brick node
+  // flush: one global float atomic per channel per non-zero brick node, by the
+  // node's owner thread
   const int nb = nseg < kBrickKMAX ? nseg : kBrickKMAX;
-  for (int k = tid; k < nb * 4 * kBrickV; k += BS) {
-    const int sc4 = k / kBrickV;  // brick * 4 + channel
-    const int idx = k - sc4 * kBrickV;
-    const int sb = sc4 >> 2;
-    const int ch = sc4 & 3;
-    const int lz = idx / kBrickSZ;
-    const int rem = idx - lz * kBrickSZ;
-    const int ly = rem / kBrickSY;
-    const int lx = rem - ly * kBrickSY;
-    if (lx > kBrickT + 1 || ly > kBrickT + 1) continue;  // padding
-    const float v = (float)brick[k];
-    if (v == 0.0f) continue;
-    const uint32_t tc = (uint32_t)seg_tile[sb];
-    int fnx = nx, fny = ny, fnz = nz;  // one scene: constants
-    int64_t foff = 0;
-    if constexpr (Scenes::kMany) {
-      fnx = seg_dims[sb][0];
-      fny = seg_dims[sb][1];
-      fnz = seg_dims[sb][2];
-      foff = seg_node_off[sb];
-    }
-    const int gx = (int)(tc & 1023u) * kBrickT + lx;
-    const int gy = (int)((tc >> 10) & 1023u) * kBrickT + ly;
-    const int gz = (int)(tc >> 20) * kBrickT + lz;
-    if (gx < fnx && gy < fny && gz < fnz) {
-      float* const d = ch == 0 ? a.gm : ch == 1 ? a.gp0 : ch == 2 ? a.gp1 : a.gp2;
-      atomicAdd(d + foff + ((int64_t)(gz * fny + gy) * fnx + gx), v);
+  if (tid < kBrickNodes) {
+    for (int sb = 0; sb < nb; ++sb) {
+      const uint32_t tc = (uint32_t)seg_tile[sb];
+      int fnx = nx, fny = ny, fnz = nz;  // one scene: constants
+      int64_t foff = g.node_off;
+      if constexpr (Scenes::kMany) {
+        fnx = seg_dims[sb][0];
+        fny = seg_dims[sb][1];
+        fnz = seg_dims[sb][2];
+        foff = seg_node_off[sb];
+      }
+      const int gx = (int)(tc & 1023u) * kBrickT + bn.lx;
+      const int gy = (int)((tc >> 10) & 1023u) * kBrickT + bn.ly;
+      const int gz = (int)(tc >> 20) * kBrickT + bn.lz;
+      if (gx >= fnx || gy >= fny || gz >= fnz) continue;
+      const int64_t node = foff + ((int64_t)(gz * fny + gy) * fnx + gx);
+      const double* const src = brick + sb * 4 * kBrickV + bn.lds;
+      float* const dst[4] = {a.gm, a.gp0, a.gp1, a.gp2};
+#pragma unroll
+      for (int ch = 0; ch < 4; ++ch) {
+        const float v = (float)src[ch * kBrickV];
+        if (v != 0.0f) atomicAdd(dst[ch] + node, v);
+      }
     }
   }
 }

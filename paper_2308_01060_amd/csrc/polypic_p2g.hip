@@ -63,6 +63,8 @@ __global__ __launch_bounds__(BS, BS == 256 ? 4 : 2) void p2g_brick_kernel(P2GArg
   // cells and their brick atomics do not collide.
   constexpr int LG = NR >= 8 ? 2 : 1;  // log2 G
   const int slot = (((lane >> LG) * NW + wv) << LG) | (lane & ((1 << LG) - 1));
+  static_assert(kBrickNodes <= BS, "one brick node per thread");
+  const BrickNode bn = brick_node(tid);
   const size_t Ps = (size_t)a.P;
   const int64_t n_chunks = (a.P + BS - 1) / BS;
   const ChunkRange cr = block_chunks(a.sched, n_chunks);
@@ -104,7 +106,10 @@ __global__ __launch_bounds__(BS, BS == 256 ? 4 : 2) void p2g_brick_kernel(P2GArg
       for (int r = 0; r < 27; ++r) cfa[r] = (r < NR) ? cp[(size_t)r * Ps] : 0.0f;
     }
     tile_of[slot] = valid ? brick_tile_id(s - s0, b0, b1, b2) : kNoTile;
-    for (int k = tid; k < kBrickKMAX * 4 * kBrickV; k += BS) brick[k] = 0.0;
+    if (tid < kBrickNodes) {
+#pragma unroll
+      for (int k = 0; k < kBrickKMAX * 4; ++k) brick[k * kBrickV + bn.lds] = 0.0;
+    }
     __syncthreads();
 
     // runs of equal tiles in slot order (thread t looks at slot t) -> segments
@@ -151,6 +156,7 @@ __global__ __launch_bounds__(BS, BS == 256 ? 4 : 2) void p2g_brick_kernel(P2GArg
       quad = pair && quad_pair != 0 && mykey == quad_key && seg == quad_seg;
     }
     const bool emit = valid && (quad ? (lane & 3) == 0 : (!pair || (lane & 1) == 0));
+    const float pair_f = pair ? 1.0f : 0.0f, quad_f = quad ? 1.0f : 0.0f;
     {
       const float m = valid ? (a.mass ? a.mass[p] : a.uniform_mass) : 0.0f;
       // rows s w_j phi_k(j) per axis; the particle mass rides on the x rows
@@ -169,12 +175,8 @@ __global__ __launch_bounds__(BS, BS == 256 ? 4 : 2) void p2g_brick_kernel(P2GArg
         double* const lbc = lb + ch * kBrickV;
         float* const gc = gch[ch];
         return [=](int jx, int jy, int jz, float v) {
-          const float v2 = v + __int_as_float(pair_swap_i(__float_as_int(v)));
-          float w = pair ? v2 : v;
-          if constexpr (LG == 2) {
-            const float v4 = v2 + __int_as_float(quad_swap_i(__float_as_int(v2)));
-            w = quad ? v4 : w;
-          }
+          float w = pair_fold(v, pair_f);
+          if constexpr (LG == 2) w = quad_fold(w, quad_f);
           if (!emit) return;
           if (lds)
             atomicAdd(lbc + jx + kBrickSY * jy + kBrickSZ * jz, (double)w);
@@ -199,35 +201,32 @@ __global__ __launch_bounds__(BS, BS == 256 ? 4 : 2) void p2g_brick_kernel(P2GArg
     }
     __syncthreads();
 
-    // flush: one global float atomic per channel per non-zero brick node
+    // flush: one global float atomic per channel per non-zero brick node, by the
+    // node's owner thread
     const int nb = nseg < kBrickKMAX ? nseg : kBrickKMAX;
-    for (int k = tid; k < nb * 4 * kBrickV; k += BS) {
-      const int sc4 = k / kBrickV;  // brick * 4 + channel
-      const int idx = k - sc4 * kBrickV;
-      const int sb = sc4 >> 2;
-      const int ch = sc4 & 3;
-      const int lz = idx / kBrickSZ;
-      const int rem = idx - lz * kBrickSZ;
-      const int ly = rem / kBrickSY;
-      const int lx = rem - ly * kBrickSY;
-      if (lx > kBrickT + 1 || ly > kBrickT + 1) continue;  // padding
-      const float v = (float)brick[k];
-      if (v == 0.0f) continue;
-      const uint32_t tc = (uint32_t)seg_tile[sb];
-      int fnx = sg.nx, fny = sg.ny, fnz = sg.nz;  // one scene: constants
-      int64_t foff = 0;
-      if constexpr (Scenes::kMany) {
-        fnx = seg_dims[sb][0];
-        fny = seg_dims[sb][1];
-        fnz = seg_dims[sb][2];
-        foff = seg_node_off[sb];
-      }
-      const int gx = (int)(tc & 1023u) * kBrickT + lx;
-      const int gy = (int)((tc >> 10) & 1023u) * kBrickT + ly;
-      const int gz = (int)(tc >> 20) * kBrickT + lz;
-      if (gx < fnx && gy < fny && gz < fnz) {
-        float* const d = ch == 0 ? a.gm : ch == 1 ? a.gp0 : ch == 2 ? a.gp1 : a.gp2;
-        atomicAdd(d + foff + ((int64_t)(gz * fny + gy) * fnx + gx), v);
+    if (tid < kBrickNodes) {
+      for (int sb = 0; sb < nb; ++sb) {
+        const uint32_t tc = (uint32_t)seg_tile[sb];
+        int fnx = sg.nx, fny = sg.ny, fnz = sg.nz;  // one scene: constants
+        int64_t foff = sg.node_off;
+        if constexpr (Scenes::kMany) {
+          fnx = seg_dims[sb][0];
+          fny = seg_dims[sb][1];
+          fnz = seg_dims[sb][2];
+          foff = seg_node_off[sb];
+        }
+        const int gx = (int)(tc & 1023u) * kBrickT + bn.lx;
+        const int gy = (int)((tc >> 10) & 1023u) * kBrickT + bn.ly;
+        const int gz = (int)(tc >> 20) * kBrickT + bn.lz;
+        if (gx >= fnx || gy >= fny || gz >= fnz) continue;
+        const int64_t node = foff + ((int64_t)(gz * fny + gy) * fnx + gx);
+        const double* const src = brick + sb * 4 * kBrickV + bn.lds;
+        float* const dst[4] = {a.gm, a.gp0, a.gp1, a.gp2};
+#pragma unroll
+        for (int ch = 0; ch < 4; ++ch) {
+          const float v = (float)src[ch * kBrickV];
+          if (v != 0.0f) atomicAdd(dst[ch] + node, v);
+        }
       }
     }
     __syncthreads();  // the next chunk reuses tile_of, seg_tile and the bricks
