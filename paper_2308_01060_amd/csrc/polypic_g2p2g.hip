@@ -35,6 +35,17 @@ __device__ __forceinline__ int fused_slot(int tid) {
   return (((lane >> LG) * NW + wv) << LG) | (lane & ((1 << LG) - 1));
 }
 
+// Streaming store of this thread's float of a workgroup row: a buffer store
+// whose descriptor (the row's base and its n valid floats) is wave-uniform, so
+// the address is a scalar base plus a 32-bit lane offset with no per-store
+// vector arithmetic (a global store of p + t costs a 64-bit vector add each).
+// Lanes at or past n are dropped by the descriptor's range check.
+__device__ __forceinline__ void row_store_nt(float v, float* row, int n, int lane_byte_off) {
+  const __amdgpu_buffer_rsrc_t r =
+      __builtin_amdgcn_make_buffer_rsrc(row, 0, n * (int)sizeof(float), 0x00020000);
+  __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, lane_byte_off, 0, 2 /* nt */);
+}
+
 // Position of slot s in a staging row (a permutation of each 32 slots).  The 64
 // slots one wavefront writes agree in their wavefront-index bits (LG, LG + 1) and
 // differ in bits 5-7, which a plain index drops from the bank number.  XORing bit 6,
@@ -113,27 +124,33 @@ __global__ __launch_bounds__(BS, Scenes::kMany ? 3 : 4) void g2p2g_kernel(G2P2GA
   static_assert(28 * BS * sizeof(float) <= sizeof(brick), "staging fits in the bricks");
   const int64_t i_out = (int64_t)blockIdx.x * BS + tid;  // slot this thread writes out
   const int put = stage_pos<LG>(slot), get = stage_pos<LG>(tid);
+  // floats of this workgroup's rows that exist, and this thread's byte in a row
+  const int row_n = (int)min((int64_t)BS, a.P - (int64_t)blockIdx.x * BS);
+  const int out_off = tid * (int)sizeof(float);
   const bool out_ok = i_out < a.P;
   {
     const Proj1D px = proj_g2p(t0);
     const Proj1D py = proj_g2p(t1);
     const Proj1D pz = proj_g2p(t2);
     const int64_t gbase = g.node_off + (int64_t)(b2 * ny + b1) * nx + b0;
+    // every lane's stencil lies in the grid (a flagged or idle lane has base node
+    // 0 and the grid at least 3 nodes per axis), so the gathers need no branch;
+    // such lanes are zeroed afterwards, only in the wavefronts that hold one
+    const bool any_idle = __ballot(!gather) != 0ull;
 #pragma unroll
     for (int ax = 0; ax < 3; ++ax) {
-      if (gather) {
-        const float* vg = a.gv + (size_t)ax * a.gstride + gbase;
-        float v[27];
+      const float* vg = a.gv + (size_t)ax * a.gstride + gbase;
+      float v[27];
 #pragma unroll
-        for (int jz = 0; jz < 3; ++jz)
+      for (int jz = 0; jz < 3; ++jz)
 #pragma unroll
-          for (int jy = 0; jy < 3; ++jy)
+        for (int jy = 0; jy < 3; ++jy)
 #pragma unroll
-            for (int jx = 0; jx < 3; ++jx) v[jx + 3 * jy + 9 * jz] = vg[jz * nxny + jy * nx + jx];
-        project_modes<NR>(v, px, py, pz, c[ax]);
-      } else {
+          for (int jx = 0; jx < 3; ++jx) v[jx + 3 * jy + 9 * jz] = vg[jz * nxny + jy * nx + jx];
+      project_modes<NR>(v, px, py, pz, c[ax]);
+      if (any_idle) {
 #pragma unroll
-        for (int r = 0; r < 27; ++r) c[ax][r] = 0.0f;
+        for (int r = 0; r < NR; ++r) c[ax][r] = gather ? c[ax][r] : 0.0f;
       }
 #pragma unroll
       for (int r = NR; r < 27; ++r) c[ax][r] = 0.0f;
@@ -142,8 +159,8 @@ __global__ __launch_bounds__(BS, Scenes::kMany ? 3 : 4) void g2p2g_kernel(G2P2GA
       xn[ax] = fminf(x1, g.hi[ax]);
       // rows of this component: the NR coefficients and x'; written once, never
       // re-read here, so streamed past the caches the gathers use
-      float* const co = a.coeff_out + (size_t)ax * NR * Ps;
-      float* const xo = a.x_out + (size_t)ax * Ps;
+      float* const co = a.coeff_out + (size_t)ax * NR * Ps + i0;  // this workgroup's slots
+      float* const xo = a.x_out + (size_t)ax * Ps + i0;
 #pragma unroll
       for (int r = 0; r < NR; ++r) stage[r * BS + put] = c[ax][r];
       stage[NR * BS + put] = xn[ax];
@@ -151,8 +168,8 @@ __global__ __launch_bounds__(BS, Scenes::kMany ? 3 : 4) void g2p2g_kernel(G2P2GA
       if (out_ok) {
 #pragma unroll
         for (int r = 0; r < NR; ++r)
-          __builtin_nontemporal_store(stage[r * BS + get], co + (size_t)r * Ps + i_out);
-        __builtin_nontemporal_store(stage[NR * BS + get], xo + i_out);
+          row_store_nt(stage[r * BS + get], co + (size_t)r * Ps, row_n, out_off);
+        row_store_nt(stage[NR * BS + get], xo, row_n, out_off);
       }
       __syncthreads();  // the next component overwrites the stage
     }
@@ -190,9 +207,9 @@ __global__ __launch_bounds__(BS, Scenes::kMany ? 3 : 4) void g2p2g_kernel(G2P2GA
       if (a.F_out) {
 #pragma unroll
         for (int e = 0; e < 9; ++e)
-          __builtin_nontemporal_store(stage[e * BS + get], a.F_out + (size_t)e * Ps + i_out);
+          row_store_nt(stage[e * BS + get], a.F_out + (size_t)e * Ps + i0, row_n, out_off);
       }
-      if (a.mass_out) __builtin_nontemporal_store(stage[9 * BS + get], a.mass_out + i_out);
+      if (a.mass_out) row_store_nt(stage[9 * BS + get], a.mass_out + i0, row_n, out_off);
     }
     __syncthreads();  // the bricks are cleared next
   }
