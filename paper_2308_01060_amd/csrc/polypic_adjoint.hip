@@ -196,14 +196,17 @@ __global__ __launch_bounds__(256) void p2g_backward_kernel(P2GBackArgs a) {
 }
 
 // ---------------------------------------------------------------- G2P adjoint
-// Scatter of v_bar into FP64 LDS bricks (as the brick P2G path: the lanes of a
-// wavefront take every NW-th slot of the workgroup's chunk) plus a gather of
-// the grid velocity for x_bar.
+// Scatter of v_bar into FP64 LDS bricks (the brick P2G scheme: lane groups of
+// consecutive slots, which usually share a cell, add their node values across
+// lanes first; the groups of a wavefront are spread over the workgroup's chunk
+// so that their atomics fall in different cells) plus a gather of the grid
+// velocity for x_bar.
 constexpr int kBackKMAX = 3;
 
 template <int NR, int BS>
 __global__ __launch_bounds__(BS) void g2p_backward_kernel(G2PBackArgs a) {
   constexpr int NW = BS / kWave;
+  constexpr int LG = NR >= 8 ? 2 : 1;  // log2 of the lane-group size
   __shared__ double brick[kBackKMAX * 3 * kBrickV];  // [brick][component][node]
   __shared__ uint32_t tile_of[BS];
   __shared__ int seg_of[BS];
@@ -213,11 +216,13 @@ __global__ __launch_bounds__(BS) void g2p_backward_kernel(G2PBackArgs a) {
   const int tid = threadIdx.x;
   const int lane = tid & (kWave - 1);
   const int wv = tid / kWave;
-  const int slot = lane * NW + wv;
+  const int slot = (((lane >> LG) * NW + wv) << LG) | (lane & ((1 << LG) - 1));
   const int64_t i = (int64_t)blockIdx.x * BS + slot;
   const size_t Ps = (size_t)a.P;
   const int nx = a.g.nx, ny = a.g.ny, nz = a.g.nz;
   const size_t N = (size_t)nx * ny * nz;
+  static_assert(kBrickNodes <= BS, "one brick node per thread");
+  const BrickNode bn = brick_node(tid);
 
   bool valid = i < a.P;
   int p = 0;
@@ -235,12 +240,17 @@ __global__ __launch_bounds__(BS) void g2p_backward_kernel(G2PBackArgs a) {
     if (!ok) {
       raise_flag(a.status, kFlagRange);
       valid = false;
+      b0 = b1 = b2 = 0;  // (stencil_axis leaves 0 on its own failing axis only)
+      t0 = t1 = t2 = 0.f;
     }
   }
   tile_of[slot] = valid ? ((uint32_t)(b0 >> 2) | ((uint32_t)(b1 >> 2) << 10) |
                            ((uint32_t)(b2 >> 2) << 20))
                         : 0xFFFFFFFFu;
-  for (int k = tid; k < kBackKMAX * 3 * kBrickV; k += BS) brick[k] = 0.0;
+  if (tid < kBrickNodes) {
+#pragma unroll
+    for (int k = 0; k < kBackKMAX * 3; ++k) brick[k * kBrickV + bn.lds] = 0.0;
+  }
   __syncthreads();
   {
     const uint32_t tt = tile_of[tid];
@@ -261,7 +271,22 @@ __global__ __launch_bounds__(BS) void g2p_backward_kernel(G2PBackArgs a) {
   for (int w = 0; w < NW; ++w) nseg += wave_heads[w];
   const int seg = seg_of[slot];
 
-  if (valid) {
+  // Lanes that share this lane's segment and base node: the pair (lane ^ 1)
+  // and, with groups of 4, the quad.  Every lane runs the node loop below (an
+  // invalid one with base node 0 and zero gradients), since the DPP folds read
+  // their partners.
+  const int mykey = valid ? ((b2 * 1024 + b1) * 1024 + b0) : -1 - lane;
+  const int pair_key = pair_swap_i(mykey), pair_seg = pair_swap_i(seg);
+  const bool pair = mykey == pair_key && seg == pair_seg;
+  bool quad = false;
+  if constexpr (LG == 2) {
+    const int quad_pair = quad_swap_i((int)pair), quad_key = quad_swap_i(mykey);
+    const int quad_seg = quad_swap_i(seg);
+    quad = pair && quad_pair != 0 && mykey == quad_key && seg == quad_seg;
+  }
+  const bool emit = valid && (quad ? (lane & 3) == 0 : (!pair || (lane & 1) == 0));
+  const float pair_f = pair ? 1.0f : 0.0f, quad_f = quad ? 1.0f : 0.0f;
+  {
     Rows Pr[3], dP[3];
     g2p_rows(t0, Pr[0], dP[0]);
     g2p_rows(t1, Pr[1], dP[1]);
@@ -270,7 +295,7 @@ __global__ __launch_bounds__(BS) void g2p_backward_kernel(G2PBackArgs a) {
     const int lbase = (b0 & 3) + kBrickSY * (b1 & 3) + kBrickSZ * (b2 & 3);
     const int nxny = nx * ny;
     const int gbase = (b2 * ny + b1) * nx + b0;
-    double* const lb = brick + (lds ? seg : 0) * 3 * kBrickV + lbase;
+    double* const lb = brick + (lds ? max(seg, 0) : 0) * 3 * kBrickV + lbase;
     float xg[3] = {0.f, 0.f, 0.f};
 #pragma unroll 1
     for (int ax = 0; ax < 3; ++ax) {
@@ -283,18 +308,22 @@ __global__ __launch_bounds__(BS) void g2p_backward_kernel(G2PBackArgs a) {
 #pragma unroll
           for (int jx = 0; jx < 3; ++jx) v[jx + 3 * jy + 9 * jz] = vg[jz * nxny + jy * nx + jx];
       float cb[27];
-      const float* cbp = a.coeff_out_grad + (size_t)ax * NR * Ps + i;
 #pragma unroll
-      for (int r = 0; r < 27; ++r) cb[r] = (r < NR) ? cbp[(size_t)r * Ps] : 0.0f;
-      if (a.x_out_grad) {
-        // advection x' = clamp(x + dt c'_0): recompute c'_0 for the clamp test
-        float o[27];
-        contract_rows<1>(v, Pr[0], Pr[1], Pr[2], o);
-        const float xn = fmaf(a.dt, o[0], xp[ax]);
-        if (xn >= a.lo[ax] && xn <= a.hi[ax]) {
-          const float xb = a.x_out_grad[(size_t)ax * Ps + i];
-          xg[ax] += xb;
-          cb[0] = fmaf(a.dt, xb, cb[0]);
+      for (int r = 0; r < 27; ++r) cb[r] = 0.0f;
+      if (valid) {
+        const float* cbp = a.coeff_out_grad + (size_t)ax * NR * Ps + i;
+#pragma unroll
+        for (int r = 0; r < NR; ++r) cb[r] = cbp[(size_t)r * Ps];
+        if (a.x_out_grad) {
+          // advection x' = clamp(x + dt c'_0): recompute c'_0 for the clamp test
+          float o[27];
+          contract_rows<1>(v, Pr[0], Pr[1], Pr[2], o);
+          const float xn = fmaf(a.dt, o[0], xp[ax]);
+          if (xn >= a.lo[ax] && xn <= a.hi[ax]) {
+            const float xb = a.x_out_grad[(size_t)ax * Ps + i];
+            xg[ax] += xb;
+            cb[0] = fmaf(a.dt, xb, cb[0]);
+          }
         }
       }
       // One pass over the nodes gives, per node j, f = sum_r P_r(j) cb_r (the
@@ -309,40 +338,44 @@ __global__ __launch_bounds__(BS) void g2p_backward_kernel(G2PBackArgs a) {
                            sx = fmaf(vj, fx, sx);
                            sy = fmaf(vj, fy, sy);
                            sz = fmaf(vj, fz, sz);
+                           float w = pair_fold(f, pair_f);
+                           if constexpr (LG == 2) w = quad_fold(w, quad_f);
+                           if (!emit) return;
                            if (lds)
-                             atomicAdd(lbc + jx + kBrickSY * jy + kBrickSZ * jz, (double)f);
+                             atomicAdd(lbc + jx + kBrickSY * jy + kBrickSZ * jz, (double)w);
                            else
-                             atomicAdd(dst + jz * nxny + jy * nx + jx, f);
+                             atomicAdd(dst + jz * nxny + jy * nx + jx, w);
                          });
       xg[0] = fmaf(a.g.inv_dx, sx, xg[0]);
       xg[1] = fmaf(a.g.inv_dx, sy, xg[1]);
       xg[2] = fmaf(a.g.inv_dx, sz, xg[2]);
     }
-    a.x_in_grad[p] += xg[0];
-    a.x_in_grad[Ps + p] += xg[1];
-    a.x_in_grad[2 * Ps + p] += xg[2];
+    if (valid) {
+      a.x_in_grad[p] += xg[0];
+      a.x_in_grad[Ps + p] += xg[1];
+      a.x_in_grad[2 * Ps + p] += xg[2];
+    }
   }
   __syncthreads();
 
+  // flush: one global float atomic per component per non-zero brick node, by
+  // the node's owner thread
   const int nb = nseg < kBackKMAX ? nseg : kBackKMAX;
-  for (int k = tid; k < nb * 3 * kBrickV; k += BS) {
-    const int sc = k / kBrickV;  // brick * 3 + component
-    const int idx = k - sc * kBrickV;
-    const int s = sc / 3;
-    const int ax = sc - 3 * s;
-    const int lz = idx / kBrickSZ;
-    const int rem = idx - lz * kBrickSZ;
-    const int ly = rem / kBrickSY;
-    const int lx = rem - ly * kBrickSY;
-    if (lx > kBrickT + 1 || ly > kBrickT + 1) continue;  // padding
-    const float v = (float)brick[k];
-    if (v == 0.0f) continue;
-    const uint32_t tl = seg_tile[s];
-    const int gx = (int)(tl & 1023u) * kBrickT + lx;
-    const int gy = (int)((tl >> 10) & 1023u) * kBrickT + ly;
-    const int gz = (int)(tl >> 20) * kBrickT + lz;
-    if (gx < nx && gy < ny && gz < nz)
-      atomicAdd(a.gvb + (size_t)ax * N + ((size_t)(gz * ny + gy) * nx + gx), v);
+  if (tid < kBrickNodes) {
+    for (int sb = 0; sb < nb; ++sb) {
+      const uint32_t tl = seg_tile[sb];
+      const int gx = (int)(tl & 1023u) * kBrickT + bn.lx;
+      const int gy = (int)((tl >> 10) & 1023u) * kBrickT + bn.ly;
+      const int gz = (int)(tl >> 20) * kBrickT + bn.lz;
+      if (gx >= nx || gy >= ny || gz >= nz) continue;
+      const size_t node = (size_t)(gz * ny + gy) * nx + gx;
+      const double* const src = brick + sb * 3 * kBrickV + bn.lds;
+#pragma unroll
+      for (int ax = 0; ax < 3; ++ax) {
+        const float v = (float)src[ax * kBrickV];
+        if (v != 0.0f) atomicAdd(a.gvb + (size_t)ax * N + node, v);
+      }
+    }
   }
 }
 
