@@ -327,25 +327,21 @@ __global__ __launch_bounds__(BS) void g2p_backward_kernel(G2PBackArgs a) {
         }
       }
       // One pass over the nodes gives, per node j, f = sum_r P_r(j) cb_r (the
-      // transpose of the projection: v_bar, scattered to the brick) and its
-      // t-derivatives, whose dot products with v are the x gradient.
+      // transpose of the projection: v_bar, scattered to the brick), and the
+      // sums of v times its t-derivatives, which are the x gradient.
       float sx = 0.0f, sy = 0.0f, sz = 0.0f;
       double* const lbc = lb + ax * kBrickV;
       float* const dst = a.gvb + (size_t)ax * N + gbase;
-      stream_modes_d<NR>(cb, Pr[0], Pr[1], Pr[2], dP[0], dP[1], dP[2],
-                         [&](int jx, int jy, int jz, float f, float fx, float fy, float fz) {
-                           const float vj = v[jx + 3 * jy + 9 * jz];
-                           sx = fmaf(vj, fx, sx);
-                           sy = fmaf(vj, fy, sy);
-                           sz = fmaf(vj, fz, sz);
-                           float w = pair_fold(f, pair_f);
-                           if constexpr (LG == 2) w = quad_fold(w, quad_f);
-                           if (!emit) return;
-                           if (lds)
-                             atomicAdd(lbc + jx + kBrickSY * jy + kBrickSZ * jz, (double)w);
-                           else
-                             atomicAdd(dst + jz * nxny + jy * nx + jx, w);
-                         });
+      stream_g2p_adjoint<NR>(cb, Pr[0], Pr[1], Pr[2], dP[0], dP[1], dP[2], v, sx, sy, sz,
+                             [&](int jx, int jy, int jz, float f) {
+                               float w = pair_fold(f, pair_f);
+                               if constexpr (LG == 2) w = quad_fold(w, quad_f);
+                               if (!emit) return;
+                               if (lds)
+                                 atomicAdd(lbc + jx + kBrickSY * jy + kBrickSZ * jz, (double)w);
+                               else
+                                 atomicAdd(dst + jz * nxny + jy * nx + jx, w);
+                             });
       xg[0] = fmaf(a.g.inv_dx, sx, xg[0]);
       xg[1] = fmaf(a.g.inv_dx, sy, xg[1]);
       xg[2] = fmaf(a.g.inv_dx, sz, xg[2]);

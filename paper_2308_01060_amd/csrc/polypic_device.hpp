@@ -393,14 +393,20 @@ __device__ __forceinline__ void stream_modes(const float (&c)[27], const Rows& R
   }
 }
 
-// As stream_modes, with the derivatives: for every node j emits
-// (jx, jy, jz, f, fx, fy, fz) where f = sum_r c_r Rx Ry Rz and fb is the same
-// sum with the derivative row dR on axis b.  The stages are shared: z with Rz
-// and dRz, y with Ry and dRy, x with Rx and dRx.
+// Transpose of the G2P projection with the x gradient, for projection rows P
+// (g2p_rows: row 2 is the constant (1/2, -1, 1/2), so dP row 2 is zero).  For
+// every node j emits (jx, jy, jz, f_j) with f = sum_r c_r Px Py Pz (v_bar), and
+// accumulates s_b = sum_j v_j f^(b)_j, f^(b) being f with dP on axis b.  The x
+// sums never form f^(b) per node: within one (jy, jz) row of nodes,
+//   sum_jx v_j f^(x)_j = sum_kx C2[kx] (dPx v)[kx],
+//   sum_jx v_j f^(y)_j = sum_kx C2y[kx] (Px v)[kx]   (and z alike),
+// where C2, C2y, C2z are the row's coefficients contracted over z and y.
 template <int NR, class Emit>
-__device__ __forceinline__ void stream_modes_d(const float (&c)[27], const Rows& Rx, const Rows& Ry,
-                                               const Rows& Rz, const Rows& dRx, const Rows& dRy,
-                                               const Rows& dRz, Emit&& emit) {
+__device__ __forceinline__ void stream_g2p_adjoint(const float (&c)[27], const Rows& Px,
+                                                   const Rows& Py, const Rows& Pz, const Rows& dPx,
+                                                   const Rows& dPy, const Rows& dPz,
+                                                   const float (&v)[27], float& sx, float& sy,
+                                                   float& sz, Emit&& emit) {
 #pragma unroll
   for (int jz = 0; jz < 3; ++jz) {
     float C1[3][3], C1z[3][3];  // [kx][ky]
@@ -414,8 +420,8 @@ __device__ __forceinline__ void stream_modes_d(const float (&c)[27], const Rows&
         for (int kz = 0; kz < 3; ++kz)
           if (has_mode<NR>(kx, ky, kz)) {
             const float cr = c[mode_index(kx, ky, kz)];
-            acc = fmaf(cr, Rz.r[kz][jz], acc);
-            accz = fmaf(cr, dRz.r[kz][jz], accz);
+            acc = fmaf(cr, Pz.r[kz][jz], acc);
+            if (kz < 2) accz = fmaf(cr, dPz.r[kz][jz], accz);
           }
         C1[kx][ky] = acc;
         C1z[kx][ky] = accz;
@@ -430,26 +436,34 @@ __device__ __forceinline__ void stream_modes_d(const float (&c)[27], const Rows&
 #pragma unroll
         for (int ky = 0; ky < 3; ++ky)
           if (any_kz<NR>(kx, ky)) {
-            acc = fmaf(C1[kx][ky], Ry.r[ky][jy], acc);
-            accy = fmaf(C1[kx][ky], dRy.r[ky][jy], accy);
-            accz = fmaf(C1z[kx][ky], Ry.r[ky][jy], accz);
+            acc = fmaf(C1[kx][ky], Py.r[ky][jy], acc);
+            if (ky < 2) accy = fmaf(C1[kx][ky], dPy.r[ky][jy], accy);
+            accz = fmaf(C1z[kx][ky], Py.r[ky][jy], accz);
           }
         C2[kx] = acc;
         C2y[kx] = accy;
         C2z[kx] = accz;
       }
+      const float* vr = v + 3 * jy + 9 * jz;
+#pragma unroll
+      for (int kx = 0; kx < 3; ++kx) {
+        if (!any_kykz<NR>(kx)) continue;
+        const float pv = kx == 2 ? 0.5f * (vr[0] + vr[2]) - vr[1]
+                                 : fmaf(Px.r[kx][2], vr[2], fmaf(Px.r[kx][1], vr[1], Px.r[kx][0] * vr[0]));
+        if (kx < 2) {
+          const float dv = fmaf(dPx.r[kx][2], vr[2], fmaf(dPx.r[kx][1], vr[1], dPx.r[kx][0] * vr[0]));
+          sx = fmaf(C2[kx], dv, sx);
+        }
+        sy = fmaf(C2y[kx], pv, sy);
+        sz = fmaf(C2z[kx], pv, sz);
+      }
 #pragma unroll
       for (int jx = 0; jx < 3; ++jx) {
-        float f = 0.0f, fx = 0.0f, fy = 0.0f, fz = 0.0f;
+        float f = 0.0f;
 #pragma unroll
         for (int kx = 0; kx < 3; ++kx)
-          if (any_kykz<NR>(kx)) {
-            f = fmaf(C2[kx], Rx.r[kx][jx], f);
-            fx = fmaf(C2[kx], dRx.r[kx][jx], fx);
-            fy = fmaf(C2y[kx], Rx.r[kx][jx], fy);
-            fz = fmaf(C2z[kx], Rx.r[kx][jx], fz);
-          }
-        emit(jx, jy, jz, f, fx, fy, fz);
+          if (any_kykz<NR>(kx)) f = fmaf(C2[kx], Px.r[kx][jx], f);
+        emit(jx, jy, jz, f);
       }
     }
   }

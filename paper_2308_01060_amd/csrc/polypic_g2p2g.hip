@@ -313,10 +313,10 @@ __global__ __launch_bounds__(BS, Scenes::kMany ? 3 : 4) void g2p2g_kernel(G2P2GA
     const int lbase = (c0 & 3) + kBrickSY * (c1 & 3) + kBrickSZ * (c2 & 3);
     const int64_t gbase = g.node_off + (int64_t)(c2 * ny + c1) * nx + c0;
     double* const lb = brick + (lds ? max(seg, 0) : 0) * 4 * kBrickV + lbase;
-    float* const gch[4] = {a.gm + gbase, a.gp0 + gbase, a.gp1 + gbase, a.gp2 + gbase};
     auto emitter = [&](int ch) {
       double* const lbc = lb + ch * kBrickV;
-      float* const gc = gch[ch];
+      // (the HBM base is formed only on that rare path, to keep registers free)
+      float* const gc = ch == 0 ? a.gm : ch == 1 ? a.gp0 : ch == 2 ? a.gp1 : a.gp2;
       return [=](int jx, int jy, int jz, float v) {
         float w = pair_fold(v, pair_f);
         if constexpr (LG == 2) w = quad_fold(w, quad_f);
@@ -324,7 +324,7 @@ __global__ __launch_bounds__(BS, Scenes::kMany ? 3 : 4) void g2p2g_kernel(G2P2GA
         if (lds)
           atomicAdd(lbc + jx + kBrickSY * jy + kBrickSZ * jz, (double)w);
         else
-          atomicAdd(gc + jz * nxny + jy * nx + jx, w);
+          atomicAdd(gc + gbase + (jz * nxny + jy * nx + jx), w);
       };
     };
     {  // mass: m W_ip

@@ -31,7 +31,7 @@ def scene(seed, P_block=6, cells=16, mass_random=False):
     return g, x, c, m
 
 
-@pytest.mark.parametrize("n_modes", [4, 27])
+@pytest.mark.parametrize("n_modes", [1, 4, 8, 27])
 def test_single_step_adjoint_matches_twin(n_modes):
     pp = require_gpu()
     gs, x, c, m = scene(3, mass_random=True)
