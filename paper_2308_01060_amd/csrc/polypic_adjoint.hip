@@ -217,7 +217,10 @@ __global__ __launch_bounds__(BS) void g2p_backward_kernel(G2PBackArgs a) {
   const int lane = tid & (kWave - 1);
   const int wv = tid / kWave;
   const int slot = (((lane >> LG) * NW + wv) << LG) | (lane & ((1 << LG) - 1));
-  const int64_t i = (int64_t)blockIdx.x * BS + slot;
+  const int64_t i0 = (int64_t)blockIdx.x * BS;
+  const int64_t i = i0 + slot;
+  const int row_n = (int)min((int64_t)BS, a.P - i0);  // slots of this workgroup
+  const int slot_off = slot * (int)sizeof(float);
   const size_t Ps = (size_t)a.P;
   const int nx = a.g.nx, ny = a.g.ny, nz = a.g.nz;
   const size_t N = (size_t)nx * ny * nz;
@@ -311,16 +314,17 @@ __global__ __launch_bounds__(BS) void g2p_backward_kernel(G2PBackArgs a) {
 #pragma unroll
       for (int r = 0; r < 27; ++r) cb[r] = 0.0f;
       if (valid) {
-        const float* cbp = a.coeff_out_grad + (size_t)ax * NR * Ps + i;
+        // this workgroup's slice of each row, read at the thread's slot
+        const float* cbp = a.coeff_out_grad + (size_t)ax * NR * Ps + i0;
 #pragma unroll
-        for (int r = 0; r < NR; ++r) cb[r] = cbp[(size_t)r * Ps];
+        for (int r = 0; r < NR; ++r) cb[r] = row_load(cbp + (size_t)r * Ps, row_n, slot_off);
         if (a.x_out_grad) {
           // advection x' = clamp(x + dt c'_0): recompute c'_0 for the clamp test
           float o[27];
           contract_rows<1>(v, Pr[0], Pr[1], Pr[2], o);
           const float xn = fmaf(a.dt, o[0], xp[ax]);
           if (xn >= a.lo[ax] && xn <= a.hi[ax]) {
-            const float xb = a.x_out_grad[(size_t)ax * Ps + i];
+            const float xb = row_load(a.x_out_grad + (size_t)ax * Ps + i0, row_n, slot_off);
             xg[ax] += xb;
             cb[0] = fmaf(a.dt, xb, cb[0]);
           }

@@ -651,6 +651,25 @@ __device__ __forceinline__ float quad_fold(float v, float f) {
   return v;
 }
 
+// ---------------------------------------------------------------- workgroup rows
+// Access to this thread's float of a workgroup's slice of a particle row, through
+// a buffer descriptor over the slice (its base and its n valid floats), which is
+// wave-uniform: the address is then a scalar base plus a 32-bit lane offset, with
+// no per-access vector arithmetic (a global access to p + t costs a 64-bit vector
+// add, and two registers while in flight).  Lanes at or past n are dropped (a
+// store) or read 0 (a load) by the descriptor's range check.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t row_rsrc(const float* row, int n) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(row), 0, n * (int)sizeof(float),
+                                           0x00020000);
+}
+__device__ __forceinline__ void row_store_nt(float v, float* row, int n, int lane_byte_off) {
+  __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), row_rsrc(row, n), lane_byte_off, 0,
+                                        2 /* nt */);
+}
+__device__ __forceinline__ float row_load(const float* row, int n, int lane_byte_off) {
+  return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(row_rsrc(row, n), lane_byte_off, 0, 0));
+}
+
 // popcount of the bits of `mask` below this lane
 __device__ __forceinline__ int lanes_below(unsigned long long mask) {
   return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),

@@ -35,17 +35,6 @@ __device__ __forceinline__ int fused_slot(int tid) {
   return (((lane >> LG) * NW + wv) << LG) | (lane & ((1 << LG) - 1));
 }
 
-// Streaming store of this thread's float of a workgroup row: a buffer store
-// whose descriptor (the row's base and its n valid floats) is wave-uniform, so
-// the address is a scalar base plus a 32-bit lane offset with no per-store
-// vector arithmetic (a global store of p + t costs a 64-bit vector add each).
-// Lanes at or past n are dropped by the descriptor's range check.
-__device__ __forceinline__ void row_store_nt(float v, float* row, int n, int lane_byte_off) {
-  const __amdgpu_buffer_rsrc_t r =
-      __builtin_amdgcn_make_buffer_rsrc(row, 0, n * (int)sizeof(float), 0x00020000);
-  __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, lane_byte_off, 0, 2 /* nt */);
-}
-
 // Position of slot s in a staging row (a permutation of each 32 slots).  The 64
 // slots one wavefront writes agree in their wavefront-index bits (LG, LG + 1) and
 // differ in bits 5-7, which a plain index drops from the bank number.  XORing bit 6,
