@@ -68,9 +68,21 @@ KERNEL_SOURCES = {
 }
 
 
+# headers every kernel source includes: a change there changes the kernels too
+KERNEL_HEADERS = (
+    "paper_2308_01060_amd/csrc/polypic_device.hpp",
+    "paper_2308_01060_amd/csrc/polypic_scene.hpp",
+    "paper_2308_01060_amd/csrc/polypic_internal.hpp",
+)
+
+
 def source_digest(kernel: str) -> str:
-    with open(os.path.join(ROOT, KERNEL_SOURCES[kernel]), "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    """Digest of the kernel's source file and the device headers it includes."""
+    h = hashlib.sha256()
+    for rel in (KERNEL_SOURCES[kernel],) + KERNEL_HEADERS:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def measured_traffic(kernel: str, workload: str):
