@@ -126,17 +126,23 @@ __global__ __launch_bounds__(BS, Scenes::kMany ? 3 : 4) void g2p2g_kernel(G2P2GA
     // 0 and the grid at least 3 nodes per axis), so the gathers need no branch;
     // such lanes are zeroed afterwards, only in the wavefronts that hold one
     const bool any_idle = __ballot(!gather) != 0ull;
-#pragma unroll
-    for (int ax = 0; ax < 3; ++ax) {
+    auto gather_nodes = [&](int ax, float(&v)[27]) {
       const float* vg = a.gv + (size_t)ax * a.gstride + gbase;
-      float v[27];
 #pragma unroll
       for (int jz = 0; jz < 3; ++jz)
 #pragma unroll
         for (int jy = 0; jy < 3; ++jy)
 #pragma unroll
           for (int jx = 0; jx < 3; ++jx) v[jx + 3 * jy + 9 * jz] = vg[jz * nxny + jy * nx + jx];
+    };
+    float v[27];
+    gather_nodes(0, v);
+#pragma unroll
+    for (int ax = 0; ax < 3; ++ax) {
       project_modes<NR>(v, px, py, pz, c[ax]);
+      // the next component's gathers go out now, ahead of this component's
+      // staging barriers and stores (v is free once projected)
+      if (ax < 2) gather_nodes(ax + 1, v);
       if (any_idle) {
 #pragma unroll
         for (int r = 0; r < NR; ++r) c[ax][r] = gather ? c[ax][r] : 0.0f;
