@@ -341,6 +341,32 @@ int32_t polypic_p2g_backward(const polypic_grid* grid, int64_t P, int32_t n_mode
                              float* mass_grad, int32_t* status_dev, void* stream);
 
 /* ------------------------------------------------------------------------
+ * Particle order.  The per-step sort (section 3.1) leaves every particle array
+ * in slot order; these move whole arrays between orders on the device.
+ *
+ * polypic_gather_rows: dst[r][i] = src[r][idx[i]] for r < rows, i < P, with
+ *   rows of P 4-byte elements (float32 or int32; the bits are copied).  src and
+ *   dst are device arrays of rows * P elements and must not overlap; idx is a
+ *   device array of P indices, each clamped into [0, P) (a bad index gives a
+ *   wrong element, never an out-of-bounds read).
+ *   Returns POLYPIC_EINVAL for a null pointer with rows * P > 0, rows < 0, P
+ *   outside [0, 2^31), or overlapping src and dst.
+ * polypic_scatter_rows: dst[r][idx[i]] = src[r][i], arguments and errors as
+ *   polypic_gather_rows.  With idx a permutation every element of dst is
+ *   written once; otherwise repeated indices race (one of the values is kept)
+ *   and elements no index names keep their previous values.
+ * polypic_invert_permutation: inv[perm[i]] = i for i < P (device arrays of P
+ *   int32, not overlapping).  perm must be a permutation of [0, P): entries
+ *   outside that range are clamped into it, and an entry of inv that no perm
+ *   entry names keeps its previous value.
+ * Both run asynchronously on `stream`. */
+int32_t polypic_gather_rows(const void* src, void* dst, const int32_t* idx, int64_t rows,
+                            int64_t P, void* stream);
+int32_t polypic_scatter_rows(const void* src, void* dst, const int32_t* idx, int64_t rows,
+                             int64_t P, void* stream);
+int32_t polypic_invert_permutation(const int32_t* perm, int32_t* inv, int64_t P, void* stream);
+
+/* ------------------------------------------------------------------------
  * Batches of independent scenes (not in the paper: many small simulations
  * stepped together).  Every scene has its own grid and particles; the
  * particle arrays of all scenes are laid end to end (flattened index), and so

@@ -49,6 +49,9 @@ EXPORTED = (
     "polypic_g2p_backward",
     "polypic_grid_update_backward",
     "polypic_p2g_backward",
+    "polypic_gather_rows",
+    "polypic_scatter_rows",
+    "polypic_invert_permutation",
     "polypic_batch_table_bytes",
     "polypic_batch_plan",
     "polypic_batch_sort_workspace_bytes",
@@ -178,6 +181,12 @@ def load() -> ctypes.CDLL:
                                                  P]
     lib.polypic_p2g_backward.restype = i32
     lib.polypic_p2g_backward.argtypes = [G, i64, i32, P, P, f32, P, P, P, P, P, P, P, P, P]
+    lib.polypic_gather_rows.restype = i32
+    lib.polypic_gather_rows.argtypes = [P, P, P, i64, i64, P]
+    lib.polypic_scatter_rows.restype = i32
+    lib.polypic_scatter_rows.argtypes = [P, P, P, i64, i64, P]
+    lib.polypic_invert_permutation.restype = i32
+    lib.polypic_invert_permutation.argtypes = [P, P, i64, P]
     B = ctypes.POINTER(polypic_batch)
     lib.polypic_batch_table_bytes.restype = i32
     lib.polypic_batch_table_bytes.argtypes = [i32, ctypes.POINTER(sz)]

@@ -58,7 +58,7 @@ class PolyPICSteps(torch.autograd.Function):
         f32 = dict(dtype=torch.float32, device=dev)
         x = x0.detach().contiguous().reshape(3, P)
         c = c0.detach().contiguous().reshape(3, n_modes, P)
-        order = torch.arange(P, dtype=torch.int64, device=dev)
+        order = torch.arange(P, dtype=torch.int32, device=dev)  # particle of each slot
         checkpoints = []
         gm = torch.empty(N, **f32)
         gp = torch.empty(3 * N, **f32)
@@ -85,7 +85,9 @@ class PolyPICSteps(torch.autograd.Function):
             else:
                 ops.polypic_g2p(grid, n_modes, dt, gv, x, c_next, perm=perm, x_out=x_next,
                                 status_dev=B.status)
-            order = order[perm.long()]
+            new_order = torch.empty_like(order)
+            ops.polypic_gather_rows(order, new_order, perm)  # slot i now holds order[perm[i]]
+            order = new_order
             x, c = x_next, c_next
         ctx.grid = grid
         ctx.params = (n_modes, n_steps, float(dt), tuple(float(g) for g in gravity),
@@ -93,10 +95,11 @@ class PolyPICSteps(torch.autograd.Function):
         ctx.checkpoints = checkpoints
         ctx.buffers = B
         ctx.save_for_backward(order)
+        # back to the caller's particle order: out[order[i]] = state[i]
         x_out = torch.empty_like(x)
         c_out = torch.empty_like(c)
-        x_out[:, order] = x
-        c_out[:, :, order] = c
+        ops.polypic_scatter_rows(x, x_out, order)
+        ops.polypic_scatter_rows(c, c_out, order)
         return x_out, c_out
 
     @staticmethod
@@ -110,8 +113,10 @@ class PolyPICSteps(torch.autograd.Function):
         if gc_out is None:
             gc_out = torch.zeros(3, n_modes, P, dtype=torch.float32, device=order.device)
         # to the slot order of the last step's outputs
-        gx = gx_out.float()[:, order].contiguous()
-        gc = gc_out.float()[:, :, order].contiguous()
+        gx = torch.empty(3, P, dtype=torch.float32, device=order.device)
+        gc = torch.empty(3, n_modes, P, dtype=torch.float32, device=order.device)
+        ops.polypic_gather_rows(gx_out.float().contiguous().reshape(3, P), gx, order)
+        ops.polypic_gather_rows(gc_out.float().contiguous().reshape(3, n_modes, P), gc, order)
         for s in range(n_steps - 1, -1, -1):
             x, c, perm, gm, gp, gv = ctx.checkpoints[s]
             gx_in = torch.zeros_like(gx)

@@ -536,6 +536,47 @@ bool g2p2g_overlap(int64_t P, int64_t N, const float* grid_vel, const float* x_i
 }
 }  // namespace
 
+namespace {
+int32_t check_rows(const void* src, const void* dst, const int32_t* idx, int64_t rows,
+                   int64_t P) {
+  int32_t st;
+  if ((st = check_P(P))) return st;
+  if (rows < 0) return POLYPIC_EINVAL;
+  if (rows == 0 || P == 0) return POLYPIC_OK;
+  if (!src || !dst || !idx) return POLYPIC_EINVAL;
+  if (rows > INT64_MAX / 4 / P) return POLYPIC_EINVAL;
+  if (overlaps(src, rows * P, dst, rows * P)) return POLYPIC_EINVAL;
+  return POLYPIC_OK;
+}
+}  // namespace
+
+int32_t polypic_gather_rows(const void* src, void* dst, const int32_t* idx, int64_t rows,
+                            int64_t P, void* stream) {
+  int32_t st;
+  if ((st = check_rows(src, dst, idx, rows, P))) return st;
+  if (rows == 0 || P == 0) return POLYPIC_OK;
+  discard_stale_error();
+  return from_hip(launch_gather_rows(src, dst, idx, rows, P, (hipStream_t)stream));
+}
+
+int32_t polypic_scatter_rows(const void* src, void* dst, const int32_t* idx, int64_t rows,
+                             int64_t P, void* stream) {
+  int32_t st;
+  if ((st = check_rows(src, dst, idx, rows, P))) return st;
+  if (rows == 0 || P == 0) return POLYPIC_OK;
+  discard_stale_error();
+  return from_hip(launch_scatter_rows(src, dst, idx, rows, P, (hipStream_t)stream));
+}
+
+int32_t polypic_invert_permutation(const int32_t* perm, int32_t* inv, int64_t P, void* stream) {
+  int32_t st;
+  if ((st = check_P(P))) return st;
+  if (P == 0) return POLYPIC_OK;
+  if (!perm || !inv || overlaps(perm, P, inv, P)) return POLYPIC_EINVAL;
+  discard_stale_error();
+  return from_hip(launch_invert_permutation(perm, inv, P, (hipStream_t)stream));
+}
+
 int32_t polypic_g2p2g(const polypic_grid* grid, int64_t P, int32_t n_modes, float dt,
                       const float* grid_vel, const float* x_in, const int32_t* perm,
                       float* x_out, float* coeff_out, const float* F_in, float* F_out,

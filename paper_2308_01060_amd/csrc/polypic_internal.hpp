@@ -194,4 +194,13 @@ struct G2PBackArgs {
 };
 hipError_t launch_g2p_backward(const G2PBackArgs& a, int n_modes, hipStream_t stream);
 
+// dst[r][i] = src[r][idx[i]], dst[r][idx[i]] = src[r][i] for rows of P 4-byte
+// elements; inv[perm[i]] = i
+hipError_t launch_gather_rows(const void* src, void* dst, const int32_t* idx, int64_t rows,
+                              int64_t P, hipStream_t stream);
+hipError_t launch_scatter_rows(const void* src, void* dst, const int32_t* idx, int64_t rows,
+                               int64_t P, hipStream_t stream);
+hipError_t launch_invert_permutation(const int32_t* perm, int32_t* inv, int64_t P,
+                                     hipStream_t stream);
+
 }  // namespace polypic

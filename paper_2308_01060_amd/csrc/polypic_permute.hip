@@ -1,0 +1,94 @@
+// Particle-order permutations, for gfx950.
+//
+// The sort (section 3.1's per-step cell ordering) leaves every particle array in
+// slot order; a caller that wants its own particle order back, or hands in data in
+// that order, permutes whole rows of 4-byte elements:
+//
+//   gather   dst[r][i] = src[r][idx[i]]        (coalesced writes, indexed reads)
+//   scatter  dst[r][idx[i]] = src[r][i]        (coalesced reads, indexed writes)
+//   invert   inv[perm[i]] = i
+#include "polypic_internal.hpp"
+
+namespace polypic {
+
+namespace {
+
+constexpr int kPermBlock = 256;
+constexpr int kPermUnroll = 8;  // rows in flight per thread
+
+// One thread per destination slot i; its source slot is read once and reused for
+// every row.  Rows go kPermUnroll at a time so that that many loads are in flight
+// before the first store.
+__global__ __launch_bounds__(kPermBlock) void gather_rows_kernel(const uint32_t* __restrict__ src,
+                                                                 uint32_t* __restrict__ dst,
+                                                                 const int32_t* __restrict__ idx,
+                                                                 int64_t rows, int64_t P) {
+  const int64_t i = (int64_t)blockIdx.x * kPermBlock + threadIdx.x;
+  if (i >= P) return;
+  // an index outside [0, P) is clamped: a bad one gives wrong results, never a fault
+  const int64_t p = min(max((int64_t)idx[i], (int64_t)0), P - 1);
+  int64_t r = 0;
+  for (; r + kPermUnroll <= rows; r += kPermUnroll) {
+    uint32_t v[kPermUnroll];
+#pragma unroll
+    for (int k = 0; k < kPermUnroll; ++k) v[k] = src[(r + k) * P + p];
+#pragma unroll
+    for (int k = 0; k < kPermUnroll; ++k) dst[(r + k) * P + i] = v[k];
+  }
+  for (; r < rows; ++r) dst[r * P + i] = src[r * P + p];
+}
+
+// dst[r][idx[i]] = src[r][i]: coalesced reads, indexed writes.
+__global__ __launch_bounds__(kPermBlock) void scatter_rows_kernel(const uint32_t* __restrict__ src,
+                                                                  uint32_t* __restrict__ dst,
+                                                                  const int32_t* __restrict__ idx,
+                                                                  int64_t rows, int64_t P) {
+  const int64_t i = (int64_t)blockIdx.x * kPermBlock + threadIdx.x;
+  if (i >= P) return;
+  const int64_t p = min(max((int64_t)idx[i], (int64_t)0), P - 1);
+  int64_t r = 0;
+  for (; r + kPermUnroll <= rows; r += kPermUnroll) {
+    uint32_t v[kPermUnroll];
+#pragma unroll
+    for (int k = 0; k < kPermUnroll; ++k) v[k] = src[(r + k) * P + i];
+#pragma unroll
+    for (int k = 0; k < kPermUnroll; ++k) dst[(r + k) * P + p] = v[k];
+  }
+  for (; r < rows; ++r) dst[r * P + p] = src[r * P + i];
+}
+
+__global__ __launch_bounds__(kPermBlock) void invert_permutation_kernel(
+    const int32_t* __restrict__ perm, int32_t* __restrict__ inv, int64_t P) {
+  const int64_t i = (int64_t)blockIdx.x * kPermBlock + threadIdx.x;
+  if (i >= P) return;
+  const int64_t p = min(max((int64_t)perm[i], (int64_t)0), P - 1);
+  inv[p] = (int32_t)i;
+}
+
+}  // namespace
+
+hipError_t launch_gather_rows(const void* src, void* dst, const int32_t* idx, int64_t rows,
+                              int64_t P, hipStream_t stream) {
+  if (P == 0 || rows == 0) return hipSuccess;
+  gather_rows_kernel<<<(unsigned)((P + kPermBlock - 1) / kPermBlock), kPermBlock, 0, stream>>>(
+      static_cast<const uint32_t*>(src), static_cast<uint32_t*>(dst), idx, rows, P);
+  return hipGetLastError();
+}
+
+hipError_t launch_scatter_rows(const void* src, void* dst, const int32_t* idx, int64_t rows,
+                               int64_t P, hipStream_t stream) {
+  if (P == 0 || rows == 0) return hipSuccess;
+  scatter_rows_kernel<<<(unsigned)((P + kPermBlock - 1) / kPermBlock), kPermBlock, 0, stream>>>(
+      static_cast<const uint32_t*>(src), static_cast<uint32_t*>(dst), idx, rows, P);
+  return hipGetLastError();
+}
+
+hipError_t launch_invert_permutation(const int32_t* perm, int32_t* inv, int64_t P,
+                                     hipStream_t stream) {
+  if (P == 0) return hipSuccess;
+  invert_permutation_kernel<<<(unsigned)((P + kPermBlock - 1) / kPermBlock), kPermBlock, 0,
+                              stream>>>(perm, inv, P);
+  return hipGetLastError();
+}
+
+}  // namespace polypic

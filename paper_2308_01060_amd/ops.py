@@ -298,6 +298,38 @@ def polypic_p2g_backward(grid: polypic_grid, n_modes: int, x: torch.Tensor, coef
         _ptr(status_dev, torch.int32, 1, "status_dev"), _stream()), "polypic_p2g_backward")
 
 
+# ---------------------------------------------------------------- particle order
+def _rows_call(name: str, src: torch.Tensor, dst: torch.Tensor, idx: torch.Tensor) -> None:
+    if src.dtype not in (torch.float32, torch.int32):
+        raise TypeError(f"src must be float32 or int32, got {src.dtype}")
+    if dst.dtype != src.dtype or dst.shape != src.shape:
+        raise ValueError("dst must have the dtype and shape of src")
+    P = src.shape[-1] if src.dim() > 0 else 0
+    rows = src.numel() // P if P else 0
+    check(getattr(_lib.load(), name)(
+        _ptr(src, src.dtype, rows * P, "src"), _ptr(dst, src.dtype, rows * P, "dst"),
+        _ptr(idx, torch.int32, P, "idx"), rows, P, _stream()), name)
+
+
+def polypic_gather_rows(src: torch.Tensor, dst: torch.Tensor, idx: torch.Tensor) -> None:
+    """dst[..., i] = src[..., idx[i]] over the last axis (P), for float32 or int32 arrays of
+    the same shape; idx is an int32 array of P indices."""
+    _rows_call("polypic_gather_rows", src, dst, idx)
+
+
+def polypic_scatter_rows(src: torch.Tensor, dst: torch.Tensor, idx: torch.Tensor) -> None:
+    """dst[..., idx[i]] = src[..., i] over the last axis (P), as polypic_gather_rows."""
+    _rows_call("polypic_scatter_rows", src, dst, idx)
+
+
+def polypic_invert_permutation(perm: torch.Tensor, inv: torch.Tensor) -> None:
+    """inv[perm[i]] = i for an int32 permutation of [0, P)."""
+    P = perm.numel()
+    check(_lib.load().polypic_invert_permutation(
+        _ptr(perm, torch.int32, P, "perm"), _ptr(inv, torch.int32, P, "inv"), P, _stream()),
+        "polypic_invert_permutation")
+
+
 # ---------------------------------------------------------------- batches
 class Batch:
     """A planned batch of scenes: the sealed C descriptor plus the device table it points to.

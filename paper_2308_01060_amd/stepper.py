@@ -19,8 +19,8 @@ whose cell changed are sorted, then merged; same result as a full sort).  G2P re
 coefficients, so by default it writes the new ones over the array P2G read
 (``coeff_in_place``): one coefficient array instead of two (1.4 GB saved at
 27 modes and 4.19 M particles).  The set takes ownership of the tensors it is
-given and overwrites them as it steps.  ``order`` tracks the
-original index of each slot (bookkeeping done with a torch gather; switch it off
+given and overwrites them as it steps.  ``order`` (int32) tracks the
+original index of each slot (one polypic_gather_rows per step; switch it off
 with ``track_order=False`` when only the transfers matter).
 """
 from __future__ import annotations
@@ -84,7 +84,7 @@ class ParticleSet:
                                   dtype=torch.uint8, device=dev)
         self.status = torch.zeros(1, dtype=torch.int32, device=dev)
         self.track_order = bool(track_order)
-        self.order = torch.arange(P, dtype=torch.int64, device=dev)
+        self.order = torch.arange(P, dtype=torch.int32, device=dev)
         # fused stepping: G2P scatters the new state into the grid at once (polypic_g2p2g);
         # grid_current says grid_mass / grid_mom hold the P2G of the current state
         self.fused = bool(fused)
@@ -160,7 +160,9 @@ class ParticleSet:
         if self.F is not None:
             self.F, self.F_next = self.F_next, self.F
         if use_perm and self.track_order:
-            self.order = self.order[self.perm.long()]
+            order = torch.empty_like(self.order)
+            ops.polypic_gather_rows(self.order, order, self.perm)
+            self.order = order
         # G2P wrote slot i from particle perm[i]: slot i was sorted under keys[i].  (Without
         # the permutation the slot order is unchanged, and so is what describes it.)
         if self.incremental_sort and use_perm:

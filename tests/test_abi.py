@@ -313,3 +313,28 @@ def test_g2p2g_rejects_bad_arguments():
     assert call(gm=gv) == 1                     # the next grid overlaps grid_vel
     assert call(gp=ctypes.c_void_p(0x10000000 + 4 * 0x1000000 + 4)) == 1  # grid_mom over grid_mass
     assert call(fi=far(7), fo=far(7)) == 1      # F_out overlaps F_in
+
+
+def test_permutation_calls_reject_bad_arguments():
+    lib = _lib.load()
+    far = lambda k: ctypes.c_void_p(0x10000000 + k * 0x1000000)  # noqa: E731  disjoint, fake
+    src, dst, idx = far(0), far(1), far(2)
+    assert lib.polypic_gather_rows(None, dst, idx, 3, 10, None) == 1
+    assert lib.polypic_gather_rows(src, None, idx, 3, 10, None) == 1
+    assert lib.polypic_gather_rows(src, dst, None, 3, 10, None) == 1
+    assert lib.polypic_gather_rows(src, dst, idx, -1, 10, None) == 1
+    assert lib.polypic_gather_rows(src, dst, idx, 3, -1, None) == 1
+    assert lib.polypic_gather_rows(src, dst, idx, 3, 2**31, None) == 1
+    assert lib.polypic_gather_rows(src, ctypes.c_void_p(0x10000000 + 100), idx, 3, 10, None) == 1
+    assert lib.polypic_gather_rows(None, None, None, 0, 10, None) == 0   # nothing to move
+    assert lib.polypic_gather_rows(None, None, None, 3, 0, None) == 0
+    assert lib.polypic_scatter_rows(None, dst, idx, 3, 10, None) == 1
+    assert lib.polypic_scatter_rows(src, dst, None, 3, 10, None) == 1
+    assert lib.polypic_scatter_rows(src, ctypes.c_void_p(0x10000000 + 100), idx, 3, 10, None) == 1
+    assert lib.polypic_scatter_rows(None, None, None, 3, 0, None) == 0
+    assert lib.polypic_invert_permutation(None, dst, 10, None) == 1
+    assert lib.polypic_invert_permutation(idx, None, 10, None) == 1
+    assert lib.polypic_invert_permutation(idx, ctypes.c_void_p(0x10000000 + 2 * 0x1000000 + 8),
+                                          10, None) == 1             # inv overlaps perm
+    assert lib.polypic_invert_permutation(idx, dst, -5, None) == 1
+    assert lib.polypic_invert_permutation(None, None, 0, None) == 0
