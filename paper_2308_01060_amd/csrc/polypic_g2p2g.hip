@@ -9,7 +9,7 @@
 //     coefficients, the advected position x' (and F', mass) at slot i;
 //   * P2G at x' with the coefficients still in registers: the stencil of x',
 //     the weighted mode rows, and the nodal mass and momentum streamed node by
-//     node into FP64 LDS bricks of 4^3-node tiles (lane groups that share a
+//     node into FP64 LDS bricks of 4^3-node tiles (lane pairs that share a
 //     base node add across lanes first), then one float atomic per brick node
 //     and channel into the next grid.
 //
@@ -53,7 +53,10 @@ __device__ __forceinline__ int stage_pos(int s) {
 template <int NR, int BS, class Scenes>
 __global__ __launch_bounds__(BS, Scenes::kMany ? 3 : 4) void g2p2g_kernel(G2P2GArgs a, Scenes sc) {
   constexpr int NW = BS / kWave;
-  constexpr int LG = NR >= 8 ? 2 : 1;  // log2 of the lane-group size
+  // log2 of the lane-group size: pairs at every mode count.  Here, where the vector
+  // ALU is the tighter limit, pairs beat the quads of polypic_p2g (one DPP fold per
+  // node value instead of two; measured, 27 modes, 4.19 M particles: 0.369 -> 0.357 ms)
+  constexpr int LG = 1;
   __shared__ double brick[kBrickKMAX * 4 * kBrickV];  // [brick][channel][node]
   __shared__ uint64_t tile_of[BS];                    // by processing slot
   __shared__ int seg_of[BS];
@@ -286,20 +289,15 @@ __global__ __launch_bounds__(BS, Scenes::kMany ? 3 : 4) void g2p2g_kernel(G2P2GA
   const int seg = run_slot < 0 ? -1 : (run_slot < kRuns ? run_brick[run_slot] : kBrickKMAX);
   const int nseg = n_bricks;
 
-  // lanes that share this lane's segment and base node: the pair (lane ^ 1) and,
-  // with groups of 4, the quad; every lane runs the exchanges (an invalid one with
-  // zero mass), since a DPP read from a lane that did not execute it is undefined
+  // the lane pair (lane ^ 1) shares this lane's segment and base node: every lane
+  // runs the exchanges (an invalid one with zero mass), since a DPP read from a
+  // lane that did not execute it is undefined
+  static_assert(LG == 1, "the node values are folded over lane pairs");
   const int mykey = valid ? ((c2 * 1024 + c1) * 1024 + c0) : -1 - lane;
   const int pair_key = pair_swap_i(mykey), pair_seg = pair_swap_i(seg);
   const bool pair = mykey == pair_key && seg == pair_seg;
-  bool quad = false;
-  if constexpr (LG == 2) {
-    const int quad_pair = quad_swap_i((int)pair), quad_key = quad_swap_i(mykey);
-    const int quad_seg = quad_swap_i(seg);
-    quad = pair && quad_pair != 0 && mykey == quad_key && seg == quad_seg;
-  }
-  const bool emit = valid && (quad ? (lane & 3) == 0 : (!pair || (lane & 1) == 0));
-  const float pair_f = pair ? 1.0f : 0.0f, quad_f = quad ? 1.0f : 0.0f;
+  const bool emit = valid && (!pair || (lane & 1) == 0);
+  const float pair_f = pair ? 1.0f : 0.0f;
   {
     const Rows Rx = p2g_rows_scaled(basis_p2g(u0), m);
     const Rows Ry = p2g_rows_scaled(basis_p2g(u1), 1.0f);
@@ -313,8 +311,7 @@ __global__ __launch_bounds__(BS, Scenes::kMany ? 3 : 4) void g2p2g_kernel(G2P2GA
       // (the HBM base is formed only on that rare path, to keep registers free)
       float* const gc = ch == 0 ? a.gm : ch == 1 ? a.gp0 : ch == 2 ? a.gp1 : a.gp2;
       return [=](int jx, int jy, int jz, float v) {
-        float w = pair_fold(v, pair_f);
-        if constexpr (LG == 2) w = quad_fold(w, quad_f);
+        const float w = pair_fold(v, pair_f);
         if (!emit) return;
         if (lds)
           atomicAdd(lbc + jx + kBrickSY * jy + kBrickSZ * jz, (double)w);
