@@ -337,14 +337,28 @@ __global__ __launch_bounds__(BS) void g2p_backward_kernel(G2PBackArgs a) {
       double* const lbc = lb + ax * kBrickV;
       float* const dst = a.gvb + (size_t)ax * N + gbase;
       stream_g2p_adjoint<NR>(cb, Pr[0], Pr[1], Pr[2], dP[0], dP[1], dP[2], v, sx, sy, sz,
-                             [&](int jx, int jy, int jz, float f) {
-                               float w = pair_fold(f, pair_f);
-                               if constexpr (LG == 2) w = quad_fold(w, quad_f);
+                             [&](int jz, float (&f)[9]) {
+                               float w[9];
+#pragma unroll
+                               for (int k = 0; k < 9; ++k) {
+                                 w[k] = pair_fold(f[k], pair_f);
+                                 if constexpr (LG == 2) w[k] = quad_fold(w[k], quad_f);
+                               }
                                if (!emit) return;
-                               if (lds)
-                                 atomicAdd(lbc + jx + kBrickSY * jy + kBrickSZ * jz, (double)w);
-                               else
-                                 atomicAdd(dst + jz * nxny + jy * nx + jx, w);
+                               if (lds) {
+#pragma unroll
+                                 for (int jy = 0; jy < 3; ++jy)
+#pragma unroll
+                                   for (int jx = 0; jx < 3; ++jx)
+                                     atomicAdd(lbc + jx + kBrickSY * jy + kBrickSZ * jz,
+                                               (double)w[jx + 3 * jy]);
+                               } else {
+#pragma unroll
+                                 for (int jy = 0; jy < 3; ++jy)
+#pragma unroll
+                                   for (int jx = 0; jx < 3; ++jx)
+                                     atomicAdd(dst + jz * nxny + jy * nx + jx, w[jx + 3 * jy]);
+                               }
                              });
       xg[0] = fmaf(a.g.inv_dx, sx, xg[0]);
       xg[1] = fmaf(a.g.inv_dx, sy, xg[1]);

@@ -393,10 +393,58 @@ __device__ __forceinline__ void stream_modes(const float (&c)[27], const Rows& R
   }
 }
 
+// As stream_modes, handing over one z plane of nodes at a time:
+// emit_plane(jz, v) with v[jx + 3 jy] the 9 nodal values of plane jz.  A caller
+// that predicates its atomics per lane then sets the lane mask once per plane
+// instead of once per node.
+template <int NR, class EmitPlane>
+__device__ __forceinline__ void stream_modes_planes(const float (&c)[27], const Rows& Rx,
+                                                    const Rows& Ry, const Rows& Rz,
+                                                    EmitPlane&& emit_plane) {
+#pragma unroll
+  for (int jz = 0; jz < 3; ++jz) {
+    float C1[3][3];  // [kx][ky]: z contracted at this jz
+#pragma unroll
+    for (int kx = 0; kx < 3; ++kx)
+#pragma unroll
+      for (int ky = 0; ky < 3; ++ky) {
+        if (!any_kz<NR>(kx, ky)) continue;
+        float acc = 0.0f;
+#pragma unroll
+        for (int kz = 0; kz < 3; ++kz)
+          if (has_mode<NR>(kx, ky, kz)) acc = fmaf(c[mode_index(kx, ky, kz)], Rz.r[kz][jz], acc);
+        C1[kx][ky] = acc;
+      }
+    float v[9];
+#pragma unroll
+    for (int jy = 0; jy < 3; ++jy) {
+      float C2[3];  // [kx]
+#pragma unroll
+      for (int kx = 0; kx < 3; ++kx) {
+        if (!any_kykz<NR>(kx)) continue;
+        float acc = 0.0f;
+#pragma unroll
+        for (int ky = 0; ky < 3; ++ky)
+          if (any_kz<NR>(kx, ky)) acc = fmaf(C1[kx][ky], Ry.r[ky][jy], acc);
+        C2[kx] = acc;
+      }
+#pragma unroll
+      for (int jx = 0; jx < 3; ++jx) {
+        float val = 0.0f;
+#pragma unroll
+        for (int kx = 0; kx < 3; ++kx)
+          if (any_kykz<NR>(kx)) val = fmaf(C2[kx], Rx.r[kx][jx], val);
+        v[jx + 3 * jy] = val;
+      }
+    }
+    emit_plane(jz, v);
+  }
+}
+
 // Transpose of the G2P projection with the x gradient, for projection rows P
 // (g2p_rows: row 2 is the constant (1/2, -1, 1/2), so dP row 2 is zero).  For
-// every node j emits (jx, jy, jz, f_j) with f = sum_r c_r Px Py Pz (v_bar), and
-// accumulates s_b = sum_j v_j f^(b)_j, f^(b) being f with dP on axis b.  The x
+// every z plane of nodes emits (jz, f) with f[jx + 3 jy] = sum_r c_r Px Py Pz
+// (v_bar), and accumulates s_b = sum_j v_j f^(b)_j, f^(b) being f with dP on axis b.  The x
 // sums never form f^(b) per node: within one (jy, jz) row of nodes,
 //   sum_jx v_j f^(x)_j = sum_kx C2[kx] (dPx v)[kx],
 //   sum_jx v_j f^(y)_j = sum_kx C2y[kx] (Px v)[kx]   (and z alike),
@@ -409,6 +457,7 @@ __device__ __forceinline__ void stream_g2p_adjoint(const float (&c)[27], const R
                                                    float& sz, Emit&& emit) {
 #pragma unroll
   for (int jz = 0; jz < 3; ++jz) {
+    float fp[9];                // f of the plane's nodes, [jx + 3 jy]
     float C1[3][3], C1z[3][3];  // [kx][ky]
 #pragma unroll
     for (int kx = 0; kx < 3; ++kx)
@@ -463,9 +512,10 @@ __device__ __forceinline__ void stream_g2p_adjoint(const float (&c)[27], const R
 #pragma unroll
         for (int kx = 0; kx < 3; ++kx)
           if (any_kykz<NR>(kx)) f = fmaf(C2[kx], Px.r[kx][jx], f);
-        emit(jx, jy, jz, f);
+        fp[jx + 3 * jy] = f;
       }
     }
+    emit(jz, fp);
   }
 }
 

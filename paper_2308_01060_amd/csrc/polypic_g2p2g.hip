@@ -306,28 +306,41 @@ __global__ __launch_bounds__(BS, Scenes::kMany ? 3 : 4) void g2p2g_kernel(G2P2GA
     const int lbase = (c0 & 3) + kBrickSY * (c1 & 3) + kBrickSZ * (c2 & 3);
     const int64_t gbase = g.node_off + (int64_t)(c2 * ny + c1) * nx + c0;
     double* const lb = brick + (lds ? max(seg, 0) : 0) * 4 * kBrickV + lbase;
+    // one plane of 9 node values at a time: the folds run on every lane, then a
+    // single predicated block per plane does the atomics
     auto emitter = [&](int ch) {
       double* const lbc = lb + ch * kBrickV;
       // (the HBM base is formed only on that rare path, to keep registers free)
       float* const gc = ch == 0 ? a.gm : ch == 1 ? a.gp0 : ch == 2 ? a.gp1 : a.gp2;
-      return [=](int jx, int jy, int jz, float v) {
-        const float w = pair_fold(v, pair_f);
+      return [=](int jz, float (&v)[9]) {
+        float w[9];
+#pragma unroll
+        for (int k = 0; k < 9; ++k) w[k] = pair_fold(v[k], pair_f);
         if (!emit) return;
-        if (lds)
-          atomicAdd(lbc + jx + kBrickSY * jy + kBrickSZ * jz, (double)w);
-        else
-          atomicAdd(gc + gbase + (jz * nxny + jy * nx + jx), w);
+        if (lds) {
+#pragma unroll
+          for (int jy = 0; jy < 3; ++jy)
+#pragma unroll
+            for (int jx = 0; jx < 3; ++jx)
+              atomicAdd(lbc + jx + kBrickSY * jy + kBrickSZ * jz, (double)w[jx + 3 * jy]);
+        } else {
+#pragma unroll
+          for (int jy = 0; jy < 3; ++jy)
+#pragma unroll
+            for (int jx = 0; jx < 3; ++jx)
+              atomicAdd(gc + gbase + (jz * nxny + jy * nx + jx), w[jx + 3 * jy]);
+        }
       };
     };
     {  // mass: m W_ip
       float one[27];
 #pragma unroll
       for (int r = 0; r < 27; ++r) one[r] = r == 0 ? 1.0f : 0.0f;
-      stream_modes<1>(one, Rx, Ry, Rz, emitter(0));
+      stream_modes_planes<1>(one, Rx, Ry, Rz, emitter(0));
     }
-    stream_modes<NR>(c[0], Rx, Ry, Rz, emitter(1));
-    stream_modes<NR>(c[1], Rx, Ry, Rz, emitter(2));
-    stream_modes<NR>(c[2], Rx, Ry, Rz, emitter(3));
+    stream_modes_planes<NR>(c[0], Rx, Ry, Rz, emitter(1));
+    stream_modes_planes<NR>(c[1], Rx, Ry, Rz, emitter(2));
+    stream_modes_planes<NR>(c[2], Rx, Ry, Rz, emitter(3));
   }
   __syncthreads();
 
