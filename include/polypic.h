@@ -359,7 +359,7 @@ int32_t polypic_p2g_backward(const polypic_grid* grid, int64_t P, int32_t n_mode
  *   int32, not overlapping).  perm must be a permutation of [0, P): entries
  *   outside that range are clamped into it, and an entry of inv that no perm
  *   entry names keeps its previous value.
- * Both run asynchronously on `stream`. */
+ * All three run asynchronously on `stream`. */
 int32_t polypic_gather_rows(const void* src, void* dst, const int32_t* idx, int64_t rows,
                             int64_t P, void* stream);
 int32_t polypic_scatter_rows(const void* src, void* dst, const int32_t* idx, int64_t rows,
