@@ -47,15 +47,16 @@ __device__ __forceinline__ int stage_pos(int s) {
   return s ^ (((s >> 6) & 1) << LG) ^ ((((s >> 7) ^ (s >> 5)) & 1) << (LG + 1));
 }
 
-// LDS (about 41 KB per 256-thread workgroup) allows 4 waves per SIMD; the launch
+// LDS (about 40 KB per 256-thread workgroup) allows 4 waves per SIMD; the launch
 // bound holds the registers to the 128 that allow them too.  At 27 modes that
-// spills 9 registers and still wins (measured, 4.19 M particles: 0.48 -> 0.44 ms).
+// spills 6 registers and still wins (measured, 4.19 M particles: 0.40 ms at 3
+// waves per SIMD without spills, 0.38 ms at 4).
 template <int NR, int BS, class Scenes>
 __global__ __launch_bounds__(BS, Scenes::kMany ? 3 : 4) void g2p2g_kernel(G2P2GArgs a, Scenes sc) {
   constexpr int NW = BS / kWave;
   // log2 of the lane-group size: pairs at every mode count.  Here, where the vector
   // ALU is the tighter limit, pairs beat the quads of polypic_p2g (one DPP fold per
-  // node value instead of two; measured, 27 modes, 4.19 M particles: 0.369 -> 0.357 ms)
+  // node value instead of two; measured, 27 modes, 4.19 M particles: 0.369 -> 0.359 ms)
   constexpr int LG = 1;
   __shared__ double brick[kBrickKMAX * 4 * kBrickV];  // [brick][channel][node]
   __shared__ uint64_t tile_of[BS];                    // by processing slot
