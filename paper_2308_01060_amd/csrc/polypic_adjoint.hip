@@ -134,10 +134,13 @@ __global__ __launch_bounds__(256) void p2g_backward_kernel(P2GBackArgs a) {
     float* cg = a.coeff_grad + (size_t)ax * NR * Ps + p;
     // all coefficients first: the compiler cannot move a load of coeff past a
     // store to coeff_grad (they might alias), so loads inside the mode loop
-    // would each wait out their full latency
+    // would each wait out their full latency.  Both streams are read or written
+    // once, so they bypass the caches the grid gathers use (measured, 27 modes,
+    // 4.19 M particles: 0.556 -> 0.510 ms)
     float c[27];
 #pragma unroll
-    for (int r = 0; r < 27; ++r) c[r] = (r < NR) ? cp[(size_t)r * Ps] : 0.0f;
+    for (int r = 0; r < 27; ++r)
+      c[r] = (r < NR) ? __builtin_nontemporal_load(cp + (size_t)r * Ps) : 0.0f;
     float sx = 0.0f, sy = 0.0f, sz = 0.0f;
 #pragma unroll
     for (int kx = 0; kx < 3; ++kx) {
@@ -176,7 +179,7 @@ __global__ __launch_bounds__(256) void p2g_backward_kernel(P2GBackArgs a) {
               fmaf(R[2].r[kz][2], By[2], fmaf(R[2].r[kz][1], By[1], R[2].r[kz][0] * By[0]));
           const float Tx =
               fmaf(R[2].r[kz][2], Bx[2], fmaf(R[2].r[kz][1], Bx[1], R[2].r[kz][0] * Bx[0]));
-          cg[(size_t)r * Ps] = m * T;
+          __builtin_nontemporal_store(m * T, cg + (size_t)r * Ps);
           mg = fmaf(cr, T, mg);
           sx = fmaf(cr, Tx, sx);
           sy = fmaf(cr, Ty, sy);
