@@ -18,7 +18,9 @@ constexpr int kPermUnroll = 8;  // rows in flight per thread
 
 // One thread per destination slot i; its source slot is read once and reused for
 // every row.  Rows go kPermUnroll at a time so that that many loads are in flight
-// before the first store.
+// before the first store.  The coalesced side of either kernel is streamed past
+// the caches, which the indexed side uses (measured, 3 x 27 rows of 4.19 M: gather
+// 1.05 -> 1.01 ms, scatter 1.72 -> 1.63 ms).
 __global__ __launch_bounds__(kPermBlock) void gather_rows_kernel(const uint32_t* __restrict__ src,
                                                                  uint32_t* __restrict__ dst,
                                                                  const int32_t* __restrict__ idx,
@@ -33,9 +35,9 @@ __global__ __launch_bounds__(kPermBlock) void gather_rows_kernel(const uint32_t*
 #pragma unroll
     for (int k = 0; k < kPermUnroll; ++k) v[k] = src[(r + k) * P + p];
 #pragma unroll
-    for (int k = 0; k < kPermUnroll; ++k) dst[(r + k) * P + i] = v[k];
+    for (int k = 0; k < kPermUnroll; ++k) __builtin_nontemporal_store(v[k], dst + (r + k) * P + i);
   }
-  for (; r < rows; ++r) dst[r * P + i] = src[r * P + p];
+  for (; r < rows; ++r) __builtin_nontemporal_store(src[r * P + p], dst + r * P + i);
 }
 
 // dst[r][idx[i]] = src[r][i]: coalesced reads, indexed writes.
@@ -50,7 +52,7 @@ __global__ __launch_bounds__(kPermBlock) void scatter_rows_kernel(const uint32_t
   for (; r + kPermUnroll <= rows; r += kPermUnroll) {
     uint32_t v[kPermUnroll];
 #pragma unroll
-    for (int k = 0; k < kPermUnroll; ++k) v[k] = src[(r + k) * P + i];
+    for (int k = 0; k < kPermUnroll; ++k) v[k] = __builtin_nontemporal_load(src + (r + k) * P + i);
 #pragma unroll
     for (int k = 0; k < kPermUnroll; ++k) dst[(r + k) * P + p] = v[k];
   }
