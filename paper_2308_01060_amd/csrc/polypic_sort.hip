@@ -277,9 +277,10 @@ hipError_t launch_sort_batch(const SceneDev* table, int n_scenes, int mbits, int
 
 // ------------------------------------------------ sort of a device-counted list
 // Sorts the first *count (key, value) pairs of a buffer sized for `cap` pairs
-// when the host does not know the count.  Launches: one histogram of every
-// pass over the active tiles (digit totals straight into device memory), then
-// one stable scatter per pass.  A scatter tile learns how many keys of each digit precede it from its
+// when the host does not know the count.  The kernel that writes the list also
+// writes the count, the digit totals of every pass and cleared look-back words
+// (the re-sort's compaction below); then comes one stable scatter launch per
+// pass.  A scatter tile learns how many keys of each digit precede it from its
 // predecessors' published counts (decoupled look-back): each tile publishes
 // its own digit counts as soon as it has them, then reads its predecessors'
 // words, nearest first and kLookWindow per round trip, until an inclusive
@@ -303,6 +304,12 @@ constexpr uint32_t kInclusive = 0x80000000u;
 constexpr int kSpinLimit = 1 << 20;  // polls without progress before giving up
 constexpr int kLookWindow = 16;      // predecessors read per round trip
 constexpr int kCountedGrid = 512;    // workgroups of the device-counted sort's launches
+// The digit totals are accumulated in kTotalsRep copies, workgroup b adding into
+// copy b % kTotalsRep: the changed particles crowd into few digits (they sit
+// near one front), and one copy's atomics from thousands of workgroups
+// serialise (measured: 6 -> 26 us for the compaction as the front grew).
+constexpr int kTotalsRep = 32;
+constexpr int kTotalsStride = kMaxPasses * kRadix;  // words per copy
 static_assert(kSortBS == kRadix, "one thread per digit");
 static_assert(kWaveKeys == kSortIPT * kWave, "a wave's keys are kSortIPT rounds of a wave");
 
@@ -322,54 +329,6 @@ __device__ __forceinline__ unsigned long long match_digit(uint32_t d, bool valid
     same &= ((d >> bit) & 1u) ? bal : ~bal;
   }
   return same;
-}
-
-// Digit totals of every pass over the first *count keys (added to `totals`,
-// cleared beforehand), and the look-back words of every active tile cleared.
-// Workgroups loop over the active tiles.
-__global__ __launch_bounds__(kSortBS) void counted_hist_kernel(const uint32_t* __restrict__ keys,
-                                                              const uint32_t* __restrict__ count,
-                                                              int passes, int cap_tiles,
-                                                              uint32_t* __restrict__ look,
-                                                              uint32_t* __restrict__ totals) {
-  __shared__ uint32_t whist[kSortWaves][kMaxPasses * kRadix];
-  const int64_t M = (int64_t)*count;
-  const int tid = threadIdx.x;
-  const int lane = tid & (kWave - 1);
-  const int wv = tid / kWave;
-  for (int64_t t = blockIdx.x; t * kSortTile < M; t += gridDim.x) {
-    const int64_t base = t * kSortTile + (int64_t)wv * kWaveKeys;
-    uint32_t key[kSortIPT];
-#pragma unroll
-    for (int j = 0; j < kSortIPT; ++j) {
-      const int64_t i = base + (int64_t)j * kWave + lane;
-      key[j] = i < M ? keys[i] : 0u;
-    }
-#pragma unroll
-    for (int w = 0; w < kSortWaves; ++w)
-#pragma unroll
-      for (int q = 0; q < kMaxPasses; ++q) whist[w][q * kRadix + tid] = 0u;
-    for (int q = 0; q < passes; ++q) look[((size_t)q * cap_tiles + t) * kRadix + tid] = 0u;
-    __syncthreads();
-#pragma unroll
-    for (int j = 0; j < kSortIPT; ++j) {
-      const bool valid = base + (int64_t)j * kWave + lane < M;
-      for (int q = 0; q < passes; ++q) {
-        const uint32_t d = (key[j] >> (8 * q)) & (kRadix - 1);
-        const unsigned long long same = match_digit(d, valid);
-        if (valid && lanes_below(same) == 0)
-          atomicAdd(&whist[wv][q * kRadix + d], (uint32_t)__popcll(same));
-      }
-    }
-    __syncthreads();
-    for (int q = 0; q < passes; ++q) {
-      uint32_t c = 0;
-#pragma unroll
-      for (int w = 0; w < kSortWaves; ++w) c += whist[w][q * kRadix + tid];
-      if (c) atomicAdd(&totals[q * kRadix + tid], c);
-    }
-    __syncthreads();  // whist is cleared again for the next tile
-  }
 }
 
 // One stable scatter pass (digit at `shift`) over the first *count pairs;
@@ -434,7 +393,9 @@ __global__ __launch_bounds__(kSortBS) void counted_scatter_kernel(
   // keys with a smaller digit, all tiles: exclusive scan of the totals
   uint32_t digit_base;
   {
-    const uint32_t v = totals[tid];
+    uint32_t v = 0;
+#pragma unroll
+    for (int r = 0; r < kTotalsRep; ++r) v += totals[r * kTotalsStride + tid];
     uint32_t sc = v;
 #pragma unroll
     for (int off = 1; off < kWave; off <<= 1) {
@@ -529,21 +490,29 @@ __device__ __forceinline__ uint32_t cell_key(const Scenes& sc, int mbits,
   return ((uint32_t)s << mbits) | morton3(b0, b1, b2);
 }
 
-// changed-slot masks, per-workgroup counts, and the order check of keys_prev
+// changed-slot masks, per-workgroup counts, and the order check of keys_prev;
+// the first workgroups also clear the digit totals (every copy) and the tile
+// counters of the changed-list sort (nothing reads them before the compaction)
 template <class Scenes>
 __global__ __launch_bounds__(kSortBS) void upd_mask_kernel(Scenes sc, int mbits, int64_t P,
                                                          const float* __restrict__ x,
                                                          const uint32_t* __restrict__ keys_prev,
                                                          unsigned long long* __restrict__ mask,
                                                          uint32_t* __restrict__ blk_count,
+                                                         uint32_t* __restrict__ totals,
+                                                         uint32_t* __restrict__ tile_ctr,
                                                          int32_t* __restrict__ status) {
   __shared__ uint32_t wcount[kSortWaves];
   const int lane = threadIdx.x & (kWave - 1);
   const int wv = threadIdx.x / kWave;
   const size_t Ps = (size_t)P;
+  for (int r = blockIdx.x; r < kTotalsRep; r += gridDim.x)
+#pragma unroll
+    for (int q = 0; q < kMaxPasses; ++q) totals[r * kTotalsStride + q * kRadix + threadIdx.x] = 0u;
+  if (blockIdx.x == 0 && threadIdx.x < kMaxPasses) tile_ctr[threadIdx.x] = 0u;
   int s = sc.first((int64_t)blockIdx.x * kUpdTile);  // slots only grow along the rounds
   uint32_t c = 0;
-#pragma unroll 2
+#pragma unroll
   for (int j = 0; j < kSortIPT; ++j) {
     const int64_t grp = (int64_t)blockIdx.x * kGroupsPerTile + j * kSortWaves + wv;
     const int64_t i = grp * kWave + lane;
@@ -570,57 +539,68 @@ __global__ __launch_bounds__(kSortBS) void upd_mask_kernel(Scenes sc, int mbits,
   }
 }
 
-// one workgroup: exclusive scan of the per-workgroup counts, total to *count;
-// also clears the digit totals and tile counters of the changed-list sort
-__global__ __launch_bounds__(1024) void upd_scan_kernel(uint32_t* __restrict__ blk, int n,
-                                                        uint32_t* __restrict__ count,
-                                                        uint32_t* __restrict__ totals,
-                                                        uint32_t* __restrict__ tile_ctr) {
-  __shared__ uint32_t wsum[1024 / kWave];
-  const int tid = threadIdx.x;
-  const int lane = tid & (kWave - 1);
-  const int wv = tid / kWave;
-  if (tid < kMaxPasses * kRadix) totals[tid] = 0u;
-  if (tid < kMaxPasses) tile_ctr[tid] = 0u;
-  uint32_t running = 0;
-  for (int base = 0; base < n; base += 1024) {
-    const int k = base + tid;
-    const uint32_t v = k < n ? blk[k] : 0u;
-    uint32_t s = v;
-#pragma unroll
-    for (int off = 1; off < kWave; off <<= 1) {
-      const uint32_t o = __shfl_up(s, off, kWave);
-      if (lane >= off) s += o;
-    }
-    if (lane == kWave - 1) wsum[wv] = s;
-    __syncthreads();
-    uint32_t pre = 0, tot = 0;
-#pragma unroll
-    for (int w = 0; w < 1024 / kWave; ++w) {
-      pre += (w < wv) ? wsum[w] : 0u;
-      tot += wsum[w];
-    }
-    if (k < n) blk[k] = running + pre + s - v;
-    running += tot;
-    __syncthreads();
-  }
-  if (tid == 0) *count = running;
-}
-
-// changed (key, index) pairs in index order; gpre[grp] = changed slots before
-// the group
+// Changed (key, index) pairs in index order, gpre[grp] = changed slots before
+// the group, and what the changed list's radix sort needs: *count, the digit
+// totals of every pass (added to copy b % kTotalsRep of totals, cleared by the
+// mask kernel) and the
+// look-back words of every tile of the changed list, cleared.  Each workgroup
+// sums the per-workgroup counts itself (n_tiles words, a few KB, read from L2),
+// which saves a launch for their scan.
 template <class Scenes>
 __global__ __launch_bounds__(kSortBS) void upd_compact_kernel(
-    Scenes sc, int mbits, int64_t P, const float* __restrict__ x,
-    const unsigned long long* __restrict__ mask, const uint32_t* __restrict__ blk_off,
-    uint32_t* __restrict__ gpre, uint32_t* __restrict__ ck, int32_t* __restrict__ cv) {
+    Scenes sc, int mbits, int64_t P, int passes, const float* __restrict__ x,
+    const unsigned long long* __restrict__ mask, const uint32_t* __restrict__ blk_count,
+    int n_tiles, uint32_t* __restrict__ gpre, uint32_t* __restrict__ count,
+    uint32_t* __restrict__ look, uint32_t* __restrict__ totals, uint32_t* __restrict__ ck,
+    int32_t* __restrict__ cv) {
   __shared__ uint32_t pre_sh[kGroupsPerTile];
+  __shared__ uint32_t wsum[2][kSortWaves];
+  __shared__ uint32_t hist[kMaxPasses * kRadix];
   __shared__ int any_sh;
   const int tid = threadIdx.x;
   const int lane = tid & (kWave - 1);
   const int wv = tid / kWave;
+  const int b = (int)blockIdx.x;
+
+  // changed slots in the workgroups before this one, and in all
+  uint32_t before = 0, all = 0;
+  for (int k0 = 0; k0 < n_tiles; k0 += 4 * kSortBS) {
+    uint32_t c[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int k = k0 + u * kSortBS + tid;
+      c[u] = k < n_tiles ? blk_count[k] : 0u;
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      all += c[u];
+      before += k0 + u * kSortBS + tid < b ? c[u] : 0u;
+    }
+  }
+#pragma unroll
+  for (int off = kWave / 2; off > 0; off >>= 1) {
+    before += __shfl_xor(before, off, kWave);
+    all += __shfl_xor(all, off, kWave);
+  }
+  if (lane == 0) {
+    wsum[0][wv] = before;
+    wsum[1][wv] = all;
+  }
+  __syncthreads();
+  before = 0;
+  all = 0;
+#pragma unroll
+  for (int w = 0; w < kSortWaves; ++w) {
+    before += wsum[0][w];
+    all += wsum[1][w];
+  }
+  if (b == 0 && tid == 0) *count = all;
+  // tile b of the changed list exists: clear its look-back words
+  if ((int64_t)b * kSortTile < (int64_t)all)
+    for (int q = 0; q < passes; ++q) look[((size_t)q * n_tiles + b) * kRadix + tid] = 0u;
+
   const int64_t n_groups = (P + kWave - 1) / kWave;
-  const int64_t g0 = (int64_t)blockIdx.x * kGroupsPerTile;
+  const int64_t g0 = (int64_t)b * kGroupsPerTile;
   if (wv == 0) {
     const bool in = lane < kGroupsPerTile && g0 + lane < n_groups;
     const uint32_t c = in ? (uint32_t)__popcll(mask[g0 + lane]) : 0u;
@@ -632,10 +612,12 @@ __global__ __launch_bounds__(kSortBS) void upd_compact_kernel(
       const uint32_t o = __shfl_up(s, off, kWave);
       if (lane >= off) s += o;
     }
-    const uint32_t p = blk_off[blockIdx.x] + s - c;
+    const uint32_t p = before + s - c;
     if (lane < kGroupsPerTile) pre_sh[lane] = p;
     if (in) gpre[g0 + lane] = p;
   }
+#pragma unroll
+  for (int q = 0; q < kMaxPasses; ++q) hist[q * kRadix + tid] = 0u;
   __syncthreads();
   if (!any_sh) return;  // uniform: no changed slot in this workgroup
   const size_t Ps = (size_t)P;
@@ -653,9 +635,17 @@ __global__ __launch_bounds__(kSortBS) void upd_compact_kernel(
       const int64_t i = (g0 + k) * kWave + lane;
       bool ok;
       const uint32_t pos = pre_sh[k] + (uint32_t)lanes_below(m[j]);
-      ck[pos] = cell_key(sc, mbits, x, Ps, i, s, ok);
+      const uint32_t key = cell_key(sc, mbits, x, Ps, i, s, ok);
+      ck[pos] = key;
       cv[pos] = (int32_t)i;
+      for (int q = 0; q < passes; ++q) atomicAdd(&hist[q * kRadix + ((key >> (8 * q)) & 255u)], 1u);
     }
+  }
+  __syncthreads();
+  uint32_t* copy = totals + (size_t)(b % kTotalsRep) * kTotalsStride;
+  for (int q = 0; q < passes; ++q) {
+    const uint32_t c = hist[q * kRadix + tid];
+    if (c) atomicAdd(&copy[q * kRadix + tid], c);
   }
 }
 
@@ -713,19 +703,19 @@ __device__ __forceinline__ int64_t wave_lower_pair(KeyAt kat, IdxAt iat, int64_t
 
 // Final place of every changed pair j (sorted): j changed pairs precede it,
 // and so do the unchanged slots before `lo`, the first slot s whose
-// (keys_prev[s], s) is not below the pair's (key, index).
-__global__ __launch_bounds__(kSortBS) void upd_place_changed_kernel(
-    int64_t P, const uint32_t* __restrict__ keys_prev, const unsigned long long* __restrict__ mask,
-    const uint32_t* __restrict__ gpre, const uint32_t* __restrict__ cks,
-    const int32_t* __restrict__ cvs, const uint32_t* __restrict__ count,
+// (keys_prev[s], s) is not below the pair's (key, index).  Workgroup `blk` of
+// `n_blk`; one pair per wavefront at a time.
+__device__ __forceinline__ void place_changed(
+    int blk, int n_blk, int64_t P, const uint32_t* __restrict__ keys_prev,
+    const unsigned long long* __restrict__ mask, const uint32_t* __restrict__ gpre,
+    const uint32_t* __restrict__ cks, const int32_t* __restrict__ cvs, uint32_t M,
     uint32_t* __restrict__ keys_out, int32_t* __restrict__ perm_out) {
-  const uint32_t M = *count;
   const int lane = threadIdx.x & (kWave - 1);
-  const int64_t waves = (int64_t)gridDim.x * kSortWaves;
+  const int64_t waves = (int64_t)n_blk * kSortWaves;
   auto pk = [&](int64_t s) { return keys_prev[s]; };
   auto ps = [&](int64_t s) { return s; };
-  for (int64_t j = (int64_t)blockIdx.x * kSortWaves + threadIdx.x / kWave; j < (int64_t)M;
-       j += waves) {  // one pair per wavefront
+  for (int64_t j = (int64_t)blk * kSortWaves + threadIdx.x / kWave; j < (int64_t)M;
+       j += waves) {
     const uint32_t key = cks[j];
     const int32_t idx = cvs[j];
     const int64_t lo = wave_lower_pair(pk, ps, 0, P, key, idx);
@@ -738,25 +728,22 @@ __global__ __launch_bounds__(kSortBS) void upd_place_changed_kernel(
   }
 }
 
-// Final place of every unchanged slot i: its rank among the unchanged plus the
-// changed pairs below (keys_prev[i], i).  The unchanged slots of a workgroup
-// lie between (keys_prev[i0], i0) and (keys_prev[i1 - 1], i1), which bound the
-// window of the changed list they can fall into; it is staged in LDS when it
-// fits.
-__global__ __launch_bounds__(kSortBS) void upd_place_unchanged_kernel(
-    int64_t P, const uint32_t* __restrict__ keys_prev, const unsigned long long* __restrict__ mask,
-    const uint32_t* __restrict__ gpre, const uint32_t* __restrict__ cks,
-    const int32_t* __restrict__ cvs, const uint32_t* __restrict__ count,
-    uint32_t* __restrict__ keys_out, int32_t* __restrict__ perm_out) {
-  __shared__ int window[2];
-  __shared__ uint32_t wk[kWindowCap];
-  __shared__ int32_t wi[kWindowCap];
+// Final place of every unchanged slot i of slot tile `blk`: its rank among the
+// unchanged plus the changed pairs below (keys_prev[i], i).  The unchanged
+// slots of a tile lie between (keys_prev[i0], i0) and (keys_prev[i1 - 1], i1),
+// which bound the window of the changed list they can fall into; it is staged
+// in LDS when it fits.
+__device__ __forceinline__ void place_unchanged(
+    int blk, int64_t P, const uint32_t* __restrict__ keys_prev,
+    const unsigned long long* __restrict__ mask, const uint32_t* __restrict__ gpre,
+    const uint32_t* __restrict__ cks, const int32_t* __restrict__ cvs, int M,
+    uint32_t* __restrict__ keys_out, int32_t* __restrict__ perm_out, int* window, uint32_t* wk,
+    int32_t* wi) {
   const int tid = threadIdx.x;
   const int lane = tid & (kWave - 1);
   const int wv = tid / kWave;
-  const int64_t i0 = (int64_t)blockIdx.x * kUpdTile;
+  const int64_t i0 = (int64_t)blk * kUpdTile;
   const int64_t i1 = min(i0 + (int64_t)kUpdTile, P);
-  const int M = (int)*count;
   auto gk = [&](int64_t m) { return cks[m]; };
   auto gi = [&](int64_t m) { return cvs[m]; };
   if (wv < 2) {  // waves 0 and 1: the two ends of the window
@@ -778,12 +765,12 @@ __global__ __launch_bounds__(kSortBS) void upd_place_unchanged_kernel(
   __syncthreads();
   auto sk = [&](int m) { return wk[m]; };
   auto si = [&](int m) { return wi[m]; };
-  const int64_t g0 = (int64_t)blockIdx.x * kGroupsPerTile;
+  const int64_t g0 = (int64_t)blk * kGroupsPerTile;
 #pragma unroll 2
   for (int j = 0; j < kSortIPT; ++j) {
     const int64_t grp = g0 + j * kSortWaves + wv;
     const int64_t i = grp * kWave + lane;
-    if (i >= P) break;  // the last group of the last workgroup only
+    if (i >= P) break;  // the last group of the last tile only
     const unsigned long long m = mask[grp];
     if ((m >> lane) & 1ull) continue;
     const uint32_t key = keys_prev[i];
@@ -795,6 +782,27 @@ __global__ __launch_bounds__(kSortBS) void upd_place_unchanged_kernel(
     keys_out[pos] = key;
     perm_out[pos] = (int32_t)i;
   }
+}
+
+// Both placements in one launch: the first kChangedBlocks workgroups place the
+// changed pairs (they start first), the rest one slot tile each.
+constexpr int kChangedBlocks = 1024;
+
+__global__ __launch_bounds__(kSortBS) void upd_place_kernel(
+    int64_t P, const uint32_t* __restrict__ keys_prev, const unsigned long long* __restrict__ mask,
+    const uint32_t* __restrict__ gpre, const uint32_t* __restrict__ cks,
+    const int32_t* __restrict__ cvs, const uint32_t* __restrict__ count,
+    uint32_t* __restrict__ keys_out, int32_t* __restrict__ perm_out) {
+  __shared__ int window[2];
+  __shared__ uint32_t wk[kWindowCap];
+  __shared__ int32_t wi[kWindowCap];
+  const uint32_t M = *count;
+  if ((int)blockIdx.x < kChangedBlocks)
+    place_changed((int)blockIdx.x, kChangedBlocks, P, keys_prev, mask, gpre, cks, cvs, M,
+                  keys_out, perm_out);
+  else
+    place_unchanged((int)blockIdx.x - kChangedBlocks, P, keys_prev, mask, gpre, cks, cvs, (int)M,
+                    keys_out, perm_out, window, wk, wi);
 }
 
 struct UpdLayout {
@@ -824,7 +832,7 @@ UpdLayout upd_layout(void* ws, int64_t P) {
   L.ck1 = (uint32_t*)take((size_t)P * 4);
   L.cv1 = (int32_t*)take((size_t)P * 4);
   L.look = (uint32_t*)take((size_t)kMaxPasses * n_tiles * kRadix * 4);
-  L.totals = (uint32_t*)take((size_t)kMaxPasses * kRadix * 4);
+  L.totals = (uint32_t*)take((size_t)kTotalsRep * kTotalsStride * 4);
   L.tile_ctr = (uint32_t*)take((size_t)kMaxPasses * 4);
   L.bytes = off;
   return L;
@@ -846,14 +854,12 @@ hipError_t sort_update_with(const Scenes& sc, int mbits, int key_bits, int64_t P
   const int passes = (key_bits + 7) / 8;
   if (passes < 1 || passes > kMaxPasses) return hipErrorInvalidValue;
   upd_mask_kernel<Scenes><<<n_tiles, kSortBS, 0, stream>>>(sc, mbits, P, x, keys_prev, L.mask,
-                                                           L.blk, status);
-  upd_scan_kernel<<<1, 1024, 0, stream>>>(L.blk, n_tiles, L.count, L.totals, L.tile_ctr);
-  upd_compact_kernel<Scenes><<<n_tiles, kSortBS, 0, stream>>>(sc, mbits, P, x, L.mask, L.blk,
-                                                              L.gpre, L.ck0, L.cv0);
+                                                           L.blk, L.totals, L.tile_ctr, status);
+  upd_compact_kernel<Scenes><<<n_tiles, kSortBS, 0, stream>>>(
+      sc, mbits, P, passes, x, L.mask, L.blk, n_tiles, L.gpre, L.count, L.look, L.totals, L.ck0,
+      L.cv0);
   // stable radix sort of the changed pairs (their number known on the device only)
   const int counted_grid = n_tiles < kCountedGrid ? n_tiles : kCountedGrid;
-  counted_hist_kernel<<<counted_grid, kSortBS, 0, stream>>>(L.ck0, L.count, passes, n_tiles,
-                                                            L.look, L.totals);
   uint32_t* ks = L.ck0;
   int32_t* vs = L.cv0;
   uint32_t* kd = L.ck1;
@@ -869,10 +875,8 @@ hipError_t sort_update_with(const Scenes& sc, int mbits, int key_bits, int64_t P
     vs = vd;
     vd = vt;
   }
-  upd_place_unchanged_kernel<<<n_tiles, kSortBS, 0, stream>>>(P, keys_prev, L.mask, L.gpre, ks, vs,
-                                                              L.count, keys_out, perm_out);
-  upd_place_changed_kernel<<<1024, kSortBS, 0, stream>>>(P, keys_prev, L.mask, L.gpre, ks, vs,
-                                                         L.count, keys_out, perm_out);
+  upd_place_kernel<<<kChangedBlocks + n_tiles, kSortBS, 0, stream>>>(
+      P, keys_prev, L.mask, L.gpre, ks, vs, L.count, keys_out, perm_out);
   return hipGetLastError();
 }
 
