@@ -744,6 +744,19 @@ __device__ __forceinline__ void place_unchanged(
   const int wv = tid / kWave;
   const int64_t i0 = (int64_t)blk * kUpdTile;
   const int64_t i1 = min(i0 + (int64_t)kUpdTile, P);
+  const int64_t g0 = (int64_t)blk * kGroupsPerTile;
+  // The tile's own slots do not depend on the window: their loads are issued
+  // first and overlap its search.  A slot past P reads as changed (skipped).
+  unsigned long long mk[kSortIPT];
+  uint32_t kp[kSortIPT], gp[kSortIPT];
+#pragma unroll
+  for (int j = 0; j < kSortIPT; ++j) {
+    const int64_t grp = g0 + j * kSortWaves + wv;
+    const bool in = grp * kWave + lane < P;
+    mk[j] = in ? mask[grp] : ~0ull;
+    kp[j] = in ? keys_prev[grp * kWave + lane] : 0u;
+    gp[j] = in ? gpre[grp] : 0u;
+  }
   auto gk = [&](int64_t m) { return cks[m]; };
   auto gi = [&](int64_t m) { return cvs[m]; };
   if (wv < 2) {  // waves 0 and 1: the two ends of the window
@@ -765,18 +778,15 @@ __device__ __forceinline__ void place_unchanged(
   __syncthreads();
   auto sk = [&](int m) { return wk[m]; };
   auto si = [&](int m) { return wi[m]; };
-  const int64_t g0 = (int64_t)blk * kGroupsPerTile;
-#pragma unroll 2
+#pragma unroll
   for (int j = 0; j < kSortIPT; ++j) {
-    const int64_t grp = g0 + j * kSortWaves + wv;
-    const int64_t i = grp * kWave + lane;
-    if (i >= P) break;  // the last group of the last tile only
-    const unsigned long long m = mask[grp];
+    const int64_t i = (g0 + j * kSortWaves + wv) * kWave + lane;
+    const unsigned long long m = mk[j];
     if ((m >> lane) & 1ull) continue;
-    const uint32_t key = keys_prev[i];
+    const uint32_t key = kp[j];
     const int below = staged ? wlo + lower_pair(sk, si, 0, wn, key, i)
                              : lower_pair(gk, gi, wlo, whi, key, i);
-    const int64_t unchanged_before = i - ((int64_t)gpre[grp] + lanes_below(m));
+    const int64_t unchanged_before = i - ((int64_t)gp[j] + lanes_below(m));
     int64_t pos = unchanged_before + below;
     pos = pos < 0 ? 0 : (pos >= P ? P - 1 : pos);  // in range even for unsorted keys_prev
     keys_out[pos] = key;

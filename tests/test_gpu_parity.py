@@ -647,6 +647,29 @@ def test_resort_cases(case):
         assert status & 1
 
 
+def test_resort_many_changed_across_many_workgroups():
+    """A re-sort whose changed list spans many sort tiles and whose compaction runs in far
+    more workgroups than there are copies of the digit totals (each workgroup adds into
+    copy b mod 32): half of the particles in the lower half of the domain move one cell up."""
+    pp = require_gpu()
+    s = W.random_scene(12, 48, 400000)
+    g = pp.grid_from_spec(s.grid)
+    og = oracle_grid(g)
+    P = s.P
+    x0 = dev(s.x)
+    keys0, perm0 = _full_sort(pp, g, x0, P)
+    xh = host(x0[:, perm0.long()].contiguous()).copy()
+    rng = np.random.default_rng(5)
+    pick = (xh[2] < 0.5) & (rng.random(P) < 0.5)
+    xh[2, pick] += np.float32(1.0 / 48)
+    note(f"resort many changed: P={P}, moved {int(pick.sum())}")
+    keys, perm, status = _resort(pp, g, dev(xh), keys0, P)
+    keys_ref, perm_ref = O.sort_keys(og, xh)
+    assert status == 0
+    assert np.array_equal(host(keys).view(np.uint32), keys_ref)
+    assert np.array_equal(host(perm), perm_ref)
+
+
 def test_resort_with_unordered_previous_keys_is_flagged_and_in_range():
     pp = require_gpu()
     s = W.random_scene(10, 24, 20000)
