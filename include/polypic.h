@@ -136,7 +136,7 @@ int32_t polypic_sort(const polypic_grid* grid, int64_t P, const float* x, uint32
  * does not happen when the launches run in order on one stream) stops
  * waiting and raises POLYPIC_FLAG_STALL, the outputs then unspecified.
  * ws: at least polypic_sort_update_workspace_bytes() bytes (about 19 B per
- * particle), contents scratch.
+ * particle plus 128 KB), contents scratch.
  * ------------------------------------------------------------------------ */
 int32_t polypic_sort_update_workspace_bytes(const polypic_grid* grid, int64_t P, size_t* bytes);
 int32_t polypic_sort_update(const polypic_grid* grid, int64_t P, const float* x,

@@ -349,6 +349,9 @@ __global__ __launch_bounds__(kSortBS) void counted_scatter_kernel(
   // Workgroups with no tile to start on leave without touching the counter
   // (a counter that every workgroup of a large grid bumps serialises them).
   if ((int64_t)blockIdx.x * kSortTile >= M) return;
+  // With no more tiles than workgroups, the first claims of the workgroups that
+  // start take every tile: each leaves after its first, without a second claim.
+  const bool one_each = (M + kSortTile - 1) / kSortTile <= (int64_t)gridDim.x;
   while (true) {
 #pragma unroll
   for (int w = 0; w < kSortWaves; ++w) whist[w][tid] = 0u;
@@ -461,6 +464,7 @@ __global__ __launch_bounds__(kSortBS) void counted_scatter_kernel(
       vals_out[pos] = val[j];
     }
   }
+  if (one_each) return;  // uniform
   __syncthreads();  // LDS is reused by the next tile
   }
 }

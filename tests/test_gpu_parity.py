@@ -670,6 +670,26 @@ def test_resort_many_changed_across_many_workgroups():
     assert np.array_equal(host(perm), perm_ref)
 
 
+def test_resort_changed_list_longer_than_the_scatter_grid():
+    """Every particle changes cell and the changed list has more sort tiles (600) than the
+    scatter launches workgroups (512), so workgroups claim a second tile."""
+    pp = require_gpu()
+    P = 600 * 2048 - 77                              # ragged last tile
+    s = W.random_scene(13, 64, P)
+    g = pp.grid_from_spec(s.grid)
+    og = oracle_grid(g)
+    x0 = dev(s.x)
+    keys0, perm0 = _full_sort(pp, g, x0, P)
+    xh = host(x0[:, perm0.long()].contiguous()).copy()
+    xh[0] += np.float32(1.0 / 64)
+    note(f"resort all changed, long list: P={P}")
+    keys, perm, status = _resort(pp, g, dev(xh), keys0, P)
+    keys_ref, perm_ref = O.sort_keys(og, xh)
+    assert status == 0
+    assert np.array_equal(host(keys).view(np.uint32), keys_ref)
+    assert np.array_equal(host(perm), perm_ref)
+
+
 def test_resort_with_unordered_previous_keys_is_flagged_and_in_range():
     pp = require_gpu()
     s = W.random_scene(10, 24, 20000)
