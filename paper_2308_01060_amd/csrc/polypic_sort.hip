@@ -543,18 +543,58 @@ __global__ __launch_bounds__(kSortBS) void upd_mask_kernel(Scenes sc, int mbits,
   }
 }
 
+// Beyond this many workgroups, summing every count in every workgroup (a cost
+// that grows with their square: 0.03 -> 0.08 ms at 12.5 K workgroups) loses to a
+// separate one-workgroup scan.
+constexpr int kFoldedScanMaxTiles = 4096;
+
+// one workgroup: exclusive scan of the per-workgroup counts in place, total to
+// *count (for more than kFoldedScanMaxTiles workgroups)
+__global__ __launch_bounds__(1024) void upd_scan_kernel(uint32_t* __restrict__ blk, int n,
+                                                        uint32_t* __restrict__ count) {
+  __shared__ uint32_t wsum[1024 / kWave];
+  const int tid = threadIdx.x;
+  const int lane = tid & (kWave - 1);
+  const int wv = tid / kWave;
+  uint32_t running = 0;
+  for (int base = 0; base < n; base += 1024) {
+    const int k = base + tid;
+    const uint32_t v = k < n ? blk[k] : 0u;
+    uint32_t s = v;
+#pragma unroll
+    for (int off = 1; off < kWave; off <<= 1) {
+      const uint32_t o = __shfl_up(s, off, kWave);
+      if (lane >= off) s += o;
+    }
+    if (lane == kWave - 1) wsum[wv] = s;
+    __syncthreads();
+    uint32_t pre = 0, tot = 0;
+#pragma unroll
+    for (int w = 0; w < 1024 / kWave; ++w) {
+      pre += (w < wv) ? wsum[w] : 0u;
+      tot += wsum[w];
+    }
+    if (k < n) blk[k] = running + pre + s - v;
+    running += tot;
+    __syncthreads();
+  }
+  if (tid == 0) *count = running;
+}
+
 // Changed (key, index) pairs in index order, gpre[grp] = changed slots before
 // the group, and what the changed list's radix sort needs: *count, the digit
 // totals of every pass (added to copy b % kTotalsRep of totals, cleared by the
 // mask kernel) and the
-// look-back words of every tile of the changed list, cleared.  Each workgroup
-// sums the per-workgroup counts itself (n_tiles words, a few KB, read from L2),
-// which saves a launch for their scan.
+// look-back words of every tile of the changed list, cleared.  Up to
+// kFoldedScanMaxTiles workgroups, each sums the per-workgroup counts itself
+// (n_tiles words, a few KB, read from L2), which saves a launch for their scan;
+// with `scanned`, upd_scan_kernel has already turned them into prefixes and
+// written *count.
 template <class Scenes>
 __global__ __launch_bounds__(kSortBS) void upd_compact_kernel(
     Scenes sc, int mbits, int64_t P, int passes, const float* __restrict__ x,
     const unsigned long long* __restrict__ mask, const uint32_t* __restrict__ blk_count,
-    int n_tiles, uint32_t* __restrict__ gpre, uint32_t* __restrict__ count,
+    int n_tiles, bool scanned, uint32_t* __restrict__ gpre, uint32_t* __restrict__ count,
     uint32_t* __restrict__ look, uint32_t* __restrict__ totals, uint32_t* __restrict__ ck,
     int32_t* __restrict__ cv) {
   __shared__ uint32_t pre_sh[kGroupsPerTile];
@@ -568,37 +608,42 @@ __global__ __launch_bounds__(kSortBS) void upd_compact_kernel(
 
   // changed slots in the workgroups before this one, and in all
   uint32_t before = 0, all = 0;
-  for (int k0 = 0; k0 < n_tiles; k0 += 4 * kSortBS) {
-    uint32_t c[4];
+  if (scanned) {
+    before = blk_count[b];
+    all = *count;
+  } else {
+    for (int k0 = 0; k0 < n_tiles; k0 += 4 * kSortBS) {
+      uint32_t c[4];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int k = k0 + u * kSortBS + tid;
-      c[u] = k < n_tiles ? blk_count[k] : 0u;
+      for (int u = 0; u < 4; ++u) {
+        const int k = k0 + u * kSortBS + tid;
+        c[u] = k < n_tiles ? blk_count[k] : 0u;
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        all += c[u];
+        before += k0 + u * kSortBS + tid < b ? c[u] : 0u;
+      }
     }
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      all += c[u];
-      before += k0 + u * kSortBS + tid < b ? c[u] : 0u;
+    for (int off = kWave / 2; off > 0; off >>= 1) {
+      before += __shfl_xor(before, off, kWave);
+      all += __shfl_xor(all, off, kWave);
     }
-  }
+    if (lane == 0) {
+      wsum[0][wv] = before;
+      wsum[1][wv] = all;
+    }
+    __syncthreads();
+    before = 0;
+    all = 0;
 #pragma unroll
-  for (int off = kWave / 2; off > 0; off >>= 1) {
-    before += __shfl_xor(before, off, kWave);
-    all += __shfl_xor(all, off, kWave);
+    for (int w = 0; w < kSortWaves; ++w) {
+      before += wsum[0][w];
+      all += wsum[1][w];
+    }
+    if (b == 0 && tid == 0) *count = all;
   }
-  if (lane == 0) {
-    wsum[0][wv] = before;
-    wsum[1][wv] = all;
-  }
-  __syncthreads();
-  before = 0;
-  all = 0;
-#pragma unroll
-  for (int w = 0; w < kSortWaves; ++w) {
-    before += wsum[0][w];
-    all += wsum[1][w];
-  }
-  if (b == 0 && tid == 0) *count = all;
   // tile b of the changed list exists: clear its look-back words
   if ((int64_t)b * kSortTile < (int64_t)all)
     for (int q = 0; q < passes; ++q) look[((size_t)q * n_tiles + b) * kRadix + tid] = 0u;
@@ -869,9 +914,11 @@ hipError_t sort_update_with(const Scenes& sc, int mbits, int key_bits, int64_t P
   if (passes < 1 || passes > kMaxPasses) return hipErrorInvalidValue;
   upd_mask_kernel<Scenes><<<n_tiles, kSortBS, 0, stream>>>(sc, mbits, P, x, keys_prev, L.mask,
                                                            L.blk, L.totals, L.tile_ctr, status);
+  const bool scanned = n_tiles > kFoldedScanMaxTiles;
+  if (scanned) upd_scan_kernel<<<1, 1024, 0, stream>>>(L.blk, n_tiles, L.count);
   upd_compact_kernel<Scenes><<<n_tiles, kSortBS, 0, stream>>>(
-      sc, mbits, P, passes, x, L.mask, L.blk, n_tiles, L.gpre, L.count, L.look, L.totals, L.ck0,
-      L.cv0);
+      sc, mbits, P, passes, x, L.mask, L.blk, n_tiles, scanned, L.gpre, L.count, L.look,
+      L.totals, L.ck0, L.cv0);
   // stable radix sort of the changed pairs (their number known on the device only)
   const int counted_grid = n_tiles < kCountedGrid ? n_tiles : kCountedGrid;
   uint32_t* ks = L.ck0;

@@ -690,6 +690,32 @@ def test_resort_changed_list_longer_than_the_scatter_grid():
     assert np.array_equal(host(perm), perm_ref)
 
 
+def test_resort_with_more_workgroups_than_the_folded_scan_takes():
+    """More than 4096 slot tiles of 2048 (8.39 M particles): the re-sort scans the
+    per-workgroup counts in a launch of its own instead of summing them in every
+    workgroup of the compaction.  Half of the particles in the lower half move a cell."""
+    pp = require_gpu()
+    P = 4097 * 2048 + 5
+    n = 96
+    spec = W.cubic_grid(n)
+    g = pp.grid_from_spec(spec)
+    og = oracle_grid(g)
+    rng = np.random.default_rng(14)
+    x = (4.0 / n + rng.random((3, P)) * ((n - 4.0) / n)).astype(np.float32)
+    x0 = dev(x)
+    keys0, perm0 = _full_sort(pp, g, x0, P)
+    xh = host(x0[:, perm0.long()].contiguous()).copy()
+    del x0
+    pick = (xh[2] < 0.5) & (rng.random(P) < 0.5)
+    xh[2, pick] += np.float32(1.0 / n)
+    note(f"resort beyond the folded scan: P={P}, moved {int(pick.sum())}")
+    keys, perm, status = _resort(pp, g, dev(xh), keys0, P)
+    keys_ref, perm_ref = O.sort_keys(og, xh)
+    assert status == 0
+    assert np.array_equal(host(keys).view(np.uint32), keys_ref)
+    assert np.array_equal(host(perm), perm_ref)
+
+
 def test_resort_with_unordered_previous_keys_is_flagged_and_in_range():
     pp = require_gpu()
     s = W.random_scene(10, 24, 20000)
