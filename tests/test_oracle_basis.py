@@ -157,3 +157,64 @@ def test_sort_is_stable_argsort():
     assert sorted(perm.tolist()) == list(range(3000))
     same = keys[1:] == keys[:-1]
     assert np.all(perm[1:][same] > perm[:-1][same])
+
+
+def _u32(x32, inv_dx):
+    """u = fl32(x * inv_dx) for a float32 x and a power-of-two inv_dx (exact)."""
+    return Fr(float(np.float32(x32) * np.float32(inv_dx)))
+
+
+@pytest.mark.parametrize("axis", [0, 1, 2])
+def test_stencil_range_check_at_the_switches(axis):
+    """The 3-node stencil of the quadratic B-spline (section 3.1: support |d| < 3/2) must
+    lie inside the N storage nodes of every axis.
+
+    The stencil is the nearest node c and its two neighbours, with c = floor(u + 1/2)
+    (a tie at u = k + 1/2 goes up), so it fits iff 1 <= c <= N - 2, i.e.
+    0 <= b <= N - 3 with b = c - 1.  Positions sit exactly at the switches
+    u = k + 1/2 and one float32 below them, on each axis in turn: b = 0 and b = N - 3
+    are accepted, b = -1 and b = N - 2 rejected, and every oracle entry point raises
+    OracleRangeError exactly for the rejected ones.  Independently of the oracle's b,
+    the test checks in exact rationals that every lattice node with a nonzero B-spline
+    weight lies in {c - 1, c, c + 1}.
+    """
+    n = 12
+    inv = 8.0
+    g = O.Grid(n, n, n, 1 / inv, inv)
+    below = lambda v: np.nextafter(np.float32(v), np.float32(-np.inf))
+    u_cases = [  # (u as float32, expected in range)
+        (np.float32(0.5), True),            # b = 0, t = -1/2
+        (below(0.5), False),                # b = -1
+        (np.float32(n - 1.5), False),       # b = N - 2, t = -1/2
+        (below(n - 1.5), True),             # b = N - 3, t just below 1/2
+        (np.float32(5.0), True),
+    ]
+    P = len(u_cases)
+    x = np.full((3, P), np.float32(5.0 / inv), np.float32)
+    for i, (u, _) in enumerate(u_cases):
+        x[axis, i] = np.float32(u) / np.float32(inv)   # exact: inv is a power of two
+    expect = np.array([ok for _, ok in u_cases])
+    b, _ = O.stencil_base(g, x)
+    np.testing.assert_array_equal(b[axis], [0, -1, n - 2, n - 3, 4])
+    np.testing.assert_array_equal(O.stencil_in_range(g, b), expect)
+
+    for i, (u32, ok) in enumerate(u_cases):
+        u = _u32(x[axis, i], inv)
+        c = (u + Fr(1, 2)).__floor__()
+        assert (1 <= c <= n - 2) == ok
+        support = [k for k in range(-4, n + 4)
+                   if float(O.quadratic_bspline(float(u - k))) > 0.0]
+        assert set(support) <= {c - 1, c, c + 1}, (u, support, c)
+
+    coeff = np.zeros((3, 1, 1), np.float32)
+    vel = np.zeros((3, n, n, n))
+    for i, (_, ok) in enumerate(u_cases):
+        xi = x[:, i:i + 1]
+        calls = [lambda: O.sort_keys(g, xi), lambda: O.p2g(g, xi, coeff, 1),
+                 lambda: O.g2p(g, vel, xi, 1)]
+        for call in calls:
+            if ok:
+                call()
+            else:
+                with pytest.raises(O.OracleRangeError):
+                    call()
