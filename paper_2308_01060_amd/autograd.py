@@ -22,7 +22,22 @@ from typing import Sequence
 
 import torch
 
-from . import ops
+from . import _lib, ops
+
+
+def _raise_on_flags(status: torch.Tensor, where: str) -> None:
+    """Read the device flag word (one synchronisation) and raise if any flag is set: an
+    out-of-range particle (skipped by every kernel), keys out of order in a re-sort, or a
+    re-sort that gave up waiting, each of which would otherwise leave wrong outputs or zero
+    gradients without an error."""
+    flags = int(status.item())
+    if flags:
+        names = [n for bit, n in ((_lib.POLYPIC_FLAG_RANGE, "a particle stencil left the grid"),
+                                  (_lib.POLYPIC_FLAG_ORDER, "re-sort keys out of order"),
+                                  (_lib.POLYPIC_FLAG_STALL, "re-sort stalled")) if flags & bit]
+        raise _lib.PolyPICError(_lib.POLYPIC_EINVAL if flags & _lib.POLYPIC_FLAG_RANGE
+                                else _lib.POLYPIC_EDEVICE,
+                                f"{where}: device flags {flags} ({'; '.join(names)})")
 
 
 class _Buffers:
@@ -50,7 +65,8 @@ class PolyPICSteps(torch.autograd.Function):
 
     @staticmethod
     def forward(ctx, x0, c0, grid, n_modes: int, n_steps: int, dt: float,
-                gravity: Sequence[float], bc_layers: int, uniform_mass: float = 1.0):
+                gravity: Sequence[float], bc_layers: int, uniform_mass: float = 1.0,
+                check_status: bool = True):
         P = x0.shape[-1]
         dev = x0.device
         B = _Buffers(grid, P, n_modes, dev)
@@ -89,7 +105,10 @@ class PolyPICSteps(torch.autograd.Function):
             ops.polypic_gather_rows(order, new_order, perm)  # slot i now holds order[perm[i]]
             order = new_order
             x, c = x_next, c_next
+        if check_status:
+            _raise_on_flags(B.status, "PolyPICSteps forward")
         ctx.grid = grid
+        ctx.check_status = bool(check_status)
         ctx.params = (n_modes, n_steps, float(dt), tuple(float(g) for g in gravity),
                       int(bc_layers), float(uniform_mass))
         ctx.checkpoints = checkpoints
@@ -131,12 +150,18 @@ class PolyPICSteps(torch.autograd.Function):
             gx, gc = gx_in, gc_in
             ctx.checkpoints[s] = None  # released as soon as its step is done
         ctx.checkpoints = None
-        return gx, gc, None, None, None, None, None, None, None
+        if ctx.check_status:
+            _raise_on_flags(B.status, "PolyPICSteps backward")
+        return gx, gc, None, None, None, None, None, None, None, None
 
 
 def polypic_steps(x0, c0, grid, n_modes: int, n_steps: int, dt: float,
                   gravity: Sequence[float] = (0.0, -9.8, 0.0), bc_layers: int = 1,
-                  uniform_mass: float = 1.0):
-    """Differentiable n_steps of transfers; returns (x_S, c_S) in the input particle order."""
+                  uniform_mass: float = 1.0, check_status: bool = True):
+    """Differentiable n_steps of transfers; returns (x_S, c_S) in the input particle order.
+
+    With check_status (the default) the forward and the backward each read the device flag
+    word once at their end and raise PolyPICError if a kernel flagged a particle out of
+    range or a failed re-sort (one synchronisation each)."""
     return PolyPICSteps.apply(x0, c0, grid, n_modes, n_steps, dt, gravity, bc_layers,
-                              uniform_mass)
+                              uniform_mass, check_status)

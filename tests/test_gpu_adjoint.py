@@ -124,3 +124,23 @@ def test_autograd_outputs_match_forward_steps():
     order = ps.order
     assert rel(host(xS[:, order]), host(ps.x)) <= 1e-6
     assert rel(host(cS[:, :, order]), host(ps.coeff)) <= 1e-5
+
+
+def test_autograd_raises_on_out_of_range_particle():
+    """A particle whose stencil leaves the grid is skipped by every kernel and flagged in
+    the device status word; the autograd forward reads the word and raises instead of
+    returning outputs (and later zero gradients) silently.  With the check switched off
+    the same call returns, and the in-range particles are stepped."""
+    pp = require_gpu()
+    gs, x, c, _ = scene(6)
+    x = x.copy()
+    x[0, 0] = np.float32(0.01)          # b_x = -1 on a 1/16 grid: out of range
+    g = pp.grid_from_spec(gs)
+    note("autograd out-of-range particle")
+    x0 = dev(x).requires_grad_(True)
+    c0 = dev(c).requires_grad_(True)
+    with pytest.raises(pp.PolyPICError, match="left the grid"):
+        pp.polypic_steps(x0, c0, g, 27, 2, 1e-3)
+    xS, cS = pp.polypic_steps(x0, c0, g, 27, 2, 1e-3, check_status=False)
+    torch.cuda.synchronize()
+    assert torch.isfinite(cS).all()
