@@ -286,8 +286,14 @@ __global__ __launch_bounds__(BS, Scenes::kMany ? 3 : 4) void g2p2g_kernel(G2P2GA
   }
   __syncthreads();
   const int run_slot = seg_of[slot];
-  // brick of this slot's run; runs past kRuns, and tiles past the brick budget, go to HBM
-  const int seg = run_slot < 0 ? -1 : (run_slot < kRuns ? run_brick[run_slot] : kBrickKMAX);
+  // brick of this slot's run; runs past kRuns, and tiles past the brick budget, go to HBM.
+  // A run past kRuns keeps a value of its own (kBrickKMAX + run index, above every
+  // distinct-tile index d < kRuns), so that two lanes of different runs never compare
+  // equal below: in a batch, slots on either side of a scene boundary can share local
+  // base-node coordinates, and folding them would add one scene's values to the other's
+  // grid.
+  const int seg = run_slot < 0 ? -1
+                               : (run_slot < kRuns ? run_brick[run_slot] : kBrickKMAX + run_slot);
   const int nseg = n_bricks;
 
   // the lane pair (lane ^ 1) shares this lane's segment and base node: every lane

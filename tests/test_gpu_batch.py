@@ -320,3 +320,52 @@ def test_out_of_range_particle_flags_and_stays_in_its_scene():
         M, Q = O.p2g(O.grid_from_spec(sc.grid), sc.x, sc.coeff, 4)
         m_k, q_k = scene_grid_arrays(bs, k, gm, gp, M.shape)
         assert rel(m_k, M) <= TOL_NORMWISE and rel(q_k, Q) <= TOL_NORMWISE, k
+
+
+@pytest.mark.parametrize("n_modes", [4, 27])
+def test_fused_p2g_does_not_fold_across_a_scene_boundary(n_modes):
+    """Two scenes of 129 particles, each particle in its own 4^3-node tile, so that the
+    first workgroup's chunk holds more than 64 runs before the scene boundary.  Scene 0's
+    last particle (slot 128) and scene 1's first (slot 129) share their local base node
+    and form one lane pair of the fused kernel's P2G half.  They belong to different
+    grids, so their node values must not be folded together: every scene's grid equals
+    the oracle's P2G (Eq. 1, 4, 13) of that scene's new state, and its mass sums to the
+    scene's particle count."""
+    pp = require_gpu()
+    n = 32
+    gs = W.cubic_grid(n)
+    og = O.grid_from_spec(gs)
+    tiles = np.array([(tx, ty, tz) for tz in range(8) for ty in range(8) for tx in range(8)]).T
+    bases = 4 * tiles + 1
+    order = np.argsort(O.morton_key(bases), kind="stable")
+    q = order[300]
+    pick = [np.concatenate([order[:128], [q]]), np.concatenate([[q], order[301:429]])]
+    rng = np.random.default_rng(11)
+    scenes = []
+    for k, sel in enumerate(pick):
+        x = ((bases[:, sel] + 1.25) * gs.dx).astype(np.float32)   # t = 1/4 on every axis
+        c = np.zeros((3, 27, x.shape[1]), np.float32)
+        c[:, 0] = rng.standard_normal((3, x.shape[1]))
+        c[:, 1:] = 0.1 * rng.standard_normal((3, 26, x.shape[1]))
+        scenes.append(W.Scene(f"boundary{k}", gs, x, c, None, 1.0, dt=0.0,
+                              gravity=(0.0, 0.0, 0.0), bc_layers=0))
+    note(f"batch fused scene boundary: n_modes={n_modes}")
+    bs = make_set(pp, scenes, n_modes)
+    bs.sort()
+    perm = host(bs.perm)
+    assert perm[128] == 128 and perm[129] == 129      # the boundary pair, as constructed
+    bs.p2g()
+    bs.grid_update()
+    bs.g2p2g()
+    torch.cuda.synchronize()
+    assert bs.status_flags() == 0
+    x1 = host(bs.x_next)
+    c1 = host(bs.coeff_next).reshape(3, n_modes, bs.P)
+    gm, gp = host(bs.grid_mass), host(bs.grid_mom)
+    for k in range(2):
+        sl = bs.scene_slice(k)
+        M_ref, Q_ref = O.p2g(og, x1[:, sl], c1[:, :, sl], n_modes)
+        M, Q = scene_grid_arrays(bs, k, gm, gp, M_ref.shape)
+        assert abs(float(M.sum()) - 129.0) <= 1e-4, (k, float(M.sum()))
+        assert rel(M, M_ref) <= TOL_NORMWISE, k
+        assert rel(Q, Q_ref) <= TOL_NORMWISE, k
