@@ -60,48 +60,60 @@ def _mode_index(n_modes: int):
             torch.tensor([MODES[r][2] for r in range(n_modes)]))
 
 
-def step(grid: Grid, x: torch.Tensor, c: torch.Tensor, n_modes: int, dt: float,
-         gravity: Sequence[float] = (0.0, -9.8, 0.0), bc_layers: int = 1,
-         mass: torch.Tensor = None, uniform_mass: float = 1.0):
-    """One differentiable step: (x (3, P), c (3, n_modes, P)) -> (x', c', grid dict).
-
-    A loop over the 27 stencil nodes; at each node all modes at once.
-    """
-    P = x.shape[1]
-    m = mass if mass is not None else torch.full((P,), float(uniform_mass), dtype=torch.float64)
-    b, t = _stencil(grid, x)
-    KX, KY, KZ = _mode_index(n_modes)
-    nn = grid.n_nodes
-    # per-axis tables over (factor k, node j, particle p)
+def _tables(t: torch.Tensor):
+    """Per-axis tables over (factor k, node j, particle p): the weights w_j, the mode
+    factors phi_k(j) = 1, zhat, ghat (Eq. 11, 14) and the G2P projection rows
+    w, w zhat, (1, -2, 1) (K(t) cancelled on quadratic axes)."""
     wt, phit, qt = [], [], []
     for a in range(3):
         w, z, g = (torch.stack(f) for f in _factors(t[a]))  # (3 j, P): w_j, zhat_j, ghat_j
         one = torch.ones_like(w)
         wt.append(w)
-        phit.append(torch.stack([one, z, g]))             # phi_k(j): 1, zhat, ghat (Eq. 11, 14)
-        # G2P projection rows (K(t) cancelled on quadratic axes): w, w zhat, (1, -2, 1)
+        phit.append(torch.stack([one, z, g]))
         qt.append(torch.stack([w, w * z, torch.stack([one[0], -2.0 * one[1], one[2]])]))
+    return wt, phit, qt
 
-    def mode_rows(f, j):
-        """(n_modes, P): f_x[kx_r, jx] f_y[ky_r, jy] f_z[kz_r, jz] at stencil node j."""
-        return f[0][KX, j[0]] * f[1][KY, j[1]] * f[2][KZ, j[2]]
 
-    # P2G (Eq. 1, 4, 13): m_i = sum_p m_p W_ip;  p_i = sum_p m_p W_ip sum_r c_pr s_r(i)
+def _mode_rows(f, j, n_modes: int):
+    """(n_modes, P): f_x[kx_r, jx] f_y[ky_r, jy] f_z[kz_r, jz] at stencil node j."""
+    KX, KY, KZ = _mode_index(n_modes)
+    return f[0][KX, j[0]] * f[1][KY, j[1]] * f[2][KZ, j[2]]
+
+
+def p2g(grid: Grid, x: torch.Tensor, c: torch.Tensor, n_modes: int,
+        mass: torch.Tensor = None, uniform_mass: float = 1.0):
+    """P2G (Eq. 1, 4, 13): m_i = sum_p m_p W_ip;  p_i = sum_p m_p W_ip sum_r c_pr s_r(i).
+
+    Returns (M (n_nodes,), Q (3, n_nodes)), flat node index x fastest."""
+    P = x.shape[1]
+    m = mass if mass is not None else torch.full((P,), float(uniform_mass), dtype=torch.float64)
+    b, t = _stencil(grid, x)
+    wt, phit, _ = _tables(t)
+    nn = grid.n_nodes
     M = torch.zeros(nn, dtype=torch.float64)
     Q = torch.zeros(3, nn, dtype=torch.float64)
     for j in STENCIL:
         node = _flat(grid, b, j)
         mW = m * wt[0][j[0]] * wt[1][j[1]] * wt[2][j[2]]    # m_p W_ip
-        V = (c * mode_rows(phit, j)).sum(dim=1)             # sum_r c_par s_r(j): (3, P)
+        V = (c * _mode_rows(phit, j, n_modes)).sum(dim=1)   # sum_r c_par s_r(j): (3, P)
         M = M.index_add(0, node, mW)
         Q = Q.index_add(1, node, mW * V)
-    # grid update (Eq. 5 + gravity + separating slip walls)
+    return M, Q
+
+
+def grid_update(grid: Grid, M: torch.Tensor, Q: torch.Tensor, dt: float,
+                gravity: Sequence[float] = (0.0, -9.8, 0.0), bc_layers: int = 1,
+                nodes: torch.Tensor = None):
+    """Grid update (Eq. 5 + gravity + separating slip walls) of M (n,), Q (3, n).
+
+    ``nodes`` gives the flat index of each entry when M and Q hold a subset of the
+    grid's nodes (default: all nodes in order); it only places the walls."""
     occ = M > 0
     Msafe = torch.where(occ, M, torch.ones_like(M))
     gvec = torch.tensor(gravity, dtype=torch.float64).reshape(3, 1)
     v = torch.where(occ, Q / Msafe + dt * gvec, torch.zeros_like(Q))
     if bc_layers > 0:
-        idx = torch.arange(nn)
+        idx = torch.arange(grid.n_nodes) if nodes is None else torch.as_tensor(nodes)
         ix = idx % grid.nx
         iy = (idx // grid.nx) % grid.ny
         iz = idx // (grid.nx * grid.ny)
@@ -115,20 +127,38 @@ def step(grid: Grid, x: torch.Tensor, c: torch.Tensor, n_modes: int, dt: float,
             va = torch.where(hi & (va > 0), torch.zeros_like(va), va)
             rows.append(va)
         v = torch.stack(rows)
-    # G2P: c'_r = <v, s_r>_W / <s_r, s_r>_W with K(t) cancelled on quadratic axes
+    return v
+
+
+def g2p(grid: Grid, v: torch.Tensor, x: torch.Tensor, n_modes: int, dt: float):
+    """G2P and advection: c'_r = <v, s_r>_W / <s_r, s_r>_W (K(t) cancelled on quadratic
+    axes), x' = x + dt c'_0 kept inside [o + 2 dx, o + (N - 2) dx].  v is (3, n_nodes)."""
+    P = x.shape[1]
+    b, t = _stencil(grid, x)
+    _, phit, qt = _tables(t)
     num = torch.zeros(3, n_modes, P, dtype=torch.float64)
     den = torch.zeros(n_modes, P, dtype=torch.float64)
     for j in STENCIL:
-        qq = mode_rows(qt, j)                               # projection weight: (n_modes, P)
+        qq = _mode_rows(qt, j, n_modes)                     # projection weight: (n_modes, P)
         num = num + qq * v[:, _flat(grid, b, j)].unsqueeze(1)
-        den = den + qq * mode_rows(phit, j)
+        den = den + qq * _mode_rows(phit, j, n_modes)
     c_out = num / den
-    # advection, kept inside [o + 2 dx, o + (N - 2) dx]
     lo = torch.tensor([grid.origin[a] + 2 * grid.dx for a in range(3)],
                       dtype=torch.float64).reshape(3, 1)
     hi = torch.tensor([grid.origin[a] + (n - 2) * grid.dx for a, n in enumerate(grid.dims)],
                       dtype=torch.float64).reshape(3, 1)
     x_out = torch.minimum(torch.maximum(x + dt * c_out[:, 0, :], lo), hi)
+    return x_out, c_out
+
+
+def step(grid: Grid, x: torch.Tensor, c: torch.Tensor, n_modes: int, dt: float,
+         gravity: Sequence[float] = (0.0, -9.8, 0.0), bc_layers: int = 1,
+         mass: torch.Tensor = None, uniform_mass: float = 1.0):
+    """One differentiable step: (x (3, P), c (3, n_modes, P)) -> (x', c', grid dict):
+    P2G, grid update, G2P with advection, in that order."""
+    M, Q = p2g(grid, x, c, n_modes, mass, uniform_mass)
+    v = grid_update(grid, M, Q, dt, gravity, bc_layers)
+    x_out, c_out = g2p(grid, v, x, n_modes, dt)
     return x_out, c_out, dict(grid_mass=M, grid_mom=Q, grid_vel=v)
 
 
