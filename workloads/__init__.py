@@ -154,14 +154,41 @@ def config1_moving(seed: int = 0, n: int = 128) -> Scene:
     return s
 
 
-def config2_fluid(seed: int = 0, n: int = 256) -> Scene:
-    """Falling liquid block: 128x64x128 cells at 16 ppc (2x2x4 jitter) on a 256^3 grid."""
+def config2_fluid(seed: int = 0, n: int = 256, coefficients: bool = True) -> Scene:
+    """Falling liquid block: 128x64x128 cells at 16 ppc (2x2x4 jitter) on a 256^3 grid.
+
+    With coefficients=False the coefficient array is left empty (shape (3, 27, 0)) for
+    callers that draw it elsewhere; the positions are the same either way."""
     rng = np.random.default_rng(seed)
     g = cubic_grid(n)
     q = n // 4
     x = jittered_block(rng, g, (q, n // 2, q), (n // 2, n // 4, n // 2), (2, 2, 4))
-    c = _coefficients(rng, x.shape[1], 1.0, 0.1)
+    c = (_coefficients(rng, x.shape[1], 1.0, 0.1) if coefficients
+         else np.zeros((3, N_MODES_MAX, 0), np.float32))
     return Scene(f"fluid_{n}cube_{x.shape[1]}", g, x, c, None, 1.0, dt=1e-4, bc_layers=1)
+
+
+def paper_dambreak_small(seed: int = 0, n: int = 64) -> Scene:
+    """A dam break at the size of the paper's smallest fluid-only scene (section 4,
+    Table 2: about 311 thousand particles, 8 modes, dt = 2e-4): a 36x36x30-cell block at
+    8 ppc (311,040 particles) at the low corner of a 64^3-cell grid, at rest.  The
+    paper's own scene geometry is not given; only its particle count, mode count and
+    time step are matched."""
+    rng = np.random.default_rng(seed)
+    g = cubic_grid(n)
+    x = jittered_block(rng, g, (0, 0, 0), (36, 36, 30), (2, 2, 2))
+    c = _coefficients(rng, x.shape[1], 1.0, 0.1, zero=True)
+    return Scene(f"paper_dambreak_{n}cube_{x.shape[1]}", g, x, c, None, 1.0, dt=2e-4,
+                 bc_layers=1, n_steps=100)
+
+
+def paper_dambreak_small_moving(seed: int = 0, n: int = 64) -> Scene:
+    """The paper-size dam break with non-trivial state: c0 ~ N(0,1), higher modes ~ N(0,0.1)."""
+    s = paper_dambreak_small(seed, n)
+    rng = np.random.default_rng(seed + 1000)
+    s.coeff = _coefficients(rng, s.P, 1.0, 0.1)
+    s.name = s.name.replace("paper_dambreak", "paper_dambreak_moving")
+    return s
 
 
 def config2_fabric(seed: int = 0, n: int = 256, side: int = 1000) -> Scene:
