@@ -70,10 +70,14 @@ def mode_value(k: int, z: Fr, t: Fr) -> Fr:
 
 
 class ParticleStencil:
-    """Exact stencil data of one particle: base node, per-axis t, node weights, modes."""
+    """Exact stencil data of one particle: base node, per-axis t, node weights, modes.
 
-    def __init__(self, x: Sequence[Fr], origin: Sequence[Fr], inv_dx: Fr):
-        self.u = [(x[a] - origin[a]) * inv_dx for a in range(3)]
+    ``shift`` (in units of dx, per axis) moves the lattice the stencil lives on: the
+    faces of a staggered grid sit at origin + (i + shift) dx."""
+
+    def __init__(self, x: Sequence[Fr], origin: Sequence[Fr], inv_dx: Fr,
+                 shift: Sequence[Fr] = (Fr(0), Fr(0), Fr(0))):
+        self.u = [(x[a] - origin[a]) * inv_dx - shift[a] for a in range(3)]
         bt = [stencil(u) for u in self.u]
         self.b = [p[0] for p in bt]
         self.t = [p[1] for p in bt]
@@ -190,3 +194,59 @@ def float32_round(v: Fr) -> np.float32:
     best = min(cand, key=lambda c: (abs(Fr(float(c)) - v),
                                     int(np.frombuffer(np.float32(c).tobytes(), np.uint32)[0]) & 1))
     return np.float32(best)
+
+
+# ---------------------------------------------------------------- staggered (MAC) grid
+# Section 3 applies the transfers on marker-and-cell grids: component alpha lives on
+# the faces at origin + (i + (1 - e_alpha)/2) dx, each with its own mass.  Every
+# component is a scalar transfer on its own shifted lattice.
+
+def face_shift(alpha: int) -> Tuple[Fr, Fr, Fr]:
+    return tuple(Fr(0) if a == alpha else Fr(1, 2) for a in range(3))
+
+
+def mac_p2g(xs, origin, inv_dx, coeffs, masses, n_modes) -> List[Dict[Node, Tuple[Fr, Fr]]]:
+    """Exact face mass and momentum of each component: [dict face -> (m, p)] * 3."""
+    out = []
+    for alpha in range(3):
+        grid: Dict[Node, Tuple[Fr, Fr]] = {}
+        for x, c, m in zip(xs, coeffs, masses):
+            ps = ParticleStencil(x, origin, inv_dx, face_shift(alpha))
+            for node, j in ps.nodes():
+                W = ps.weight(j)
+                mi, pi = grid.get(node, (Fr(0), Fr(0)))
+                val = sum((c[alpha][r] * ps.mode(r, j) for r in range(n_modes)), Fr(0))
+                grid[node] = (mi + m * W, pi + m * W * val)
+        out.append(grid)
+    return out
+
+
+def mac_grid_update(grids, dims, dt: Fr, gravity: Sequence[Fr], bc_layers: int):
+    """Exact v = p/m + dt g_alpha on faces with m > 0, then the walls of axis alpha."""
+    out = []
+    for alpha, grid in enumerate(grids):
+        vel: Dict[Node, Fr] = {}
+        for node, (m, p) in grid.items():
+            v = p / m + dt * gravity[alpha] if m > 0 else Fr(0)
+            if bc_layers > 0:
+                if node[alpha] <= 1 + bc_layers and v < 0:
+                    v = Fr(0)
+                if node[alpha] >= dims[alpha] - 1 - bc_layers and v > 0:
+                    v = Fr(0)
+            vel[node] = v
+        out.append(vel)
+    return out
+
+
+def mac_g2p(xs, origin, inv_dx, vels, n_modes):
+    """Per particle c[alpha][r]: the least-squares fit of component alpha over its own
+    face stencil (as g2p_particle, one component at a time)."""
+    res = []
+    for x in xs:
+        c = []
+        for alpha in range(3):
+            ps = ParticleStencil(x, origin, inv_dx, face_shift(alpha))
+            v3 = {node: [v, v, v] for node, v in vels[alpha].items()}
+            c.append(g2p_particle(ps, v3, n_modes)[alpha])
+        res.append(c)
+    return res

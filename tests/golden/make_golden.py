@@ -6,7 +6,7 @@ paper prints no worked numeric example, so these tiny hand-placed cases stand
 in for one; they cover the stencil offsets t = -1/2 (degenerate weights),
 t = 0 and t = 1/2 - 2^-20, unequal masses, and all four mode counts.
 
-Run:  python tests/golden/make_golden.py
+Run:  python tests/golden/make_golden.py   (writes tiny_exact.json and tiny_exact_mac.json)
 """
 from __future__ import annotations
 
@@ -23,6 +23,7 @@ sys.path.insert(0, ROOT)
 from oracle import exact  # noqa: E402
 
 OUT = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tiny_exact.json")
+OUT_MAC = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tiny_exact_mac.json")
 
 # grid: 4 cells per axis -> 8 nodes per axis, dx = 1/4, origin 0, domain [0.5, 1.5)
 NODES = (8, 8, 8)
@@ -104,6 +105,58 @@ def main():
     with open(OUT, "w") as f:
         json.dump(doc, f, indent=1)
     print("wrote", OUT)
+    write_mac(xs, masses, coeffs)
+
+
+def write_mac(xs, masses, coeffs):
+    """The same particles on a staggered (MAC) grid: component alpha on the faces at
+    origin + (i + (1 - e_alpha)/2) dx, each face with its own mass (section 3).  The
+    staggered offsets t = frac(u) - 1/2 include -1/2 (u integral) on some axes."""
+    cases = []
+    lo = [ORIGIN[a] + 2 * DX for a in range(3)]
+    for n_modes in (1, 4, 8, 27):
+        grids = exact.mac_p2g(xs, ORIGIN, INV_DX, coeffs, masses, n_modes)
+        vels = exact.mac_grid_update(grids, NODES, DT, GRAVITY, BC_LAYERS)
+        cs = exact.mac_g2p(xs, ORIGIN, INV_DX, vels, n_modes)
+        x_out = []
+        for x, c in zip(xs, cs):
+            row = []
+            for a in range(3):
+                xn = exact.float32_round(x[a] + DT * c[a][0])
+                top = np.float32(float(ORIGIN[a] + (NODES[a] - 2) * DX))
+                hi = np.nextafter(top, np.float32(-np.inf))
+                xn = min(max(xn, np.float32(float(lo[a]))), hi)
+                row.append(float(xn))
+            x_out.append(row)
+        comps = []
+        for alpha in range(3):
+            faces = sorted(grids[alpha].keys())
+            comps.append(dict(
+                faces=[list(f) for f in faces],
+                face_mass=[fstr(grids[alpha][f][0]) for f in faces],
+                face_mom=[fstr(grids[alpha][f][1]) for f in faces],
+                face_vel=[fstr(vels[alpha][f]) for f in faces],
+            ))
+        cases.append(dict(
+            n_modes=n_modes,
+            components=comps,
+            coeff=[[[fstr(v) for v in c[a]] for a in range(3)] for c in cs],
+            x_out=x_out,
+        ))
+    doc = dict(
+        description="Exact-rational P2G -> grid update -> G2P on a staggered (MAC) grid, "
+                    "6 hand-placed particles (written by tests/golden/make_golden.py from "
+                    "oracle/exact.py)",
+        nodes=list(NODES), dx=fstr(DX), inv_dx=fstr(INV_DX), origin=[fstr(o) for o in ORIGIN],
+        dt=fstr(DT), gravity=[fstr(g) for g in GRAVITY], bc_layers=BC_LAYERS,
+        x=[[fstr(v) for v in x] for x in xs],
+        mass=[fstr(m) for m in masses],
+        coeff_in=[[[fstr(v) for v in c[a]] for a in range(3)] for c in coeffs],
+        cases=cases,
+    )
+    with open(OUT_MAC, "w") as f:
+        json.dump(doc, f, indent=1)
+    print("wrote", OUT_MAC)
 
 
 if __name__ == "__main__":
