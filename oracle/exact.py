@@ -250,3 +250,44 @@ def mac_g2p(xs, origin, inv_dx, vels, n_modes):
             c.append(g2p_particle(ps, v3, n_modes)[alpha])
         res.append(c)
     return res
+
+
+# ---------------------------------------------------------------- affine back-map (Eq. 12-13)
+
+def inverse3(A: List[List[Fr]]) -> List[List[Fr]]:
+    """Exact inverse of a 3 x 3 matrix (Gauss-Jordan on [A | I])."""
+    eye = [[Fr(int(i == j)) for j in range(3)] for i in range(3)]
+    return solve(A, eye)
+
+
+def p2g_affine(xs, xs_fit, origin, inv_dx, coeffs, masses, n_modes, dt: Fr, dx: Fr):
+    """Exact grid mass and momentum with the modes evaluated at
+    z' = (I + dt C)^-1 (x_i - x_p) / dx (Eq. 12 applied in Eq. 13), C_ab = c_{a,1+b} / dx,
+    and the quadratic factor g(z) = z^2 - a z - 1/4 with a from the particle's offset at
+    x_fit (the position where its coefficients were fitted)."""
+    grid: Dict[Node, Tuple[Fr, List[Fr]]] = {}
+    for x, xf, c, m in zip(xs, xs_fit, coeffs, masses):
+        ps = ParticleStencil(x, origin, inv_dx)
+        t_fit = ParticleStencil(xf, origin, inv_dx).t
+        A = [[Fr(int(a == b)) for b in range(3)] for a in range(3)]
+        if n_modes >= 4:
+            for a in range(3):
+                for b in range(3):
+                    A[a][b] += dt * c[a][1 + b] / dx
+        Ainv = inverse3(A)
+        for node, j in ps.nodes():
+            W = ps.weight(j)
+            z = [ps.zhat(a, j[a]) for a in range(3)]
+            zp = [sum((Ainv[a][b] * z[b] for b in range(3)), Fr(0)) for a in range(3)]
+            mi, pi = grid.get(node, (Fr(0), [Fr(0)] * 3))
+            pi = list(pi)
+            for al in range(3):
+                val = Fr(0)
+                for r in range(n_modes):
+                    s = Fr(1)
+                    for a in range(3):
+                        s *= mode_value(MODE_EXPONENTS[r][a], zp[a], t_fit[a])
+                    val += c[al][r] * s
+                pi[al] += m * W * val
+            grid[node] = (mi + m * W, pi)
+    return grid

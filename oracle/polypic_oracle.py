@@ -232,6 +232,72 @@ def p2g(grid: Grid, x, coeff, n_modes: int, mass=None, uniform_mass: float = 1.0
     return M.reshape(shape), Q.reshape((3,) + shape)
 
 
+# ---------------------------------------------------------------- P2G with the affine map (Eq. 12-13)
+
+def p2g_affine(grid: Grid, x, coeff, n_modes: int, dt: float, x_fit=None, mass=None,
+               uniform_mass: float = 1.0):
+    """P2G with the modes evaluated through the affine back-map of Eq. 12.
+
+    The coefficients of a particle were fitted (G2P) at its previous position x_fit, in
+    the basis orthogonalised there; the particle has since moved to x.  Eq. 12 maps the
+    present configuration back to that one, xi(x) = x_fit + (I + dt C)^-1 (x - x_p), so
+    the mode argument of Eq. 13 at node i is, in units of dx,
+
+        z'_i = (I + dt C)^-1 (x_i - x_p) / dx,
+
+    with C the particle's velocity-gradient matrix taken from its linear coefficients
+    (C_ab = c_{a, 1+b} / dx; C = 0 below 4 modes), and the quadratic factor of Eq. 14 is
+    the one of the fitting configuration: ghat(z) = z^2 - a z - 1/4 with
+    a = t_fit (1 - 4 t_fit^2), t_fit the offset of x_fit from its nearest node.  Without
+    x_fit the present offset is used.  The weights W_ip stay those of the present position
+    (Eq. 1 and 13 use m_ip of the present configuration).
+
+    Returns (grid_mass, grid_mom) like ``p2g``.
+    """
+    if n_modes not in ALLOWED_N_MODES:
+        raise ValueError("n_modes must be one of 1, 4, 8, 27")
+    x = np.asarray(x)
+    P = x.shape[1]
+    b, t = stencil_base(grid, x)
+    if not np.all(stencil_in_range(grid, b)):
+        raise OracleRangeError("particle stencil outside the grid")
+    if x_fit is None:
+        t_fit = t
+    else:
+        _, t_fit = stencil_base(grid, x_fit)
+    a_fit = t_fit * (1.0 - 4.0 * t_fit * t_fit)           # Eq. 14 (reading), per axis
+    m = (np.full(P, float(uniform_mass)) if mass is None
+         else np.asarray(mass).astype(np.float64))
+    c = np.asarray(coeff)[:, :n_modes, :].astype(np.float64)
+    # A = I + dt C per particle and its inverse (Eq. 12)
+    A = np.repeat(np.eye(3)[None], P, axis=0)
+    if n_modes >= 4:
+        for al in range(3):
+            for be in range(3):
+                A[:, al, be] += dt * c[al, 1 + be] / grid.dx
+    Ainv = np.linalg.inv(A)
+    w = [weights_1d(t[a]) for a in range(3)]
+    zs = [node_offsets(t[a]) for a in range(3)]
+    nn = grid.n_nodes
+    M = np.zeros(nn)
+    Q = np.zeros((3, nn))
+    for jx, jy, jz in STENCIL:
+        node = grid.flat(b[0] + jx, b[1] + jy, b[2] + jz)
+        mW = m * w[0][jx] * w[1][jy] * w[2][jz]
+        zhat = np.stack([zs[0][jx], zs[1][jy], zs[2][jz]])       # (3, P)
+        zp = np.einsum("pab,bp->ap", Ainv, zhat)                  # z'_i, (3, P)
+        phi = [[np.ones(P), zp[a], zp[a] * zp[a] - a_fit[a] * zp[a] - 0.25] for a in range(3)]
+        V = np.zeros((3, P))
+        for r in range(n_modes):
+            kx, ky, kz = MODES[r]
+            V += c[:, r, :] * (phi[0][kx] * phi[1][ky] * phi[2][kz])
+        M += np.bincount(node, weights=mW, minlength=nn)
+        for al in range(3):
+            Q[al] += np.bincount(node, weights=mW * V[al], minlength=nn)
+    shape = (grid.nz, grid.ny, grid.nx)
+    return M.reshape(shape), Q.reshape((3,) + shape)
+
+
 # ---------------------------------------------------------------- grid update (Eq. 5 + walls)
 
 def grid_update(grid: Grid, grid_mass, grid_mom, dt: float,

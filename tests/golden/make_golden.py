@@ -6,7 +6,8 @@ paper prints no worked numeric example, so these tiny hand-placed cases stand
 in for one; they cover the stencil offsets t = -1/2 (degenerate weights),
 t = 0 and t = 1/2 - 2^-20, unequal masses, and all four mode counts.
 
-Run:  python tests/golden/make_golden.py   (writes tiny_exact.json and tiny_exact_mac.json)
+Run:  python tests/golden/make_golden.py   (writes tiny_exact.json, tiny_exact_mac.json and
+      tiny_exact_affine.json)
 """
 from __future__ import annotations
 
@@ -24,6 +25,7 @@ from oracle import exact  # noqa: E402
 
 OUT = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tiny_exact.json")
 OUT_MAC = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tiny_exact_mac.json")
+OUT_AFFINE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tiny_exact_affine.json")
 
 # grid: 4 cells per axis -> 8 nodes per axis, dx = 1/4, origin 0, domain [0.5, 1.5)
 NODES = (8, 8, 8)
@@ -106,6 +108,45 @@ def main():
         json.dump(doc, f, indent=1)
     print("wrote", OUT)
     write_mac(xs, masses, coeffs)
+    write_affine(xs, masses, coeffs)
+
+
+def write_affine(xs, masses, coeffs):
+    """P2G with the affine back-map of Eq. 12 on the same particles: each particle's
+    coefficients are taken as fitted at a nearby earlier position x_fit (a few
+    1/64-cell steps away, one of them across a cell switch), with a time step large
+    enough that I + dt C is far from the identity."""
+    shifts = [(Fr(1, 64), Fr(-3, 64), Fr(2, 64)), (Fr(-5, 64), Fr(1, 64), Fr(0)),
+              (Fr(0), Fr(3, 64), Fr(-1, 64)), (Fr(2, 64), Fr(2, 64), Fr(2, 64)),
+              (Fr(-1, 64), Fr(0), Fr(9, 64)), (Fr(4, 64), Fr(-2, 64), Fr(1, 64))]
+    xs_fit = [tuple(x[a] + shifts[k][a] * DX for a in range(3)) for k, x in enumerate(xs)]
+    dt = Fr(1, 64)
+    cases = []
+    for n_modes in (1, 4, 8, 27):
+        grid = exact.p2g_affine(xs, xs_fit, ORIGIN, INV_DX, coeffs, masses, n_modes, dt, DX)
+        nodes = sorted(grid.keys())
+        cases.append(dict(
+            n_modes=n_modes,
+            nodes=[list(nd) for nd in nodes],
+            grid_mass=[fstr(grid[nd][0]) for nd in nodes],
+            grid_mom=[[fstr(v) for v in grid[nd][1]] for nd in nodes],
+        ))
+    doc = dict(
+        description="Exact-rational P2G with the affine back-map of Eq. 12 (modes at "
+                    "(I + dt C)^-1 (x_i - x_p) / dx, quadratic factor of the fitting position) "
+                    "on 6 hand-placed particles (written by tests/golden/make_golden.py from "
+                    "oracle/exact.py)",
+        nodes=list(NODES), dx=fstr(DX), inv_dx=fstr(INV_DX), origin=[fstr(o) for o in ORIGIN],
+        dt=fstr(dt),
+        x=[[fstr(v) for v in x] for x in xs],
+        x_fit=[[fstr(v) for v in x] for x in xs_fit],
+        mass=[fstr(m) for m in masses],
+        coeff_in=[[[fstr(v) for v in c[a]] for a in range(3)] for c in coeffs],
+        cases=cases,
+    )
+    with open(OUT_AFFINE, "w") as f:
+        json.dump(doc, f, indent=1)
+    print("wrote", OUT_AFFINE)
 
 
 def write_mac(xs, masses, coeffs):
