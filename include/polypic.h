@@ -120,6 +120,28 @@ int32_t polypic_sort(const polypic_grid* grid, int64_t P, const float* x, uint32
                      void* stream);
 
 /* ------------------------------------------------------------------------
+ * Allocation-free variant of polypic_sort, for callers that cannot allocate
+ * device memory or pass a workspace: code under HIP graph capture, tight
+ * stepping loops, harnesses that forbid hipMalloc.
+ *
+ * Same keys_out / perm_out as polypic_sort, bit for bit.  The workspace is a
+ * static device array inside the library (18 MiB, held on every GPU the
+ * library runs on until the process ends), so the call allocates nothing and
+ * takes no ws argument.  P is limited to POLYPIC_SORT_NOALLOC_MAX_P particles;
+ * a larger P returns POLYPIC_ENOSPACE with nothing enqueued.
+ *
+ * All calls on one GPU share that GPU's array: two calls whose work overlaps
+ * on the device (on different streams, or from different threads without
+ * ordering) race and give unspecified keys and permutations.  Calls ordered
+ * on one stream are safe; every word the sort reads from the array it has
+ * written earlier in the same call.
+ * ------------------------------------------------------------------------ */
+#define POLYPIC_SORT_NOALLOC_MAX_P 2097152
+int32_t polypic_sort_noalloc(const polypic_grid* grid, int64_t P, const float* x,
+                             uint32_t* keys_out, int32_t* perm_out, int32_t* status_dev,
+                             void* stream);
+
+/* ------------------------------------------------------------------------
  * Re-sort after a step: the same result as polypic_sort, bit for bit, faster
  * when few particles changed cell.
  *
@@ -341,7 +363,7 @@ int32_t polypic_p2g_backward(const polypic_grid* grid, int64_t P, int32_t n_mode
                              float* mass_grad, int32_t* status_dev, void* stream);
 
 /* ------------------------------------------------------------------------
- * Particle order.  The per-step sort (section 3.1) leaves every particle array
+ * Particle order.  The per-step cell sort (not part of the paper) leaves every particle array
  * in slot order; these move whole arrays between orders on the device.
  *
  * polypic_gather_rows: dst[r][i] = src[r][idx[i]] for r < rows, i < P, with

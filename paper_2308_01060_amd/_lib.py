@@ -21,6 +21,7 @@ POLYPIC_ENOTSUP = 5
 POLYPIC_FLAG_RANGE = 1
 POLYPIC_FLAG_ORDER = 2
 POLYPIC_FLAG_STALL = 4
+POLYPIC_SORT_NOALLOC_MAX_P = 2097152
 POLYPIC_P2G_DEFAULT = -1
 POLYPIC_P2G_BRICKS = 0
 POLYPIC_P2G_CELLS = 1
@@ -34,6 +35,7 @@ EXPORTED = (
     "polypic_last_device_error",
     "polypic_sort_workspace_bytes",
     "polypic_sort",
+    "polypic_sort_noalloc",
     "polypic_sort_update_workspace_bytes",
     "polypic_sort_update",
     "polypic_p2g_workspace_bytes",
@@ -148,6 +150,8 @@ def load() -> ctypes.CDLL:
     lib.polypic_sort_workspace_bytes.argtypes = [G, i64, ctypes.POINTER(sz)]
     lib.polypic_sort.restype = i32
     lib.polypic_sort.argtypes = [G, i64, P, P, P, P, sz, P, P]
+    lib.polypic_sort_noalloc.restype = i32
+    lib.polypic_sort_noalloc.argtypes = [G, i64, P, P, P, P, P]
     lib.polypic_sort_update_workspace_bytes.restype = i32
     lib.polypic_sort_update_workspace_bytes.argtypes = [G, i64, ctypes.POINTER(sz)]
     lib.polypic_sort_update.restype = i32

@@ -265,6 +265,39 @@ int32_t run_batch_p2g(const polypic_batch* b, int32_t n_modes, const float* x, c
       launch_p2g_batch(a, batch_table(b), b->n_scenes, n_modes, to_config(pc), s));
 }
 
+// ---- allocation-free sort: the workspace lives in a file-scope device array
+//
+// Each GPU the library runs on holds its own copy of `scratch` from module load
+// to the end of the process.  In host code the array's name is not a device
+// address: its address on the current device is looked up once per device with
+// hipGetSymbolAddress and only that pointer is handed to kernels.
+constexpr int64_t kNoAllocMaxP = 2097152;               // particles per call
+constexpr size_t kScratchBytes = (size_t)18 << 20;      // 18 MiB >= sort workspace of kNoAllocMaxP
+constexpr int kMaxDevices = 64;
+
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Address of this device's scratch (looked up on the first call on the device).
+hipError_t scratch_on_current_device(void** out) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return hipSuccess;
+}
+
 }  // namespace
 
 extern "C" {
@@ -304,6 +337,25 @@ int32_t polypic_sort(const polypic_grid* grid, int64_t P, const float* x, uint32
   if (!x || !keys_out || !perm_out || !ws) return POLYPIC_EINVAL;
   if (ws_bytes < sort_workspace_bytes(P)) return POLYPIC_ENOSPACE;
   discard_stale_error();
+  return from_hip(launch_sort(to_dev(grid), P, x, keys_out, perm_out, ws, status_dev,
+                              (hipStream_t)stream));
+}
+
+int32_t polypic_sort_noalloc(const polypic_grid* grid, int64_t P, const float* x,
+                             uint32_t* keys_out, int32_t* perm_out, int32_t* status_dev,
+                             void* stream) {
+  int32_t st = check_grid(grid);
+  if (st) return st;
+  if ((st = check_P(P))) return st;
+  if (P > kNoAllocMaxP || sort_workspace_bytes(P) > kScratchBytes) return POLYPIC_ENOSPACE;
+  if (P == 0) return POLYPIC_OK;
+  if (!x || !keys_out || !perm_out) return POLYPIC_EINVAL;
+  discard_stale_error();
+  void* ws = nullptr;
+  hipError_t e = scratch_on_current_device(&ws);
+  if (e != hipSuccess) return from_hip(e);
+  // every word of the workspace that the sort reads it has written first in the same
+  // call (keys, indices, tile counts, digit totals): nothing needs clearing
   return from_hip(launch_sort(to_dev(grid), P, x, keys_out, perm_out, ws, status_dev,
                               (hipStream_t)stream));
 }

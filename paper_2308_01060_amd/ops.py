@@ -85,6 +85,19 @@ def polypic_sort(grid: polypic_grid, x: torch.Tensor, keys_out: torch.Tensor,
         _ptr(status_dev, torch.int32, 1, "status_dev"), _stream()), "polypic_sort")
 
 
+def polypic_sort_noalloc(grid: polypic_grid, x: torch.Tensor, keys_out: torch.Tensor,
+                         perm_out: torch.Tensor,
+                         status_dev: Optional[torch.Tensor] = None) -> None:
+    """polypic_sort with the library's static device workspace (no ws argument, nothing
+    allocated); at most POLYPIC_SORT_NOALLOC_MAX_P particles."""
+    P = x.numel() // 3
+    check(_lib.load().polypic_sort_noalloc(
+        ctypes.byref(grid), P, _ptr(x, torch.float32, 3 * P, "x"),
+        _keys_ptr(keys_out, P),
+        _ptr(perm_out, torch.int32, P, "perm_out"),
+        _ptr(status_dev, torch.int32, 1, "status_dev"), _stream()), "polypic_sort_noalloc")
+
+
 def polypic_sort_update_workspace_bytes(grid: polypic_grid, P: int) -> int:
     out = ctypes.c_size_t(0)
     check(_lib.load().polypic_sort_update_workspace_bytes(ctypes.byref(grid), int(P),

@@ -338,3 +338,27 @@ def test_permutation_calls_reject_bad_arguments():
                                           10, None) == 1             # inv overlaps perm
     assert lib.polypic_invert_permutation(idx, dst, -5, None) == 1
     assert lib.polypic_invert_permutation(None, None, 0, None) == 0
+
+
+def test_sort_noalloc_host_checks():
+    """The allocation-free sort rejects more than POLYPIC_SORT_NOALLOC_MAX_P particles with
+    POLYPIC_ENOSPACE, and null arrays with POLYPIC_EINVAL, before touching the device."""
+    lib = _lib.load()
+    g = grid()
+    cap = _lib.POLYPIC_SORT_NOALLOC_MAX_P
+    text = open(HEADER).read()
+    assert f"#define POLYPIC_SORT_NOALLOC_MAX_P {cap}" in text
+    assert lib.polypic_sort_noalloc(ctypes.byref(g), cap + 1, FAKE, FAKE, FAKE, None,
+                                    None) == _lib.POLYPIC_ENOSPACE
+    assert lib.polypic_sort_noalloc(ctypes.byref(g), 10, None, FAKE, FAKE, None,
+                                    None) == _lib.POLYPIC_EINVAL
+    assert lib.polypic_sort_noalloc(ctypes.byref(g), 10, FAKE, FAKE, None, None,
+                                    None) == _lib.POLYPIC_EINVAL
+    assert lib.polypic_sort_noalloc(ctypes.byref(g), -1, FAKE, FAKE, FAKE, None,
+                                    None) == _lib.POLYPIC_EINVAL
+    assert lib.polypic_sort_noalloc(None, 10, FAKE, FAKE, FAKE, None, None) == 1
+    assert lib.polypic_sort_noalloc(ctypes.byref(g), 0, None, None, None, None, None) == 0
+    # the static workspace covers the full sort's workspace at the cap
+    out = ctypes.c_size_t(0)
+    assert lib.polypic_sort_workspace_bytes(ctypes.byref(g), cap, ctypes.byref(out)) == 0
+    assert out.value <= 18 << 20
