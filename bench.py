@@ -63,6 +63,12 @@ def g2p2g_bytes_per_particle(n_modes: int) -> int:
     return 12 + 4 + 12 + 12 * n_modes
 
 
+#   a material-point set also reads and writes its deformation gradient (2 x 36 B) and its
+#   mass (2 x 4 B; in place of the 4 B of the permutation it still reads)
+def g2p2g_bytes_per_point_with_f(n_modes: int) -> int:
+    return g2p2g_bytes_per_particle(n_modes) + 2 * 36 + 2 * 4
+
+
 KERNEL_SOURCES = {
     "p2g": "paper_2308_01060_amd/csrc/polypic_p2g.hip",
     "g2p": "paper_2308_01060_amd/csrc/polypic_g2p.hip",
@@ -131,6 +137,12 @@ def parse_args():
     ap.add_argument("--batch-steps", type=int, default=10, help="steps in the batched timing")
     ap.add_argument("--adjoint-steps", type=int, default=10,
                     help="differentiable steps in the bwd/fwd timing")
+    ap.add_argument("--no-moving", action="store_true",
+                    help="skip the dam break with moving state")
+    ap.add_argument("--no-liquid-fabric", action="store_true",
+                    help="skip the 256^3 liquid + fabric workload")
+    ap.add_argument("--no-paper-scale", action="store_true",
+                    help="skip the paper-size dam break at 8 modes")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run only a plain device copy of known size (counter calibration)")
     return ap.parse_args()
@@ -390,6 +402,132 @@ def batch_timing(pp, torch, W, n_modes: int, steps: int, warmup: int):
     }
 
 
+def _set_timing(pp, torch, ps, steps: int, warmup: int, bpp: int, workload: str):
+    """Warm up, autotune and time one fused ParticleSet; rate, phases and the roofline of its
+    G2P2G call (bpp algorithmic bytes per particle over the call's mean event time)."""
+    for _ in range(warmup):
+        ps.step()
+    choice = ps.autotune()
+    torch.cuda.synchronize()
+    wall, phase = time_steps(ps, steps, torch)
+    if ps.status_flags() != 0:
+        raise RuntimeError(f"device status flags {ps.status_flags()} in {workload}")
+    achieved = bpp * ps.P / (phase["g2p2g"] * 1e-3) / 1e9
+    return {
+        "workload": workload,
+        "particles": ps.P,
+        "n_modes": ps.n_modes,
+        "steps": steps,
+        "ms_per_step": wall * 1e3 / steps,
+        "transfers_per_s": ps.P * steps / wall,
+        "p2g_g2p_transfers_per_s": ps.P / (transfer_ms(phase) * 1e-3),
+        "phase_ms": {k: round(v, 4) for k, v in phase.items()},
+        "p2g_config": {"path": "cells" if choice.path == 1 else "bricks",
+                       "block": choice.block, "schedule": choice.schedule},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": measured_traffic("g2p2g", workload), "kernel": "g2p2g",
+                     "bytes_per_particle": bpp},
+    }
+
+
+def moving_timing(pp, torch, W, cells: int, n_modes: int, steps: int, warmup: int):
+    """The dam-break geometry with moving state (c0 ~ N(0,1), higher modes ~ N(0,0.1)):
+    thousands of particles change cell per step, against tens at rest, and every momentum
+    channel is non-zero."""
+    import numpy as np
+
+    s = W.config1_moving(0, n=cells)
+    g = pp.grid_from_spec(s.grid)
+    ps = pp.ParticleSet(g, n_modes, torch.from_numpy(s.x).cuda(),
+                        torch.from_numpy(np.ascontiguousarray(s.coeff[:, :n_modes])).cuda(),
+                        dt=s.dt, gravity=s.gravity, bc_layers=s.bc_layers, track_order=False)
+    del s
+    out = _set_timing(pp, torch, ps, steps, warmup, g2p2g_bytes_per_particle(n_modes),
+                      f"dambreak_moving_{cells}cube_{ps.P}")
+    out["data"] = "synthetic (seeded jittered dam-break block, workloads.config1_moving)"
+    return out
+
+
+def liquid_fabric_timing(pp, torch, W, n_modes: int, steps: int, warmup: int):
+    """The liquid + fabric workload: a falling block of 16,777,216 fluid particles (128 x 64
+    x 128 cells at 16 per cell) and a 1000 x 1000 fabric sheet of 1,000,000 material
+    points (per-point mass, deformation gradient F), each set on its own 256^3-cell grid
+    (260^3 nodes), both at n_modes and stepped fused.  A step is one step of each set.
+
+    Fluid positions come from workloads.config2_fluid(0); its coefficients (mode 0 ~ N(0,1),
+    higher modes ~ N(0,0.1)) are drawn on the device from a seeded torch generator.  The
+    fabric set is workloads.config2_fabric(0)."""
+    import numpy as np
+
+    sf = W.config2_fluid(0, coefficients=False)
+    gf = pp.grid_from_spec(sf.grid)
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(30_000)
+    cf = torch.randn(3, n_modes, sf.P, generator=gen, device="cuda")
+    cf[:, 1:] *= 0.1
+    fluid = pp.ParticleSet(gf, n_modes, torch.from_numpy(sf.x).cuda(), cf, dt=sf.dt,
+                           gravity=sf.gravity, bc_layers=sf.bc_layers, track_order=False)
+    del cf
+    fl = _set_timing(pp, torch, fluid, steps, warmup, g2p2g_bytes_per_particle(n_modes),
+                     f"fluid_256cube_{sf.P}")
+    del fluid
+    sb = W.config2_fabric(0)
+    gb = pp.grid_from_spec(sb.grid)
+    fabric = pp.ParticleSet(gb, n_modes, torch.from_numpy(sb.x).cuda(),
+                            torch.from_numpy(np.ascontiguousarray(sb.coeff[:, :n_modes])).cuda(),
+                            mass=torch.from_numpy(sb.mass).cuda(), F=torch.from_numpy(sb.F).cuda(),
+                            dt=sb.dt, gravity=sb.gravity, bc_layers=sb.bc_layers,
+                            track_order=False)
+    fb = _set_timing(pp, torch, fabric, steps, warmup, g2p2g_bytes_per_point_with_f(n_modes),
+                     f"fabric_256cube_{sb.P}")
+    del fabric
+    P = sf.P + sb.P
+    ms = fl["ms_per_step"] + fb["ms_per_step"]
+    return {
+        "workload": f"liquid_fabric_256cube_{sf.P}_{sb.P}",
+        "particles": P,
+        "n_modes": n_modes,
+        "ms_per_step": ms,
+        "transfers_per_s": P / (ms * 1e-3),
+        "fluid": fl,
+        "fabric": fb,
+        "note": "one fused step of each set on its own 260^3-node grid (sort, grid update, "
+                "G2P2G); fabric bytes add F read and written (72 B) and the mass read and "
+                "written (8 B) per point",
+    }
+
+
+def paper_scale_timing(pp, torch, W, steps: int, warmup: int):
+    """The paper's smallest fluid-only scene at its own size, mode count and time step
+    (section 4, Table 2: about 311 thousand particles, 8 modes, dt = 2e-4): a
+    36 x 36 x 30-cell block at 8 per cell (311,040 particles) on a 64^3-cell grid, at rest,
+    at 8 modes (PolyPIC) and at 4 (APIC).  The paper's figures are whole steps of its
+    liquid solver on one CPU; they are quoted beside the GPU transfer times as context."""
+    import numpy as np
+
+    s = W.paper_dambreak_small(0)
+    g = pp.grid_from_spec(s.grid)
+    out = {"workload": s.name, "particles": s.P, "dt": s.dt}
+    for nm in (8, 4):
+        ps = pp.ParticleSet(g, nm, torch.from_numpy(s.x).cuda(),
+                            torch.from_numpy(np.ascontiguousarray(s.coeff[:, :nm])).cuda(),
+                            dt=s.dt, gravity=s.gravity, bc_layers=s.bc_layers,
+                            track_order=False)
+        r = _set_timing(pp, torch, ps, steps, warmup, g2p2g_bytes_per_particle(nm), s.name)
+        del ps
+        out[f"modes_{nm}"] = {k: r[k] for k in ("ms_per_step", "transfers_per_s",
+                                                "p2g_g2p_transfers_per_s", "phase_ms")}
+    out["paper_table2_context"] = {
+        "hardware": "Intel i9-12900K CPU (the paper's runs)",
+        "what": "seconds per whole simulation step of the paper's liquid solver, transfers "
+                "and everything else; not a transfer-only figure",
+        "polypic_8_modes_s_per_step": 1.172, "apic_s_per_step": 0.510,
+        "particles": {"polypic": 310839, "apic": 310929},
+    }
+    return out
+
+
 # Workers of the all-cores oracle run: the state they need is set before the pool
 # forks, so nothing large is pickled on the way in.
 _ORACLE = {}
@@ -408,6 +546,22 @@ def _oracle_g2p_part(k):
     lo, hi = st["bounds"][k], st["bounds"][k + 1]
     O.g2p(st["og"], st["v"], st["x"][:, lo:hi], st["n_modes"], st["dt"])
     return hi - lo
+
+
+def _cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _config0_scene():
+    import workloads as W
+    return W.config0(0)
 
 
 def _one_thread():
@@ -454,6 +608,15 @@ def cpu_baseline(scene, n_modes: int, sample: int):
     tn = time.perf_counter() - t0
     _ORACLE.clear()
     assert done == S
+    # configs[0] in full (32,768 particles), one core
+    s0 = _config0_scene()
+    og0 = O.grid_from_spec(s0.grid)
+    with threadpool_limits(1):
+        t0 = time.perf_counter()
+        M0, Q0 = O.p2g(og0, s0.x, s0.coeff, n_modes)
+        v0 = O.grid_update(og0, M0, Q0, s0.dt, s0.gravity, s0.bc_layers)
+        O.g2p(og0, v0, s0.x, n_modes, s0.dt)
+        t_c0 = time.perf_counter() - t0
     sample_txt = (f"{S} particles (the first {S // (scene.P // (scene.grid.cells[2] // 2))} "
                   f"z-layers of cells of the dam-break block), one P2G + grid update + G2P at "
                   f"{n_modes} modes in float64 numpy")
@@ -463,6 +626,16 @@ def cpu_baseline(scene, n_modes: int, sample: int):
         "cores": 1,
         "kind": "oracle",
         "sample": f"{sample_txt}, {t1:.1f} s on one core",
+        "cpu_model": _cpu_model(),
+        "host_cpus": {"os_cpu_count": os.cpu_count(),
+                      "affinity": len(os.sched_getaffinity(0)),
+                      "share_used": n,
+                      "note": "the all-cores run uses at most 16 workers: one GPU's share of "
+                              "the host on this machine type"},
+        "config0_full": {"value": s0.P / t_c0, "unit": UNIT, "cores": 1, "kind": "oracle",
+                         "sample": f"all {s0.P} particles of the 32^3-cell parity case, one "
+                                   f"P2G + grid update + G2P at {n_modes} modes, "
+                                   f"{t_c0:.2f} s"},
         "all_cores": {"value": S / tn, "unit": UNIT, "cores": n, "kind": "oracle",
                       "sample": f"{sample_txt} over {n} particle chunks in {n} forked worker "
                                 f"processes (grids summed between P2G and the update), "
@@ -579,9 +752,30 @@ def main():
                 "traffic": measured_traffic(dom, workload), "kernel": dom,
                 "bytes_per_particle": bpp, "note": note}
 
+    moving = None
+    if not args.no_moving:
+        moving = moving_timing(pp, torch, W, args.cells, n_modes, args.steps, args.warmup)
+
+    liquid_fabric = None
+    if not args.no_liquid_fabric:
+        liquid_fabric = liquid_fabric_timing(pp, torch, W, n_modes, args.steps, args.warmup)
+
+    paper_scale = None
+    if not args.no_paper_scale:
+        paper_scale = paper_scale_timing(pp, torch, W, args.steps, args.warmup)
+
     adj = None
     if not args.no_adjoint:
         adj = adjoint_timing(pp, torch, W, args.cells, n_modes, args.adjoint_steps)
+        if moving is not None:
+            # one backward step (the three adjoint calls, event times) against one forward
+            # step of the same moving state (sort, grid update, G2P2G, event times): the
+            # ratio long rollouts converge to, without the forward's fixed costs
+            bwd_step = sum(adj["bwd_step_phase_ms"].values())
+            fwd_step = sum(moving["phase_ms"].values())
+            adj["per_step"] = {"bwd_step_ms": round(bwd_step, 4),
+                               "fwd_step_ms": round(fwd_step, 4),
+                               "bwd_fwd_ratio": round(bwd_step / fwd_step, 3)}
 
     batch = None
     if not args.no_batch:
@@ -613,7 +807,12 @@ def main():
         "sort": {"timed": "polypic_sort_update (exact re-sort from the previous step's keys)",
                  "full_sort_ms": round(float(np.median(full_sort_ms)), 4)},
         "apic_4mode": apic,
+        "moving": moving,
+        "liquid_fabric": liquid_fabric,
+        "paper_scale": paper_scale,
         "bwd_fwd_ratio": None if adj is None else round(adj["bwd_fwd_ratio"], 3),
+        "bwd_fwd_ratio_per_step": (None if adj is None or "per_step" not in adj
+                                   else adj["per_step"]["bwd_fwd_ratio"]),
         "adjoint": adj,
         "batched": batch,
         "roofline": roofline,
