@@ -391,6 +391,67 @@ def g2p(grid: Grid, grid_vel, x, n_modes: int, dt: float = 0.0, F=None):
     return c_out, x_out, F_out
 
 
+# ---------------------------------------------------------------- shared-grid mixture (section 3.4)
+
+FLUID, SOLID = 0, 1
+
+
+def _phase_masses(phase, mass_f, mass_s):
+    """Per-particle transfer mass: m_f for a fluid particle (Eq. 15), m_s + m_f for a solid
+    particle with its absorbed fluid (Eq. 18)."""
+    phase = np.asarray(phase)
+    if np.any((phase != FLUID) & (phase != SOLID)):
+        raise ValueError("phase must be 0 (fluid) or 1 (solid)")
+    mf = np.asarray(mass_f).astype(np.float64)
+    ms = np.zeros_like(mf) if mass_s is None else np.asarray(mass_s).astype(np.float64)
+    return phase, np.where(phase == SOLID, ms + mf, mf)
+
+
+def mixture_p2g(grid: Grid, x, coeff, n_modes: int, phase, mass_f, mass_s=None):
+    """Liquid and fabric particles on one grid (section 3.4): each node carries a fluid
+    set of channels (m_f, m_f v_f; Eq. 15-16, fluid particles only, mass m_f) and a solid
+    set (mixture mass and momentum; Eq. 18-19, solid particles only, mass m_s + m_f with
+    the absorbed fluid).  Returns (grid_mass (2, nz, ny, nx), grid_mom (2, 3, nz, ny, nx)),
+    index 0 the fluid set and 1 the solid one."""
+    phase, m = _phase_masses(phase, mass_f, mass_s)
+    x = np.asarray(x)
+    c = np.asarray(coeff)
+    M = np.zeros((2, grid.nz, grid.ny, grid.nx))
+    Q = np.zeros((2, 3, grid.nz, grid.ny, grid.nx))
+    for k in (FLUID, SOLID):
+        sel = np.flatnonzero(phase == k)
+        M[k], Q[k] = p2g(grid, x[:, sel], c[:, :, sel], n_modes, m[sel])
+    return M, Q
+
+
+def mixture_grid_update(grid: Grid, grid_mass, grid_mom, dt: float,
+                        gravity: Sequence[float] = (0.0, -9.8, 0.0), bc_layers: int = 1):
+    """v_f = (m_f v_f) / m_f (Eq. 17) and v_s = (m_s v_s) / (m_s + m_f) (Eq. 20, the
+    grid-summed mixture mass), each with the explicit update of ``grid_update``."""
+    return np.stack([grid_update(grid, grid_mass[k], grid_mom[k], dt, gravity, bc_layers)
+                     for k in (FLUID, SOLID)])
+
+
+def mixture_g2p(grid: Grid, grid_vel, x, phase, n_modes: int, dt: float = 0.0, F=None):
+    """G2P of each particle from its own phase's velocity field (grid_vel (2, 3, ...)),
+    otherwise as ``g2p``; outputs in input order."""
+    phase = np.asarray(phase)
+    x = np.asarray(x, np.float32)
+    P = x.shape[1]
+    c_out = np.zeros((3, n_modes, P))
+    x_out = np.zeros((3, P), np.float32)
+    F_out = None if F is None else np.zeros((9, P))
+    for k in (FLUID, SOLID):
+        sel = np.flatnonzero(phase == k)
+        Fk = None if F is None else np.asarray(F)[:, sel]
+        ck, xk, fk = g2p(grid, grid_vel[k], x[:, sel], n_modes, dt, Fk)
+        c_out[:, :, sel] = ck
+        x_out[:, sel] = xk
+        if F is not None:
+            F_out[:, sel] = fk
+    return c_out, x_out, F_out
+
+
 # ---------------------------------------------------------------- one step
 
 def step(grid: Grid, x, coeff, n_modes: int, dt: float, gravity=(0.0, -9.8, 0.0),

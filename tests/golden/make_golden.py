@@ -6,8 +6,8 @@ paper prints no worked numeric example, so these tiny hand-placed cases stand
 in for one; they cover the stencil offsets t = -1/2 (degenerate weights),
 t = 0 and t = 1/2 - 2^-20, unequal masses, and all four mode counts.
 
-Run:  python tests/golden/make_golden.py   (writes tiny_exact.json, tiny_exact_mac.json and
-      tiny_exact_affine.json)
+Run:  python tests/golden/make_golden.py   (writes tiny_exact.json, tiny_exact_mac.json,
+      tiny_exact_affine.json and tiny_exact_mixture.json)
 """
 from __future__ import annotations
 
@@ -26,6 +26,7 @@ from oracle import exact  # noqa: E402
 OUT = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tiny_exact.json")
 OUT_MAC = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tiny_exact_mac.json")
 OUT_AFFINE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tiny_exact_affine.json")
+OUT_MIXTURE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tiny_exact_mixture.json")
 
 # grid: 4 cells per axis -> 8 nodes per axis, dx = 1/4, origin 0, domain [0.5, 1.5)
 NODES = (8, 8, 8)
@@ -109,6 +110,59 @@ def main():
     print("wrote", OUT)
     write_mac(xs, masses, coeffs)
     write_affine(xs, masses, coeffs)
+    write_mixture(xs, masses, coeffs)
+
+
+def write_mixture(xs, masses, coeffs):
+    """Liquid and fabric particles on one grid (section 3.4): particles 1, 3 and 4 are
+    solid (fabric) with solid mass m_s and absorbed fluid m_f, the others fluid with mass
+    m_f.  The fluid channels get the fluid particles at m_f (Eq. 15-16), the solid
+    channels the solid ones at m_s + m_f (Eq. 18-19); each phase's velocity (Eq. 17, 20)
+    is fitted back only by its own particles."""
+    phase = [0, 1, 0, 1, 1, 0]
+    mass_f = [Fr(3, 4), Fr(1, 4), Fr(5, 4), Fr(0), Fr(3, 8), Fr(1)]
+    mass_s = masses
+    cases = []
+    for n_modes in (1, 4, 8, 27):
+        per = []
+        for k in (0, 1):
+            sel = [p for p in range(len(xs)) if phase[p] == k]
+            m = [mass_f[p] if k == 0 else mass_s[p] + mass_f[p] for p in sel]
+            grid = exact.p2g([xs[p] for p in sel], ORIGIN, INV_DX, [coeffs[p] for p in sel], m,
+                             n_modes)
+            vel = exact.grid_update(grid, NODES, DT, GRAVITY, BC_LAYERS)
+            per.append((grid, vel))
+        cs = [exact.g2p([x], ORIGIN, INV_DX, per[phase[p]][1], n_modes)[0]
+              for p, x in enumerate(xs)]
+        phases = []
+        for k in (0, 1):
+            grid, vel = per[k]
+            nodes = sorted(grid.keys())
+            phases.append(dict(
+                nodes=[list(nd) for nd in nodes],
+                grid_mass=[fstr(grid[nd][0]) for nd in nodes],
+                grid_mom=[[fstr(v) for v in grid[nd][1]] for nd in nodes],
+                grid_vel=[[fstr(v) for v in vel[nd]] for nd in nodes],
+            ))
+        cases.append(dict(n_modes=n_modes, phases=phases,
+                          coeff=[[[fstr(v) for v in c[a]] for a in range(3)] for c in cs]))
+    doc = dict(
+        description="Exact-rational shared-grid liquid-fabric transfers: P2G of each phase "
+                    "into its own channels, grid update, G2P of each particle from its "
+                    "phase's velocity (written by tests/golden/make_golden.py from "
+                    "oracle/exact.py)",
+        nodes=list(NODES), dx=fstr(DX), inv_dx=fstr(INV_DX), origin=[fstr(o) for o in ORIGIN],
+        dt=fstr(DT), gravity=[fstr(g) for g in GRAVITY], bc_layers=BC_LAYERS,
+        x=[[fstr(v) for v in x] for x in xs],
+        phase=phase,
+        mass_s=[fstr(m) for m in mass_s],
+        mass_f=[fstr(m) for m in mass_f],
+        coeff_in=[[[fstr(v) for v in c[a]] for a in range(3)] for c in coeffs],
+        cases=cases,
+    )
+    with open(OUT_MIXTURE, "w") as f:
+        json.dump(doc, f, indent=1)
+    print("wrote", OUT_MIXTURE)
 
 
 def write_affine(xs, masses, coeffs):
