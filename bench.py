@@ -141,6 +141,7 @@ def parse_args():
                     help="skip the dam break with moving state")
     ap.add_argument("--no-liquid-fabric", action="store_true",
                     help="skip the 256^3 liquid + fabric workload")
+    ap.add_argument("--no-mac", action="store_true", help="skip the staggered-grid timing")
     ap.add_argument("--no-paper-scale", action="store_true",
                     help="skip the paper-size dam break at 8 modes")
     ap.add_argument("--calib-copy", action="store_true",
@@ -447,6 +448,48 @@ def moving_timing(pp, torch, W, cells: int, n_modes: int, steps: int, warmup: in
                       f"dambreak_moving_{cells}cube_{ps.P}")
     out["data"] = "synthetic (seeded jittered dam-break block, workloads.config1_moving)"
     return out
+
+
+def mac_timing(pp, torch, W, cells: int, n_modes: int, steps: int, warmup: int):
+    """The moving dam break on a staggered (MAC) grid: every velocity component on its own
+    faces with its own face mass.  A step is sort (re-sort) -> MAC P2G -> MAC grid update ->
+    MAC G2P + advection, as separate calls.  Rooflines: P2G reads x, the permutation and
+    the coefficients (12 + 4 + 12 n_modes B per particle); G2P reads x and the permutation
+    and writes the coefficients and x (12 + 4 + 12 n_modes + 12 B)."""
+    import numpy as np
+
+    s = W.config1_moving(0, n=cells)
+    g = pp.grid_from_spec(s.grid)
+    ps = pp.MacParticleSet(g, n_modes, torch.from_numpy(s.x).cuda(),
+                           torch.from_numpy(np.ascontiguousarray(s.coeff[:, :n_modes])).cuda(),
+                           dt=s.dt, gravity=s.gravity, bc_layers=s.bc_layers, track_order=False)
+    del s
+    for _ in range(warmup):
+        ps.step()
+    torch.cuda.synchronize()
+    wall, phase = time_steps(ps, steps, torch)
+    if ps.status_flags() != 0:
+        raise RuntimeError(f"device status flags {ps.status_flags()} in the MAC timing")
+    P = ps.P
+    roof = {}
+    for k, bpp in (("p2g", p2g_bytes_per_particle(n_modes)),
+                   ("g2p", g2p_bytes_per_particle(n_modes) + 4)):
+        achieved = bpp * P / (phase[k] * 1e-3) / 1e9
+        roof[k] = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                   "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                   "bytes_per_particle": bpp}
+    return {
+        "workload": f"dambreak_moving_mac_{cells}cube_{P}",
+        "particles": P,
+        "n_modes": n_modes,
+        "steps": steps,
+        "ms_per_step": wall * 1e3 / steps,
+        "transfers_per_s": P * steps / wall,
+        "p2g_g2p_transfers_per_s": P / (transfer_ms(phase) * 1e-3),
+        "phase_ms": {k: round(v, 4) for k, v in phase.items()},
+        "roofline": roof,
+        "note": "staggered grid: 3 face-mass and 3 face-momentum arrays; separate calls",
+    }
 
 
 def liquid_fabric_timing(pp, torch, W, n_modes: int, steps: int, warmup: int):
@@ -760,6 +803,10 @@ def main():
     if not args.no_liquid_fabric:
         liquid_fabric = liquid_fabric_timing(pp, torch, W, n_modes, args.steps, args.warmup)
 
+    mac = None
+    if not args.no_mac:
+        mac = mac_timing(pp, torch, W, args.cells, n_modes, args.steps, args.warmup)
+
     paper_scale = None
     if not args.no_paper_scale:
         paper_scale = paper_scale_timing(pp, torch, W, args.steps, args.warmup)
@@ -810,6 +857,7 @@ def main():
         "moving": moving,
         "liquid_fabric": liquid_fabric,
         "paper_scale": paper_scale,
+        "mac": mac,
         "bwd_fwd_ratio": None if adj is None else round(adj["bwd_fwd_ratio"], 3),
         "bwd_fwd_ratio_per_step": (None if adj is None or "per_step" not in adj
                                    else adj["per_step"]["bwd_fwd_ratio"]),

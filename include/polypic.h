@@ -82,6 +82,9 @@ extern "C" {
 #define POLYPIC_FLAG_ORDER 2 /* polypic_sort_update was given keys_prev out of order */
 #define POLYPIC_FLAG_STALL 4 /* a re-sort pass gave up waiting on an earlier tile (a tile that
                               * waits far longer than any run takes); outputs unspecified */
+#define POLYPIC_FLAG_PHASE 8 /* a mixture particle's phase was neither 0 (fluid) nor 1 (solid);
+                              * it was skipped */
+#define POLYPIC_FLAG_MAP 16  /* a singular I + dt C in the affine back-map; particle skipped */
 
 /* Collocated grid description (host struct, passed by pointer). */
 typedef struct polypic_grid {
@@ -317,6 +320,78 @@ int32_t polypic_g2p2g(const polypic_grid* grid, int64_t P, int32_t n_modes, floa
                       float* x_out, float* coeff_out, const float* F_in, float* F_out,
                       const float* mass_in, float* mass_out, float uniform_mass,
                       float* grid_mass, float* grid_mom, int32_t* status_dev, void* stream);
+
+/* ------------------------------------------------------------------------
+ * P2G with the affine back-map of Eq. 12 (section 3.3).  The coefficients of a
+ * particle were fitted by G2P at an earlier position x_fit, in the basis
+ * orthogonalised there; the particle has since moved to x.  Eq. 12 maps the
+ * present configuration back to that one, so the modes of Eq. 13 are evaluated at
+ *     z'_i = (I + dt C)^-1 (x_i - x_p) / dx,   C_ab = coeff[a][1 + b] / dx
+ * (C = 0 below 4 modes), with the quadratic factor of Eq. 14 of the fitting
+ * position, ghat(z) = z^2 - a z - 1/4, a = t_fit (1 - 4 t_fit^2), t_fit the
+ * offset of x_fit from its nearest node per axis.  The weights W_ip are those of
+ * the present position x.  grid_mass is the plain P2G mass (the map does not
+ * enter it); grid_mom[a] = sum_p m_p W_ip sum_r c_{p a r} s_r(z'_i).
+ *
+ * x_fit[3][P] may be NULL (the present offsets are used).  dt is the step that
+ * carried x_fit to x.  With dt = 0 and x_fit NULL the result is polypic_p2g's.
+ * Other arguments as polypic_p2g (no sorted-cell path; pass the perm of
+ * polypic_sort for speed).  A particle with a singular I + dt C raises
+ * POLYPIC_FLAG_MAP, one with x or x_fit out of range POLYPIC_FLAG_RANGE; either
+ * is skipped.
+ * ------------------------------------------------------------------------ */
+int32_t polypic_p2g_affine(const polypic_grid* grid, int64_t P, int32_t n_modes, float dt,
+                           const float* x, const float* x_fit, const float* mass,
+                           float uniform_mass, const float* coeff, const int32_t* perm,
+                           float* grid_mass, float* grid_mom, int32_t accumulate,
+                           int32_t* status_dev, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Staggered (marker-and-cell) grid.  The paper applies its transfers on MAC
+ * grids (section 3; Table 1's per-face mass m_{i a}, momentum (mv)_{i a} and
+ * velocity v_{i a}): velocity component a lives on the faces of component a,
+ * face (ix, iy, iz) of component a at
+ *     origin + ((ix, iy, iz) + (1 - e_a) / 2) * dx,
+ * i.e. on the node lattice along axis a and half a spacing up along the two
+ * other axes.  Each face carries its own mass.  Every component is a scalar
+ * transfer on its own lattice with its own quadratic B-spline stencil: along an
+ * axis where component a is staggered, u' = u - 1/2 (exact in float32),
+ * b = floor(u' - 1/2), t = u' - b - 1.  A particle is in range when the
+ * stencils of all three components fit: 0 <= b <= n_axis - 3 for both the
+ * node form and the shifted form on every axis (1 <= u < n_axis - 3/2).
+ * Modes, coefficient units and the projection are those of the collocated
+ * calls, per component over its own stencil.
+ *
+ * Arrays: face_mass[3][N], face_mom[3][N], face_vel[3][N], component a's faces
+ * at a * N + (iz * ny + iy) * nx + ix, N = nx * ny * nz (the grid struct's node
+ * counts are the face counts of every component).
+ *
+ * polypic_mac_p2g: face_mass[a] = sum_p m_p W_{ip a};
+ *   face_mom[a] = sum_p m_p W_{ip a} sum_r c_{p r a} s_r (Eq. 1, 4, 13 per face).
+ *   Other arguments as polypic_p2g (no sorted-cell path: the workspace-free
+ *   brick kernel accumulates runs of equal 4^3 tiles of the particles' node
+ *   bases, so pass the perm of polypic_sort for speed; any order is correct).
+ * polypic_mac_grid_update: per component, v = p / m + dt g_a where m > 0, else
+ *   0 (Eq. 5 per face); walls as polypic_grid_update, on the face index along
+ *   the component's own axis.
+ * polypic_mac_g2p: c'_{p r a} = <v_a, s_r>_{W_a} / <s_r, s_r>_{W_a} over
+ *   component a's face stencil (Eq. 6-8 per face, section 3.3); advection,
+ *   clamp, F update and the optional mass copy as polypic_g2p.
+ * Out-of-range particles raise POLYPIC_FLAG_RANGE and are skipped (P2G) or get
+ *   zero coefficients (G2P).
+ * ------------------------------------------------------------------------ */
+int32_t polypic_mac_p2g(const polypic_grid* grid, int64_t P, int32_t n_modes, const float* x,
+                        const float* mass, float uniform_mass, const float* coeff,
+                        const int32_t* perm, float* face_mass, float* face_mom,
+                        int32_t accumulate, int32_t* status_dev, void* stream);
+int32_t polypic_mac_grid_update(const polypic_grid* grid, float dt, const float* gravity,
+                                int32_t bc_layers, const float* face_mass, const float* face_mom,
+                                float* face_vel, void* stream);
+int32_t polypic_mac_g2p(const polypic_grid* grid, int64_t P, int32_t n_modes, float dt,
+                        const float* face_vel, const float* x_in, const int32_t* perm,
+                        float* x_out, float* coeff_out, const float* F_in, float* F_out,
+                        const float* mass_in, float* mass_out, int32_t* status_dev,
+                        void* stream);
 
 /* ------------------------------------------------------------------------
  * Adjoint (reverse mode) of one step.  For a scalar loss L of the step's

@@ -21,6 +21,8 @@ POLYPIC_ENOTSUP = 5
 POLYPIC_FLAG_RANGE = 1
 POLYPIC_FLAG_ORDER = 2
 POLYPIC_FLAG_STALL = 4
+POLYPIC_FLAG_PHASE = 8
+POLYPIC_FLAG_MAP = 16
 POLYPIC_SORT_NOALLOC_MAX_P = 2097152
 POLYPIC_P2G_DEFAULT = -1
 POLYPIC_P2G_BRICKS = 0
@@ -48,6 +50,10 @@ EXPORTED = (
     "polypic_grid_update",
     "polypic_g2p",
     "polypic_g2p2g",
+    "polypic_p2g_affine",
+    "polypic_mac_p2g",
+    "polypic_mac_grid_update",
+    "polypic_mac_g2p",
     "polypic_g2p_backward",
     "polypic_grid_update_backward",
     "polypic_p2g_backward",
@@ -176,6 +182,14 @@ def load() -> ctypes.CDLL:
     lib.polypic_grid_update.argtypes = [G, f32, ctypes.POINTER(f32), i32, P, P, P, P]
     lib.polypic_g2p.restype = i32
     lib.polypic_g2p.argtypes = [G, i64, i32, f32, P, P, P, P, P, P, P, P, P, P, P]
+    lib.polypic_p2g_affine.restype = i32
+    lib.polypic_p2g_affine.argtypes = [G, i64, i32, f32, P, P, P, f32, P, P, P, P, i32, P, P]
+    lib.polypic_mac_p2g.restype = i32
+    lib.polypic_mac_p2g.argtypes = [G, i64, i32, P, P, f32, P, P, P, P, i32, P, P]
+    lib.polypic_mac_grid_update.restype = i32
+    lib.polypic_mac_grid_update.argtypes = [G, f32, ctypes.POINTER(f32), i32, P, P, P, P]
+    lib.polypic_mac_g2p.restype = i32
+    lib.polypic_mac_g2p.argtypes = [G, i64, i32, f32, P, P, P, P, P, P, P, P, P, P, P]
     lib.polypic_g2p2g.restype = i32
     lib.polypic_g2p2g.argtypes = [G, i64, i32, f32, P, P, P, P, P, P, P, P, P, f32, P, P, P, P]
     lib.polypic_g2p_backward.restype = i32

@@ -563,6 +563,121 @@ int32_t polypic_g2p(const polypic_grid* grid, int64_t P, int32_t n_modes, float 
   return from_hip(launch_g2p(a, n_modes, (hipStream_t)stream));
 }
 
+// ---- P2G with the affine back-map of Eq. 12
+int32_t polypic_p2g_affine(const polypic_grid* grid, int64_t P, int32_t n_modes, float dt,
+                           const float* x, const float* x_fit, const float* mass,
+                           float uniform_mass, const float* coeff, const int32_t* perm,
+                           float* grid_mass, float* grid_mom, int32_t accumulate,
+                           int32_t* status_dev, void* stream) {
+  int32_t st = check_grid(grid);
+  if (st) return st;
+  if ((st = check_P(P))) return st;
+  if (!valid_modes(n_modes) || !isfinite(dt)) return POLYPIC_EINVAL;
+  if (!grid_mass || !grid_mom) return POLYPIC_EINVAL;
+  if (P > 0 && (!x || !coeff)) return POLYPIC_EINVAL;
+  if (!mass && !isfinite(uniform_mass)) return POLYPIC_EINVAL;
+  AffineP2GArgs a;
+  a.g = to_dev(grid);
+  a.P = P;
+  a.dt = dt;
+  a.x = x;
+  a.x_fit = x_fit;
+  a.mass = mass;
+  a.uniform_mass = uniform_mass;
+  a.coeff = coeff;
+  a.perm = perm;
+  a.gm = grid_mass;
+  a.gp = grid_mom;
+  a.status = status_dev;
+  discard_stale_error();
+  return from_hip(launch_p2g_affine(a, n_modes, accumulate != 0, (hipStream_t)stream));
+}
+
+// ---- staggered (MAC) grid
+int32_t polypic_mac_p2g(const polypic_grid* grid, int64_t P, int32_t n_modes, const float* x,
+                        const float* mass, float uniform_mass, const float* coeff,
+                        const int32_t* perm, float* face_mass, float* face_mom,
+                        int32_t accumulate, int32_t* status_dev, void* stream) {
+  int32_t st = check_grid(grid);
+  if (st) return st;
+  if ((st = check_P(P))) return st;
+  if (!valid_modes(n_modes)) return POLYPIC_EINVAL;
+  if (!face_mass || !face_mom) return POLYPIC_EINVAL;
+  if (P > 0 && (!x || !coeff)) return POLYPIC_EINVAL;
+  if (!mass && !isfinite(uniform_mass)) return POLYPIC_EINVAL;
+  MacP2GArgs a;
+  a.g = to_dev(grid);
+  a.P = P;
+  a.x = x;
+  a.mass = mass;
+  a.uniform_mass = uniform_mass;
+  a.coeff = coeff;
+  a.perm = perm;
+  a.fm = face_mass;
+  a.fp = face_mom;
+  a.status = status_dev;
+  discard_stale_error();
+  return from_hip(launch_mac_p2g(a, n_modes, accumulate != 0, (hipStream_t)stream));
+}
+
+int32_t polypic_mac_grid_update(const polypic_grid* grid, float dt, const float* gravity,
+                                int32_t bc_layers, const float* face_mass, const float* face_mom,
+                                float* face_vel, void* stream) {
+  int32_t st = check_grid(grid);
+  if (st) return st;
+  if (!gravity || !face_mass || !face_mom || !face_vel) return POLYPIC_EINVAL;
+  if (!isfinite(dt) || bc_layers < 0) return POLYPIC_EINVAL;
+  for (int k = 0; k < 3; ++k)
+    if (!isfinite(gravity[k])) return POLYPIC_EINVAL;
+  MacUpdateArgs a;
+  a.nx = grid->nx;
+  a.ny = grid->ny;
+  a.nz = grid->nz;
+  a.dt = dt;
+  a.g0 = gravity[0];
+  a.g1 = gravity[1];
+  a.g2 = gravity[2];
+  a.bc_layers = bc_layers;
+  a.fm = face_mass;
+  a.fp = face_mom;
+  a.fv = face_vel;
+  discard_stale_error();
+  return from_hip(launch_mac_grid_update(a, (hipStream_t)stream));
+}
+
+int32_t polypic_mac_g2p(const polypic_grid* grid, int64_t P, int32_t n_modes, float dt,
+                        const float* face_vel, const float* x_in, const int32_t* perm,
+                        float* x_out, float* coeff_out, const float* F_in, float* F_out,
+                        const float* mass_in, float* mass_out, int32_t* status_dev,
+                        void* stream) {
+  int32_t st = check_grid(grid);
+  if (st) return st;
+  if ((st = check_P(P))) return st;
+  if (!valid_modes(n_modes) || !isfinite(dt)) return POLYPIC_EINVAL;
+  if (P == 0) return POLYPIC_OK;
+  if (!face_vel || !x_in || !coeff_out) return POLYPIC_EINVAL;
+  if ((F_in == nullptr) != (F_out == nullptr)) return POLYPIC_EINVAL;
+  if ((mass_in == nullptr) != (mass_out == nullptr)) return POLYPIC_EINVAL;
+  MacG2PArgs a;
+  a.g = to_dev(grid);
+  a.P = P;
+  a.dt = dt;
+  a.dx = grid->dx;
+  clamp_bounds(grid, a.lo, a.hi);
+  a.fv = face_vel;
+  a.x_in = x_in;
+  a.perm = perm;
+  a.x_out = x_out;
+  a.coeff_out = coeff_out;
+  a.F_in = F_in;
+  a.F_out = F_out;
+  a.mass_in = mass_in;
+  a.mass_out = mass_out;
+  a.status = status_dev;
+  discard_stale_error();
+  return from_hip(launch_mac_g2p(a, n_modes, (hipStream_t)stream));
+}
+
 namespace {
 // [a, a + na) and [b, b + nb) floats overlap (either may be null)
 bool overlaps(const void* a, int64_t na, const void* b, int64_t nb) {

@@ -17,6 +17,8 @@ constexpr int kWave = 64;
 constexpr int kFlagRange = 1;
 constexpr int kFlagOrder = 2;  // a re-sort was given previous keys out of order
 constexpr int kFlagStall = 4;  // a sort's chained tile prefixes did not complete
+constexpr int kFlagPhase = 8;  // a mixture particle with a phase other than 0 (fluid) or 1 (solid)
+constexpr int kFlagMap = 16;   // a singular I + dt C in the affine back-map
 
 struct GridDev {
   int nx, ny, nz;

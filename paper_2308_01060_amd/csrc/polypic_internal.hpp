@@ -203,4 +203,66 @@ hipError_t launch_scatter_rows(const void* src, void* dst, const int32_t* idx, i
 hipError_t launch_invert_permutation(const int32_t* perm, int32_t* inv, int64_t P,
                                      hipStream_t stream);
 
+// ---- staggered (MAC) grid: component a on the faces at origin + (i + (1 - e_a)/2) dx
+struct MacP2GArgs {
+  GridDev g;
+  int64_t P;
+  const float* x;       // [3][P]
+  const float* mass;    // [P] or nullptr
+  float uniform_mass;
+  const float* coeff;   // [3][NR][P]
+  const int32_t* perm;  // [P] or nullptr
+  float* fm;            // face masses [3][N]
+  float* fp;            // face momenta [3][N]
+  int32_t* status;
+};
+hipError_t launch_mac_p2g(const MacP2GArgs& a, int n_modes, bool accumulate, hipStream_t s);
+
+struct MacUpdateArgs {
+  int nx, ny, nz;
+  float dt;
+  float g0, g1, g2;
+  int bc_layers;
+  const float* fm;  // [3][N]
+  const float* fp;  // [3][N]
+  float* fv;        // [3][N]
+};
+hipError_t launch_mac_grid_update(const MacUpdateArgs& a, hipStream_t s);
+
+struct MacG2PArgs {
+  GridDev g;
+  int64_t P;
+  float dt;
+  float dx;
+  float lo[3], hi[3];
+  const float* fv;      // face velocities [3][N]
+  const float* x_in;
+  const int32_t* perm;
+  float* x_out;
+  float* coeff_out;
+  const float* F_in;
+  float* F_out;
+  const float* mass_in;
+  float* mass_out;
+  int32_t* status;
+};
+hipError_t launch_mac_g2p(const MacG2PArgs& a, int n_modes, hipStream_t s);
+
+// ---- P2G with the affine back-map of Eq. 12
+struct AffineP2GArgs {
+  GridDev g;
+  int64_t P;
+  float dt;
+  const float* x;       // [3][P] present positions
+  const float* x_fit;   // [3][P] positions of the fit (nullptr: the present ones)
+  const float* mass;    // [P] or nullptr
+  float uniform_mass;
+  const float* coeff;   // [3][NR][P]
+  const int32_t* perm;  // [P] or nullptr
+  float* gm;            // [N]
+  float* gp;            // [3][N]
+  int32_t* status;
+};
+hipError_t launch_p2g_affine(const AffineP2GArgs& a, int n_modes, bool accumulate, hipStream_t s);
+
 }  // namespace polypic

@@ -231,6 +231,74 @@ def polypic_g2p(grid: polypic_grid, n_modes: int, dt: float, grid_vel: torch.Ten
         _ptr(status_dev, torch.int32, 1, "status_dev"), _stream()), "polypic_g2p")
 
 
+def polypic_p2g_affine(grid: polypic_grid, n_modes: int, dt: float, x: torch.Tensor,
+                       coeff: torch.Tensor, grid_mass: torch.Tensor, grid_mom: torch.Tensor,
+                       x_fit: Optional[torch.Tensor] = None, mass: Optional[torch.Tensor] = None,
+                       uniform_mass: float = 1.0, perm: Optional[torch.Tensor] = None,
+                       accumulate: bool = False,
+                       status_dev: Optional[torch.Tensor] = None) -> None:
+    """P2G with the modes evaluated through the affine back-map of Eq. 12."""
+    P = x.numel() // 3
+    N = n_nodes(grid)
+    check(_lib.load().polypic_p2g_affine(
+        ctypes.byref(grid), P, int(n_modes), float(dt), _ptr(x, torch.float32, 3 * P, "x"),
+        _ptr(x_fit, torch.float32, 3 * P, "x_fit"), _ptr(mass, torch.float32, P, "mass"),
+        float(uniform_mass), _ptr(coeff, torch.float32, 3 * int(n_modes) * P, "coeff"),
+        _ptr(perm, torch.int32, P, "perm"), _ptr(grid_mass, torch.float32, N, "grid_mass"),
+        _ptr(grid_mom, torch.float32, 3 * N, "grid_mom"), int(bool(accumulate)),
+        _ptr(status_dev, torch.int32, 1, "status_dev"), _stream()), "polypic_p2g_affine")
+
+
+# ---- staggered (MAC) grid: face arrays [3][N], component a's faces at a * N + node index
+def polypic_mac_p2g(grid: polypic_grid, n_modes: int, x: torch.Tensor, coeff: torch.Tensor,
+                    face_mass: torch.Tensor, face_mom: torch.Tensor,
+                    mass: Optional[torch.Tensor] = None, uniform_mass: float = 1.0,
+                    perm: Optional[torch.Tensor] = None, accumulate: bool = False,
+                    status_dev: Optional[torch.Tensor] = None) -> None:
+    P = x.numel() // 3
+    N = n_nodes(grid)
+    check(_lib.load().polypic_mac_p2g(
+        ctypes.byref(grid), P, int(n_modes), _ptr(x, torch.float32, 3 * P, "x"),
+        _ptr(mass, torch.float32, P, "mass"), float(uniform_mass),
+        _ptr(coeff, torch.float32, 3 * int(n_modes) * P, "coeff"),
+        _ptr(perm, torch.int32, P, "perm"),
+        _ptr(face_mass, torch.float32, 3 * N, "face_mass"),
+        _ptr(face_mom, torch.float32, 3 * N, "face_mom"), int(bool(accumulate)),
+        _ptr(status_dev, torch.int32, 1, "status_dev"), _stream()), "polypic_mac_p2g")
+
+
+def polypic_mac_grid_update(grid: polypic_grid, dt: float, gravity: Sequence[float],
+                            bc_layers: int, face_mass: torch.Tensor, face_mom: torch.Tensor,
+                            face_vel: torch.Tensor) -> None:
+    N = n_nodes(grid)
+    g3 = (ctypes.c_float * 3)(*[float(v) for v in gravity])
+    check(_lib.load().polypic_mac_grid_update(
+        ctypes.byref(grid), float(dt), g3, int(bc_layers),
+        _ptr(face_mass, torch.float32, 3 * N, "face_mass"),
+        _ptr(face_mom, torch.float32, 3 * N, "face_mom"),
+        _ptr(face_vel, torch.float32, 3 * N, "face_vel"), _stream()), "polypic_mac_grid_update")
+
+
+def polypic_mac_g2p(grid: polypic_grid, n_modes: int, dt: float, face_vel: torch.Tensor,
+                    x_in: torch.Tensor, coeff_out: torch.Tensor,
+                    perm: Optional[torch.Tensor] = None, x_out: Optional[torch.Tensor] = None,
+                    F_in: Optional[torch.Tensor] = None, F_out: Optional[torch.Tensor] = None,
+                    mass_in: Optional[torch.Tensor] = None,
+                    mass_out: Optional[torch.Tensor] = None,
+                    status_dev: Optional[torch.Tensor] = None) -> None:
+    P = x_in.numel() // 3
+    N = n_nodes(grid)
+    check(_lib.load().polypic_mac_g2p(
+        ctypes.byref(grid), P, int(n_modes), float(dt),
+        _ptr(face_vel, torch.float32, 3 * N, "face_vel"),
+        _ptr(x_in, torch.float32, 3 * P, "x_in"), _ptr(perm, torch.int32, P, "perm"),
+        _ptr(x_out, torch.float32, 3 * P, "x_out"),
+        _ptr(coeff_out, torch.float32, 3 * int(n_modes) * P, "coeff_out"),
+        _ptr(F_in, torch.float32, 9 * P, "F_in"), _ptr(F_out, torch.float32, 9 * P, "F_out"),
+        _ptr(mass_in, torch.float32, P, "mass_in"), _ptr(mass_out, torch.float32, P, "mass_out"),
+        _ptr(status_dev, torch.int32, 1, "status_dev"), _stream()), "polypic_mac_g2p")
+
+
 def polypic_g2p2g(grid: polypic_grid, n_modes: int, dt: float, grid_vel: torch.Tensor,
                   x_in: torch.Tensor, x_out: torch.Tensor, coeff_out: torch.Tensor,
                   grid_mass: torch.Tensor, grid_mom: torch.Tensor,

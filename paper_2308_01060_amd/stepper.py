@@ -189,3 +189,88 @@ class ParticleSet:
 
     def status_flags(self) -> int:
         return int(self.status.item())
+
+
+class MacParticleSet(ParticleSet):
+    """A particle set on a staggered (MAC) grid: component a of the velocity on its own
+    faces, each face with its own mass (three face-mass arrays instead of one node mass).
+
+    A step is sort -> polypic_mac_p2g -> polypic_mac_grid_update -> polypic_mac_g2p
+    (separate calls; the sort and re-sort, buffer swaps and order tracking are those of
+    ParticleSet: the cell key of the node stencil also orders the face stencils)."""
+
+    def __init__(self, grid, n_modes: int, x: torch.Tensor, coeff: torch.Tensor, **kw):
+        kw["fused"] = False
+        super().__init__(grid, n_modes, x, coeff, **kw)
+        N = ops.n_nodes(grid)
+        dev = self.x.device
+        self.grid_mass = torch.empty(3 * N, dtype=torch.float32, device=dev)  # face masses
+
+    def p2g(self, use_perm: bool = True, use_keys: bool = True):
+        ops.polypic_mac_p2g(self.grid, self.n_modes, self.x, self.coeff, self.grid_mass,
+                            self.grid_mom, mass=self.mass, uniform_mass=self.uniform_mass,
+                            perm=self.perm if use_perm else None, status_dev=self.status)
+        self.grid_current = True
+
+    def autotune(self):
+        """The MAC kernels have one configuration: only the sort runs."""
+        self.sort()
+        return None
+
+    def grid_update(self):
+        ops.polypic_mac_grid_update(self.grid, self.dt, self.gravity, self.bc_layers,
+                                    self.grid_mass, self.grid_mom, self.grid_vel)
+
+    def g2p(self, use_perm: bool = True, advect: bool = True):
+        ops.polypic_mac_g2p(self.grid, self.n_modes, self.dt, self.grid_vel, self.x,
+                            self.coeff_next, perm=self.perm if use_perm else None,
+                            x_out=self.x_next if advect else None, F_in=self.F, F_out=self.F_next,
+                            mass_in=self.mass, mass_out=self.mass_next, status_dev=self.status)
+        self._next_grid_current = False
+
+    def g2p2g(self, use_perm: bool = True):
+        raise RuntimeError("a MAC set steps with separate P2G and G2P calls (fused=False)")
+
+
+class AffineParticleSet(ParticleSet):
+    """A particle set whose P2G evaluates the modes through the affine back-map of Eq. 12
+    (polypic_p2g_affine): the coefficients a G2P fitted at the positions x^n are carried
+    to the grid from x^{n+1} at z' = (I + dt C)^-1 (x_i - x^{n+1}) / dx, with the quadratic
+    factor of x^n.  The set keeps x^n in slot order beside the positions (x_fit: one
+    polypic_gather_rows of 3 rows per step).  The first step's coefficients count as
+    fitted at the initial positions (plain P2G).  Separate P2G and G2P calls."""
+
+    def __init__(self, grid, n_modes: int, x: torch.Tensor, coeff: torch.Tensor, **kw):
+        kw["fused"] = False
+        super().__init__(grid, n_modes, x, coeff, **kw)
+        self.x_fit = torch.empty_like(self.x)
+        self.x_fit_next = torch.empty_like(self.x)
+        self.fit_valid = False
+        self._next_fit_valid = False
+
+    def p2g(self, use_perm: bool = True, use_keys: bool = True):
+        if not self.fit_valid:
+            return super().p2g(use_perm, use_keys)
+        ops.polypic_p2g_affine(self.grid, self.n_modes, self.dt, self.x, self.coeff,
+                               self.grid_mass, self.grid_mom, x_fit=self.x_fit, mass=self.mass,
+                               uniform_mass=self.uniform_mass,
+                               perm=self.perm if use_perm else None, status_dev=self.status)
+        self.grid_current = True
+
+    def g2p(self, use_perm: bool = True, advect: bool = True):
+        super().g2p(use_perm, advect)
+        # the new coefficients are fitted at the present positions, slot i at x[perm[i]]
+        if use_perm:
+            ops.polypic_gather_rows(self.x, self.x_fit_next, self.perm)
+        else:
+            self.x_fit_next.copy_(self.x)
+        self._next_fit_valid = True
+
+    def g2p2g(self, use_perm: bool = True):
+        raise RuntimeError("an affine-map set steps with separate P2G and G2P calls")
+
+    def swap(self, use_perm: bool = True):
+        super().swap(use_perm)
+        self.x_fit, self.x_fit_next = self.x_fit_next, self.x_fit
+        self.fit_valid = self._next_fit_valid
+        self._next_fit_valid = False

@@ -362,3 +362,39 @@ def test_sort_noalloc_host_checks():
     out = ctypes.c_size_t(0)
     assert lib.polypic_sort_workspace_bytes(ctypes.byref(g), cap, ctypes.byref(out)) == 0
     assert out.value <= 18 << 20
+
+
+def test_mac_calls_reject_bad_arguments_on_the_host():
+    """The staggered-grid calls validate like their collocated counterparts."""
+    lib = _lib.load()
+    g = grid()
+    g3 = (ctypes.c_float * 3)(0.0, -9.8, 0.0)
+    # P2G: bad mode count, null face arrays, null inputs with P > 0, bad P, bad grid
+    assert lib.polypic_mac_p2g(ctypes.byref(g), 10, 5, FAKE, None, 1.0, FAKE, None, FAKE, FAKE,
+                               0, None, None) == _lib.POLYPIC_EINVAL
+    assert lib.polypic_mac_p2g(ctypes.byref(g), 10, 4, FAKE, None, 1.0, FAKE, None, None, FAKE,
+                               0, None, None) == _lib.POLYPIC_EINVAL
+    assert lib.polypic_mac_p2g(ctypes.byref(g), 10, 4, None, None, 1.0, FAKE, None, FAKE, FAKE,
+                               0, None, None) == _lib.POLYPIC_EINVAL
+    assert lib.polypic_mac_p2g(ctypes.byref(g), -1, 4, FAKE, None, 1.0, FAKE, None, FAKE, FAKE,
+                               0, None, None) == _lib.POLYPIC_EINVAL
+    assert lib.polypic_mac_p2g(ctypes.byref(grid(2, 36, 36)), 10, 4, FAKE, None, 1.0, FAKE, None,
+                               FAKE, FAKE, 0, None, None) == _lib.POLYPIC_EINVAL
+    # grid update: null arrays, negative bc_layers, null gravity
+    assert lib.polypic_mac_grid_update(ctypes.byref(g), 1e-4, g3, 1, None, FAKE, FAKE,
+                                       None) == _lib.POLYPIC_EINVAL
+    assert lib.polypic_mac_grid_update(ctypes.byref(g), 1e-4, g3, -1, FAKE, FAKE, FAKE,
+                                       None) == _lib.POLYPIC_EINVAL
+    assert lib.polypic_mac_grid_update(ctypes.byref(g), 1e-4, None, 1, FAKE, FAKE, FAKE,
+                                       None) == _lib.POLYPIC_EINVAL
+    # G2P: unpaired F / mass, null output, bad mode count; P = 0 is a no-op
+    assert lib.polypic_mac_g2p(ctypes.byref(g), 10, 4, 1e-4, FAKE, FAKE, None, None, FAKE, FAKE,
+                               None, None, None, None, None) == _lib.POLYPIC_EINVAL
+    assert lib.polypic_mac_g2p(ctypes.byref(g), 10, 4, 1e-4, FAKE, FAKE, None, None, FAKE, None,
+                               None, FAKE, None, None, None) == _lib.POLYPIC_EINVAL
+    assert lib.polypic_mac_g2p(ctypes.byref(g), 10, 4, 1e-4, FAKE, FAKE, None, None, None, None,
+                               None, None, None, None, None) == _lib.POLYPIC_EINVAL
+    assert lib.polypic_mac_g2p(ctypes.byref(g), 10, 9, 1e-4, FAKE, FAKE, None, None, FAKE, None,
+                               None, None, None, None, None) == _lib.POLYPIC_EINVAL
+    assert lib.polypic_mac_g2p(ctypes.byref(g), 0, 4, 1e-4, None, None, None, None, None, None,
+                               None, None, None, None, None) == _lib.POLYPIC_OK
