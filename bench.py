@@ -142,6 +142,10 @@ def parse_args():
     ap.add_argument("--no-liquid-fabric", action="store_true",
                     help="skip the 256^3 liquid + fabric workload")
     ap.add_argument("--no-mac", action="store_true", help="skip the staggered-grid timing")
+    ap.add_argument("--no-shared-grid", action="store_true",
+                    help="skip the liquid + fabric timing on one shared grid")
+    ap.add_argument("--no-affine", action="store_true",
+                    help="skip the affine back-map timing")
     ap.add_argument("--no-paper-scale", action="store_true",
                     help="skip the paper-size dam break at 8 modes")
     ap.add_argument("--calib-copy", action="store_true",
@@ -492,6 +496,95 @@ def mac_timing(pp, torch, W, cells: int, n_modes: int, steps: int, warmup: int):
     }
 
 
+def affine_timing(pp, torch, W, cells: int, n_modes: int, steps: int, warmup: int):
+    """The moving dam break stepped with the affine back-map of Eq. 12 in P2G
+    (AffineParticleSet: sort -> affine P2G -> grid update -> G2P, plus the gather of the
+    fitting positions).  The affine P2G evaluates every mode at every node (no separable
+    contraction), so its roofline is taken against the vector ALU as well: per particle
+    27 nodes x 3 components x (27 + 9 + 3) multiply-adds on the mode factors, plus the
+    mapped offsets and quadratic factors (27 x 3 x 15), at 2 flop each."""
+    import numpy as np
+
+    s = W.config1_moving(0, n=cells)
+    g = pp.grid_from_spec(s.grid)
+    ps = pp.AffineParticleSet(g, n_modes, torch.from_numpy(s.x).cuda(),
+                              torch.from_numpy(np.ascontiguousarray(s.coeff[:, :n_modes])).cuda(),
+                              dt=s.dt, gravity=s.gravity, bc_layers=s.bc_layers,
+                              track_order=False)
+    del s
+    for _ in range(warmup):
+        ps.step()
+    torch.cuda.synchronize()
+    wall, phase = time_steps(ps, steps, torch)
+    if ps.status_flags() != 0:
+        raise RuntimeError(f"device status flags {ps.status_flags()} in the affine timing")
+    P = ps.P
+    t = phase["p2g"] * 1e-3
+    bpp = p2g_bytes_per_particle(n_modes) + 12      # + the fitting positions
+    flops = 2 * 27 * 3 * (27 + 9 + 3 + 15) if n_modes == 27 else None
+    out = {
+        "workload": f"dambreak_moving_affine_{cells}cube_{P}",
+        "particles": P,
+        "n_modes": n_modes,
+        "steps": steps,
+        "ms_per_step": wall * 1e3 / steps,
+        "transfers_per_s": P * steps / wall,
+        "phase_ms": {k: round(v, 4) for k, v in phase.items()},
+        "p2g_roofline_hbm": {"achieved": round(bpp * P / t / 1e9, 1), "peak": HBM_PEAK_GBS,
+                             "unit": "GB/s", "frac": round(bpp * P / t / 1e9 / HBM_PEAK_GBS, 4),
+                             "bytes_per_particle": bpp},
+    }
+    if flops:
+        out["p2g_roofline_alu"] = {"achieved": round(flops * P / t / 1e12, 2),
+                                   "peak": 157.3, "unit": "TFLOP/s",
+                                   "frac": round(flops * P / t / 1e12 / 157.3, 4),
+                                   "flops_per_particle": flops}
+    return out
+
+
+def shared_grid_timing(pp, torch, W, n_modes: int, steps: int, warmup: int):
+    """The liquid + fabric workload with both sets on ONE 260^3-node grid (section 3.4):
+    16,777,216 fluid particles and 1,000,000 fabric points in one array, tagged by phase;
+    fluid and solid channel sets per node.  A step is sort -> mixture P2G -> mixture grid
+    update -> mixture G2P, separate calls.  Positions, masses and F from
+    workloads.liquid_fabric_shared(0) without its coefficients, which are drawn on the
+    device from a seeded torch generator."""
+    import numpy as np
+
+    s = W.liquid_fabric_shared(0)
+    g = pp.grid_from_spec(s.grid)
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(40_000)
+    c = torch.randn(3, n_modes, s.P, generator=gen, device="cuda")
+    c[:, 1:] *= 0.1
+    ps = pp.MixtureParticleSet(g, n_modes, torch.from_numpy(s.x).cuda(), c,
+                               torch.from_numpy(s.phase).cuda(), torch.from_numpy(s.mass_f).cuda(),
+                               mass_s=torch.from_numpy(s.mass_s).cuda(),
+                               F=torch.from_numpy(s.F).cuda(), dt=s.dt, gravity=s.gravity,
+                               bc_layers=s.bc_layers, track_order=False)
+    name = s.name
+    del s, c
+    for _ in range(warmup):
+        ps.step()
+    torch.cuda.synchronize()
+    wall, phase = time_steps(ps, steps, torch)
+    if ps.status_flags() != 0:
+        raise RuntimeError(f"device status flags {ps.status_flags()} in the shared-grid timing")
+    P = ps.P
+    return {
+        "workload": name,
+        "particles": P,
+        "n_modes": n_modes,
+        "steps": steps,
+        "ms_per_step": wall * 1e3 / steps,
+        "transfers_per_s": P * steps / wall,
+        "p2g_g2p_transfers_per_s": P / (transfer_ms(phase) * 1e-3),
+        "phase_ms": {k: round(v, 4) for k, v in phase.items()},
+        "note": "one particle array (phase, m_f, m_s, F per particle) and one grid with a "
+                "fluid and a solid channel set; separate P2G and G2P calls",
+    }
+
+
 def liquid_fabric_timing(pp, torch, W, n_modes: int, steps: int, warmup: int):
     """The liquid + fabric workload: a falling block of 16,777,216 fluid particles (128 x 64
     x 128 cells at 16 per cell) and a 1000 x 1000 fabric sheet of 1,000,000 material
@@ -807,6 +900,14 @@ def main():
     if not args.no_mac:
         mac = mac_timing(pp, torch, W, args.cells, n_modes, args.steps, args.warmup)
 
+    shared = None
+    if not args.no_shared_grid:
+        shared = shared_grid_timing(pp, torch, W, n_modes, args.steps, args.warmup)
+
+    affine = None
+    if not args.no_affine:
+        affine = affine_timing(pp, torch, W, args.cells, n_modes, args.steps, args.warmup)
+
     paper_scale = None
     if not args.no_paper_scale:
         paper_scale = paper_scale_timing(pp, torch, W, args.steps, args.warmup)
@@ -858,6 +959,8 @@ def main():
         "liquid_fabric": liquid_fabric,
         "paper_scale": paper_scale,
         "mac": mac,
+        "shared_grid": shared,
+        "affine_map": affine,
         "bwd_fwd_ratio": None if adj is None else round(adj["bwd_fwd_ratio"], 3),
         "bwd_fwd_ratio_per_step": (None if adj is None or "per_step" not in adj
                                    else adj["per_step"]["bwd_fwd_ratio"]),

@@ -347,6 +347,46 @@ int32_t polypic_p2g_affine(const polypic_grid* grid, int64_t P, int32_t n_modes,
                            int32_t* status_dev, void* stream);
 
 /* ------------------------------------------------------------------------
+ * Liquid and fabric particles on one grid (section 3.4, Eq. 15-20).  One
+ * particle array holds both phases, phase[p] = 0 for a fluid particle and 1 for
+ * a solid (fabric) point; every node carries a fluid and a solid set of channels:
+ *   grid_mass[2][N]   fluid mass m_f,i (Eq. 16's sum of Eq. 1 over fluid
+ *                     particles), then the solid mixture mass (m_s + m_f)_i
+ *                     (Eq. 18-19 summed over solid points: the point and its
+ *                     absorbed fluid);
+ *   grid_mom[2][3][N] the momenta of the two sets (Eq. 15-16, 18-19 with the
+ *                     polynomial modes of Eq. 13);
+ *   grid_vel[2][3][N] the velocities of the two sets.
+ * Set k's arrays start at k * N (mass) and k * 3 * N (momentum, velocity).
+ *
+ * polypic_mixture_p2g: a fluid particle scatters with mass mass_f[p]; a solid
+ *   one with mass_s[p] + mass_f[p] (mass_s NULL: 0).  phase and mass_f are
+ *   required for P > 0.  A phase other than 0 or 1 raises POLYPIC_FLAG_PHASE and
+ *   the particle is skipped.  Other arguments as polypic_p2g (no sorted-cell
+ *   path; pass the perm of polypic_sort for speed).
+ * polypic_mixture_grid_update: v = p / m + dt g where m > 0, else 0, and the walls
+ *   of polypic_grid_update, for each set with its own mass (Eq. 17 and 20, the
+ *   latter's mixture mass read as the grid sum).
+ * polypic_mixture_g2p: each particle is fitted (as polypic_g2p) from the
+ *   velocity of its own phase; phase_out, mass_f_out and mass_s_out (optional,
+ *   each paired with its input) receive the per-particle arrays in slot order.
+ * ------------------------------------------------------------------------ */
+int32_t polypic_mixture_p2g(const polypic_grid* grid, int64_t P, int32_t n_modes,
+                            const float* x, const int32_t* phase, const float* mass_f,
+                            const float* mass_s, const float* coeff, const int32_t* perm,
+                            float* grid_mass, float* grid_mom, int32_t accumulate,
+                            int32_t* status_dev, void* stream);
+int32_t polypic_mixture_grid_update(const polypic_grid* grid, float dt, const float* gravity,
+                                    int32_t bc_layers, const float* grid_mass,
+                                    const float* grid_mom, float* grid_vel, void* stream);
+int32_t polypic_mixture_g2p(const polypic_grid* grid, int64_t P, int32_t n_modes, float dt,
+                            const float* grid_vel, const float* x_in, const int32_t* phase_in,
+                            const int32_t* perm, float* x_out, float* coeff_out,
+                            const float* F_in, float* F_out, int32_t* phase_out,
+                            const float* mass_f_in, float* mass_f_out, const float* mass_s_in,
+                            float* mass_s_out, int32_t* status_dev, void* stream);
+
+/* ------------------------------------------------------------------------
  * Staggered (marker-and-cell) grid.  The paper applies its transfers on MAC
  * grids (section 3; Table 1's per-face mass m_{i a}, momentum (mv)_{i a} and
  * velocity v_{i a}): velocity component a lives on the faces of component a,

@@ -44,7 +44,8 @@ from .ops import (  # noqa: E402
     polypic_sort_update_workspace_bytes,
     polypic_sort_workspace_bytes,
 )
-from .stepper import AffineParticleSet, MacParticleSet, ParticleSet  # noqa: E402
+from .stepper import (AffineParticleSet, MacParticleSet, MixtureParticleSet,  # noqa: E402
+                      ParticleSet)
 from .batch import BatchedParticleSet  # noqa: E402
 from .autograd import PolyPICSteps, polypic_steps  # noqa: E402
 
@@ -56,5 +57,5 @@ __all__ = [
     "polypic_get_g2p_schedule", "polypic_set_g2p_schedule", "P2GChoice", "Batch",
     "POLYPIC_P2G_BRICKS", "POLYPIC_P2G_CELLS", "POLYPIC_P2G_DEFAULT", "POLYPIC_SCHED_LINEAR",
     "POLYPIC_SCHED_PERSISTENT", "POLYPIC_SCHED_XCD",
-    "ParticleSet", "MacParticleSet", "AffineParticleSet", "BatchedParticleSet", "PolyPICSteps", "polypic_steps",
+    "ParticleSet", "MacParticleSet", "AffineParticleSet", "MixtureParticleSet", "BatchedParticleSet", "PolyPICSteps", "polypic_steps",
 ]

@@ -51,6 +51,9 @@ EXPORTED = (
     "polypic_g2p",
     "polypic_g2p2g",
     "polypic_p2g_affine",
+    "polypic_mixture_p2g",
+    "polypic_mixture_grid_update",
+    "polypic_mixture_g2p",
     "polypic_mac_p2g",
     "polypic_mac_grid_update",
     "polypic_mac_g2p",
@@ -182,6 +185,13 @@ def load() -> ctypes.CDLL:
     lib.polypic_grid_update.argtypes = [G, f32, ctypes.POINTER(f32), i32, P, P, P, P]
     lib.polypic_g2p.restype = i32
     lib.polypic_g2p.argtypes = [G, i64, i32, f32, P, P, P, P, P, P, P, P, P, P, P]
+    lib.polypic_mixture_p2g.restype = i32
+    lib.polypic_mixture_p2g.argtypes = [G, i64, i32, P, P, P, P, P, P, P, P, i32, P, P]
+    lib.polypic_mixture_grid_update.restype = i32
+    lib.polypic_mixture_grid_update.argtypes = [G, f32, ctypes.POINTER(f32), i32, P, P, P, P]
+    lib.polypic_mixture_g2p.restype = i32
+    lib.polypic_mixture_g2p.argtypes = [G, i64, i32, f32, P, P, P, P, P, P, P, P, P, P, P, P,
+                                        P, P, P]
     lib.polypic_p2g_affine.restype = i32
     lib.polypic_p2g_affine.argtypes = [G, i64, i32, f32, P, P, P, f32, P, P, P, P, i32, P, P]
     lib.polypic_mac_p2g.restype = i32

@@ -593,6 +593,102 @@ int32_t polypic_p2g_affine(const polypic_grid* grid, int64_t P, int32_t n_modes,
   return from_hip(launch_p2g_affine(a, n_modes, accumulate != 0, (hipStream_t)stream));
 }
 
+// ---- liquid and fabric particles on one grid
+int32_t polypic_mixture_p2g(const polypic_grid* grid, int64_t P, int32_t n_modes,
+                            const float* x, const int32_t* phase, const float* mass_f,
+                            const float* mass_s, const float* coeff, const int32_t* perm,
+                            float* grid_mass, float* grid_mom, int32_t accumulate,
+                            int32_t* status_dev, void* stream) {
+  int32_t st = check_grid(grid);
+  if (st) return st;
+  if ((st = check_P(P))) return st;
+  if (!valid_modes(n_modes)) return POLYPIC_EINVAL;
+  if (!grid_mass || !grid_mom) return POLYPIC_EINVAL;
+  if (P > 0 && (!x || !coeff || !phase || !mass_f)) return POLYPIC_EINVAL;
+  MixtureP2GArgs a;
+  a.g = to_dev(grid);
+  a.P = P;
+  a.x = x;
+  a.phase = phase;
+  a.mass_f = mass_f;
+  a.mass_s = mass_s;
+  a.coeff = coeff;
+  a.perm = perm;
+  a.gm = grid_mass;
+  a.gp = grid_mom;
+  a.status = status_dev;
+  discard_stale_error();
+  return from_hip(launch_mixture_p2g(a, n_modes, accumulate != 0, (hipStream_t)stream));
+}
+
+int32_t polypic_mixture_grid_update(const polypic_grid* grid, float dt, const float* gravity,
+                                    int32_t bc_layers, const float* grid_mass,
+                                    const float* grid_mom, float* grid_vel, void* stream) {
+  int32_t st = check_grid(grid);
+  if (st) return st;
+  if (!gravity || !grid_mass || !grid_mom || !grid_vel) return POLYPIC_EINVAL;
+  if (!isfinite(dt) || bc_layers < 0) return POLYPIC_EINVAL;
+  for (int k = 0; k < 3; ++k)
+    if (!isfinite(gravity[k])) return POLYPIC_EINVAL;
+  const size_t N = (size_t)n_nodes(grid);
+  discard_stale_error();
+  for (int ph = 0; ph < 2; ++ph) {
+    GridUpdateArgs a;
+    a.nx = grid->nx;
+    a.ny = grid->ny;
+    a.nz = grid->nz;
+    a.dt = dt;
+    a.g0 = gravity[0];
+    a.g1 = gravity[1];
+    a.g2 = gravity[2];
+    a.bc_layers = bc_layers;
+    a.gm = grid_mass + ph * N;
+    a.gp = grid_mom + ph * 3 * N;
+    a.gv = grid_vel + ph * 3 * N;
+    if ((st = from_hip(launch_grid_update(a, (hipStream_t)stream)))) return st;
+  }
+  return POLYPIC_OK;
+}
+
+int32_t polypic_mixture_g2p(const polypic_grid* grid, int64_t P, int32_t n_modes, float dt,
+                            const float* grid_vel, const float* x_in, const int32_t* phase_in,
+                            const int32_t* perm, float* x_out, float* coeff_out,
+                            const float* F_in, float* F_out, int32_t* phase_out,
+                            const float* mass_f_in, float* mass_f_out, const float* mass_s_in,
+                            float* mass_s_out, int32_t* status_dev, void* stream) {
+  int32_t st = check_grid(grid);
+  if (st) return st;
+  if ((st = check_P(P))) return st;
+  if (!valid_modes(n_modes) || !isfinite(dt)) return POLYPIC_EINVAL;
+  if (P == 0) return POLYPIC_OK;
+  if (!grid_vel || !x_in || !phase_in || !coeff_out) return POLYPIC_EINVAL;
+  if ((F_in == nullptr) != (F_out == nullptr)) return POLYPIC_EINVAL;
+  if ((mass_f_in == nullptr) != (mass_f_out == nullptr)) return POLYPIC_EINVAL;
+  if ((mass_s_in == nullptr) != (mass_s_out == nullptr)) return POLYPIC_EINVAL;
+  MixtureG2PArgs a;
+  a.g = to_dev(grid);
+  a.P = P;
+  a.dt = dt;
+  a.dx = grid->dx;
+  clamp_bounds(grid, a.lo, a.hi);
+  a.gv = grid_vel;
+  a.x_in = x_in;
+  a.phase_in = phase_in;
+  a.perm = perm;
+  a.x_out = x_out;
+  a.coeff_out = coeff_out;
+  a.F_in = F_in;
+  a.F_out = F_out;
+  a.phase_out = phase_out;
+  a.mass_f_in = mass_f_in;
+  a.mass_f_out = mass_f_out;
+  a.mass_s_in = mass_s_in;
+  a.mass_s_out = mass_s_out;
+  a.status = status_dev;
+  discard_stale_error();
+  return from_hip(launch_mixture_g2p(a, n_modes, (hipStream_t)stream));
+}
+
 // ---- staggered (MAC) grid
 int32_t polypic_mac_p2g(const polypic_grid* grid, int64_t P, int32_t n_modes, const float* x,
                         const float* mass, float uniform_mass, const float* coeff,

@@ -265,4 +265,44 @@ struct AffineP2GArgs {
 };
 hipError_t launch_p2g_affine(const AffineP2GArgs& a, int n_modes, bool accumulate, hipStream_t s);
 
+// ---- liquid and fabric particles on one grid (two channel sets per node)
+struct MixtureP2GArgs {
+  GridDev g;
+  int64_t P;
+  const float* x;       // [3][P]
+  const int32_t* phase; // [P]: 0 fluid, 1 solid
+  const float* mass_f;  // [P] fluid mass (absorbed fluid of a solid particle)
+  const float* mass_s;  // [P] solid mass or nullptr (0)
+  const float* coeff;   // [3][NR][P]
+  const int32_t* perm;  // [P] or nullptr
+  float* gm;            // [2][N]
+  float* gp;            // [2][3][N]
+  int32_t* status;
+};
+hipError_t launch_mixture_p2g(const MixtureP2GArgs& a, int n_modes, bool accumulate,
+                              hipStream_t s);
+
+struct MixtureG2PArgs {
+  GridDev g;
+  int64_t P;
+  float dt;
+  float dx;
+  float lo[3], hi[3];
+  const float* gv;        // [2][3][N]
+  const float* x_in;
+  const int32_t* phase_in;
+  const int32_t* perm;
+  float* x_out;
+  float* coeff_out;
+  const float* F_in;
+  float* F_out;
+  int32_t* phase_out;
+  const float* mass_f_in;
+  float* mass_f_out;
+  const float* mass_s_in;
+  float* mass_s_out;
+  int32_t* status;
+};
+hipError_t launch_mixture_g2p(const MixtureG2PArgs& a, int n_modes, hipStream_t s);
+
 }  // namespace polypic

@@ -249,6 +249,64 @@ def polypic_p2g_affine(grid: polypic_grid, n_modes: int, dt: float, x: torch.Ten
         _ptr(status_dev, torch.int32, 1, "status_dev"), _stream()), "polypic_p2g_affine")
 
 
+# ---- liquid and fabric particles on one grid: grid_mass [2][N], grid_mom / grid_vel [2][3][N]
+def polypic_mixture_p2g(grid: polypic_grid, n_modes: int, x: torch.Tensor, phase: torch.Tensor,
+                        mass_f: torch.Tensor, coeff: torch.Tensor, grid_mass: torch.Tensor,
+                        grid_mom: torch.Tensor, mass_s: Optional[torch.Tensor] = None,
+                        perm: Optional[torch.Tensor] = None, accumulate: bool = False,
+                        status_dev: Optional[torch.Tensor] = None) -> None:
+    P = x.numel() // 3
+    N = n_nodes(grid)
+    check(_lib.load().polypic_mixture_p2g(
+        ctypes.byref(grid), P, int(n_modes), _ptr(x, torch.float32, 3 * P, "x"),
+        _ptr(phase, torch.int32, P, "phase"), _ptr(mass_f, torch.float32, P, "mass_f"),
+        _ptr(mass_s, torch.float32, P, "mass_s"),
+        _ptr(coeff, torch.float32, 3 * int(n_modes) * P, "coeff"),
+        _ptr(perm, torch.int32, P, "perm"), _ptr(grid_mass, torch.float32, 2 * N, "grid_mass"),
+        _ptr(grid_mom, torch.float32, 6 * N, "grid_mom"), int(bool(accumulate)),
+        _ptr(status_dev, torch.int32, 1, "status_dev"), _stream()), "polypic_mixture_p2g")
+
+
+def polypic_mixture_grid_update(grid: polypic_grid, dt: float, gravity: Sequence[float],
+                                bc_layers: int, grid_mass: torch.Tensor, grid_mom: torch.Tensor,
+                                grid_vel: torch.Tensor) -> None:
+    N = n_nodes(grid)
+    g3 = (ctypes.c_float * 3)(*[float(v) for v in gravity])
+    check(_lib.load().polypic_mixture_grid_update(
+        ctypes.byref(grid), float(dt), g3, int(bc_layers),
+        _ptr(grid_mass, torch.float32, 2 * N, "grid_mass"),
+        _ptr(grid_mom, torch.float32, 6 * N, "grid_mom"),
+        _ptr(grid_vel, torch.float32, 6 * N, "grid_vel"), _stream()),
+        "polypic_mixture_grid_update")
+
+
+def polypic_mixture_g2p(grid: polypic_grid, n_modes: int, dt: float, grid_vel: torch.Tensor,
+                        x_in: torch.Tensor, phase_in: torch.Tensor, coeff_out: torch.Tensor,
+                        perm: Optional[torch.Tensor] = None, x_out: Optional[torch.Tensor] = None,
+                        F_in: Optional[torch.Tensor] = None, F_out: Optional[torch.Tensor] = None,
+                        phase_out: Optional[torch.Tensor] = None,
+                        mass_f_in: Optional[torch.Tensor] = None,
+                        mass_f_out: Optional[torch.Tensor] = None,
+                        mass_s_in: Optional[torch.Tensor] = None,
+                        mass_s_out: Optional[torch.Tensor] = None,
+                        status_dev: Optional[torch.Tensor] = None) -> None:
+    P = x_in.numel() // 3
+    N = n_nodes(grid)
+    check(_lib.load().polypic_mixture_g2p(
+        ctypes.byref(grid), P, int(n_modes), float(dt),
+        _ptr(grid_vel, torch.float32, 6 * N, "grid_vel"),
+        _ptr(x_in, torch.float32, 3 * P, "x_in"), _ptr(phase_in, torch.int32, P, "phase_in"),
+        _ptr(perm, torch.int32, P, "perm"), _ptr(x_out, torch.float32, 3 * P, "x_out"),
+        _ptr(coeff_out, torch.float32, 3 * int(n_modes) * P, "coeff_out"),
+        _ptr(F_in, torch.float32, 9 * P, "F_in"), _ptr(F_out, torch.float32, 9 * P, "F_out"),
+        _ptr(phase_out, torch.int32, P, "phase_out"),
+        _ptr(mass_f_in, torch.float32, P, "mass_f_in"),
+        _ptr(mass_f_out, torch.float32, P, "mass_f_out"),
+        _ptr(mass_s_in, torch.float32, P, "mass_s_in"),
+        _ptr(mass_s_out, torch.float32, P, "mass_s_out"),
+        _ptr(status_dev, torch.int32, 1, "status_dev"), _stream()), "polypic_mixture_g2p")
+
+
 # ---- staggered (MAC) grid: face arrays [3][N], component a's faces at a * N + node index
 def polypic_mac_p2g(grid: polypic_grid, n_modes: int, x: torch.Tensor, coeff: torch.Tensor,
                     face_mass: torch.Tensor, face_mom: torch.Tensor,

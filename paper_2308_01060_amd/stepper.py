@@ -274,3 +274,67 @@ class AffineParticleSet(ParticleSet):
         self.x_fit, self.x_fit_next = self.x_fit_next, self.x_fit
         self.fit_valid = self._next_fit_valid
         self._next_fit_valid = False
+
+
+class MixtureParticleSet(ParticleSet):
+    """Liquid and fabric particles in one array on one grid (section 3.4): per particle a
+    phase (0 fluid, 1 solid), the fluid mass m_f (for a solid point, its absorbed fluid)
+    and the solid mass m_s; the grid holds a fluid and a solid set of channels
+    (grid_mass [2][N], grid_mom and grid_vel [2][3][N]).  A step is sort ->
+    polypic_mixture_p2g -> polypic_mixture_grid_update -> polypic_mixture_g2p, and the
+    per-particle arrays follow the sort like the positions."""
+
+    def __init__(self, grid, n_modes: int, x: torch.Tensor, coeff: torch.Tensor,
+                 phase: torch.Tensor, mass_f: torch.Tensor,
+                 mass_s: Optional[torch.Tensor] = None, **kw):
+        kw["fused"] = False
+        kw.pop("mass", None)
+        super().__init__(grid, n_modes, x, coeff, **kw)
+        dev = self.x.device
+        N = ops.n_nodes(grid)
+        f32 = dict(dtype=torch.float32, device=dev)
+        self.phase = phase.to(dtype=torch.int32, device=dev).contiguous()
+        self.mass_f = mass_f.to(**f32).contiguous()
+        self.mass_s = None if mass_s is None else mass_s.to(**f32).contiguous()
+        self.phase_next = torch.empty_like(self.phase)
+        self.mass_f_next = torch.empty_like(self.mass_f)
+        self.mass_s_next = None if self.mass_s is None else torch.empty_like(self.mass_s)
+        self.grid_mass = torch.empty(2 * N, **f32)
+        self.grid_mom = torch.empty(6 * N, **f32)
+        self.grid_vel = torch.empty(6 * N, **f32)
+
+    def p2g(self, use_perm: bool = True, use_keys: bool = True):
+        ops.polypic_mixture_p2g(self.grid, self.n_modes, self.x, self.phase, self.mass_f,
+                                self.coeff, self.grid_mass, self.grid_mom, mass_s=self.mass_s,
+                                perm=self.perm if use_perm else None, status_dev=self.status)
+        self.grid_current = True
+
+    def autotune(self):
+        """The mixture kernels have one configuration: only the sort runs."""
+        self.sort()
+        return None
+
+    def grid_update(self):
+        ops.polypic_mixture_grid_update(self.grid, self.dt, self.gravity, self.bc_layers,
+                                        self.grid_mass, self.grid_mom, self.grid_vel)
+
+    def g2p(self, use_perm: bool = True, advect: bool = True):
+        ops.polypic_mixture_g2p(self.grid, self.n_modes, self.dt, self.grid_vel, self.x,
+                                self.phase, self.coeff_next,
+                                perm=self.perm if use_perm else None,
+                                x_out=self.x_next if advect else None, F_in=self.F,
+                                F_out=self.F_next, phase_out=self.phase_next,
+                                mass_f_in=self.mass_f, mass_f_out=self.mass_f_next,
+                                mass_s_in=self.mass_s, mass_s_out=self.mass_s_next,
+                                status_dev=self.status)
+        self._next_grid_current = False
+
+    def g2p2g(self, use_perm: bool = True):
+        raise RuntimeError("a mixture set steps with separate P2G and G2P calls")
+
+    def swap(self, use_perm: bool = True):
+        super().swap(use_perm)
+        self.phase, self.phase_next = self.phase_next, self.phase
+        self.mass_f, self.mass_f_next = self.mass_f_next, self.mass_f
+        if self.mass_s is not None:
+            self.mass_s, self.mass_s_next = self.mass_s_next, self.mass_s

@@ -398,3 +398,32 @@ def test_mac_calls_reject_bad_arguments_on_the_host():
                                None, None, None, None, None) == _lib.POLYPIC_EINVAL
     assert lib.polypic_mac_g2p(ctypes.byref(g), 0, 4, 1e-4, None, None, None, None, None, None,
                                None, None, None, None, None) == _lib.POLYPIC_OK
+
+
+def test_mixture_and_affine_calls_reject_bad_arguments_on_the_host():
+    lib = _lib.load()
+    g = grid()
+    g3 = (ctypes.c_float * 3)(0.0, -9.8, 0.0)
+    # mixture P2G: phase and mass_f are required for P > 0
+    assert lib.polypic_mixture_p2g(ctypes.byref(g), 10, 4, FAKE, None, FAKE, None, FAKE, None,
+                                   FAKE, FAKE, 0, None, None) == _lib.POLYPIC_EINVAL
+    assert lib.polypic_mixture_p2g(ctypes.byref(g), 10, 4, FAKE, FAKE, None, None, FAKE, None,
+                                   FAKE, FAKE, 0, None, None) == _lib.POLYPIC_EINVAL
+    assert lib.polypic_mixture_p2g(ctypes.byref(g), 10, 3, FAKE, FAKE, FAKE, None, FAKE, None,
+                                   FAKE, FAKE, 0, None, None) == _lib.POLYPIC_EINVAL
+    assert lib.polypic_mixture_grid_update(ctypes.byref(g), 1e-4, g3, -1, FAKE, FAKE, FAKE,
+                                           None) == _lib.POLYPIC_EINVAL
+    # mixture G2P: phase_in required, unpaired per-particle arrays rejected
+    assert lib.polypic_mixture_g2p(ctypes.byref(g), 10, 4, 1e-4, FAKE, FAKE, None, None, None,
+                                   FAKE, None, None, None, None, None, None, None, None,
+                                   None) == _lib.POLYPIC_EINVAL
+    assert lib.polypic_mixture_g2p(ctypes.byref(g), 10, 4, 1e-4, FAKE, FAKE, FAKE, None, None,
+                                   FAKE, None, None, None, FAKE, None, None, None, None,
+                                   None) == _lib.POLYPIC_EINVAL
+    # affine P2G: bad dt, bad mode count, null outputs
+    assert lib.polypic_p2g_affine(ctypes.byref(g), 10, 4, float("nan"), FAKE, None, None, 1.0,
+                                  FAKE, None, FAKE, FAKE, 0, None, None) == _lib.POLYPIC_EINVAL
+    assert lib.polypic_p2g_affine(ctypes.byref(g), 10, 2, 1e-4, FAKE, None, None, 1.0, FAKE,
+                                  None, FAKE, FAKE, 0, None, None) == _lib.POLYPIC_EINVAL
+    assert lib.polypic_p2g_affine(ctypes.byref(g), 10, 4, 1e-4, FAKE, None, None, 1.0, FAKE,
+                                  None, None, FAKE, 0, None, None) == _lib.POLYPIC_EINVAL

@@ -71,6 +71,9 @@ def test_affine_p2g_matches_oracle(n_modes, sort):
 
 
 def test_affine_p2g_at_zero_dt_equals_polypic_p2g():
+    """dt = 0 without x_fit is the plain P2G (Eq. 13).  The two kernels sum in different
+    float32 orders (mode products per node against three separable contractions), so
+    they agree to the parity bar, not bit for bit."""
     pp = require_gpu()
     gs, x, _, c, m = _scene(2)
     g = pp.grid_from_spec(gs)
@@ -80,7 +83,7 @@ def test_affine_p2g_at_zero_dt_equals_polypic_p2g():
     gp0 = torch.empty(3 * N, device="cuda")
     pp.ops.polypic_p2g(g, 27, dev(x), dev(c), gm0, gp0, mass=dev(m))
     torch.cuda.synchronize()
-    assert rel(gm, host(gm0)) <= 1e-6 and rel(gp, host(gp0)) <= 1e-6
+    assert rel(gm, host(gm0)) <= TOL_NORMWISE and rel(gp, host(gp0)) <= TOL_NORMWISE
 
 
 @pytest.mark.parametrize("case_idx", range(4))

@@ -220,6 +220,46 @@ def config2_fabric(seed: int = 0, n: int = 256, side: int = 1000) -> Scene:
     return Scene(f"fabric_{n}cube_{P}", g, x, c, mass, 1.0, F=F, dt=1e-4, bc_layers=1)
 
 
+@dataclasses.dataclass
+class MixtureScene:
+    """Fluid particles and fabric points in one array on one grid (phase 0 / 1)."""
+
+    name: str
+    grid: GridSpec
+    x: np.ndarray        # (3, P) float32
+    coeff: np.ndarray    # (3, 27, P) float32
+    phase: np.ndarray    # (P,) int32: 0 fluid, 1 solid
+    mass_f: np.ndarray   # (P,) float32: fluid mass, or a fabric point's absorbed fluid
+    mass_s: np.ndarray   # (P,) float32: solid mass (0 for fluid particles)
+    F: np.ndarray        # (9, P) float32 (identity for fluid particles)
+    dt: float = 1e-4
+    gravity: Tuple[float, float, float] = GRAVITY
+    bc_layers: int = 1
+
+    @property
+    def P(self) -> int:
+        return int(self.x.shape[1])
+
+
+def liquid_fabric_shared(seed: int = 0, n: int = 256, side: int = 1000) -> MixtureScene:
+    """The liquid + fabric workload with both sets on ONE grid: the falling fluid block of
+    config2_fluid (fluid mass 1) above the fabric sheet of config2_fabric (solid mass
+    m_s = 1, absorbed fluid m_f ~ U[0, 0.5], F = I + N(0, 0.01)), fluid first.  Smaller n
+    and side give the same layout at test sizes."""
+    fl = config2_fluid(seed, n)
+    fb = config2_fabric(seed, n, side)
+    Pf, Pb = fl.P, fb.P
+    x = np.concatenate([fl.x, fb.x], axis=1)
+    c = np.concatenate([fl.coeff, fb.coeff], axis=2)
+    phase = np.concatenate([np.zeros(Pf, np.int32), np.ones(Pb, np.int32)])
+    mass_f = np.concatenate([np.ones(Pf, np.float32), (fb.mass - 1.0).astype(np.float32)])
+    mass_s = np.concatenate([np.zeros(Pf, np.float32), np.ones(Pb, np.float32)])
+    F = np.concatenate([np.tile(np.eye(3, dtype=np.float32).reshape(9, 1), (1, Pf)), fb.F],
+                       axis=1)
+    return MixtureScene(f"liquid_fabric_shared_{n}cube_{Pf}_{Pb}", fl.grid, x, c, phase,
+                        mass_f, mass_s, F, dt=1e-4, bc_layers=1)
+
+
 def config3_fd(seed: int = 0) -> Scene:
     """Small differentiable case: 16^3 cells, 8^3-cell central block, 8 ppc (4,096)."""
     rng = np.random.default_rng(seed)
