@@ -413,6 +413,7 @@ def _set_timing(pp, torch, ps, steps: int, warmup: int, bpp: int, workload: str)
     for _ in range(warmup):
         ps.step()
     choice = ps.autotune()
+    lane_group = ps.autotune_fused()
     torch.cuda.synchronize()
     wall, phase = time_steps(ps, steps, torch)
     if ps.status_flags() != 0:
@@ -429,6 +430,7 @@ def _set_timing(pp, torch, ps, steps: int, warmup: int, bpp: int, workload: str)
         "phase_ms": {k: round(v, 4) for k, v in phase.items()},
         "p2g_config": {"path": "cells" if choice.path == 1 else "bricks",
                        "block": choice.block, "schedule": choice.schedule},
+        "g2p2g_lane_group": lane_group,
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": measured_traffic("g2p2g", workload), "kernel": "g2p2g",
@@ -814,7 +816,8 @@ def main():
                         bc_layers=scene.bc_layers, track_order=False)
     for _ in range(args.warmup):
         ps.step()
-    p2g_choice = ps.autotune()  # library autotuner, outside the timed region
+    p2g_choice = ps.autotune()  # library autotuners, outside the timed region
+    lane_group = ps.autotune_fused()
     torch.cuda.synchronize()
     wall, phase = time_steps(ps, args.steps, torch)
     if ps.status_flags() != 0:
@@ -950,6 +953,7 @@ def main():
         "p2g_config": {"path": "cells" if p2g_choice.path == 1 else "bricks",
                        "block": p2g_choice.block, "schedule": p2g_choice.schedule,
                        "chosen_by": "polypic_autotune_p2g"},
+        "g2p2g_config": {"lane_group": lane_group, "chosen_by": "polypic_autotune_g2p2g"},
         "phase_ms": {k: round(v, 4) for k, v in phase.items()},
         "unfused": unfused,
         "sort": {"timed": "polypic_sort_update (exact re-sort from the previous step's keys)",

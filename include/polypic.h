@@ -433,6 +433,25 @@ int32_t polypic_mac_g2p(const polypic_grid* grid, int64_t P, int32_t n_modes, fl
                         const float* mass_in, float* mass_out, int32_t* status_dev,
                         void* stream);
 
+/* Launch choice of polypic_g2p2g per mode count: the number of particles of
+ * consecutive sorted slots whose node values are added across lanes before one
+ * brick atomic (2, the default, or 4; -1 restores the default).  The lanes' groups
+ * are spread over the workgroup's chunk 8 or 16 slots apart, so 4 suits about 16
+ * particles per cell.  polypic_autotune_g2p2g runs the call (same arguments and
+ * outputs as polypic_g2p2g) once per candidate, timed with HIP events on `stream`
+ * (one untimed and three timed runs each; it synchronises the stream), keeps the
+ * fastest for later calls at this mode count and writes it to *lane_group_out;
+ * the outputs are those of a final run with the choice.  The choice changes only
+ * the order of the grid sums. */
+int32_t polypic_set_g2p2g_config(int32_t n_modes, int32_t lane_group);
+int32_t polypic_get_g2p2g_config(int32_t n_modes, int32_t* lane_group);
+int32_t polypic_autotune_g2p2g(const polypic_grid* grid, int64_t P, int32_t n_modes, float dt,
+                               const float* grid_vel, const float* x_in, const int32_t* perm,
+                               float* x_out, float* coeff_out, const float* F_in, float* F_out,
+                               const float* mass_in, float* mass_out, float uniform_mass,
+                               float* grid_mass, float* grid_mom, int32_t* lane_group_out,
+                               void* stream);
+
 /* ------------------------------------------------------------------------
  * Adjoint (reverse mode) of one step.  For a scalar loss L of the step's
  * outputs, these propagate dL/d(output) to dL/d(input) through the same

@@ -50,6 +50,9 @@ EXPORTED = (
     "polypic_grid_update",
     "polypic_g2p",
     "polypic_g2p2g",
+    "polypic_set_g2p2g_config",
+    "polypic_get_g2p2g_config",
+    "polypic_autotune_g2p2g",
     "polypic_p2g_affine",
     "polypic_mixture_p2g",
     "polypic_mixture_grid_update",
@@ -202,6 +205,13 @@ def load() -> ctypes.CDLL:
     lib.polypic_mac_g2p.argtypes = [G, i64, i32, f32, P, P, P, P, P, P, P, P, P, P, P]
     lib.polypic_g2p2g.restype = i32
     lib.polypic_g2p2g.argtypes = [G, i64, i32, f32, P, P, P, P, P, P, P, P, P, f32, P, P, P, P]
+    lib.polypic_set_g2p2g_config.restype = i32
+    lib.polypic_set_g2p2g_config.argtypes = [i32, i32]
+    lib.polypic_get_g2p2g_config.restype = i32
+    lib.polypic_get_g2p2g_config.argtypes = [i32, pi]
+    lib.polypic_autotune_g2p2g.restype = i32
+    lib.polypic_autotune_g2p2g.argtypes = [G, i64, i32, f32, P, P, P, P, P, P, P, P, P, f32, P,
+                                           P, pi, P]
     lib.polypic_g2p_backward.restype = i32
     lib.polypic_g2p_backward.argtypes = [G, i64, i32, f32, P, P, P, P, P, P, i32, P, P, P]
     lib.polypic_grid_update_backward.restype = i32

@@ -11,10 +11,12 @@
 // 27 modes cost 27 + 9 + 3 multiply-adds on the per-axis factors (1, z', ghat(z')),
 // against 3 x 81 per component for the whole separable stencil of the plain P2G.
 //
-// Scatter: one thread per sorted slot (the lanes of a wavefront every fourth slot of
-// the chunk), FP64 LDS bricks of 6^3 nodes x 4 channels for the first three distinct
-// 4^3 tiles of the chunk, one float atomic per non-zero brick value at the flush;
-// other tiles add straight to HBM.
+// Scatter: one thread per sorted slot, lane pairs on consecutive slots and the pairs
+// of a wavefront spread over the chunk; a pair with the same stencil adds its node
+// values across lanes (one DPP fold each), and one lane adds them, one z plane at a
+// time, to FP64 LDS bricks of 6^3 nodes x 4 channels for the first three distinct 4^3
+// tiles of the chunk; one float atomic per non-zero brick value at the flush; other
+// tiles add straight to HBM.
 #include "polypic_bricks.hpp"
 #include "polypic_internal.hpp"
 
@@ -36,7 +38,7 @@ __global__ __launch_bounds__(kAffBS) void affine_p2g_kernel(AffineP2GArgs a) {
   const int tid = threadIdx.x;
   const int lane = tid & (kWave - 1);
   const int wv = tid / kWave;
-  const int slot = lane * NW + wv;
+  const int slot = pair_slot<NW>(tid);
   const int64_t i = (int64_t)blockIdx.x * BS + slot;
   const bool in = i < a.P;
   const size_t Ps = (size_t)a.P;
@@ -110,26 +112,58 @@ __global__ __launch_bounds__(kAffBS) void affine_p2g_kernel(AffineP2GArgs a) {
   const int seg = plan_bricks<BS, kAffK>(plan, seg_tile, tid, slot,
                                          valid ? brick_tile_id(0, b[0], b[1], b[2]) : kNoTile);
   const bool lds = valid && seg >= 0 && seg < kAffK;
-
-  if (valid) {
+  // a pair folds when both lanes share stencil and brick; every lane runs the scatter
+  // below (an idle one with zero mass and coefficients), since the folds read the
+  // partner lane through DPP
+  const PairFold pf = pair_fold_plan(valid ? ((b[2] * 1024 + b[1]) * 1024 + b[0]) : -1 - lane,
+                                     seg, valid, lane);
+  {
     const Basis1D bx = basis_p2g(t[0]), by = basis_p2g(t[1]), bz = basis_p2g(t[2]);
     const int lbase = (b[0] & 3) + kBrickSY * (b[1] & 3) + kBrickSZ * (b[2] & 3);
     const size_t N = (size_t)nx * ny * nz;
     const size_t gbase = ((size_t)b[2] * ny + b[1]) * nx + b[0];
     const size_t sy = (size_t)nx, sz = (size_t)nx * ny;
+    // fold a plane of node values over the pair and add it to channel ch
+    auto emit_plane = [&](int ch, int jz, float (&v)[9]) {
+      float w[9];
+#pragma unroll
+      for (int k = 0; k < 9; ++k) w[k] = pair_fold(v[k], pf.f);
+      if (!pf.emit) return;
+      if (lds) {
+        double* const bb = brick + ((lds ? seg : 0) * 4 + ch) * kBrickV + lbase + kBrickSZ * jz;
+#pragma unroll
+        for (int jy = 0; jy < 3; ++jy)
+#pragma unroll
+          for (int jx = 0; jx < 3; ++jx)
+            atomicAdd(bb + jx + kBrickSY * jy, (double)w[jx + 3 * jy]);
+      } else {
+        float* const gc = (ch == 0 ? a.gm : a.gp + (size_t)(ch - 1) * N) + gbase + sz * jz;
+#pragma unroll
+        for (int jy = 0; jy < 3; ++jy)
+#pragma unroll
+          for (int jx = 0; jx < 3; ++jx) atomicAdd(gc + jx + sy * jy, w[jx + 3 * jy]);
+      }
+    };
 #pragma unroll 1
     for (int al = 0; al < 3; ++al) {
       float c[27];
 #pragma unroll
-      for (int r = 0; r < NR; ++r) c[r] = a.coeff[((size_t)al * NR + r) * Ps + p];
+      for (int r = 0; r < 27; ++r) c[r] = 0.0f;
+      if (valid) {
+#pragma unroll
+        for (int r = 0; r < NR; ++r) c[r] = a.coeff[((size_t)al * NR + r) * Ps + p];
+      }
       // one z plane at a time keeps the node values' temporaries few (not unrolled)
 #pragma unroll 1
-      for (int jz = 0; jz < 3; ++jz)
+      for (int jz = 0; jz < 3; ++jz) {
+        const float zz = jz == 0 ? bz.z[0] : (jz == 1 ? bz.z[1] : bz.z[2]);
+        const float wz = jz == 0 ? bz.w[0] : (jz == 1 ? bz.w[1] : bz.w[2]);
+        float wv[9], vv[9];
 #pragma unroll
         for (int jy = 0; jy < 3; ++jy)
 #pragma unroll
           for (int jx = 0; jx < 3; ++jx) {
-            const float zh[3] = {bx.z[jx], by.z[jy], jz == 0 ? bz.z[0] : (jz == 1 ? bz.z[1] : bz.z[2])};
+            const float zh[3] = {bx.z[jx], by.z[jy], zz};
             float phi[3][3];
 #pragma unroll
             for (int ax = 0; ax < 3; ++ax) {
@@ -156,19 +190,13 @@ __global__ __launch_bounds__(kAffBS) void affine_p2g_kernel(AffineP2GArgs a) {
               }
               V = kx == 0 ? V + sxy : fmaf(sxy, phi[0][kx], V);
             }
-            const float wz = jz == 0 ? bz.w[0] : (jz == 1 ? bz.w[1] : bz.w[2]);
             const float W = m * bx.w[jx] * by.w[jy] * wz;
-            const int lo = jx + kBrickSY * jy + kBrickSZ * jz;
-            const size_t go = gbase + jx + sy * jy + sz * jz;
-            if (lds) {
-              double* const bb = brick + seg * 4 * kBrickV + lbase + lo;
-              if (al == 0) atomicAdd(bb, (double)W);
-              atomicAdd(bb + (1 + al) * kBrickV, (double)(W * V));
-            } else {
-              if (al == 0) atomicAdd(a.gm + go, W);
-              atomicAdd(a.gp + (size_t)al * N + go, W * V);
-            }
+            wv[jx + 3 * jy] = W;
+            vv[jx + 3 * jy] = W * V;
           }
+        if (al == 0) emit_plane(0, jz, wv);
+        emit_plane(1 + al, jz, vv);
+      }
     }
   }
   __syncthreads();

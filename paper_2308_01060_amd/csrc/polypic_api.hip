@@ -100,6 +100,13 @@ P2GConfig to_config(const P2GChoice& c) {
 }
 
 std::atomic<int> g_g2p_sched{POLYPIC_SCHED_LINEAR};
+// lane-group size of the fused G2P2G kernel per mode count (0: the default, pairs)
+std::atomic<int> g_fused_lane[28];
+
+int fused_lane_group(int n_modes) {
+  const int v = g_fused_lane[n_modes].load();
+  return v == 4 ? 4 : 2;
+}
 std::mutex g_tune_mutex;
 P2GChoice g_tune[28];
 
@@ -880,8 +887,59 @@ int32_t polypic_g2p2g(const polypic_grid* grid, int64_t P, int32_t n_modes, floa
   a.gp2 = grid_mom + 2 * N;
   a.status = status_dev;
   a.gstride = N;
+  a.lane_group = fused_lane_group(n_modes);
   discard_stale_error();
   return from_hip(launch_g2p2g(a, n_modes, (hipStream_t)stream));
+}
+
+int32_t polypic_set_g2p2g_config(int32_t n_modes, int32_t lane_group) {
+  if (!valid_modes(n_modes)) return POLYPIC_EINVAL;
+  if (lane_group != -1 && lane_group != 2 && lane_group != 4) return POLYPIC_EINVAL;
+  g_fused_lane[n_modes].store(lane_group == -1 ? 0 : lane_group);
+  return POLYPIC_OK;
+}
+
+int32_t polypic_get_g2p2g_config(int32_t n_modes, int32_t* lane_group) {
+  if (!valid_modes(n_modes) || !lane_group) return POLYPIC_EINVAL;
+  *lane_group = fused_lane_group(n_modes);
+  return POLYPIC_OK;
+}
+
+int32_t polypic_autotune_g2p2g(const polypic_grid* grid, int64_t P, int32_t n_modes, float dt,
+                               const float* grid_vel, const float* x_in, const int32_t* perm,
+                               float* x_out, float* coeff_out, const float* F_in, float* F_out,
+                               const float* mass_in, float* mass_out, float uniform_mass,
+                               float* grid_mass, float* grid_mom, int32_t* lane_group_out,
+                               void* stream) {
+  // the candidates run the call itself: validate once through it with the default
+  const int keep = g_fused_lane[n_modes < 0 || n_modes > 27 ? 0 : n_modes].load();
+  int32_t st = polypic_g2p2g(grid, P, n_modes, dt, grid_vel, x_in, perm, x_out, coeff_out, F_in,
+                             F_out, mass_in, mass_out, uniform_mass, grid_mass, grid_mom, nullptr,
+                             stream);
+  if (st) return st;
+  const hipStream_t s = (hipStream_t)stream;
+  const int cand[2] = {2, 4};
+  int bi = 0;
+  st = time_candidates(
+      2, s,
+      [&](int k) {
+        g_fused_lane[n_modes].store(cand[k]);
+        return polypic_g2p2g(grid, P, n_modes, dt, grid_vel, x_in, perm, x_out, coeff_out, F_in,
+                             F_out, mass_in, mass_out, uniform_mass, grid_mass, grid_mom,
+                             nullptr, stream);
+      },
+      &bi);
+  if (st) {
+    g_fused_lane[n_modes].store(keep);
+    return st;
+  }
+  g_fused_lane[n_modes].store(cand[bi]);
+  if (lane_group_out) *lane_group_out = cand[bi];
+  // the outputs hold the last candidate's results: rerun the chosen one so that they
+  // are the call's (the two differ only in the order of the grid sums)
+  return polypic_g2p2g(grid, P, n_modes, dt, grid_vel, x_in, perm, x_out, coeff_out, F_in,
+                       F_out, mass_in, mass_out, uniform_mass, grid_mass, grid_mom, nullptr,
+                       stream);
 }
 
 int32_t polypic_g2p_backward(const polypic_grid* grid, int64_t P, int32_t n_modes, float dt,
@@ -1201,6 +1259,7 @@ int32_t polypic_batch_g2p2g(const polypic_batch* batch, int32_t n_modes, float d
   a.gp2 = grid_mom + 2 * N;
   a.status = status_dev;
   a.gstride = N;
+  a.lane_group = 2;  // the batched kernel folds lane pairs
   discard_stale_error();
   return from_hip(launch_g2p2g_batch(a, batch_table(batch), batch->n_scenes, n_modes,
                                      (hipStream_t)stream));

@@ -71,6 +71,33 @@ __device__ __forceinline__ int plan_bricks(BrickPlan<BS>& plan, uint64_t* seg_ti
   return run < 0 ? -1 : (run < kWave ? plan.run_brick[run] : K + run);
 }
 
+// Slot of a thread for lane-pair scatters: pairs of consecutive sorted slots (which in
+// cell order usually share a cell, hence a stencil), the pairs of a wavefront spread
+// over the chunk NW pairs apart so that they sit in different cells.
+template <int NW>
+__device__ __forceinline__ int pair_slot(int tid) {
+  const int lane = tid & (kWave - 1);
+  const int wv = tid / kWave;
+  return ((((lane >> 1) * NW + wv)) << 1) | (lane & 1);
+}
+
+// Lane-pair fold of a scatter: `key` identifies what a lane scatters to (its stencil
+// base, and anything else that must match; unique per lane when it scatters nothing),
+// `seg` its brick.  Both lanes of a pair call it (it exchanges through DPP).  The even
+// lane of a matching pair emits the sum of both lanes' node values, every other
+// scattering lane its own.
+struct PairFold {
+  float f;    // 1 where the partner's values are added, else 0
+  bool emit;  // this lane does the atomics
+};
+__device__ __forceinline__ PairFold pair_fold_plan(int key, int seg, bool scatters, int lane) {
+  const bool pair = key == pair_swap_i(key) && seg == pair_swap_i(seg);
+  PairFold pf;
+  pf.f = pair ? 1.0f : 0.0f;
+  pf.emit = scatters && (!pair || (lane & 1) == 0);
+  return pf;
+}
+
 // Origin (first node) of the brick of tile `tl` along each axis, for bricks that start
 // `below` nodes under the tile's first base node.
 __device__ __forceinline__ void brick_origin(uint64_t tl, int below, int& o0, int& o1, int& o2) {

@@ -51,13 +51,16 @@ __device__ __forceinline__ int stage_pos(int s) {
 // bound holds the registers to the 128 that allow them too.  At 27 modes that
 // spills 6 registers and still wins (measured, 4.19 M particles: 0.40 ms at 3
 // waves per SIMD without spills, 0.38 ms at 4).
-template <int NR, int BS, class Scenes>
+// LG: log2 of the lane-group size.  Pairs (LG = 1) are the default: where the vector
+// ALU is the tighter limit, one DPP fold per node value beats the two of quads
+// (measured, 27 modes, 4.19 M particles at 8 per cell: 0.369 -> 0.359 ms).  Quads
+// (LG = 2) spread a wavefront's groups 16 slots apart instead of 8, so that at 16
+// particles per cell two groups of a wavefront do not share a cell and its LDS
+// addresses; the fused autotuner picks between them on the caller's data.
+template <int NR, int BS, class Scenes, int LG>
 __global__ __launch_bounds__(BS, Scenes::kMany ? 3 : 4) void g2p2g_kernel(G2P2GArgs a, Scenes sc) {
   constexpr int NW = BS / kWave;
-  // log2 of the lane-group size: pairs at every mode count.  Here, where the vector
-  // ALU is the tighter limit, pairs beat the quads of polypic_p2g (one DPP fold per
-  // node value instead of two; measured, 27 modes, 4.19 M particles: 0.369 -> 0.359 ms)
-  constexpr int LG = 1;
+  static_assert(LG == 1 || LG == 2, "lane pairs or quads");
   __shared__ double brick[kBrickKMAX * 4 * kBrickV];  // [brick][channel][node]
   __shared__ uint64_t tile_of[BS];                    // by processing slot
   __shared__ int seg_of[BS];
@@ -296,15 +299,21 @@ __global__ __launch_bounds__(BS, Scenes::kMany ? 3 : 4) void g2p2g_kernel(G2P2GA
                                : (run_slot < kRuns ? run_brick[run_slot] : kBrickKMAX + run_slot);
   const int nseg = n_bricks;
 
-  // the lane pair (lane ^ 1) shares this lane's segment and base node: every lane
-  // runs the exchanges (an invalid one with zero mass), since a DPP read from a
-  // lane that did not execute it is undefined
-  static_assert(LG == 1, "the node values are folded over lane pairs");
+  // the lane pair (lane ^ 1), and with quads the other pair of the quad, share this
+  // lane's segment and base node: every lane runs the exchanges (an invalid one with
+  // zero mass), since a DPP read from a lane that did not execute it is undefined
   const int mykey = valid ? ((c2 * 1024 + c1) * 1024 + c0) : -1 - lane;
   const int pair_key = pair_swap_i(mykey), pair_seg = pair_swap_i(seg);
   const bool pair = mykey == pair_key && seg == pair_seg;
-  const bool emit = valid && (!pair || (lane & 1) == 0);
+  bool quad = false;
+  if constexpr (LG == 2) {
+    const int quad_pair = quad_swap_i((int)pair), quad_key = quad_swap_i(mykey);
+    const int quad_seg = quad_swap_i(seg);
+    quad = pair && quad_pair != 0 && mykey == quad_key && seg == quad_seg;
+  }
+  const bool emit = valid && (quad ? (lane & 3) == 0 : (!pair || (lane & 1) == 0));
   const float pair_f = pair ? 1.0f : 0.0f;
+  const float quad_f = quad ? 1.0f : 0.0f;
   {
     const Rows Rx = p2g_rows_scaled(basis_p2g(u0), m);
     const Rows Ry = p2g_rows_scaled(basis_p2g(u1), 1.0f);
@@ -322,7 +331,10 @@ __global__ __launch_bounds__(BS, Scenes::kMany ? 3 : 4) void g2p2g_kernel(G2P2GA
       return [=](int jz, float (&v)[9]) {
         float w[9];
 #pragma unroll
-        for (int k = 0; k < 9; ++k) w[k] = pair_fold(v[k], pair_f);
+        for (int k = 0; k < 9; ++k) {
+          w[k] = pair_fold(v[k], pair_f);
+          if constexpr (LG == 2) w[k] = quad_fold(w[k], quad_f);
+        }
         if (!emit) return;
         if (lds) {
 #pragma unroll
@@ -385,7 +397,10 @@ template <int NR, class Scenes>
 hipError_t launch_nr(const G2P2GArgs& a, const Scenes& sc, hipStream_t stream) {
   constexpr int BS = 256;
   const unsigned blocks = (unsigned)((a.P + BS - 1) / BS);
-  g2p2g_kernel<NR, BS, Scenes><<<blocks, BS, 0, stream>>>(a, sc);
+  if (a.lane_group == 4)
+    g2p2g_kernel<NR, BS, Scenes, 2><<<blocks, BS, 0, stream>>>(a, sc);
+  else
+    g2p2g_kernel<NR, BS, Scenes, 1><<<blocks, BS, 0, stream>>>(a, sc);
   return hipGetLastError();
 }
 

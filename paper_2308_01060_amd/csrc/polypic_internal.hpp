@@ -141,6 +141,7 @@ struct G2P2GArgs {
   float* gp2;
   int32_t* status;
   int64_t gstride;       // channel stride of gv
+  int lane_group;        // particles folded per brick atomic: 2 (default) or 4
 };
 hipError_t launch_g2p2g(const G2P2GArgs& a, int n_modes, hipStream_t stream);
 // over a batch of scenes (a.g, a.lo, a.hi, a.dx unused; a.gstride = total nodes)

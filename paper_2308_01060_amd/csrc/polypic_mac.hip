@@ -9,16 +9,19 @@
 // shifted one (u' = u - 1/2, b' = floor(u' - 1/2) = b or b - 1, used by the two
 // other components).  Their union spans 4 faces per axis, [b - 1, b + 2].
 //
-// P2G: one thread per sorted slot; the lanes of a wavefront take every fourth slot
-// of the workgroup's chunk so that they sit in different cells.  Per distinct 4^3
-// tile of node bases (the cell-key sort makes them contiguous) a workgroup keeps an
-// FP64 LDS brick of 7^3 faces x 6 channels (3 face masses, 3 face momenta), one
-// face below the tile and two above; a component's 27 face values per channel go
-// to it with LDS atomics, and the brick is flushed with one float atomic per
-// non-zero face value.  Tiles past the brick budget add straight to HBM.
+// P2G: one thread per sorted slot; lane pairs take consecutive slots (which usually
+// share a cell) and the pairs of a wavefront are spread over the workgroup's chunk.
+// Per distinct 4^3 tile of node bases (the cell-key sort makes them contiguous) a
+// workgroup keeps an FP64 LDS brick of 7^3 faces x 6 channels (3 face masses, 3 face
+// momenta), one face below the tile and two above.  A component's 27 face values per
+// channel are added across a pair whose stencils of that component coincide (one DPP
+// fold each), and one lane of the pair adds them to the brick with LDS atomics, one z
+// plane at a time; the brick is flushed with one float atomic per non-zero face
+// value.  Tiles past the brick budget add straight to HBM.
 // G2P: one thread per output slot, gathering each component's 27 face velocities
 // and projecting them with that component's rows (section 3.3), then advection and
 // the F update, as on the collocated grid.
+#include "polypic_bricks.hpp"
 #include "polypic_internal.hpp"
 
 namespace polypic {
@@ -27,9 +30,10 @@ namespace {
 
 constexpr int kMacN = 7;                                       // brick edge in faces
 constexpr int kMacNodes = kMacN * kMacN * kMacN;               // 343
-constexpr int kMacSY = 8;                                      // y stride (doubles)
-constexpr int kMacSZ = 60;                                     // z stride (doubles)
-constexpr int kMacV = (kMacN - 1) * (1 + kMacSY + kMacSZ) + 2; // 416 doubles per channel
+constexpr int kMacSY = 7;                                      // y stride (doubles)
+constexpr int kMacSZ = 49;                                     // z stride (doubles)
+constexpr int kMacV = kMacNodes;                               // 343 doubles per channel:
+                                                               // 36 KB of LDS, 4 groups per CU
 constexpr int kMacCh = 6;                                      // m_x m_y m_z p_x p_y p_z
 constexpr int kMacK = 2;                                       // bricks per workgroup
 constexpr int kMacBS = 256;
@@ -55,18 +59,12 @@ __global__ __launch_bounds__(kMacBS) void mac_p2g_kernel(MacP2GArgs a) {
   constexpr int BS = kMacBS;
   constexpr int NW = BS / kWave;
   __shared__ double brick[kMacK * kMacCh * kMacV];
-  __shared__ uint64_t tile_of[BS];
-  __shared__ int run_of[BS];
-  __shared__ uint64_t run_tile[kWave];
-  __shared__ int run_brick[kWave];
+  __shared__ BrickPlan<BS> plan;
   __shared__ uint64_t seg_tile[kMacK];
-  __shared__ int wave_heads[NW];
-  __shared__ int n_bricks;
 
   const int tid = threadIdx.x;
   const int lane = tid & (kWave - 1);
-  const int wv = tid / kWave;
-  const int slot = lane * NW + wv;
+  const int slot = pair_slot<NW>(tid);
   const int64_t i = (int64_t)blockIdx.x * BS + slot;
   const bool in = i < a.P;
   const size_t Ps = (size_t)a.P;
@@ -88,55 +86,20 @@ __global__ __launch_bounds__(kMacBS) void mac_p2g_kernel(MacP2GArgs a) {
     }
   }
   const float m = valid ? (a.mass ? a.mass[p] : a.uniform_mass) : 0.0f;
-  tile_of[slot] = valid ? brick_tile_id(0, b[0], b[1], b[2]) : kNoTile;
   for (int n = tid; n < kMacNodes; n += BS) {
     const int lz = n / (kMacN * kMacN), ly = (n / kMacN) % kMacN, lx = n % kMacN;
     const int off = lx + kMacSY * ly + kMacSZ * lz;
 #pragma unroll
     for (int k = 0; k < kMacK * kMacCh; ++k) brick[k * kMacV + off] = 0.0;
   }
-  __syncthreads();
-
-  // runs of equal tiles in slot order (thread t looks at slot t), then the first
-  // kWave runs' tiles deduplicated in order of appearance by wavefront 0
-  {
-    const uint64_t tt = tile_of[tid];
-    const bool head = tt != kNoTile && (tid == 0 || tile_of[tid - 1] != tt);
-    const unsigned long long hb = __ballot(head);
-    if (lane == 0) wave_heads[wv] = __popcll(hb);
-    __syncthreads();
-    int pre = 0;
-#pragma unroll
-    for (int w = 0; w < NW; ++w) pre += (w < wv) ? wave_heads[w] : 0;
-    const int run = pre + lanes_below(hb) + (head ? 1 : 0) - 1;
-    run_of[tid] = run;
-    if (head && run < kWave) run_tile[run] = tt;
-  }
-  __syncthreads();
-  if (wv == 0) {
-    int nruns = 0;
-#pragma unroll
-    for (int w = 0; w < NW; ++w) nruns += wave_heads[w];
-    const int nr = nruns < kWave ? nruns : kWave;
-    const uint64_t mine = lane < nr ? run_tile[lane] : kNoTile;
-    int first_same = lane;
-    for (int q = nr - 1; q >= 0; --q)
-      if (q < lane && run_tile[q] == mine) first_same = q;
-    const bool first = lane < nr && first_same == lane;
-    const unsigned long long fb = __ballot(first);
-    const int d_first = lanes_below(fb);
-    const int d = __shfl(d_first, first_same, kWave);
-    if (lane < nr) run_brick[lane] = d;
-    if (first && d < kMacK) seg_tile[d] = mine;
-    if (lane == 0) n_bricks = __popcll(fb);
-  }
-  __syncthreads();
-  const int run = run_of[slot];
-  const int seg = run < 0 ? -1 : (run < kWave ? run_brick[run] : kMacK);
+  const int seg = plan_bricks<BS, kMacK>(plan, seg_tile, tid, slot,
+                                         valid ? brick_tile_id(0, b[0], b[1], b[2]) : kNoTile);
   const bool lds = valid && seg >= 0 && seg < kMacK;
   // brick origin: one face below the tile of node bases, on every axis
   const int o0 = (b[0] & ~3) - 1, o1 = (b[1] & ~3) - 1, o2 = (b[2] & ~3) - 1;
 
+  // Every lane runs the component loop (an idle one with zero mass and coefficients),
+  // since the pair folds read the partner lane through DPP.
 #pragma unroll 1
   for (int ax = 0; ax < 3; ++ax) {
     // component ax: node stencil along axis ax, shifted stencil along the others
@@ -153,52 +116,56 @@ __global__ __launch_bounds__(kMacBS) void mac_p2g_kernel(MacP2GArgs a) {
 #pragma unroll
       for (int r = 0; r < NR; ++r) c[r] = cp[(size_t)r * Ps];
     }
-    if (lds) {
-      const int lbase = (c0 - o0) + kMacSY * (c1 - o1) + kMacSZ * (c2 - o2);
-      double* const bm = brick + (seg * kMacCh + ax) * kMacV + lbase;
-      double* const bp = brick + (seg * kMacCh + 3 + ax) * kMacV + lbase;
+    // a pair folds when both lanes' stencils of this component coincide
+    const PairFold pf = pair_fold_plan(valid ? ((c2 * 1024 + c1) * 1024 + c0) : -1 - lane, seg,
+                                       valid, lane);
+    const int lbase = (c0 - o0) + kMacSY * (c1 - o1) + kMacSZ * (c2 - o2);
+    const size_t gb = ((size_t)c2 * ny + c1) * nx + c0;
+    const size_t sy = (size_t)nx, sz = (size_t)nx * ny;
+    auto emitter = [&](int ch) {
+      double* const lbc = brick + ((lds ? seg : 0) * kMacCh + ch) * kMacV + lbase;
+      float* const gc = (ch < 3 ? a.fm : a.fp) + (size_t)(ch % 3) * N + gb;
+      return [=](int jz, float (&v)[9]) {
+        float w[9];
 #pragma unroll
-      for (int jz = 0; jz < 3; ++jz)
+        for (int k = 0; k < 9; ++k) w[k] = pair_fold(v[k], pf.f);
+        if (!pf.emit) return;
+        if (lds) {
 #pragma unroll
-        for (int jy = 0; jy < 3; ++jy) {
-          const float wyz = Ry.r[0][jy] * Rz.r[0][jz];
+          for (int jy = 0; jy < 3; ++jy)
 #pragma unroll
-          for (int jx = 0; jx < 3; ++jx)
-            atomicAdd(bm + jx + kMacSY * jy + kMacSZ * jz, (double)(Rx.r[0][jx] * wyz));
+            for (int jx = 0; jx < 3; ++jx)
+              atomicAdd(lbc + jx + kMacSY * jy + kMacSZ * jz, (double)w[jx + 3 * jy]);
+        } else {
+#pragma unroll
+          for (int jy = 0; jy < 3; ++jy)
+#pragma unroll
+            for (int jx = 0; jx < 3; ++jx)
+              atomicAdd(gc + jx + sy * jy + sz * jz, w[jx + 3 * jy]);
         }
-      stream_modes<NR>(c, Rx, Ry, Rz, [&](int jx, int jy, int jz, float v) {
-        atomicAdd(bp + jx + kMacSY * jy + kMacSZ * jz, (double)v);
-      });
-    } else if (valid) {
-      const size_t gb = (size_t)ax * N + ((size_t)c2 * ny + c1) * nx + c0;
-      float* const gm = a.fm + gb;
-      float* const gp = a.fp + gb;
-      const size_t sy = (size_t)nx, sz = (size_t)nx * ny;
+      };
+    };
+    {  // face mass of this component: m W
+      float one[27];
 #pragma unroll
-      for (int jz = 0; jz < 3; ++jz)
-#pragma unroll
-        for (int jy = 0; jy < 3; ++jy) {
-          const float wyz = Ry.r[0][jy] * Rz.r[0][jz];
-#pragma unroll
-          for (int jx = 0; jx < 3; ++jx) atomicAdd(gm + jx + sy * jy + sz * jz, Rx.r[0][jx] * wyz);
-        }
-      stream_modes<NR>(c, Rx, Ry, Rz, [&](int jx, int jy, int jz, float v) {
-        atomicAdd(gp + jx + sy * jy + sz * jz, v);
-      });
+      for (int r = 0; r < 27; ++r) one[r] = r == 0 ? 1.0f : 0.0f;
+      stream_modes_planes<1>(one, Rx, Ry, Rz, emitter(ax));
     }
+    stream_modes_planes<NR>(c, Rx, Ry, Rz, emitter(3 + ax));
   }
   __syncthreads();
 
   // flush: thread t owns faces t, t + BS, ... of every brick
-  const int nb = n_bricks < kMacK ? n_bricks : kMacK;
+  const int nb = plan.n_bricks < kMacK ? plan.n_bricks : kMacK;
   for (int n = tid; n < kMacNodes; n += BS) {
     const int lz = n / (kMacN * kMacN), ly = (n / kMacN) % kMacN, lx = n % kMacN;
     const int off = lx + kMacSY * ly + kMacSZ * lz;
     for (int k = 0; k < nb; ++k) {
-      const uint64_t tl = seg_tile[k];
-      const int gx = 4 * (int)(tl & 1023u) - 1 + lx;
-      const int gy = 4 * (int)((tl >> 10) & 1023u) - 1 + ly;
-      const int gz = 4 * (int)((tl >> 20) & 1023u) - 1 + lz;
+      int gx, gy, gz;
+      brick_origin(seg_tile[k], 1, gx, gy, gz);
+      gx += lx;
+      gy += ly;
+      gz += lz;
       if (gx < 0 || gy < 0 || gz < 0 || gx >= nx || gy >= ny || gz >= nz) continue;
       const size_t f = ((size_t)gz * ny + gy) * nx + gx;
 #pragma unroll
@@ -213,8 +180,12 @@ __global__ __launch_bounds__(kMacBS) void mac_p2g_kernel(MacP2GArgs a) {
   }
 }
 
+// 512 threads: each output row is written in 2 KB runs per workgroup (the plain G2P's
+// measured choice)
+constexpr int kMacG2PBS = 512;
+
 template <int NR>
-__global__ __launch_bounds__(256) void mac_g2p_kernel(MacG2PArgs a) {
+__global__ __launch_bounds__(kMacG2PBS) void mac_g2p_kernel(MacG2PArgs a) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= a.P) return;
   const size_t Ps = (size_t)a.P;
@@ -318,8 +289,8 @@ hipError_t mac_p2g_nr(const MacP2GArgs& a, hipStream_t s) {
 
 template <int NR>
 hipError_t mac_g2p_nr(const MacG2PArgs& a, hipStream_t s) {
-  const unsigned blocks = (unsigned)((a.P + 255) / 256);
-  mac_g2p_kernel<NR><<<blocks, 256, 0, s>>>(a);
+  const unsigned blocks = (unsigned)((a.P + kMacG2PBS - 1) / kMacG2PBS);
+  mac_g2p_kernel<NR><<<blocks, kMacG2PBS, 0, s>>>(a);
   return hipGetLastError();
 }
 

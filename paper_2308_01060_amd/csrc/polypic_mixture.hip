@@ -7,11 +7,13 @@
 // point and its absorbed fluid).  The velocity of each set is its momentum over its
 // own grid-summed mass (Eq. 17, 20), and G2P fits each particle from its own phase.
 //
-// P2G: one thread per sorted slot (the lanes of a wavefront every fourth slot), FP64
-// LDS bricks of 6^3 nodes x 8 channels for the first two distinct 4^3 tiles of the
-// workgroup's chunk -- fluid and solid particles of a tile share its brick -- and one
-// float atomic per non-zero brick value at the flush; other tiles add to HBM.  The
-// nodal values are the separable three-stage contraction of the plain P2G.
+// P2G: one thread per sorted slot; lane pairs take consecutive slots and the pairs of
+// a wavefront are spread over the workgroup's chunk.  FP64 LDS bricks of 6^3 nodes x 8
+// channels for the first two distinct 4^3 tiles of the chunk -- fluid and solid
+// particles of a tile share its brick -- take the node values, added first across a
+// pair with the same stencil and phase (one DPP fold each), one z plane at a time;
+// one float atomic per non-zero brick value at the flush; other tiles add to HBM.
+// The nodal values are the separable three-stage contraction of the plain P2G.
 #include "polypic_bricks.hpp"
 #include "polypic_internal.hpp"
 
@@ -22,19 +24,22 @@ namespace {
 constexpr int kMixK = 2;
 constexpr int kMixCh = 8;  // fluid m, p_x, p_y, p_z, then solid m, p_x, p_y, p_z
 constexpr int kMixBS = 256;
+// dense 6^3 bricks (27 KB of LDS for two bricks of 8 channels: 5 groups per CU)
+constexpr int kMixSY = 6;
+constexpr int kMixSZ = 36;
+constexpr int kMixV = kBrickNodes;
 
 template <int NR>
 __global__ __launch_bounds__(kMixBS) void mixture_p2g_kernel(MixtureP2GArgs a) {
   constexpr int BS = kMixBS;
   constexpr int NW = BS / kWave;
-  __shared__ double brick[kMixK * kMixCh * kBrickV];
+  __shared__ double brick[kMixK * kMixCh * kMixV];
   __shared__ BrickPlan<BS> plan;
   __shared__ uint64_t seg_tile[kMixK];
 
   const int tid = threadIdx.x;
   const int lane = tid & (kWave - 1);
-  const int wv = tid / kWave;
-  const int slot = lane * NW + wv;
+  const int slot = pair_slot<NW>(tid);
   const int64_t i = (int64_t)blockIdx.x * BS + slot;
   const bool in = i < a.P;
   const size_t Ps = (size_t)a.P;
@@ -59,56 +64,74 @@ __global__ __launch_bounds__(kMixBS) void mixture_p2g_kernel(MixtureP2GArgs a) {
     valid = ok && ph_ok;
     if (valid) m = a.mass_f[p] + (ph == 1 && a.mass_s ? a.mass_s[p] : 0.0f);
   }
+  if (!valid) {
+    ph = 0;
+    b[0] = b[1] = b[2] = 0;
+    t[0] = t[1] = t[2] = 0.0f;
+  }
 
   for (int n = tid; n < kBrickNodes; n += BS) {
-    const int off = brick_node(n).lds;
+    const BrickNode bn = brick_node(n);
+    const int off = bn.lx + kMixSY * bn.ly + kMixSZ * bn.lz;
 #pragma unroll
-    for (int k = 0; k < kMixK * kMixCh; ++k) brick[k * kBrickV + off] = 0.0;
+    for (int k = 0; k < kMixK * kMixCh; ++k) brick[k * kMixV + off] = 0.0;
   }
   const int seg = plan_bricks<BS, kMixK>(plan, seg_tile, tid, slot,
                                          valid ? brick_tile_id(0, b[0], b[1], b[2]) : kNoTile);
   const bool lds = valid && seg >= 0 && seg < kMixK;
-
-  if (valid) {
+  // a pair folds when both lanes share stencil, brick and phase; every lane runs the
+  // scatter below (an idle one with zero mass), since the folds read the partner lane
+  const PairFold pf = pair_fold_plan(valid ? ((ph << 30) | ((b[2] * 1024 + b[1]) * 1024 + b[0]))
+                                           : -1 - lane,
+                                     seg, valid, lane);
+  {
     const Rows Rx = p2g_rows_scaled(basis_p2g(t[0]), m);
     const Rows Ry = p2g_rows_scaled(basis_p2g(t[1]), 1.0f);
     const Rows Rz = p2g_rows_scaled(basis_p2g(t[2]), 1.0f);
-    const int lbase = (b[0] & 3) + kBrickSY * (b[1] & 3) + kBrickSZ * (b[2] & 3);
+    const int lbase = (b[0] & 3) + kMixSY * (b[1] & 3) + kMixSZ * (b[2] & 3);
     const size_t gbase = ((size_t)b[2] * ny + b[1]) * nx + b[0];
     const size_t sy = (size_t)nx, sz = (size_t)nx * ny;
-    double* const lb = brick + ((lds ? seg : 0) * kMixCh + 4 * ph) * kBrickV + lbase;
-    float* const gmass = a.gm + (size_t)ph * N + gbase;
-    float* const gmom = a.gp + (size_t)ph * 3 * N + gbase;
-    // mass channel: the weights alone
+    // channel ch of this particle's phase: 0 mass, 1-3 momentum
+    auto emitter = [&](int ch) {
+      double* const lbc = brick + ((lds ? seg : 0) * kMixCh + 4 * ph + ch) * kMixV + lbase;
+      float* const gc = ch == 0 ? a.gm + (size_t)ph * N + gbase
+                                : a.gp + ((size_t)ph * 3 + (ch - 1)) * N + gbase;
+      return [=](int jz, float (&v)[9]) {
+        float w[9];
 #pragma unroll
-    for (int jz = 0; jz < 3; ++jz)
+        for (int k = 0; k < 9; ++k) w[k] = pair_fold(v[k], pf.f);
+        if (!pf.emit) return;
+        if (lds) {
 #pragma unroll
-      for (int jy = 0; jy < 3; ++jy) {
-        const float wyz = Ry.r[0][jy] * Rz.r[0][jz];
+          for (int jy = 0; jy < 3; ++jy)
 #pragma unroll
-        for (int jx = 0; jx < 3; ++jx) {
-          const float v = Rx.r[0][jx] * wyz;
-          if (lds)
-            atomicAdd(lb + jx + kBrickSY * jy + kBrickSZ * jz, (double)v);
-          else
-            atomicAdd(gmass + jx + sy * jy + sz * jz, v);
+            for (int jx = 0; jx < 3; ++jx)
+              atomicAdd(lbc + jx + kMixSY * jy + kMixSZ * jz, (double)w[jx + 3 * jy]);
+        } else {
+#pragma unroll
+          for (int jy = 0; jy < 3; ++jy)
+#pragma unroll
+            for (int jx = 0; jx < 3; ++jx)
+              atomicAdd(gc + jx + sy * jy + sz * jz, w[jx + 3 * jy]);
         }
-      }
+      };
+    };
+    {
+      float one[27];
+#pragma unroll
+      for (int r = 0; r < 27; ++r) one[r] = r == 0 ? 1.0f : 0.0f;
+      stream_modes_planes<1>(one, Rx, Ry, Rz, emitter(0));
+    }
 #pragma unroll 1
     for (int al = 0; al < 3; ++al) {
       float c[27];
 #pragma unroll
       for (int r = 0; r < 27; ++r) c[r] = 0.0f;
+      if (valid) {
 #pragma unroll
-      for (int r = 0; r < NR; ++r) c[r] = a.coeff[((size_t)al * NR + r) * Ps + p];
-      double* const lbc = lb + (1 + al) * kBrickV;
-      float* const gc = gmom + (size_t)al * N;
-      stream_modes<NR>(c, Rx, Ry, Rz, [&](int jx, int jy, int jz, float v) {
-        if (lds)
-          atomicAdd(lbc + jx + kBrickSY * jy + kBrickSZ * jz, (double)v);
-        else
-          atomicAdd(gc + jx + sy * jy + sz * jz, v);
-      });
+        for (int r = 0; r < NR; ++r) c[r] = a.coeff[((size_t)al * NR + r) * Ps + p];
+      }
+      stream_modes_planes<NR>(c, Rx, Ry, Rz, emitter(1 + al));
     }
   }
   __syncthreads();
@@ -116,6 +139,7 @@ __global__ __launch_bounds__(kMixBS) void mixture_p2g_kernel(MixtureP2GArgs a) {
   const int nb = plan.n_bricks < kMixK ? plan.n_bricks : kMixK;
   for (int n = tid; n < kBrickNodes; n += BS) {
     const BrickNode bn = brick_node(n);
+    const int off = bn.lx + kMixSY * bn.ly + kMixSZ * bn.lz;
     for (int k = 0; k < nb; ++k) {
       int o0, o1, o2;
       brick_origin(seg_tile[k], 0, o0, o1, o2);
@@ -124,7 +148,7 @@ __global__ __launch_bounds__(kMixBS) void mixture_p2g_kernel(MixtureP2GArgs a) {
       const size_t f = ((size_t)gz * ny + gy) * nx + gx;
 #pragma unroll
       for (int ch = 0; ch < kMixCh; ++ch) {
-        const double v = brick[(k * kMixCh + ch) * kBrickV + bn.lds];
+        const double v = brick[(k * kMixCh + ch) * kMixV + off];
         if (v == 0.0) continue;
         const int k4 = ch & 3, phase = ch >> 2;
         float* dst = k4 == 0 ? a.gm + (size_t)phase * N + f
@@ -135,8 +159,11 @@ __global__ __launch_bounds__(kMixBS) void mixture_p2g_kernel(MixtureP2GArgs a) {
   }
 }
 
+// 512 threads: each output row is written in 2 KB runs per workgroup
+constexpr int kMixG2PBS = 512;
+
 template <int NR>
-__global__ __launch_bounds__(256) void mixture_g2p_kernel(MixtureG2PArgs a) {
+__global__ __launch_bounds__(kMixG2PBS) void mixture_g2p_kernel(MixtureG2PArgs a) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= a.P) return;
   const size_t Ps = (size_t)a.P;
@@ -221,8 +248,8 @@ hipError_t mix_p2g_nr(const MixtureP2GArgs& a, hipStream_t s) {
 
 template <int NR>
 hipError_t mix_g2p_nr(const MixtureG2PArgs& a, hipStream_t s) {
-  const unsigned blocks = (unsigned)((a.P + 255) / 256);
-  mixture_g2p_kernel<NR><<<blocks, 256, 0, s>>>(a);
+  const unsigned blocks = (unsigned)((a.P + kMixG2PBS - 1) / kMixG2PBS);
+  mixture_g2p_kernel<NR><<<blocks, kMixG2PBS, 0, s>>>(a);
   return hipGetLastError();
 }
 

@@ -381,6 +381,48 @@ def polypic_g2p2g(grid: polypic_grid, n_modes: int, dt: float, grid_vel: torch.T
         _ptr(status_dev, torch.int32, 1, "status_dev"), _stream()), "polypic_g2p2g")
 
 
+def polypic_set_g2p2g_config(n_modes: int, lane_group: int) -> None:
+    """Lane-group size (2 or 4; -1 for the default) of polypic_g2p2g at this mode count."""
+    check(_lib.load().polypic_set_g2p2g_config(int(n_modes), int(lane_group)),
+          "polypic_set_g2p2g_config")
+
+
+def polypic_get_g2p2g_config(n_modes: int) -> int:
+    out = ctypes.c_int32(0)
+    check(_lib.load().polypic_get_g2p2g_config(int(n_modes), ctypes.byref(out)),
+          "polypic_get_g2p2g_config")
+    return int(out.value)
+
+
+def polypic_autotune_g2p2g(grid: polypic_grid, n_modes: int, dt: float, grid_vel: torch.Tensor,
+                           x_in: torch.Tensor, x_out: torch.Tensor, coeff_out: torch.Tensor,
+                           grid_mass: torch.Tensor, grid_mom: torch.Tensor,
+                           perm: Optional[torch.Tensor] = None,
+                           F_in: Optional[torch.Tensor] = None,
+                           F_out: Optional[torch.Tensor] = None,
+                           mass_in: Optional[torch.Tensor] = None,
+                           mass_out: Optional[torch.Tensor] = None,
+                           uniform_mass: float = 1.0) -> int:
+    """Times polypic_g2p2g with lane groups of 2 and 4 on these arguments (synchronises),
+    keeps the faster for this mode count and returns it; the outputs are the call's."""
+    P = x_in.numel() // 3
+    N = n_nodes(grid)
+    out = ctypes.c_int32(0)
+    check(_lib.load().polypic_autotune_g2p2g(
+        ctypes.byref(grid), P, int(n_modes), float(dt),
+        _ptr(grid_vel, torch.float32, 3 * N, "grid_vel"),
+        _ptr(x_in, torch.float32, 3 * P, "x_in"), _ptr(perm, torch.int32, P, "perm"),
+        _ptr(x_out, torch.float32, 3 * P, "x_out"),
+        _ptr(coeff_out, torch.float32, 3 * int(n_modes) * P, "coeff_out"),
+        _ptr(F_in, torch.float32, 9 * P, "F_in"), _ptr(F_out, torch.float32, 9 * P, "F_out"),
+        _ptr(mass_in, torch.float32, P, "mass_in"), _ptr(mass_out, torch.float32, P, "mass_out"),
+        float(uniform_mass),
+        _ptr(grid_mass, torch.float32, N, "grid_mass"),
+        _ptr(grid_mom, torch.float32, 3 * N, "grid_mom"), ctypes.byref(out), _stream()),
+        "polypic_autotune_g2p2g")
+    return int(out.value)
+
+
 def polypic_g2p_backward(grid: polypic_grid, n_modes: int, dt: float, grid_vel: torch.Tensor,
                          x_in: torch.Tensor, coeff_out_grad: torch.Tensor,
                          grid_vel_grad: torch.Tensor, x_in_grad: torch.Tensor,

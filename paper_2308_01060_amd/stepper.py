@@ -129,6 +129,22 @@ class ParticleSet:
         ops.polypic_grid_update(self.grid, self.dt, self.gravity, self.bc_layers,
                                 self.grid_mass, self.grid_mom, self.grid_vel)
 
+    def autotune_fused(self) -> int:
+        """One step in which the library times the fused G2P2G's lane groups on this set and
+        keeps the faster for later calls at this mode count (synchronises); returns it."""
+        self.sort()
+        if not self.grid_current:
+            self.p2g()
+        self.grid_update()
+        lg = ops.polypic_autotune_g2p2g(self.grid, self.n_modes, self.dt, self.grid_vel, self.x,
+                                        self.x_next, self.coeff_next, self.grid_mass,
+                                        self.grid_mom, perm=self.perm, F_in=self.F,
+                                        F_out=self.F_next, mass_in=self.mass,
+                                        mass_out=self.mass_next, uniform_mass=self.uniform_mass)
+        self._next_grid_current = True
+        self.swap()
+        return lg
+
     def g2p(self, use_perm: bool = True, advect: bool = True):
         ops.polypic_g2p(self.grid, self.n_modes, self.dt, self.grid_vel, self.x, self.coeff_next,
                         perm=self.perm if use_perm else None,
