@@ -270,6 +270,18 @@ int32_t polypic_grid_update(const polypic_grid* grid, float dt, const float* gra
                             float* grid_vel, void* stream);
 
 /* ------------------------------------------------------------------------
+ * polypic_grid_update that also clears its inputs: each node's mass and
+ * momentum are set to zero once read, so that the next fused call
+ * (polypic_g2p2g with accumulate = 1) scatters into a cleared grid without a
+ * pass of its own.  Not in the paper: a merge of two passes over the grid.
+ * grid_mass and grid_mom are read, then overwritten with zeros; grid_vel as
+ * polypic_grid_update.
+ * ------------------------------------------------------------------------ */
+int32_t polypic_grid_update_clear(const polypic_grid* grid, float dt, const float* gravity,
+                                  int32_t bc_layers, float* grid_mass, float* grid_mom,
+                                  float* grid_vel, void* stream);
+
+/* ------------------------------------------------------------------------
  * G2P gather + projection.  Eq. 6-8 generalised as in section 3.3: the
  * coefficients minimise sum_i W_ip (v_i - sum_r c_r s_r(z_ip))^2.  The modes
  * are W-orthogonal (Eq. 14), so mode by mode
@@ -311,15 +323,17 @@ int32_t polypic_g2p(const polypic_grid* grid, int64_t P, int32_t n_modes, float 
  * x_out[3][P] is required (the scatter is at the advected positions);
  * F_in/F_out and mass_in/mass_out are optional pairs as in polypic_g2p; without
  * mass_in every particle has mass uniform_mass.  grid_mass[N] and grid_mom[3][N]
- * are overwritten (cleared first).  They, x_out, F_out and mass_out may not
- * overlap grid_vel, x_in, perm, F_in or mass_in; coeff_out may be the
+ * are overwritten (cleared first), or with accumulate = 1 added to (the caller
+ * cleared them, e.g. with polypic_grid_update_clear).  They, x_out, F_out and
+ * mass_out may not overlap grid_vel, x_in, perm, F_in or mass_in; coeff_out may be the
  * coefficient array of the preceding P2G (nothing reads coefficients here).
  * ------------------------------------------------------------------------ */
 int32_t polypic_g2p2g(const polypic_grid* grid, int64_t P, int32_t n_modes, float dt,
                       const float* grid_vel, const float* x_in, const int32_t* perm,
                       float* x_out, float* coeff_out, const float* F_in, float* F_out,
                       const float* mass_in, float* mass_out, float uniform_mass,
-                      float* grid_mass, float* grid_mom, int32_t* status_dev, void* stream);
+                      float* grid_mass, float* grid_mom, int32_t accumulate,
+                      int32_t* status_dev, void* stream);
 
 /* ------------------------------------------------------------------------
  * P2G with the affine back-map of Eq. 12 (section 3.3).  The coefficients of a

@@ -38,6 +38,7 @@ from .ops import (  # noqa: E402
     polypic_g2p,
     polypic_g2p2g,
     polypic_grid_update,
+    polypic_grid_update_clear,
     polypic_p2g,
     polypic_sort,
     polypic_sort_update,
@@ -52,10 +53,12 @@ from .autograd import PolyPICSteps, polypic_steps  # noqa: E402
 __all__ = [
     "LIB_PATH", "PolyPICError", "polypic_grid", "ops", "make_grid", "grid_from_spec",
     "polypic_sort", "polypic_sort_workspace_bytes", "polypic_p2g", "polypic_grid_update",
-    "polypic_g2p", "polypic_g2p2g", "polypic_sort_update",
-    "polypic_sort_update_workspace_bytes", "polypic_autotune_p2g", "polypic_get_p2g_config", "polypic_set_p2g_config",
-    "polypic_get_g2p_schedule", "polypic_set_g2p_schedule", "P2GChoice", "Batch",
+    "polypic_grid_update_clear", "polypic_g2p", "polypic_g2p2g", "polypic_sort_update",
+    "polypic_sort_update_workspace_bytes", "polypic_autotune_p2g", "polypic_get_p2g_config",
+    "polypic_set_p2g_config", "polypic_get_g2p_schedule", "polypic_set_g2p_schedule",
+    "P2GChoice", "Batch",
     "POLYPIC_P2G_BRICKS", "POLYPIC_P2G_CELLS", "POLYPIC_P2G_DEFAULT", "POLYPIC_SCHED_LINEAR",
     "POLYPIC_SCHED_PERSISTENT", "POLYPIC_SCHED_XCD",
-    "ParticleSet", "MacParticleSet", "AffineParticleSet", "MixtureParticleSet", "BatchedParticleSet", "PolyPICSteps", "polypic_steps",
+    "ParticleSet", "MacParticleSet", "AffineParticleSet", "MixtureParticleSet",
+    "BatchedParticleSet", "PolyPICSteps", "polypic_steps",
 ]

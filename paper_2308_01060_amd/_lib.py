@@ -48,6 +48,7 @@ EXPORTED = (
     "polypic_set_g2p_schedule",
     "polypic_get_g2p_schedule",
     "polypic_grid_update",
+    "polypic_grid_update_clear",
     "polypic_g2p",
     "polypic_g2p2g",
     "polypic_set_g2p2g_config",
@@ -186,6 +187,8 @@ def load() -> ctypes.CDLL:
     lib.polypic_get_g2p_schedule.argtypes = [pi]
     lib.polypic_grid_update.restype = i32
     lib.polypic_grid_update.argtypes = [G, f32, ctypes.POINTER(f32), i32, P, P, P, P]
+    lib.polypic_grid_update_clear.restype = i32
+    lib.polypic_grid_update_clear.argtypes = [G, f32, ctypes.POINTER(f32), i32, P, P, P, P]
     lib.polypic_g2p.restype = i32
     lib.polypic_g2p.argtypes = [G, i64, i32, f32, P, P, P, P, P, P, P, P, P, P, P]
     lib.polypic_mixture_p2g.restype = i32
@@ -204,7 +207,8 @@ def load() -> ctypes.CDLL:
     lib.polypic_mac_g2p.restype = i32
     lib.polypic_mac_g2p.argtypes = [G, i64, i32, f32, P, P, P, P, P, P, P, P, P, P, P]
     lib.polypic_g2p2g.restype = i32
-    lib.polypic_g2p2g.argtypes = [G, i64, i32, f32, P, P, P, P, P, P, P, P, P, f32, P, P, P, P]
+    lib.polypic_g2p2g.argtypes = [G, i64, i32, f32, P, P, P, P, P, P, P, P, P, f32, P, P, i32,
+                                  P, P]
     lib.polypic_set_g2p2g_config.restype = i32
     lib.polypic_set_g2p2g_config.argtypes = [i32, i32]
     lib.polypic_get_g2p2g_config.restype = i32

@@ -26,12 +26,11 @@ namespace {
 
 // ---------------------------------------------------------------- grid update
 __global__ __launch_bounds__(256) void grid_update_backward_kernel(GridUpdateBackArgs a) {
-  const int ix = blockIdx.x * blockDim.x + threadIdx.x;
-  const int iy = blockIdx.y;
-  const int iz = blockIdx.z;
-  if (ix >= a.nx) return;
+  uint32_t n32;
+  int ix, iy, iz;
+  if (!flat_node(a.nx, a.ny, a.nz, n32, ix, iy, iz)) return;
   const size_t N = (size_t)a.nx * a.ny * a.nz;
-  const size_t n = ((size_t)iz * a.ny + iy) * a.nx + ix;
+  const size_t n = n32;
   const float m = a.gm[n];
   float mb = 0.0f, pb0 = 0.0f, pb1 = 0.0f, pb2 = 0.0f;
   if (m > 0.0f) {
@@ -412,8 +411,7 @@ hipError_t launch_g2p_back_nr(const G2PBackArgs& a, hipStream_t s) {
 }  // namespace
 
 hipError_t launch_grid_update_backward(const GridUpdateBackArgs& a, hipStream_t stream) {
-  dim3 grid((unsigned)((a.nx + 255) / 256), (unsigned)a.ny, (unsigned)a.nz);
-  grid_update_backward_kernel<<<grid, 256, 0, stream>>>(a);
+  grid_update_backward_kernel<<<node_blocks(a.nx, a.ny, a.nz), 256, 0, stream>>>(a);
   return hipGetLastError();
 }
 

@@ -18,6 +18,14 @@ constexpr int32_t kVersion = 100;  // 0.1.0
 
 bool valid_modes(int32_t n) { return n == 1 || n == 4 || n == 8 || n == 27; }
 
+// [a, a + na) and [b, b + nb) floats overlap (either may be null)
+bool overlaps(const void* a, int64_t na, const void* b, int64_t nb) {
+  if (!a || !b) return false;
+  const char* pa = (const char*)a;
+  const char* pb = (const char*)b;
+  return pa < pb + nb * 4 && pb < pa + na * 4;
+}
+
 int32_t check_grid(const polypic_grid* g) {
   if (!g) return POLYPIC_EINVAL;
   const int32_t d[3] = {g->nx, g->ny, g->nz};
@@ -532,6 +540,38 @@ int32_t polypic_grid_update(const polypic_grid* grid, float dt, const float* gra
   a.gm = grid_mass;
   a.gp = grid_mom;
   a.gv = grid_vel;
+  a.clear_gm = nullptr;
+  a.clear_gp = nullptr;
+  discard_stale_error();
+  return from_hip(launch_grid_update(a, (hipStream_t)stream));
+}
+
+int32_t polypic_grid_update_clear(const polypic_grid* grid, float dt, const float* gravity,
+                                  int32_t bc_layers, float* grid_mass, float* grid_mom,
+                                  float* grid_vel, void* stream) {
+  int32_t st = check_grid(grid);
+  if (st) return st;
+  if (!gravity || !grid_mass || !grid_mom || !grid_vel) return POLYPIC_EINVAL;
+  if (!isfinite(dt) || bc_layers < 0) return POLYPIC_EINVAL;
+  for (int k = 0; k < 3; ++k)
+    if (!isfinite(gravity[k])) return POLYPIC_EINVAL;
+  const int64_t N = n_nodes(grid);
+  if (overlaps(grid_vel, 3 * N, grid_mass, N) || overlaps(grid_vel, 3 * N, grid_mom, 3 * N))
+    return POLYPIC_EINVAL;
+  GridUpdateArgs a;
+  a.nx = grid->nx;
+  a.ny = grid->ny;
+  a.nz = grid->nz;
+  a.dt = dt;
+  a.g0 = gravity[0];
+  a.g1 = gravity[1];
+  a.g2 = gravity[2];
+  a.bc_layers = bc_layers;
+  a.gm = grid_mass;
+  a.gp = grid_mom;
+  a.gv = grid_vel;
+  a.clear_gm = grid_mass;
+  a.clear_gp = grid_mom;
   discard_stale_error();
   return from_hip(launch_grid_update(a, (hipStream_t)stream));
 }
@@ -652,6 +692,8 @@ int32_t polypic_mixture_grid_update(const polypic_grid* grid, float dt, const fl
     a.gm = grid_mass + ph * N;
     a.gp = grid_mom + ph * 3 * N;
     a.gv = grid_vel + ph * 3 * N;
+    a.clear_gm = nullptr;
+    a.clear_gp = nullptr;
     if ((st = from_hip(launch_grid_update(a, (hipStream_t)stream)))) return st;
   }
   return POLYPIC_OK;
@@ -782,14 +824,6 @@ int32_t polypic_mac_g2p(const polypic_grid* grid, int64_t P, int32_t n_modes, fl
 }
 
 namespace {
-// [a, a + na) and [b, b + nb) floats overlap (either may be null)
-bool overlaps(const void* a, int64_t na, const void* b, int64_t nb) {
-  if (!a || !b) return false;
-  const char* pa = (const char*)a;
-  const char* pb = (const char*)b;
-  return pa < pb + nb * 4 && pb < pa + na * 4;
-}
-
 // an output of the fused call overlaps an input it reads, or the two grid outputs overlap
 bool g2p2g_overlap(int64_t P, int64_t N, const float* grid_vel, const float* x_in,
                    const int32_t* perm, const float* F_in, const float* mass_in,
@@ -851,7 +885,8 @@ int32_t polypic_g2p2g(const polypic_grid* grid, int64_t P, int32_t n_modes, floa
                       const float* grid_vel, const float* x_in, const int32_t* perm,
                       float* x_out, float* coeff_out, const float* F_in, float* F_out,
                       const float* mass_in, float* mass_out, float uniform_mass,
-                      float* grid_mass, float* grid_mom, int32_t* status_dev, void* stream) {
+                      float* grid_mass, float* grid_mom, int32_t accumulate,
+                      int32_t* status_dev, void* stream) {
   int32_t st = check_grid(grid);
   if (st) return st;
   if ((st = check_P(P))) return st;
@@ -888,6 +923,7 @@ int32_t polypic_g2p2g(const polypic_grid* grid, int64_t P, int32_t n_modes, floa
   a.status = status_dev;
   a.gstride = N;
   a.lane_group = fused_lane_group(n_modes);
+  a.accumulate = accumulate != 0;
   discard_stale_error();
   return from_hip(launch_g2p2g(a, n_modes, (hipStream_t)stream));
 }
@@ -914,8 +950,8 @@ int32_t polypic_autotune_g2p2g(const polypic_grid* grid, int64_t P, int32_t n_mo
   // the candidates run the call itself: validate once through it with the default
   const int keep = g_fused_lane[n_modes < 0 || n_modes > 27 ? 0 : n_modes].load();
   int32_t st = polypic_g2p2g(grid, P, n_modes, dt, grid_vel, x_in, perm, x_out, coeff_out, F_in,
-                             F_out, mass_in, mass_out, uniform_mass, grid_mass, grid_mom, nullptr,
-                             stream);
+                             F_out, mass_in, mass_out, uniform_mass, grid_mass, grid_mom, 0,
+                             nullptr, stream);
   if (st) return st;
   const hipStream_t s = (hipStream_t)stream;
   const int cand[2] = {2, 4};
@@ -925,7 +961,7 @@ int32_t polypic_autotune_g2p2g(const polypic_grid* grid, int64_t P, int32_t n_mo
       [&](int k) {
         g_fused_lane[n_modes].store(cand[k]);
         return polypic_g2p2g(grid, P, n_modes, dt, grid_vel, x_in, perm, x_out, coeff_out, F_in,
-                             F_out, mass_in, mass_out, uniform_mass, grid_mass, grid_mom,
+                             F_out, mass_in, mass_out, uniform_mass, grid_mass, grid_mom, 0,
                              nullptr, stream);
       },
       &bi);
@@ -938,7 +974,7 @@ int32_t polypic_autotune_g2p2g(const polypic_grid* grid, int64_t P, int32_t n_mo
   // the outputs hold the last candidate's results: rerun the chosen one so that they
   // are the call's (the two differ only in the order of the grid sums)
   return polypic_g2p2g(grid, P, n_modes, dt, grid_vel, x_in, perm, x_out, coeff_out, F_in,
-                       F_out, mass_in, mass_out, uniform_mass, grid_mass, grid_mom, nullptr,
+                       F_out, mass_in, mass_out, uniform_mass, grid_mass, grid_mom, 0, nullptr,
                        stream);
 }
 
@@ -1179,6 +1215,8 @@ int32_t polypic_batch_grid_update(const polypic_batch* batch, float dt, const fl
   a.gm = grid_mass;
   a.gp = grid_mom;
   a.gv = grid_vel;
+  a.clear_gm = nullptr;
+  a.clear_gp = nullptr;
   discard_stale_error();
   return from_hip(launch_grid_update_batch(a, batch_table(batch), batch->n_scenes,
                                            batch->max_nodes, batch->N, (hipStream_t)stream));
@@ -1259,6 +1297,7 @@ int32_t polypic_batch_g2p2g(const polypic_batch* batch, int32_t n_modes, float d
   a.gp2 = grid_mom + 2 * N;
   a.status = status_dev;
   a.gstride = N;
+  a.accumulate = 0;
   a.lane_group = 2;  // the batched kernel folds lane pairs
   discard_stale_error();
   return from_hip(launch_g2p2g_batch(a, batch_table(batch), batch->n_scenes, n_modes,

@@ -732,4 +732,18 @@ __device__ __forceinline__ void raise_flag(int32_t* status, int flag) {
   if (status) atomicOr(status, flag);
 }
 
+// Node of this thread in a flat launch over an nx x ny x nz grid (x fastest, one
+// node per thread): its flat index and coordinates; false past the last node.
+// Flat, every wavefront covers 64 consecutive nodes whatever the row length.
+__device__ __forceinline__ bool flat_node(int nx, int ny, int nz, uint32_t& n, int& ix, int& iy,
+                                          int& iz) {
+  n = blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= (uint32_t)nx * (uint32_t)ny * (uint32_t)nz) return false;
+  const uint32_t r = n / (uint32_t)nx;
+  ix = (int)(n - r * (uint32_t)nx);
+  iz = (int)(r / (uint32_t)ny);
+  iy = (int)(r - (uint32_t)iz * (uint32_t)ny);
+  return true;
+}
+
 }  // namespace polypic

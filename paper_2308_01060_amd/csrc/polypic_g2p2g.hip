@@ -407,8 +407,11 @@ hipError_t launch_nr(const G2P2GArgs& a, const Scenes& sc, hipStream_t stream) {
 template <class Scenes>
 hipError_t launch_modes(const G2P2GArgs& a, const Scenes& sc, int n_modes, int64_t n_nodes,
                         hipStream_t stream) {
-  hipError_t e = launch_grid_clear(a.gm, a.gp0, n_nodes, nullptr, stream);
-  if (e != hipSuccess || a.P == 0) return e;
+  if (!a.accumulate) {
+    hipError_t e = launch_grid_clear(a.gm, a.gp0, n_nodes, nullptr, stream);
+    if (e != hipSuccess) return e;
+  }
+  if (a.P == 0) return hipSuccess;
   switch (n_modes) {
     case 1: return launch_nr<1>(a, sc, stream);
     case 4: return launch_nr<4>(a, sc, stream);

@@ -1,6 +1,8 @@
 // Grid update: v = (mv) / m (Eq. 5) where m > 0, plus gravity and separating
-// slip walls, for gfx950.  One thread per node along x; y and z come from the
-// block grid, so the wall tests need no division.
+// slip walls, for gfx950.  One thread per node of a flat launch (x fastest), so
+// every wavefront streams 64 consecutive nodes whatever the row length.  Optionally the pass also zeroes
+// the mass and momentum it has read, so that the next step's scatter can
+// accumulate into them without a separate clear.
 #include "polypic_internal.hpp"
 
 namespace polypic {
@@ -29,15 +31,19 @@ __device__ __forceinline__ void update_node(const GridUpdateArgs& a, int ix, int
   a.gv[n] = v0;
   a.gv[N + n] = v1;
   a.gv[2 * N + n] = v2;
+  if (a.clear_gm) {  // the sums are consumed: leave them zero for the next accumulation
+    a.clear_gm[n] = 0.0f;
+    a.clear_gp[n] = 0.0f;
+    a.clear_gp[N + n] = 0.0f;
+    a.clear_gp[2 * N + n] = 0.0f;
+  }
 }
 
 __global__ __launch_bounds__(256) void grid_update_kernel(GridUpdateArgs a) {
-  const int ix = blockIdx.x * blockDim.x + threadIdx.x;
-  const int iy = blockIdx.y;
-  const int iz = blockIdx.z;
-  if (ix >= a.nx) return;
+  uint32_t n;
+  int ix, iy, iz;
+  if (!flat_node(a.nx, a.ny, a.nz, n, ix, iy, iz)) return;
   const size_t N = (size_t)a.nx * a.ny * a.nz;
-  const size_t n = ((size_t)iz * a.ny + iy) * a.nx + ix;
   update_node(a, ix, iy, iz, a.nx, a.ny, a.nz, n, N);
 }
 
@@ -47,13 +53,14 @@ __global__ __launch_bounds__(256) void grid_update_batch_kernel(GridUpdateArgs a
                                                                 int64_t stride) {
   const SceneDev& d = t[blockIdx.y];
   const int nx = d.nx, ny = d.ny, nz = d.nz;
-  const int64_t nn = (int64_t)nx * ny * nz;
-  const int64_t step = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < nn; k += step) {
-    const int64_t r = k / nx;
-    const int ix = (int)(k - r * nx);
-    const int iz = (int)(r / ny);
-    const int iy = (int)(r - (int64_t)iz * ny);
+  // a scene grid has at most 1026^3 nodes: 32-bit node indices and divisions
+  const uint32_t nn = (uint32_t)nx * (uint32_t)ny * (uint32_t)nz;
+  const uint32_t step = gridDim.x * blockDim.x;
+  for (uint32_t k = blockIdx.x * blockDim.x + threadIdx.x; k < nn; k += step) {
+    const uint32_t r = k / (uint32_t)nx;
+    const int ix = (int)(k - r * (uint32_t)nx);
+    const int iz = (int)(r / (uint32_t)ny);
+    const int iy = (int)(r - (uint32_t)iz * (uint32_t)ny);
     update_node(a, ix, iy, iz, nx, ny, nz, (size_t)(d.node_off + k), (size_t)stride);
   }
 }
@@ -74,8 +81,7 @@ hipError_t launch_zero(float* p, int64_t n, hipStream_t stream) {
 }
 
 hipError_t launch_grid_update(const GridUpdateArgs& a, hipStream_t stream) {
-  dim3 grid((unsigned)((a.nx + 255) / 256), (unsigned)a.ny, (unsigned)a.nz);
-  grid_update_kernel<<<grid, 256, 0, stream>>>(a);
+  grid_update_kernel<<<node_blocks(a.nx, a.ny, a.nz), 256, 0, stream>>>(a);
   return hipGetLastError();
 }
 

@@ -14,6 +14,12 @@ inline size_t align_up(size_t n, size_t a = 256) { return (n + a - 1) / a * a; }
 
 constexpr int kComputeUnits = 256;  // MI355X
 
+// workgroups of 256 threads for a flat one-node-per-thread launch over a grid
+// (grids are at most 1026^3 nodes: the count fits 32 bits)
+inline unsigned node_blocks(int nx, int ny, int nz) {
+  return (unsigned)(((int64_t)nx * ny * nz + 255) / 256);
+}
+
 // ---- sort
 size_t sort_workspace_bytes(int64_t P);
 int sort_key_bits(const GridDev& g);
@@ -85,6 +91,8 @@ struct GridUpdateArgs {
   const float* gm;
   const float* gp;  // [3][N]
   float* gv;        // [3][N]
+  float* clear_gm;  // gm and gp again when the update zeroes them after reading (or nullptr)
+  float* clear_gp;
 };
 hipError_t launch_grid_update(const GridUpdateArgs& a, hipStream_t stream);
 // batch of scenes: a.nx/ny/nz unused; gm, gp, gv span `stride` nodes per channel
@@ -142,6 +150,7 @@ struct G2P2GArgs {
   int32_t* status;
   int64_t gstride;       // channel stride of gv
   int lane_group;        // particles folded per brick atomic: 2 (default) or 4
+  int accumulate;        // 1: add to the grid as it is (the caller cleared it)
 };
 hipError_t launch_g2p2g(const G2P2GArgs& a, int n_modes, hipStream_t stream);
 // over a batch of scenes (a.g, a.lo, a.hi, a.dx unused; a.gstride = total nodes)

@@ -258,12 +258,11 @@ __global__ __launch_bounds__(kMacG2PBS) void mac_g2p_kernel(MacG2PArgs a) {
 
 // Face velocities from face sums: per component, its own mass and walls normal to its axis.
 __global__ __launch_bounds__(256) void mac_grid_update_kernel(MacUpdateArgs a) {
-  const int ix = blockIdx.x * blockDim.x + threadIdx.x;
-  const int iy = blockIdx.y;
-  const int iz = blockIdx.z;
-  if (ix >= a.nx) return;
+  uint32_t n32;
+  int ix, iy, iz;
+  if (!flat_node(a.nx, a.ny, a.nz, n32, ix, iy, iz)) return;
   const size_t N = (size_t)a.nx * a.ny * a.nz;
-  const size_t n = ((size_t)iz * a.ny + iy) * a.nx + ix;
+  const size_t n = n32;
   const int idx[3] = {ix, iy, iz};
   const int dims[3] = {a.nx, a.ny, a.nz};
   const float g[3] = {a.g0, a.g1, a.g2};
@@ -314,8 +313,7 @@ hipError_t launch_mac_p2g(const MacP2GArgs& a, int n_modes, bool accumulate, hip
 }
 
 hipError_t launch_mac_grid_update(const MacUpdateArgs& a, hipStream_t s) {
-  dim3 grid((unsigned)((a.nx + 255) / 256), (unsigned)a.ny, (unsigned)a.nz);
-  mac_grid_update_kernel<<<grid, 256, 0, s>>>(a);
+  mac_grid_update_kernel<<<node_blocks(a.nx, a.ny, a.nz), 256, 0, s>>>(a);
   return hipGetLastError();
 }
 

@@ -212,6 +212,20 @@ def polypic_grid_update(grid: polypic_grid, dt: float, gravity: Sequence[float],
         _ptr(grid_vel, torch.float32, 3 * N, "grid_vel"), _stream()), "polypic_grid_update")
 
 
+def polypic_grid_update_clear(grid: polypic_grid, dt: float, gravity: Sequence[float],
+                              bc_layers: int, grid_mass: torch.Tensor, grid_mom: torch.Tensor,
+                              grid_vel: torch.Tensor) -> None:
+    """polypic_grid_update that zeroes grid_mass and grid_mom once read."""
+    N = n_nodes(grid)
+    g3 = (ctypes.c_float * 3)(*[float(v) for v in gravity])
+    check(_lib.load().polypic_grid_update_clear(
+        ctypes.byref(grid), float(dt), g3, int(bc_layers),
+        _ptr(grid_mass, torch.float32, N, "grid_mass"),
+        _ptr(grid_mom, torch.float32, 3 * N, "grid_mom"),
+        _ptr(grid_vel, torch.float32, 3 * N, "grid_vel"), _stream()),
+        "polypic_grid_update_clear")
+
+
 def polypic_g2p(grid: polypic_grid, n_modes: int, dt: float, grid_vel: torch.Tensor,
                 x_in: torch.Tensor, coeff_out: torch.Tensor,
                 perm: Optional[torch.Tensor] = None, x_out: Optional[torch.Tensor] = None,
@@ -364,7 +378,8 @@ def polypic_g2p2g(grid: polypic_grid, n_modes: int, dt: float, grid_vel: torch.T
                   F_in: Optional[torch.Tensor] = None, F_out: Optional[torch.Tensor] = None,
                   mass_in: Optional[torch.Tensor] = None, mass_out: Optional[torch.Tensor] = None,
                   uniform_mass: float = 1.0,
-                  status_dev: Optional[torch.Tensor] = None) -> None:
+                  status_dev: Optional[torch.Tensor] = None, accumulate: bool = False) -> None:
+    """accumulate: add to grid_mass / grid_mom instead of clearing them first."""
     P = x_in.numel() // 3
     N = n_nodes(grid)
     check(_lib.load().polypic_g2p2g(
@@ -377,7 +392,7 @@ def polypic_g2p2g(grid: polypic_grid, n_modes: int, dt: float, grid_vel: torch.T
         _ptr(mass_in, torch.float32, P, "mass_in"), _ptr(mass_out, torch.float32, P, "mass_out"),
         float(uniform_mass),
         _ptr(grid_mass, torch.float32, N, "grid_mass"),
-        _ptr(grid_mom, torch.float32, 3 * N, "grid_mom"),
+        _ptr(grid_mom, torch.float32, 3 * N, "grid_mom"), int(bool(accumulate)),
         _ptr(status_dev, torch.int32, 1, "status_dev"), _stream()), "polypic_g2p2g")
 
 

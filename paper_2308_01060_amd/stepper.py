@@ -125,9 +125,14 @@ class ParticleSet:
                                         uniform_mass=self.uniform_mass, perm=self.perm,
                                         keys_sorted=self.keys, ws=self.p2g_ws)
 
-    def grid_update(self):
-        ops.polypic_grid_update(self.grid, self.dt, self.gravity, self.bc_layers,
-                                self.grid_mass, self.grid_mom, self.grid_vel)
+    def grid_update(self, clear: bool = False):
+        """Grid velocities from grid_mass / grid_mom; with clear=True those two are zeroed
+        once read (polypic_grid_update_clear), ready for g2p2g(accumulate=True)."""
+        fn = ops.polypic_grid_update_clear if clear else ops.polypic_grid_update
+        fn(self.grid, self.dt, self.gravity, self.bc_layers, self.grid_mass, self.grid_mom,
+           self.grid_vel)
+        if clear:
+            self.grid_current = False
 
     def autotune_fused(self) -> int:
         """One step in which the library times the fused G2P2G's lane groups on this set and
@@ -153,14 +158,16 @@ class ParticleSet:
                         mass_in=self.mass, mass_out=self.mass_next, status_dev=self.status)
         self._next_grid_current = False
 
-    def g2p2g(self, use_perm: bool = True):
+    def g2p2g(self, use_perm: bool = True, accumulate: bool = False):
         """G2P + advection, and the P2G of the new state into grid_mass / grid_mom (the grid
-        velocity has been computed from them already)."""
+        velocity has been computed from them already).  accumulate=True adds to the two
+        (zeroed by grid_update(clear=True)) instead of clearing them first."""
         ops.polypic_g2p2g(self.grid, self.n_modes, self.dt, self.grid_vel, self.x, self.x_next,
                           self.coeff_next, self.grid_mass, self.grid_mom,
                           perm=self.perm if use_perm else None, F_in=self.F, F_out=self.F_next,
                           mass_in=self.mass, mass_out=self.mass_next,
-                          uniform_mass=self.uniform_mass, status_dev=self.status)
+                          uniform_mass=self.uniform_mass, status_dev=self.status,
+                          accumulate=accumulate)
         self._next_grid_current = True
 
     def invalidate_grid(self):
@@ -190,13 +197,14 @@ class ParticleSet:
         """One full step: sort, P2G, grid update, G2P + advection, then swap buffers.  Fused
         (default), the P2G of a step was done by the G2P of the step before (polypic_g2p2g),
         so a step is sort, grid update, G2P2G -- with a P2G first when the grid is not
-        current (the first step)."""
+        current (the first step).  The grid update zeroes the sums it read, and G2P2G adds
+        into them, so the grid is not cleared in a pass of its own."""
         self.sort()
         if self.fused:
             if not self.grid_current:
                 self.p2g()
-            self.grid_update()
-            self.g2p2g()
+            self.grid_update(clear=True)
+            self.g2p2g(accumulate=True)
         else:
             self.p2g()
             self.grid_update()
@@ -233,7 +241,9 @@ class MacParticleSet(ParticleSet):
         self.sort()
         return None
 
-    def grid_update(self):
+    def grid_update(self, clear: bool = False):
+        if clear:
+            raise RuntimeError("no clearing grid update for this set (it steps unfused)")
         ops.polypic_mac_grid_update(self.grid, self.dt, self.gravity, self.bc_layers,
                                     self.grid_mass, self.grid_mom, self.grid_vel)
 
@@ -330,7 +340,9 @@ class MixtureParticleSet(ParticleSet):
         self.sort()
         return None
 
-    def grid_update(self):
+    def grid_update(self, clear: bool = False):
+        if clear:
+            raise RuntimeError("no clearing grid update for this set (it steps unfused)")
         ops.polypic_mixture_grid_update(self.grid, self.dt, self.gravity, self.bc_layers,
                                         self.grid_mass, self.grid_mom, self.grid_vel)
 

@@ -124,6 +124,15 @@ def test_grid_update_and_sort_reject_bad_arguments():
     assert lib.polypic_grid_update(ctypes.byref(g), 1e-4, None, 1, FAKE, FAKE, FAKE, None) == 1
     assert lib.polypic_grid_update(ctypes.byref(g), 1e-4, grav, -1, FAKE, FAKE, FAKE, None) == 1
     assert lib.polypic_grid_update(ctypes.byref(g), 1e-4, grav, 1, None, FAKE, FAKE, None) == 1
+    far = lambda k: ctypes.c_void_p(0x10000000 + k * 0x1000000)  # noqa: E731  disjoint, fake
+    clear = lib.polypic_grid_update_clear
+    assert clear(ctypes.byref(g), 1e-4, None, 1, far(0), far(1), far(2), None) == 1
+    assert clear(ctypes.byref(g), 1e-4, grav, -1, far(0), far(1), far(2), None) == 1
+    assert clear(ctypes.byref(g), float("nan"), grav, 1, far(0), far(1), far(2), None) == 1
+    assert clear(ctypes.byref(g), 1e-4, grav, 1, None, far(1), far(2), None) == 1
+    assert clear(ctypes.byref(g), 1e-4, grav, 1, far(0), None, far(2), None) == 1
+    assert clear(ctypes.byref(g), 1e-4, grav, 1, far(0), far(1), far(1), None) == 1  # aliasing
+    assert clear(None, 1e-4, grav, 1, far(0), far(1), far(2), None) == 1
     assert lib.polypic_sort(ctypes.byref(g), 100, FAKE, FAKE, FAKE, FAKE, 16, None, None) == 4
     assert lib.polypic_sort(ctypes.byref(g), 100, None, FAKE, FAKE, FAKE, 1 << 20, None,
                             None) == 1
@@ -298,9 +307,9 @@ def test_g2p2g_rejects_bad_arguments():
     gv, x, xo, co, gm, gp = (far(k) for k in range(6))
 
     def call(n_modes=27, dt=1e-4, gv=gv, x=x, perm=None, xo=xo, co=co, fi=None, fo=None,
-             mi=None, mo=None, um=1.0, gm=gm, gp=gp):
+             mi=None, mo=None, um=1.0, gm=gm, gp=gp, acc=0):
         return lib.polypic_g2p2g(ctypes.byref(g), 10, n_modes, dt, gv, x, perm, xo, co, fi, fo,
-                                 mi, mo, um, gm, gp, None, None)
+                                 mi, mo, um, gm, gp, acc, None, None)
     assert call(n_modes=5) == 1
     assert call(dt=float("nan")) == 1
     assert call(xo=None) == 1                   # the scatter needs the advected positions
@@ -313,6 +322,8 @@ def test_g2p2g_rejects_bad_arguments():
     assert call(gm=gv) == 1                     # the next grid overlaps grid_vel
     assert call(gp=ctypes.c_void_p(0x10000000 + 4 * 0x1000000 + 4)) == 1  # grid_mom over grid_mass
     assert call(fi=far(7), fo=far(7)) == 1      # F_out overlaps F_in
+    assert call(acc=1, xo=None) == 1            # accumulating changes none of the checks
+    assert call(acc=1, gm=gv) == 1
 
 
 def test_permutation_calls_reject_bad_arguments():

@@ -312,6 +312,66 @@ def test_g2p2g_empty_clears_the_grid():
     assert float(gm.abs().max()) == 0.0 and float(gp.abs().max()) == 0.0
 
 
+def test_g2p2g_empty_accumulate_leaves_the_grid():
+    pp = require_gpu()
+    g = pp.make_grid((12, 12, 12), 1 / 8)
+    gm = torch.full((12 ** 3,), 7.0, device="cuda")
+    gp = torch.full((3 * 12 ** 3,), 5.0, device="cuda")
+    gv = torch.zeros(3 * 12 ** 3, device="cuda")
+    e = torch.empty(0, device="cuda")
+    pp.polypic_g2p2g(g, 27, 1e-4, gv, e, e.clone(), e.clone(), gm, gp, accumulate=True)
+    torch.cuda.synchronize()
+    assert bool((gm == 7.0).all()) and bool((gp == 5.0).all())
+
+
+def test_grid_update_clear_matches_grid_update_and_zeroes_its_inputs():
+    """polypic_grid_update_clear: the same velocities bit for bit (same arithmetic per
+    node), and the mass and momentum it read are left exactly zero."""
+    pp = require_gpu()
+    s = W.config0(4)
+    _, g, ps = particle_set(s, 27, dt=1e-3, gravity=(0.0, -9.8, 0.0), bc_layers=1)
+    ps.sort()
+    ps.p2g()
+    ps.grid_update()
+    torch.cuda.synchronize()
+    v_ref = host(ps.grid_vel).copy()
+    assert float(ps.grid_mass.max()) > 0.0
+    ps.grid_vel.fill_(123.0)
+    ps.grid_update(clear=True)
+    torch.cuda.synchronize()
+    assert np.array_equal(host(ps.grid_vel), v_ref)
+    assert float(ps.grid_mass.abs().max()) == 0.0 and float(ps.grid_mom.abs().max()) == 0.0
+    assert not ps.grid_current
+
+
+@pytest.mark.parametrize("n_modes", [4, 27])
+def test_g2p2g_accumulates_into_a_given_grid(n_modes):
+    """polypic_g2p2g with accumulate = 1 onto a grid that already holds sums: the result
+    is those sums plus the oracle's P2G of the state the call wrote."""
+    pp = require_gpu()
+    s = W.config0(5)
+    _, g, ps = particle_set(s, n_modes, dt=1e-3)
+    og = oracle_grid(g)
+    note(f"g2p2g accumulate: n_modes={n_modes} P={s.P}")
+    ps.sort()
+    ps.p2g()
+    ps.grid_update()
+    rng = np.random.default_rng(11)
+    M0 = rng.random(og.n_nodes).astype(np.float32)
+    Q0 = rng.standard_normal(3 * og.n_nodes).astype(np.float32)
+    ps.grid_mass.copy_(torch.from_numpy(M0))
+    ps.grid_mom.copy_(torch.from_numpy(Q0))
+    ps.g2p2g(accumulate=True)
+    torch.cuda.synchronize()
+    assert ps.status_flags() == 0
+    M_ref, Q_ref = O.p2g(og, host(ps.x_next), host(ps.coeff_next).reshape(3, n_modes, s.P),
+                         n_modes)
+    M_ref = M_ref + M0.astype(np.float64).reshape(M_ref.shape)
+    Q_ref = Q_ref + Q0.astype(np.float64).reshape(Q_ref.shape)
+    assert rel(host(ps.grid_mass).reshape(M_ref.shape), M_ref) <= TOL_NORMWISE
+    assert rel(host(ps.grid_mom).reshape(Q_ref.shape), Q_ref) <= TOL_NORMWISE
+
+
 # ---------------------------------------------------------------- exact fixture and edges
 
 @pytest.mark.parametrize("case_idx", range(4))
