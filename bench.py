@@ -172,8 +172,9 @@ PHASE_EVERY = 5  # steps between two steps timed phase by phase
 def time_steps(ps, steps: int, torch):
     """Run `steps` full steps; returns (wall_s, per-phase mean ms dict).
 
-    Fused sets (the default) step as sort -> grid update -> G2P2G, the P2G of each
-    step having been done by the G2P2G of the step before; unfused sets as
+    Fused sets (the default) step as sort -> grid update (of the active regions) ->
+    G2P2G, the P2G of each step having been done by the G2P2G of the step before;
+    unfused sets as
     sort -> P2G -> grid update -> G2P.  Every PHASE_EVERY-th step records a timing
     event at each phase boundary, and the phase means come from those steps.  The
     others record none: on this stack each timing event recorded between two
@@ -183,9 +184,12 @@ def time_steps(ps, steps: int, torch):
     if ps.fused:
         if not ps.grid_current:
             raise RuntimeError("a fused set needs its grid current before the timed steps")
+        if not ps.regions_valid:
+            ps.step()  # (untimed) a step whose G2P2G flags the regions it scatters into
         names = ("sort", "grid_update", "g2p2g")
-        # the grid update zeroes the sums it read; the fused call then adds into them
-        calls = (ps.sort, lambda: ps.grid_update(clear=True), lambda: ps.g2p2g(accumulate=True))
+        # the grid update visits the flagged regions only and zeroes the sums it read; the
+        # fused call adds into them and flags where it lands
+        calls = (ps.sort, ps.grid_update_active, lambda: ps.g2p2g(accumulate=True))
     else:
         names = ("sort", "p2g", "grid_update", "g2p")
         calls = (ps.sort, ps.p2g, ps.grid_update, ps.g2p)
@@ -414,7 +418,7 @@ def _set_timing(pp, torch, ps, steps: int, warmup: int, bpp: int, workload: str)
     for _ in range(warmup):
         ps.step()
     choice = ps.autotune()
-    lane_group = ps.autotune_fused()
+    fused_choice = ps.autotune_fused()
     torch.cuda.synchronize()
     wall, phase = time_steps(ps, steps, torch)
     if ps.status_flags() != 0:
@@ -431,7 +435,8 @@ def _set_timing(pp, torch, ps, steps: int, warmup: int, bpp: int, workload: str)
         "phase_ms": {k: round(v, 4) for k, v in phase.items()},
         "p2g_config": {"path": "cells" if choice.path == 1 else "bricks",
                        "block": choice.block, "schedule": choice.schedule},
-        "g2p2g_lane_group": lane_group,
+        "g2p2g_config": {"lane_group": fused_choice.lane_group,
+                         "schedule": "xcd" if fused_choice.schedule == 1 else "linear"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": measured_traffic("g2p2g", workload), "kernel": "g2p2g",
@@ -818,7 +823,7 @@ def main():
     for _ in range(args.warmup):
         ps.step()
     p2g_choice = ps.autotune()  # library autotuners, outside the timed region
-    lane_group = ps.autotune_fused()
+    fused_choice = ps.autotune_fused()
     torch.cuda.synchronize()
     wall, phase = time_steps(ps, args.steps, torch)
     if ps.status_flags() != 0:
@@ -955,7 +960,9 @@ def main():
         "p2g_config": {"path": "cells" if p2g_choice.path == 1 else "bricks",
                        "block": p2g_choice.block, "schedule": p2g_choice.schedule,
                        "chosen_by": "polypic_autotune_p2g"},
-        "g2p2g_config": {"lane_group": lane_group, "chosen_by": "polypic_autotune_g2p2g"},
+        "g2p2g_config": {"lane_group": fused_choice.lane_group,
+                         "schedule": "xcd" if fused_choice.schedule == 1 else "linear",
+                         "chosen_by": "polypic_autotune_g2p2g"},
         "phase_ms": {k: round(v, 4) for k, v in phase.items()},
         "unfused": unfused,
         "sort": {"timed": "polypic_sort_update (exact re-sort from the previous step's keys)",

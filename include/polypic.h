@@ -282,6 +282,34 @@ int32_t polypic_grid_update_clear(const polypic_grid* grid, float dt, const floa
                                   float* grid_vel, void* stream);
 
 /* ------------------------------------------------------------------------
+ * Active regions: the grid passes of a stepped simulation restricted to where
+ * the particles are.  Not in the paper (the grid is dense there); bookkeeping
+ * that spares the passes the empty part of a large grid.
+ *
+ * The nodes are grouped in regions of 16 x 4 x 4 (x fastest; the last region of
+ * an axis may be partial), numbered x fastest: region (qx, qy, qz) has index
+ * (qz * ry + qy) * rx + qx with rx = ceil(nx / 16), ry = ceil(ny / 4);
+ * polypic_region_count gives their number R.  The caller owns the region state:
+ * R uint32 flags (word q for region q), zero at first.
+ *
+ * polypic_g2p2g with region_state non-NULL sets the flag of every region its
+ * scatter adds to (and possibly of a few next to them).
+ * polypic_grid_update_active then does what polypic_grid_update_clear does, on
+ * the flagged regions only, and resets their flags.  It requires grid_mass and
+ * grid_mom to be zero outside the flagged regions; it leaves them zero
+ * everywhere, and grid_vel unchanged outside the flagged regions (velocities a
+ * later G2P does not read: a G2P reads the nodes of its particles' stencils, all
+ * in regions the scatter of the same positions flagged).  A stepped run keeps
+ * the requirement: after a dense update with clearing, every later step is
+ * polypic_grid_update_active, then polypic_g2p2g with accumulate = 1 and the
+ * region state.
+ * ------------------------------------------------------------------------ */
+int32_t polypic_region_count(const polypic_grid* grid, int64_t* count);
+int32_t polypic_grid_update_active(const polypic_grid* grid, float dt, const float* gravity,
+                                   int32_t bc_layers, float* grid_mass, float* grid_mom,
+                                   float* grid_vel, uint32_t* region_state, void* stream);
+
+/* ------------------------------------------------------------------------
  * G2P gather + projection.  Eq. 6-8 generalised as in section 3.3: the
  * coefficients minimise sum_i W_ip (v_i - sum_r c_r s_r(z_ip))^2.  The modes
  * are W-orthogonal (Eq. 14), so mode by mode
@@ -324,7 +352,8 @@ int32_t polypic_g2p(const polypic_grid* grid, int64_t P, int32_t n_modes, float 
  * F_in/F_out and mass_in/mass_out are optional pairs as in polypic_g2p; without
  * mass_in every particle has mass uniform_mass.  grid_mass[N] and grid_mom[3][N]
  * are overwritten (cleared first), or with accumulate = 1 added to (the caller
- * cleared them, e.g. with polypic_grid_update_clear).  They, x_out, F_out and
+ * cleared them, e.g. with polypic_grid_update_clear).  region_state (optional)
+ * is flagged as described under "Active regions".  They, x_out, F_out and
  * mass_out may not overlap grid_vel, x_in, perm, F_in or mass_in; coeff_out may be the
  * coefficient array of the preceding P2G (nothing reads coefficients here).
  * ------------------------------------------------------------------------ */
@@ -333,7 +362,7 @@ int32_t polypic_g2p2g(const polypic_grid* grid, int64_t P, int32_t n_modes, floa
                       float* x_out, float* coeff_out, const float* F_in, float* F_out,
                       const float* mass_in, float* mass_out, float uniform_mass,
                       float* grid_mass, float* grid_mom, int32_t accumulate,
-                      int32_t* status_dev, void* stream);
+                      uint32_t* region_state, int32_t* status_dev, void* stream);
 
 /* ------------------------------------------------------------------------
  * P2G with the affine back-map of Eq. 12 (section 3.3).  The coefficients of a
@@ -447,24 +476,30 @@ int32_t polypic_mac_g2p(const polypic_grid* grid, int64_t P, int32_t n_modes, fl
                         const float* mass_in, float* mass_out, int32_t* status_dev,
                         void* stream);
 
-/* Launch choice of polypic_g2p2g per mode count: the number of particles of
- * consecutive sorted slots whose node values are added across lanes before one
- * brick atomic (2, the default, or 4; -1 restores the default).  The lanes' groups
- * are spread over the workgroup's chunk 8 or 16 slots apart, so 4 suits about 16
- * particles per cell.  polypic_autotune_g2p2g runs the call (same arguments and
- * outputs as polypic_g2p2g) once per candidate, timed with HIP events on `stream`
- * (one untimed and three timed runs each; it synchronises the stream), keeps the
- * fastest for later calls at this mode count and writes it to *lane_group_out;
- * the outputs are those of a final run with the choice.  The choice changes only
- * the order of the grid sums. */
-int32_t polypic_set_g2p2g_config(int32_t n_modes, int32_t lane_group);
-int32_t polypic_get_g2p2g_config(int32_t n_modes, int32_t* lane_group);
+/* Launch choice of polypic_g2p2g per mode count:
+ *   lane_group: the number of particles of consecutive sorted slots whose node
+ *     values are added across lanes before one brick atomic (2, the default, or
+ *     4).  The lanes' groups are spread over the workgroup's chunk 8 or 16 slots
+ *     apart, so 4 suits about 16 particles per cell.
+ *   schedule: the order in which workgroups take the chunks of slots,
+ *     POLYPIC_SCHED_LINEAR (the default: in launch order) or POLYPIC_SCHED_XCD
+ *     (each XCD takes a contiguous eighth, so that neighbouring chunks, which
+ *     gather and scatter the same nodes, share one L2).
+ * -1 restores a default.  polypic_autotune_g2p2g runs the call (same arguments
+ * and outputs as polypic_g2p2g) once per candidate pair, timed with HIP events on
+ * `stream` (one untimed and three timed runs each; it synchronises the stream),
+ * keeps the fastest for later calls at this mode count and writes it to
+ * *lane_group_out and *schedule_out (either may be NULL); the outputs are those of
+ * a final run with the choice.  The choice changes only the order of the grid
+ * sums.  (polypic_batch_g2p2g always uses pairs in the XCD order.) */
+int32_t polypic_set_g2p2g_config(int32_t n_modes, int32_t lane_group, int32_t schedule);
+int32_t polypic_get_g2p2g_config(int32_t n_modes, int32_t* lane_group, int32_t* schedule);
 int32_t polypic_autotune_g2p2g(const polypic_grid* grid, int64_t P, int32_t n_modes, float dt,
                                const float* grid_vel, const float* x_in, const int32_t* perm,
                                float* x_out, float* coeff_out, const float* F_in, float* F_out,
                                const float* mass_in, float* mass_out, float uniform_mass,
                                float* grid_mass, float* grid_mom, int32_t* lane_group_out,
-                               void* stream);
+                               int32_t* schedule_out, void* stream);
 
 /* ------------------------------------------------------------------------
  * Adjoint (reverse mode) of one step.  For a scalar loss L of the step's
@@ -589,6 +624,7 @@ typedef struct polypic_batch {
   int32_t max_nodes;   /* largest scene node count */
   int64_t P;           /* total particles */
   int64_t N;           /* total nodes per grid channel */
+  int64_t n_regions;   /* active regions of all scenes */
   const void* table;   /* device scene table (in the caller's buffer) */
   uint64_t seal;       /* written by polypic_batch_plan */
 } polypic_batch;
@@ -624,14 +660,23 @@ int32_t polypic_batch_g2p(const polypic_batch* batch, int32_t n_modes, float dt,
                           void* stream);
 /* polypic_batch_g2p2g: polypic_g2p2g over every scene of the batch (each scene's
  * G2P, advection and next P2G on its own grid; grid_mass / grid_mom span batch->N
- * nodes and are cleared first).  Arguments as polypic_batch_g2p plus uniform_mass,
- * grid_mass and grid_mom, with the aliasing rules of polypic_g2p2g. */
+ * nodes and are cleared first unless accumulate = 1).  Arguments as
+ * polypic_batch_g2p plus uniform_mass, grid_mass, grid_mom, accumulate and
+ * region_state (batch->n_regions flags: the regions of the scenes in order,
+ * each scene's numbered as for its grid alone), with the rules of
+ * polypic_g2p2g. */
 int32_t polypic_batch_g2p2g(const polypic_batch* batch, int32_t n_modes, float dt,
                             const float* grid_vel, const float* x_in, const int32_t* perm,
                             float* x_out, float* coeff_out, const float* F_in, float* F_out,
                             const float* mass_in, float* mass_out, float uniform_mass,
-                            float* grid_mass, float* grid_mom, int32_t* status_dev,
-                            void* stream);
+                            float* grid_mass, float* grid_mom, int32_t accumulate,
+                            uint32_t* region_state, int32_t* status_dev, void* stream);
+/* polypic_batch_grid_update_active: polypic_grid_update_active over every scene of
+ * the batch, with the batch layouts. */
+int32_t polypic_batch_grid_update_active(const polypic_batch* batch, float dt,
+                                         const float* gravity, int32_t bc_layers,
+                                         float* grid_mass, float* grid_mom, float* grid_vel,
+                                         uint32_t* region_state, void* stream);
 int32_t polypic_batch_set_config(int32_t n_modes, int32_t block, int32_t schedule,
                                  int32_t per_cu);
 int32_t polypic_batch_get_config(int32_t n_modes, int32_t* block, int32_t* schedule,

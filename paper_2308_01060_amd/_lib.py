@@ -49,6 +49,8 @@ EXPORTED = (
     "polypic_get_g2p_schedule",
     "polypic_grid_update",
     "polypic_grid_update_clear",
+    "polypic_region_count",
+    "polypic_grid_update_active",
     "polypic_g2p",
     "polypic_g2p2g",
     "polypic_set_g2p2g_config",
@@ -77,6 +79,7 @@ EXPORTED = (
     "polypic_batch_grid_update",
     "polypic_batch_g2p",
     "polypic_batch_g2p2g",
+    "polypic_batch_grid_update_active",
     "polypic_batch_set_config",
     "polypic_batch_get_config",
     "polypic_batch_autotune",
@@ -117,6 +120,7 @@ class polypic_batch(ctypes.Structure):
         ("max_nodes", ctypes.c_int32),
         ("P", ctypes.c_int64),
         ("N", ctypes.c_int64),
+        ("n_regions", ctypes.c_int64),
         ("table", ctypes.c_void_p),
         ("seal", ctypes.c_uint64),
     ]
@@ -189,6 +193,10 @@ def load() -> ctypes.CDLL:
     lib.polypic_grid_update.argtypes = [G, f32, ctypes.POINTER(f32), i32, P, P, P, P]
     lib.polypic_grid_update_clear.restype = i32
     lib.polypic_grid_update_clear.argtypes = [G, f32, ctypes.POINTER(f32), i32, P, P, P, P]
+    lib.polypic_region_count.restype = i32
+    lib.polypic_region_count.argtypes = [G, ctypes.POINTER(i64)]
+    lib.polypic_grid_update_active.restype = i32
+    lib.polypic_grid_update_active.argtypes = [G, f32, ctypes.POINTER(f32), i32, P, P, P, P, P]
     lib.polypic_g2p.restype = i32
     lib.polypic_g2p.argtypes = [G, i64, i32, f32, P, P, P, P, P, P, P, P, P, P, P]
     lib.polypic_mixture_p2g.restype = i32
@@ -208,14 +216,14 @@ def load() -> ctypes.CDLL:
     lib.polypic_mac_g2p.argtypes = [G, i64, i32, f32, P, P, P, P, P, P, P, P, P, P, P]
     lib.polypic_g2p2g.restype = i32
     lib.polypic_g2p2g.argtypes = [G, i64, i32, f32, P, P, P, P, P, P, P, P, P, f32, P, P, i32,
-                                  P, P]
+                                  P, P, P]
     lib.polypic_set_g2p2g_config.restype = i32
-    lib.polypic_set_g2p2g_config.argtypes = [i32, i32]
+    lib.polypic_set_g2p2g_config.argtypes = [i32, i32, i32]
     lib.polypic_get_g2p2g_config.restype = i32
-    lib.polypic_get_g2p2g_config.argtypes = [i32, pi]
+    lib.polypic_get_g2p2g_config.argtypes = [i32, pi, pi]
     lib.polypic_autotune_g2p2g.restype = i32
     lib.polypic_autotune_g2p2g.argtypes = [G, i64, i32, f32, P, P, P, P, P, P, P, P, P, f32, P,
-                                           P, pi, P]
+                                           P, pi, pi, P]
     lib.polypic_g2p_backward.restype = i32
     lib.polypic_g2p_backward.argtypes = [G, i64, i32, f32, P, P, P, P, P, P, i32, P, P, P]
     lib.polypic_grid_update_backward.restype = i32
@@ -249,7 +257,11 @@ def load() -> ctypes.CDLL:
     lib.polypic_batch_g2p.restype = i32
     lib.polypic_batch_g2p.argtypes = [B, i32, f32, P, P, P, P, P, P, P, P, P, P, P]
     lib.polypic_batch_g2p2g.restype = i32
-    lib.polypic_batch_g2p2g.argtypes = [B, i32, f32, P, P, P, P, P, P, P, P, P, f32, P, P, P, P]
+    lib.polypic_batch_g2p2g.argtypes = [B, i32, f32, P, P, P, P, P, P, P, P, P, f32, P, P, i32, P,
+                                        P, P]
+    lib.polypic_batch_grid_update_active.restype = i32
+    lib.polypic_batch_grid_update_active.argtypes = [B, f32, ctypes.POINTER(f32), i32, P, P, P,
+                                                     P, P]
     lib.polypic_batch_set_config.restype = i32
     lib.polypic_batch_set_config.argtypes = [i32, i32, i32, i32]
     lib.polypic_batch_get_config.restype = i32

@@ -13,6 +13,11 @@ the G2P of a step and the P2G of the next are one call,
 ``polypic_batch_g2p2g``, as in ``ParticleSet``: a step is sort -> grid update ->
 G2P2G, with a P2G first when the grid does not hold the current state.
 
+Fused steps keep the grid passes to the active regions (16 x 4 x 4-node boxes)
+that the previous G2P2G flagged: after the first step, the grid update is
+``polypic_batch_grid_update_active`` (which also clears the grid) and G2P2G adds
+into the cleared grid, flagging where it lands.
+
 A step can be captured once as a HIP graph (``capture``) and replayed
 (``replay``): the positions ping-pong between two buffers, so two graphs are
 captured, one per direction.  The coefficients are updated in place (G2P reads
@@ -72,6 +77,11 @@ class BatchedParticleSet:
         self.fused = bool(fused)
         self.grid_current = False  # grid_mass / grid_mom hold the P2G of the current state
         self._next_grid_current = False
+        # active regions: the fused scatter flags them; regions_valid says that grid_mass /
+        # grid_mom are zero outside the flagged regions (the last writer was a flagging G2P2G)
+        self.region_state = torch.zeros(ops.region_state_words(self.batch.n_regions),
+                                        dtype=torch.int32, device=device)
+        self.regions_valid = False
 
     @property
     def P(self) -> int:
@@ -107,10 +117,19 @@ class BatchedParticleSet:
                               self.grid_mom, mass=self.mass, uniform_mass=self.uniform_mass,
                               perm=self.perm if use_perm else None, status_dev=self.status)
         self.grid_current = True
+        self.regions_valid = False
 
     def grid_update(self):
         ops.polypic_batch_grid_update(self.batch, self.dt, self.gravity, self.bc_layers,
                                       self.grid_mass, self.grid_mom, self.grid_vel)
+
+    def grid_update_active(self):
+        """The grid update on the flagged regions only; it leaves the grid cleared."""
+        if not self.regions_valid:
+            raise RuntimeError("the grid is not confined to flagged regions")
+        ops.polypic_batch_grid_update_active(self.batch, self.dt, self.gravity, self.bc_layers,
+                                             self.grid_mass, self.grid_mom, self.grid_vel,
+                                             self.region_state)
 
     def g2p(self, use_perm: bool = True):
         ops.polypic_batch_g2p(self.batch, self.n_modes, self.dt, self.grid_vel, self.x,
@@ -119,14 +138,18 @@ class BatchedParticleSet:
                               status_dev=self.status)
         self._next_grid_current = False
 
-    def g2p2g(self, use_perm: bool = True):
-        """G2P + advection of every scene, and the P2G of the new state into the grid."""
+    def g2p2g(self, use_perm: bool = True, accumulate: bool = False):
+        """G2P + advection of every scene, and the P2G of the new state into the grid
+        (cleared first, or with accumulate=True added to a grid the active update cleared),
+        flagging the regions it lands in."""
         ops.polypic_batch_g2p2g(self.batch, self.n_modes, self.dt, self.grid_vel, self.x,
                                 self.x_next, self.coeff_next, self.grid_mass, self.grid_mom,
                                 perm=self.perm if use_perm else None, mass_in=self.mass,
                                 mass_out=self.mass_next, uniform_mass=self.uniform_mass,
-                                status_dev=self.status)
+                                status_dev=self.status, accumulate=accumulate,
+                                region_state=self.region_state)
         self._next_grid_current = True
+        self.regions_valid = True
 
     def swap(self):
         self.x, self.x_next = self.x_next, self.x
@@ -141,8 +164,12 @@ class BatchedParticleSet:
     def _step_calls(self):
         """One step after the sort, the grid holding the current state's P2G when fused."""
         if self.fused:
-            self.grid_update()
-            self.g2p2g()
+            if self.regions_valid:
+                self.grid_update_active()
+                self.g2p2g(accumulate=True)
+            else:
+                self.grid_update()
+                self.g2p2g()
         else:
             self.p2g()
             self.grid_update()
@@ -164,18 +191,23 @@ class BatchedParticleSet:
     def autotune(self):
         """Sort, then let the library time its batched P2G configurations (synchronises)."""
         self.sort()
+        self.regions_valid = False  # the timed P2G calls rewrite the grid
         return ops.polypic_batch_autotune(self.batch, self.n_modes, self.x, self.coeff,
                                           self.grid_mass, self.grid_mom, mass=self.mass,
                                           uniform_mass=self.uniform_mass, perm=self.perm)
 
     # ---- graph capture
     def capture(self):
-        """Capture one step in each buffer direction as a HIP graph (no work is run).
+        """Capture one step in each buffer direction as a HIP graph.
 
-        Fused, the graphs hold sort -> grid update -> G2P2G, so the grid must hold the
-        current state's P2G before the first replay (one eager step does that)."""
+        Fused, the graphs hold sort -> active grid update -> G2P2G, so the grid must hold
+        the current state's P2G, confined to flagged regions, before the first replay: one
+        eager step does that, and capture runs one itself when the grid holds the current
+        state but its regions are not known (after the autotuner's P2G calls)."""
         if self.fused and not self.grid_current:
             raise RuntimeError("fused capture needs the grid current: run one step() first")
+        if self.fused and not self.regions_valid:
+            self.step()
         torch.cuda.synchronize()
         graphs = []
         for _ in range(2):

@@ -41,7 +41,8 @@ __global__ __launch_bounds__(256) void grid_update_backward_kernel(GridUpdateBac
     float pb[3];
 #pragma unroll
     for (int ax = 0; ax < 3; ++ax) {
-      const float v = p[ax] / m + a.dt * g[ax];
+      // the forward's rounding: fl(fl(p / m) + fl(dt g)), not contracted
+      const float v = __fadd_rn(p[ax] / m, __fmul_rn(a.dt, g[ax]));
       bool pass = true;  // derivative of the wall clamp
       if (a.bc_layers > 0) {
         if (idx[ax] <= 1 + a.bc_layers && v < 0.0f) pass = false;

@@ -110,10 +110,14 @@ P2GConfig to_config(const P2GChoice& c) {
 std::atomic<int> g_g2p_sched{POLYPIC_SCHED_LINEAR};
 // lane-group size of the fused G2P2G kernel per mode count (0: the default, pairs)
 std::atomic<int> g_fused_lane[28];
+std::atomic<int> g_fused_sched[28];  // POLYPIC_SCHED_LINEAR (the default) or _XCD
 
 int fused_lane_group(int n_modes) {
   const int v = g_fused_lane[n_modes].load();
   return v == 4 ? 4 : 2;
+}
+int fused_sched(int n_modes) {
+  return g_fused_sched[n_modes].load() == POLYPIC_SCHED_XCD ? kSchedXcd : kSchedLinear;
 }
 std::mutex g_tune_mutex;
 P2GChoice g_tune[28];
@@ -218,6 +222,7 @@ uint64_t batch_seal(const polypic_batch* b) {
   mix((uint32_t)b->max_nodes);
   mix((uint64_t)b->P);
   mix((uint64_t)b->N);
+  mix((uint64_t)b->n_regions);
   mix((uint64_t)(uintptr_t)b->table);
   return h;
 }
@@ -542,6 +547,8 @@ int32_t polypic_grid_update(const polypic_grid* grid, float dt, const float* gra
   a.gv = grid_vel;
   a.clear_gm = nullptr;
   a.clear_gp = nullptr;
+  a.regions = nullptr;
+  a.n_regions = 0;
   discard_stale_error();
   return from_hip(launch_grid_update(a, (hipStream_t)stream));
 }
@@ -572,8 +579,50 @@ int32_t polypic_grid_update_clear(const polypic_grid* grid, float dt, const floa
   a.gv = grid_vel;
   a.clear_gm = grid_mass;
   a.clear_gp = grid_mom;
+  a.regions = nullptr;
+  a.n_regions = 0;
   discard_stale_error();
   return from_hip(launch_grid_update(a, (hipStream_t)stream));
+}
+
+int32_t polypic_region_count(const polypic_grid* grid, int64_t* count) {
+  int32_t st = check_grid(grid);
+  if (st) return st;
+  if (!count) return POLYPIC_EINVAL;
+  *count = region_count(grid->nx, grid->ny, grid->nz);
+  return POLYPIC_OK;
+}
+
+int32_t polypic_grid_update_active(const polypic_grid* grid, float dt, const float* gravity,
+                                   int32_t bc_layers, float* grid_mass, float* grid_mom,
+                                   float* grid_vel, uint32_t* region_state, void* stream) {
+  int32_t st = check_grid(grid);
+  if (st) return st;
+  if (!gravity || !grid_mass || !grid_mom || !grid_vel || !region_state) return POLYPIC_EINVAL;
+  if (!isfinite(dt) || bc_layers < 0) return POLYPIC_EINVAL;
+  for (int k = 0; k < 3; ++k)
+    if (!isfinite(gravity[k])) return POLYPIC_EINVAL;
+  const int64_t N = n_nodes(grid);
+  if (overlaps(grid_vel, 3 * N, grid_mass, N) || overlaps(grid_vel, 3 * N, grid_mom, 3 * N))
+    return POLYPIC_EINVAL;
+  GridUpdateArgs a;
+  a.nx = grid->nx;
+  a.ny = grid->ny;
+  a.nz = grid->nz;
+  a.dt = dt;
+  a.g0 = gravity[0];
+  a.g1 = gravity[1];
+  a.g2 = gravity[2];
+  a.bc_layers = bc_layers;
+  a.gm = grid_mass;
+  a.gp = grid_mom;
+  a.gv = grid_vel;
+  a.clear_gm = grid_mass;
+  a.clear_gp = grid_mom;
+  a.regions = region_state;
+  a.n_regions = region_count(grid->nx, grid->ny, grid->nz);
+  discard_stale_error();
+  return from_hip(launch_grid_update_active(a, (hipStream_t)stream));
 }
 
 int32_t polypic_g2p(const polypic_grid* grid, int64_t P, int32_t n_modes, float dt,
@@ -694,6 +743,8 @@ int32_t polypic_mixture_grid_update(const polypic_grid* grid, float dt, const fl
     a.gv = grid_vel + ph * 3 * N;
     a.clear_gm = nullptr;
     a.clear_gp = nullptr;
+    a.regions = nullptr;
+    a.n_regions = 0;
     if ((st = from_hip(launch_grid_update(a, (hipStream_t)stream)))) return st;
   }
   return POLYPIC_OK;
@@ -886,7 +937,7 @@ int32_t polypic_g2p2g(const polypic_grid* grid, int64_t P, int32_t n_modes, floa
                       float* x_out, float* coeff_out, const float* F_in, float* F_out,
                       const float* mass_in, float* mass_out, float uniform_mass,
                       float* grid_mass, float* grid_mom, int32_t accumulate,
-                      int32_t* status_dev, void* stream) {
+                      uint32_t* region_state, int32_t* status_dev, void* stream) {
   int32_t st = check_grid(grid);
   if (st) return st;
   if ((st = check_P(P))) return st;
@@ -924,20 +975,27 @@ int32_t polypic_g2p2g(const polypic_grid* grid, int64_t P, int32_t n_modes, floa
   a.gstride = N;
   a.lane_group = fused_lane_group(n_modes);
   a.accumulate = accumulate != 0;
+  a.sched = fused_sched(n_modes);
+  a.regions = region_state;
+  a.n_regions = region_count(grid->nx, grid->ny, grid->nz);
   discard_stale_error();
   return from_hip(launch_g2p2g(a, n_modes, (hipStream_t)stream));
 }
 
-int32_t polypic_set_g2p2g_config(int32_t n_modes, int32_t lane_group) {
+int32_t polypic_set_g2p2g_config(int32_t n_modes, int32_t lane_group, int32_t schedule) {
   if (!valid_modes(n_modes)) return POLYPIC_EINVAL;
   if (lane_group != -1 && lane_group != 2 && lane_group != 4) return POLYPIC_EINVAL;
+  if (schedule != -1 && schedule != POLYPIC_SCHED_LINEAR && schedule != POLYPIC_SCHED_XCD)
+    return POLYPIC_EINVAL;
   g_fused_lane[n_modes].store(lane_group == -1 ? 0 : lane_group);
+  g_fused_sched[n_modes].store(schedule == -1 ? POLYPIC_SCHED_LINEAR : schedule);
   return POLYPIC_OK;
 }
 
-int32_t polypic_get_g2p2g_config(int32_t n_modes, int32_t* lane_group) {
-  if (!valid_modes(n_modes) || !lane_group) return POLYPIC_EINVAL;
+int32_t polypic_get_g2p2g_config(int32_t n_modes, int32_t* lane_group, int32_t* schedule) {
+  if (!valid_modes(n_modes) || !lane_group || !schedule) return POLYPIC_EINVAL;
   *lane_group = fused_lane_group(n_modes);
+  *schedule = fused_sched(n_modes) == kSchedXcd ? POLYPIC_SCHED_XCD : POLYPIC_SCHED_LINEAR;
   return POLYPIC_OK;
 }
 
@@ -946,36 +1004,44 @@ int32_t polypic_autotune_g2p2g(const polypic_grid* grid, int64_t P, int32_t n_mo
                                float* x_out, float* coeff_out, const float* F_in, float* F_out,
                                const float* mass_in, float* mass_out, float uniform_mass,
                                float* grid_mass, float* grid_mom, int32_t* lane_group_out,
-                               void* stream) {
-  // the candidates run the call itself: validate once through it with the default
-  const int keep = g_fused_lane[n_modes < 0 || n_modes > 27 ? 0 : n_modes].load();
+                               int32_t* schedule_out, void* stream) {
+  // the candidates run the call itself: validate once through it with the setting it has
+  const int m = n_modes < 0 || n_modes > 27 ? 0 : n_modes;
+  const int keep_lane = g_fused_lane[m].load(), keep_sched = g_fused_sched[m].load();
   int32_t st = polypic_g2p2g(grid, P, n_modes, dt, grid_vel, x_in, perm, x_out, coeff_out, F_in,
                              F_out, mass_in, mass_out, uniform_mass, grid_mass, grid_mom, 0,
-                             nullptr, stream);
+                             nullptr, nullptr, stream);
   if (st) return st;
   const hipStream_t s = (hipStream_t)stream;
-  const int cand[2] = {2, 4};
+  // lane groups x chunk orders
+  const int cand_lane[4] = {2, 4, 2, 4};
+  const int cand_sched[4] = {POLYPIC_SCHED_LINEAR, POLYPIC_SCHED_LINEAR, POLYPIC_SCHED_XCD,
+                             POLYPIC_SCHED_XCD};
   int bi = 0;
   st = time_candidates(
-      2, s,
+      4, s,
       [&](int k) {
-        g_fused_lane[n_modes].store(cand[k]);
+        g_fused_lane[n_modes].store(cand_lane[k]);
+        g_fused_sched[n_modes].store(cand_sched[k]);
         return polypic_g2p2g(grid, P, n_modes, dt, grid_vel, x_in, perm, x_out, coeff_out, F_in,
                              F_out, mass_in, mass_out, uniform_mass, grid_mass, grid_mom, 0,
-                             nullptr, stream);
+                             nullptr, nullptr, stream);
       },
       &bi);
   if (st) {
-    g_fused_lane[n_modes].store(keep);
+    g_fused_lane[n_modes].store(keep_lane);
+    g_fused_sched[n_modes].store(keep_sched);
     return st;
   }
-  g_fused_lane[n_modes].store(cand[bi]);
-  if (lane_group_out) *lane_group_out = cand[bi];
+  g_fused_lane[n_modes].store(cand_lane[bi]);
+  g_fused_sched[n_modes].store(cand_sched[bi]);
+  if (lane_group_out) *lane_group_out = cand_lane[bi];
+  if (schedule_out) *schedule_out = cand_sched[bi];
   // the outputs hold the last candidate's results: rerun the chosen one so that they
   // are the call's (the two differ only in the order of the grid sums)
   return polypic_g2p2g(grid, P, n_modes, dt, grid_vel, x_in, perm, x_out, coeff_out, F_in,
                        F_out, mass_in, mass_out, uniform_mass, grid_mass, grid_mom, 0, nullptr,
-                       stream);
+                       nullptr, stream);
 }
 
 int32_t polypic_g2p_backward(const polypic_grid* grid, int64_t P, int32_t n_modes, float dt,
@@ -1086,7 +1152,7 @@ int32_t polypic_batch_plan(const polypic_scene* scenes, int32_t n_scenes, int64_
   if (n_scenes < 1 || n_scenes > kMaxScenes || n_nodes_total < 1) return POLYPIC_EINVAL;
   if (table_bytes < (size_t)n_scenes * sizeof(SceneDev)) return POLYPIC_ENOSPACE;
   std::vector<SceneDev> host((size_t)n_scenes);
-  int64_t p_next = 0, node_end = 0, max_nodes = 0;
+  int64_t p_next = 0, node_end = 0, max_nodes = 0, chunks = 0, regions = 0;
   int mbits = 0;
   for (int32_t k = 0; k < n_scenes; ++k) {
     const polypic_scene& sc = scenes[k];
@@ -1113,6 +1179,10 @@ int32_t polypic_batch_plan(const polypic_scene* scenes, int32_t n_scenes, int64_
     d.p_begin = sc.p_offset;
     d.p_end = sc.p_offset + sc.n_particles;
     d.node_off = sc.node_offset;
+    d.chunk_begin = chunks;
+    chunks += (sc.n_particles + kSceneChunk - 1) / kSceneChunk;
+    d.region_begin = regions;
+    regions += region_count(sc.grid.nx, sc.grid.ny, sc.grid.nz);
   }
   int sbits = 0;
   while (((int64_t)1 << sbits) < (int64_t)n_scenes) ++sbits;
@@ -1129,6 +1199,7 @@ int32_t polypic_batch_plan(const polypic_scene* scenes, int32_t n_scenes, int64_
   batch->max_nodes = (int32_t)max_nodes;
   batch->P = p_next;
   batch->N = n_nodes_total;
+  batch->n_regions = regions;
   batch->table = table_dev;
   batch->seal = batch_seal(batch);
   return POLYPIC_OK;
@@ -1217,9 +1288,43 @@ int32_t polypic_batch_grid_update(const polypic_batch* batch, float dt, const fl
   a.gv = grid_vel;
   a.clear_gm = nullptr;
   a.clear_gp = nullptr;
+  a.regions = nullptr;
+  a.n_regions = 0;
   discard_stale_error();
   return from_hip(launch_grid_update_batch(a, batch_table(batch), batch->n_scenes,
                                            batch->max_nodes, batch->N, (hipStream_t)stream));
+}
+
+int32_t polypic_batch_grid_update_active(const polypic_batch* batch, float dt,
+                                         const float* gravity, int32_t bc_layers,
+                                         float* grid_mass, float* grid_mom, float* grid_vel,
+                                         uint32_t* region_state, void* stream) {
+  int32_t st = check_batch(batch);
+  if (st) return st;
+  if (!gravity || !grid_mass || !grid_mom || !grid_vel || !region_state) return POLYPIC_EINVAL;
+  if (!isfinite(dt) || bc_layers < 0) return POLYPIC_EINVAL;
+  for (int a = 0; a < 3; ++a)
+    if (!isfinite(gravity[a])) return POLYPIC_EINVAL;
+  const int64_t N = batch->N;
+  if (overlaps(grid_vel, 3 * N, grid_mass, N) || overlaps(grid_vel, 3 * N, grid_mom, 3 * N))
+    return POLYPIC_EINVAL;
+  GridUpdateArgs a;
+  a.nx = a.ny = a.nz = 0;  // per scene, from the table
+  a.dt = dt;
+  a.g0 = gravity[0];
+  a.g1 = gravity[1];
+  a.g2 = gravity[2];
+  a.bc_layers = bc_layers;
+  a.gm = grid_mass;
+  a.gp = grid_mom;
+  a.gv = grid_vel;
+  a.clear_gm = grid_mass;
+  a.clear_gp = grid_mom;
+  a.regions = region_state;
+  a.n_regions = batch->n_regions;
+  discard_stale_error();
+  return from_hip(launch_grid_update_active_batch(a, batch_table(batch), batch->n_scenes, N,
+                                                  (hipStream_t)stream));
 }
 
 int32_t polypic_batch_g2p(const polypic_batch* batch, int32_t n_modes, float dt,
@@ -1261,8 +1366,8 @@ int32_t polypic_batch_g2p2g(const polypic_batch* batch, int32_t n_modes, float d
                             const float* grid_vel, const float* x_in, const int32_t* perm,
                             float* x_out, float* coeff_out, const float* F_in, float* F_out,
                             const float* mass_in, float* mass_out, float uniform_mass,
-                            float* grid_mass, float* grid_mom, int32_t* status_dev,
-                            void* stream) {
+                            float* grid_mass, float* grid_mom, int32_t accumulate,
+                            uint32_t* region_state, int32_t* status_dev, void* stream) {
   int32_t st = check_batch(batch);
   if (st) return st;
   if (!valid_modes(n_modes) || !isfinite(dt)) return POLYPIC_EINVAL;
@@ -1297,8 +1402,14 @@ int32_t polypic_batch_g2p2g(const polypic_batch* batch, int32_t n_modes, float d
   a.gp2 = grid_mom + 2 * N;
   a.status = status_dev;
   a.gstride = N;
-  a.accumulate = 0;
-  a.lane_group = 2;  // the batched kernel folds lane pairs
+  a.accumulate = accumulate != 0;
+  a.regions = region_state;
+  a.n_regions = batch->n_regions;
+  // lane pairs; chunks XCD-contiguous: a batch's grids do not stay in the last-level
+  // cache between the passes, so neighbouring chunks share one L2 (measured, 64
+  // scenes, 25.7 M particles: 3.81 -> 3.57 ms per graph step)
+  a.sched = kSchedXcd;
+  a.lane_group = 2;
   discard_stale_error();
   return from_hip(launch_g2p2g_batch(a, batch_table(batch), batch->n_scenes, n_modes,
                                      (hipStream_t)stream));

@@ -652,6 +652,36 @@ __device__ __forceinline__ BrickNode brick_node(int t) {
   return n;
 }
 
+// ---------------------------------------------------------------- active regions
+// Nodes grouped in boxes of 16 x 4 x 4 (x fastest; the last box of an axis may be
+// partial), numbered x fastest, one uint32 flag each.  The scatter of a stepped
+// simulation sets the flags of the boxes it touches (plain stores: nothing waits on
+// them) and the next grid pass visits only flagged boxes, resetting their flags.  A
+// row of a box is 64 bytes of one channel.
+constexpr int kRegX = 16, kRegY = 4, kRegZ = 4;
+
+__host__ __device__ inline int regions_along(int n, int e) { return (n + e - 1) / e; }
+
+// region of node (gx, gy, gz) of an nx x ny grid
+__device__ __forceinline__ int64_t region_of(int nx, int ny, int gx, int gy, int gz) {
+  const int rx = regions_along(nx, kRegX), ry = regions_along(ny, kRegY);
+  return ((int64_t)(gz / kRegZ) * ry + gy / kRegY) * rx + gx / kRegX;
+}
+
+// Flags every region that holds a node of the box [lo, lo + ext) per axis (ext <= 16
+// on y and z, <= 32 on x: at most two regions per axis, found from the box's corners),
+// clipped to the grid; corner in [0, 8) selects one corner: call it for each.  A flag
+// holds 1 + the scene of the region (0 for one grid), so the pass that visits it needs
+// no lookup.
+__device__ __forceinline__ void flag_box_corner(uint32_t* flags, int64_t region_off,
+                                                uint32_t scene, int nx, int ny, int nz, int lo0,
+                                                int lo1, int lo2, int ext, int corner) {
+  const int gx = min(lo0 + ((corner & 1) ? ext - 1 : 0), nx - 1);
+  const int gy = min(lo1 + ((corner & 2) ? ext - 1 : 0), ny - 1);
+  const int gz = min(lo2 + ((corner & 4) ? ext - 1 : 0), nz - 1);
+  flags[region_off + region_of(nx, ny, gx, gy, gz)] = scene + 1u;
+}
+
 // ---------------------------------------------------------------- Morton key
 __device__ __forceinline__ uint32_t spread_bits3(uint32_t v) {
   v &= 0x3ffu;

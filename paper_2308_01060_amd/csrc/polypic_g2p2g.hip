@@ -58,38 +58,33 @@ __device__ __forceinline__ int stage_pos(int s) {
 // particles per cell two groups of a wavefront do not share a cell and its LDS
 // addresses; the fused autotuner picks between them on the caller's data.
 template <int NR, int BS, class Scenes, int LG>
-__global__ __launch_bounds__(BS, Scenes::kMany ? 3 : 4) void g2p2g_kernel(G2P2GArgs a, Scenes sc) {
+__global__ __launch_bounds__(BS, 4) void g2p2g_kernel(G2P2GArgs a, Scenes sc) {
   constexpr int NW = BS / kWave;
   static_assert(LG == 1 || LG == 2, "lane pairs or quads");
+  static_assert(!Scenes::kMany, "a workgroup's slots lie in one scene (OneScene, SceneChunks)");
   __shared__ double brick[kBrickKMAX * 4 * kBrickV];  // [brick][channel][node]
   __shared__ uint64_t tile_of[BS];                    // by processing slot
   __shared__ int seg_of[BS];
   __shared__ uint64_t seg_tile[kBrickKMAX];
   __shared__ int wave_heads[NW];
-  // tile of each of the first 64 runs: in tile_of's storage, written only after the
-  // last read of tile_of (the run index needs the barrier that follows those reads)
-  uint64_t* const run_tile = tile_of;
+  __shared__ uint64_t run_tile[kWave];  // tile of each of the first 64 runs
   __shared__ int run_brick[kWave];      // brick (distinct-tile index) of each run
   __shared__ int n_bricks;
-  // grid of each brick's scene (batches only; one scene folds to constants)
-  __shared__ int seg_dims[kBrickKMAX][3];
-  __shared__ int64_t seg_node_off[kBrickKMAX];
 
   const int tid = threadIdx.x;
   const int lane = tid & (kWave - 1);
   const int wv = tid / kWave;
   const int slot = fused_slot<LG, NW>(tid);
   const size_t Ps = (size_t)a.P;
-  const int64_t i0 = (int64_t)blockIdx.x * BS;
+  // this workgroup's chunk (in launch order, or XCD-contiguous), its slots
+  // [i0, i0 + n_slots) and the scene of the first
+  const Chunk ck = sc.template chunk<BS>(a.P, block_chunks(a.sched, gridDim.x).begin);
+  if (ck.n <= 0) return;  // (whole workgroup: past the last chunk of a scene-chunked launch)
+  const int64_t i0 = ck.i0;
+  const int n_slots = ck.n;
   const int64_t i = i0 + slot;
-  const bool in = i < a.P;
-  // scene of the slot; one wave-uniform lookup unless the wavefront straddles scenes
-  const int s0 = sc.first(i0);
-  const int s = in ? sc.of(i, s0) : s0;
-  SceneGrid g = sc.grid(s0);
-  if constexpr (Scenes::kMany) {
-    if (__ballot(s != s0) != 0ull) g = sc.grid(s);
-  }
+  const bool in = slot < n_slots;
+  const SceneGrid g = sc.grid(ck.s);  // uniform over the workgroup
   const int nx = g.nx, ny = g.ny, nz = g.nz;
   const int nxny = nx * ny;
   // a caller permutation is clamped into [0, P): a bad one gives wrong results, never a fault
@@ -118,12 +113,12 @@ __global__ __launch_bounds__(BS, Scenes::kMany ? 3 : 4) void g2p2g_kernel(G2P2GA
   // a round is stage[k * BS + stage_pos(slot)], read back at stage_pos(tid).
   float* const stage = reinterpret_cast<float*>(brick);
   static_assert(28 * BS * sizeof(float) <= sizeof(brick), "staging fits in the bricks");
-  const int64_t i_out = (int64_t)blockIdx.x * BS + tid;  // slot this thread writes out
+  const int64_t i_out = i0 + tid;  // slot this thread writes out
   const int put = stage_pos<LG>(slot), get = stage_pos<LG>(tid);
   // floats of this workgroup's rows that exist, and this thread's byte in a row
-  const int row_n = (int)min((int64_t)BS, a.P - (int64_t)blockIdx.x * BS);
+  const int row_n = n_slots;
   const int out_off = tid * (int)sizeof(float);
-  const bool out_ok = i_out < a.P;
+  const bool out_ok = tid < n_slots;
   {
     const Proj1D px = proj_g2p(t0);
     const Proj1D py = proj_g2p(t1);
@@ -230,7 +225,7 @@ __global__ __launch_bounds__(BS, Scenes::kMany ? 3 : 4) void g2p2g_kernel(G2P2GA
     }
   }
   if (!valid) m = 0.0f;
-  tile_of[slot] = valid ? brick_tile_id(s - s0, c0, c1, c2) : kNoTile;
+  tile_of[slot] = valid ? brick_tile_id(0, c0, c1, c2) : kNoTile;
   static_assert(kBrickNodes <= BS, "one brick node per thread");
   const BrickNode bn = brick_node(tid);
   if (tid < kBrickNodes) {
@@ -275,16 +270,7 @@ __global__ __launch_bounds__(BS, Scenes::kMany ? 3 : 4) void g2p2g_kernel(G2P2GA
     const int d_first = lanes_below(fb);
     const int d = __shfl(d_first, first_same, kWave);
     if (lane < nr) run_brick[lane] = d;
-    if (first && d < kBrickKMAX) {
-      seg_tile[d] = mine;
-      if constexpr (Scenes::kMany) {
-        const SceneGrid fg = sc.grid(s0 + (int)(mine >> 32));
-        seg_dims[d][0] = fg.nx;
-        seg_dims[d][1] = fg.ny;
-        seg_dims[d][2] = fg.nz;
-        seg_node_off[d] = fg.node_off;
-      }
-    }
+    if (first && d < kBrickKMAX) seg_tile[d] = mine;
     if (lane == 0) n_bricks = __popcll(fb);
   }
   __syncthreads();
@@ -292,13 +278,31 @@ __global__ __launch_bounds__(BS, Scenes::kMany ? 3 : 4) void g2p2g_kernel(G2P2GA
   // brick of this slot's run; runs past kRuns, and tiles past the brick budget, go to HBM.
   // A run past kRuns keeps a value of its own (kBrickKMAX + run index, above every
   // distinct-tile index d < kRuns), so that two lanes of different runs never compare
-  // equal below: in a batch, slots on either side of a scene boundary can share local
-  // base-node coordinates, and folding them would add one scene's values to the other's
-  // grid.
+  // equal below.
   const int seg = run_slot < 0 ? -1
                                : (run_slot < kRuns ? run_brick[run_slot] : kBrickKMAX + run_slot);
   const int nseg = n_bricks;
-
+  if (a.regions) {
+    // the regions the scatter lands in: each brick's 6^3 nodes, and the 6^3 nodes of
+    // the tile of every slot that went to HBM directly (a box holding its stencil);
+    // from the run bookkeeping, before the scatter holds its node values (plain stores)
+    const int nb = nseg < kBrickKMAX ? nseg : kBrickKMAX;
+    if (tid < 8 * nb) {
+      const uint32_t tc = (uint32_t)seg_tile[tid >> 3];
+      flag_box_corner(a.regions, g.region_off, (uint32_t)ck.s, nx, ny, nz,
+                      (int)(tc & 1023u) * kBrickT, (int)((tc >> 10) & 1023u) * kBrickT,
+                      (int)(tc >> 20) * kBrickT, kBrickN, tid & 7);
+    }
+    const int run_t = seg_of[tid];
+    if (run_t >= 0 && (run_t >= kRuns || run_brick[run_t] >= kBrickKMAX)) {
+      const uint32_t tc = (uint32_t)tile_of[tid];
+#pragma unroll
+      for (int corner = 0; corner < 8; ++corner)
+        flag_box_corner(a.regions, g.region_off, (uint32_t)ck.s, nx, ny, nz,
+                        (int)(tc & 1023u) * kBrickT, (int)((tc >> 10) & 1023u) * kBrickT,
+                        (int)(tc >> 20) * kBrickT, kBrickN, corner);
+    }
+  }
   // the lane pair (lane ^ 1), and with quads the other pair of the quad, share this
   // lane's segment and base node: every lane runs the exchanges (an invalid one with
   // zero mass), since a DPP read from a lane that did not execute it is undefined
@@ -366,22 +370,15 @@ __global__ __launch_bounds__(BS, Scenes::kMany ? 3 : 4) void g2p2g_kernel(G2P2GA
   // flush: one global float atomic per channel per non-zero brick node, by the
   // node's owner thread
   const int nb = nseg < kBrickKMAX ? nseg : kBrickKMAX;
+
   if (tid < kBrickNodes) {
     for (int sb = 0; sb < nb; ++sb) {
       const uint32_t tc = (uint32_t)seg_tile[sb];
-      int fnx = nx, fny = ny, fnz = nz;  // one scene: constants
-      int64_t foff = g.node_off;
-      if constexpr (Scenes::kMany) {
-        fnx = seg_dims[sb][0];
-        fny = seg_dims[sb][1];
-        fnz = seg_dims[sb][2];
-        foff = seg_node_off[sb];
-      }
       const int gx = (int)(tc & 1023u) * kBrickT + bn.lx;
       const int gy = (int)((tc >> 10) & 1023u) * kBrickT + bn.ly;
       const int gz = (int)(tc >> 20) * kBrickT + bn.lz;
-      if (gx >= fnx || gy >= fny || gz >= fnz) continue;
-      const int64_t node = foff + ((int64_t)(gz * fny + gy) * fnx + gx);
+      if (gx >= nx || gy >= ny || gz >= nz) continue;
+      const int64_t node = g.node_off + ((int64_t)(gz * ny + gy) * nx + gx);
       const double* const src = brick + sb * 4 * kBrickV + bn.lds;
       float* const dst[4] = {a.gm, a.gp0, a.gp1, a.gp2};
 #pragma unroll
@@ -394,9 +391,8 @@ __global__ __launch_bounds__(BS, Scenes::kMany ? 3 : 4) void g2p2g_kernel(G2P2GA
 }
 
 template <int NR, class Scenes>
-hipError_t launch_nr(const G2P2GArgs& a, const Scenes& sc, hipStream_t stream) {
-  constexpr int BS = 256;
-  const unsigned blocks = (unsigned)((a.P + BS - 1) / BS);
+hipError_t launch_nr(const G2P2GArgs& a, const Scenes& sc, unsigned blocks, hipStream_t stream) {
+  constexpr int BS = kSceneChunk;
   if (a.lane_group == 4)
     g2p2g_kernel<NR, BS, Scenes, 2><<<blocks, BS, 0, stream>>>(a, sc);
   else
@@ -404,19 +400,20 @@ hipError_t launch_nr(const G2P2GArgs& a, const Scenes& sc, hipStream_t stream) {
   return hipGetLastError();
 }
 
+// blocks: workgroups of kSceneChunk threads that cover every chunk
 template <class Scenes>
 hipError_t launch_modes(const G2P2GArgs& a, const Scenes& sc, int n_modes, int64_t n_nodes,
-                        hipStream_t stream) {
+                        unsigned blocks, hipStream_t stream) {
   if (!a.accumulate) {
     hipError_t e = launch_grid_clear(a.gm, a.gp0, n_nodes, nullptr, stream);
     if (e != hipSuccess) return e;
   }
   if (a.P == 0) return hipSuccess;
   switch (n_modes) {
-    case 1: return launch_nr<1>(a, sc, stream);
-    case 4: return launch_nr<4>(a, sc, stream);
-    case 8: return launch_nr<8>(a, sc, stream);
-    case 27: return launch_nr<27>(a, sc, stream);
+    case 1: return launch_nr<1>(a, sc, blocks, stream);
+    case 4: return launch_nr<4>(a, sc, blocks, stream);
+    case 8: return launch_nr<8>(a, sc, blocks, stream);
+    case 27: return launch_nr<27>(a, sc, blocks, stream);
     default: return hipErrorInvalidValue;
   }
 }
@@ -438,13 +435,17 @@ hipError_t launch_g2p2g(const G2P2GArgs& a, int n_modes, hipStream_t stream) {
     one.sg.hi[k] = a.hi[k];
   }
   one.sg.node_off = 0;
-  return launch_modes(a, one, n_modes, (int64_t)a.g.nx * a.g.ny * a.g.nz, stream);
+  one.sg.region_off = 0;
+  const unsigned blocks = (unsigned)((a.P + kSceneChunk - 1) / kSceneChunk);
+  return launch_modes(a, one, n_modes, (int64_t)a.g.nx * a.g.ny * a.g.nz, blocks, stream);
 }
 
 hipError_t launch_g2p2g_batch(const G2P2GArgs& a, const SceneDev* table, int n_scenes,
                               int n_modes, hipStream_t stream) {
-  SceneTable st{table, n_scenes};
-  return launch_modes(a, st, n_modes, a.gstride, stream);
+  // each scene in chunks of its own: at most one partial chunk per scene
+  SceneChunks sc{table, n_scenes};
+  const unsigned blocks = (unsigned)(a.P / kSceneChunk + n_scenes + 1);
+  return launch_modes(a, sc, n_modes, a.gstride, blocks, stream);
 }
 
 }  // namespace polypic

@@ -20,6 +20,11 @@ inline unsigned node_blocks(int nx, int ny, int nz) {
   return (unsigned)(((int64_t)nx * ny * nz + 255) / 256);
 }
 
+// active regions of an nx x ny x nz grid
+inline int64_t region_count(int nx, int ny, int nz) {
+  return (int64_t)regions_along(nx, kRegX) * regions_along(ny, kRegY) * regions_along(nz, kRegZ);
+}
+
 // ---- sort
 size_t sort_workspace_bytes(int64_t P);
 int sort_key_bits(const GridDev& g);
@@ -93,8 +98,15 @@ struct GridUpdateArgs {
   float* gv;        // [3][N]
   float* clear_gm;  // gm and gp again when the update zeroes them after reading (or nullptr)
   float* clear_gp;
+  uint32_t* regions;  // region flags (the active update only)
+  int64_t n_regions;
 };
 hipError_t launch_grid_update(const GridUpdateArgs& a, hipStream_t stream);
+// the flagged regions only (a.regions, a.n_regions, a.clear_gm and a.clear_gp set): each
+// visited node is updated and cleared, each visited flag reset
+hipError_t launch_grid_update_active(const GridUpdateArgs& a, hipStream_t stream);
+hipError_t launch_grid_update_active_batch(const GridUpdateArgs& a, const SceneDev* table,
+                                           int n_scenes, int64_t stride, hipStream_t stream);
 // batch of scenes: a.nx/ny/nz unused; gm, gp, gv span `stride` nodes per channel
 hipError_t launch_grid_update_batch(const GridUpdateArgs& a, const SceneDev* table, int n_scenes,
                                     int max_nodes, int64_t stride, hipStream_t stream);
@@ -151,6 +163,9 @@ struct G2P2GArgs {
   int64_t gstride;       // channel stride of gv
   int lane_group;        // particles folded per brick atomic: 2 (default) or 4
   int accumulate;        // 1: add to the grid as it is (the caller cleared it)
+  int sched;             // chunk order: kSchedLinear or kSchedXcd
+  uint32_t* regions;     // region flags to set where the scatter lands (or nullptr)
+  int64_t n_regions;
 };
 hipError_t launch_g2p2g(const G2P2GArgs& a, int n_modes, hipStream_t stream);
 // over a batch of scenes (a.g, a.lo, a.hi, a.dx unused; a.gstride = total nodes)

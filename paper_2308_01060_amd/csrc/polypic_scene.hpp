@@ -10,7 +10,13 @@
 //   grids occupy disjoint node ranges [node_off, node_off + nx*ny*nz) of the
 //   flattened grid arrays.  A sort permutation from the batched sort keeps
 //   every particle inside its scene's slot range, so the scene of slot i is
-//   the scene of the particle read there.
+//   the scene of the particle read there.  A workgroup's chunk of kSceneChunk
+//   slots may straddle scenes.
+// * SceneChunks -- the same layout, but every workgroup takes a chunk inside one
+//   scene (each scene is cut into chunks of its own, the last one partial), so
+//   that the scene's grid is uniform over the workgroup and lives in scalar
+//   registers.  The launch has (total particles) / kSceneChunk + (scenes) + 1
+//   workgroups at most; those past the last chunk return at once.
 #pragma once
 
 #include "polypic_device.hpp"
@@ -28,6 +34,19 @@ struct alignas(16) SceneDev {
   int64_t p_begin;   // flattened particle range [p_begin, p_end)
   int64_t p_end;
   int64_t node_off;  // first node of the scene in the flattened grid arrays
+  int64_t chunk_begin;  // chunks of kSceneChunk slots of the scenes before this one
+  int64_t region_begin; // active regions of the scenes before this one
+};
+
+// slots per workgroup chunk of the SceneChunks schedule
+constexpr int kSceneChunk = 256;
+
+// Slots a workgroup processes: [i0, i0 + n) (n <= 0: none), in scene s (the scene
+// of slot i0).
+struct Chunk {
+  int64_t i0;
+  int n;
+  int s;
 };
 
 // What a kernel needs to know about the grid of one scene.
@@ -38,11 +57,18 @@ struct SceneGrid {
   float dx;
   float lo[3], hi[3];
   int64_t node_off;
+  int64_t region_off;  // first region flag of the scene
 };
 
 struct OneScene {
   static constexpr bool kMany = false;
   SceneGrid sg;
+  // chunk b of the launch (b < the launch's workgroups)
+  template <int BS>
+  __device__ __forceinline__ Chunk chunk(int64_t P, int64_t b) const {
+    const int64_t i0 = b * BS;
+    return {i0, (int)min((int64_t)BS, P - i0), 0};
+  }
   __device__ __forceinline__ int first(int64_t) const { return 0; }
   __device__ __forceinline__ int of(int64_t, int) const { return 0; }
   __device__ __forceinline__ SceneGrid grid(int) const { return sg; }
@@ -52,6 +78,11 @@ struct SceneTable {
   static constexpr bool kMany = true;
   const SceneDev* t;
   int n;
+  template <int BS>
+  __device__ __forceinline__ Chunk chunk(int64_t P, int64_t b) const {
+    const int64_t i0 = b * BS;
+    return {i0, (int)min((int64_t)BS, P - i0), first(i0)};
+  }
   // Scene holding slot i (0 <= i < total particles): the last scene whose
   // range starts at or before i.  Empty scenes share their start with the
   // next one, so the last such scene is the one that holds i.
@@ -88,8 +119,36 @@ struct SceneTable {
       g.hi[k] = d.hi[k];
     }
     g.node_off = d.node_off;
+    g.region_off = d.region_begin;
     return g;
   }
+};
+
+struct SceneChunks {
+  static constexpr bool kMany = false;  // one scene per workgroup
+  const SceneDev* t;
+  int n;
+  // Chunk b: the last scene whose first chunk is at or before b (empty scenes share
+  // their first chunk with the next scene, so the last such is the one holding it),
+  // and the chunk's slots in that scene.
+  template <int BS>
+  __device__ __forceinline__ Chunk chunk(int64_t, int64_t b) const {
+    static_assert(BS == kSceneChunk, "chunks are planned for kSceneChunk slots");
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (t[mid].chunk_begin <= b)
+        lo = mid;
+      else
+        hi = mid - 1;
+    }
+    const SceneDev& d = t[lo];
+    const int64_t i0 = d.p_begin + (b - d.chunk_begin) * BS;
+    const int64_t left = d.p_end - i0;
+    return {i0, (int)(left < 0 ? 0 : (left < BS ? left : BS)), lo};
+  }
+  __device__ __forceinline__ int of(int64_t, int s) const { return s; }
+  __device__ __forceinline__ SceneGrid grid(int s) const { return SceneTable{t, n}.grid(s); }
 };
 
 // ------------------------------------------------------------ chunk schedule

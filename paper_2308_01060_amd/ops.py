@@ -226,6 +226,39 @@ def polypic_grid_update_clear(grid: polypic_grid, dt: float, gravity: Sequence[f
         "polypic_grid_update_clear")
 
 
+def region_state_words(n_regions: int) -> int:
+    """uint32 words of a region state: one flag per region."""
+    return int(n_regions)
+
+
+def _regions_ptr(state: Optional[torch.Tensor], n_regions: int) -> Optional[int]:
+    """The region state is uint32 in the C ABI; an int32 tensor holds the same bits."""
+    return _ptr(state, torch.int32, region_state_words(n_regions), "region_state")
+
+
+def polypic_region_count(grid: polypic_grid) -> int:
+    """Active regions of a grid (boxes of 16 x 4 x 4 nodes)."""
+    out = ctypes.c_int64(0)
+    check(_lib.load().polypic_region_count(ctypes.byref(grid), ctypes.byref(out)),
+          "polypic_region_count")
+    return int(out.value)
+
+
+def polypic_grid_update_active(grid: polypic_grid, dt: float, gravity: Sequence[float],
+                               bc_layers: int, grid_mass: torch.Tensor, grid_mom: torch.Tensor,
+                               grid_vel: torch.Tensor, region_state: torch.Tensor) -> None:
+    """polypic_grid_update_clear on the flagged regions only; resets their flags."""
+    N = n_nodes(grid)
+    g3 = (ctypes.c_float * 3)(*[float(v) for v in gravity])
+    check(_lib.load().polypic_grid_update_active(
+        ctypes.byref(grid), float(dt), g3, int(bc_layers),
+        _ptr(grid_mass, torch.float32, N, "grid_mass"),
+        _ptr(grid_mom, torch.float32, 3 * N, "grid_mom"),
+        _ptr(grid_vel, torch.float32, 3 * N, "grid_vel"),
+        _regions_ptr(region_state, polypic_region_count(grid)), _stream()),
+        "polypic_grid_update_active")
+
+
 def polypic_g2p(grid: polypic_grid, n_modes: int, dt: float, grid_vel: torch.Tensor,
                 x_in: torch.Tensor, coeff_out: torch.Tensor,
                 perm: Optional[torch.Tensor] = None, x_out: Optional[torch.Tensor] = None,
@@ -378,8 +411,10 @@ def polypic_g2p2g(grid: polypic_grid, n_modes: int, dt: float, grid_vel: torch.T
                   F_in: Optional[torch.Tensor] = None, F_out: Optional[torch.Tensor] = None,
                   mass_in: Optional[torch.Tensor] = None, mass_out: Optional[torch.Tensor] = None,
                   uniform_mass: float = 1.0,
-                  status_dev: Optional[torch.Tensor] = None, accumulate: bool = False) -> None:
-    """accumulate: add to grid_mass / grid_mom instead of clearing them first."""
+                  status_dev: Optional[torch.Tensor] = None, accumulate: bool = False,
+                  region_state: Optional[torch.Tensor] = None) -> None:
+    """accumulate: add to grid_mass / grid_mom instead of clearing them first;
+    region_state: flag the regions the scatter lands in."""
     P = x_in.numel() // 3
     N = n_nodes(grid)
     check(_lib.load().polypic_g2p2g(
@@ -393,20 +428,29 @@ def polypic_g2p2g(grid: polypic_grid, n_modes: int, dt: float, grid_vel: torch.T
         float(uniform_mass),
         _ptr(grid_mass, torch.float32, N, "grid_mass"),
         _ptr(grid_mom, torch.float32, 3 * N, "grid_mom"), int(bool(accumulate)),
+        _regions_ptr(region_state, polypic_region_count(grid)),
         _ptr(status_dev, torch.int32, 1, "status_dev"), _stream()), "polypic_g2p2g")
 
 
-def polypic_set_g2p2g_config(n_modes: int, lane_group: int) -> None:
-    """Lane-group size (2 or 4; -1 for the default) of polypic_g2p2g at this mode count."""
-    check(_lib.load().polypic_set_g2p2g_config(int(n_modes), int(lane_group)),
+class FusedChoice(NamedTuple):
+    """Launch choice of polypic_g2p2g: lane-group size and chunk order (POLYPIC_SCHED_*)."""
+
+    lane_group: int
+    schedule: int
+
+
+def polypic_set_g2p2g_config(n_modes: int, lane_group: int = -1, schedule: int = -1) -> None:
+    """Lane-group size (2 or 4) and chunk order (POLYPIC_SCHED_LINEAR or _XCD) of
+    polypic_g2p2g at this mode count; -1 for a default."""
+    check(_lib.load().polypic_set_g2p2g_config(int(n_modes), int(lane_group), int(schedule)),
           "polypic_set_g2p2g_config")
 
 
-def polypic_get_g2p2g_config(n_modes: int) -> int:
-    out = ctypes.c_int32(0)
-    check(_lib.load().polypic_get_g2p2g_config(int(n_modes), ctypes.byref(out)),
+def polypic_get_g2p2g_config(n_modes: int) -> FusedChoice:
+    lg, sc = ctypes.c_int32(0), ctypes.c_int32(0)
+    check(_lib.load().polypic_get_g2p2g_config(int(n_modes), ctypes.byref(lg), ctypes.byref(sc)),
           "polypic_get_g2p2g_config")
-    return int(out.value)
+    return FusedChoice(int(lg.value), int(sc.value))
 
 
 def polypic_autotune_g2p2g(grid: polypic_grid, n_modes: int, dt: float, grid_vel: torch.Tensor,
@@ -417,12 +461,13 @@ def polypic_autotune_g2p2g(grid: polypic_grid, n_modes: int, dt: float, grid_vel
                            F_out: Optional[torch.Tensor] = None,
                            mass_in: Optional[torch.Tensor] = None,
                            mass_out: Optional[torch.Tensor] = None,
-                           uniform_mass: float = 1.0) -> int:
-    """Times polypic_g2p2g with lane groups of 2 and 4 on these arguments (synchronises),
-    keeps the faster for this mode count and returns it; the outputs are the call's."""
+                           uniform_mass: float = 1.0) -> FusedChoice:
+    """Times polypic_g2p2g with lane groups of 2 and 4, in launch and in XCD chunk order, on
+    these arguments (synchronises), keeps the fastest for this mode count and returns it;
+    the outputs are the call's."""
     P = x_in.numel() // 3
     N = n_nodes(grid)
-    out = ctypes.c_int32(0)
+    out, sched = ctypes.c_int32(0), ctypes.c_int32(0)
     check(_lib.load().polypic_autotune_g2p2g(
         ctypes.byref(grid), P, int(n_modes), float(dt),
         _ptr(grid_vel, torch.float32, 3 * N, "grid_vel"),
@@ -433,9 +478,9 @@ def polypic_autotune_g2p2g(grid: polypic_grid, n_modes: int, dt: float, grid_vel
         _ptr(mass_in, torch.float32, P, "mass_in"), _ptr(mass_out, torch.float32, P, "mass_out"),
         float(uniform_mass),
         _ptr(grid_mass, torch.float32, N, "grid_mass"),
-        _ptr(grid_mom, torch.float32, 3 * N, "grid_mom"), ctypes.byref(out), _stream()),
-        "polypic_autotune_g2p2g")
-    return int(out.value)
+        _ptr(grid_mom, torch.float32, 3 * N, "grid_mom"), ctypes.byref(out),
+        ctypes.byref(sched), _stream()), "polypic_autotune_g2p2g")
+    return FusedChoice(int(out.value), int(sched.value))
 
 
 def polypic_g2p_backward(grid: polypic_grid, n_modes: int, dt: float, grid_vel: torch.Tensor,
@@ -565,6 +610,7 @@ class Batch:
               "polypic_batch_plan")
         self.P = int(self.desc.P)
         self.N = int(self.desc.N)
+        self.n_regions = int(self.desc.n_regions)
         self.n_scenes = n
 
     def ref(self):
@@ -658,7 +704,8 @@ def polypic_batch_g2p2g(batch: Batch, n_modes: int, dt: float, grid_vel: torch.T
                         F_in: Optional[torch.Tensor] = None, F_out: Optional[torch.Tensor] = None,
                         mass_in: Optional[torch.Tensor] = None,
                         mass_out: Optional[torch.Tensor] = None, uniform_mass: float = 1.0,
-                        status_dev: Optional[torch.Tensor] = None) -> None:
+                        status_dev: Optional[torch.Tensor] = None, accumulate: bool = False,
+                        region_state: Optional[torch.Tensor] = None) -> None:
     P, N = batch.P, batch.N
     check(_lib.load().polypic_batch_g2p2g(
         batch.ref(), int(n_modes), float(dt), _ptr(grid_vel, torch.float32, 3 * N, "grid_vel"),
@@ -668,8 +715,24 @@ def polypic_batch_g2p2g(batch: Batch, n_modes: int, dt: float, grid_vel: torch.T
         _ptr(F_in, torch.float32, 9 * P, "F_in"), _ptr(F_out, torch.float32, 9 * P, "F_out"),
         _ptr(mass_in, torch.float32, P, "mass_in"), _ptr(mass_out, torch.float32, P, "mass_out"),
         float(uniform_mass), _ptr(grid_mass, torch.float32, N, "grid_mass"),
-        _ptr(grid_mom, torch.float32, 3 * N, "grid_mom"),
+        _ptr(grid_mom, torch.float32, 3 * N, "grid_mom"), int(bool(accumulate)),
+        _regions_ptr(region_state, batch.n_regions),
         _ptr(status_dev, torch.int32, 1, "status_dev"), _stream()), "polypic_batch_g2p2g")
+
+
+def polypic_batch_grid_update_active(batch: Batch, dt: float, gravity: Sequence[float],
+                                     bc_layers: int, grid_mass: torch.Tensor,
+                                     grid_mom: torch.Tensor, grid_vel: torch.Tensor,
+                                     region_state: torch.Tensor) -> None:
+    N = batch.N
+    g3 = (ctypes.c_float * 3)(*[float(v) for v in gravity])
+    check(_lib.load().polypic_batch_grid_update_active(
+        batch.ref(), float(dt), g3, int(bc_layers),
+        _ptr(grid_mass, torch.float32, N, "grid_mass"),
+        _ptr(grid_mom, torch.float32, 3 * N, "grid_mom"),
+        _ptr(grid_vel, torch.float32, 3 * N, "grid_vel"),
+        _regions_ptr(region_state, batch.n_regions), _stream()),
+        "polypic_batch_grid_update_active")
 
 
 class BatchChoice(NamedTuple):

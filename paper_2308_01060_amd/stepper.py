@@ -90,6 +90,13 @@ class ParticleSet:
         self.fused = bool(fused)
         self.grid_current = False
         self._next_grid_current = False
+        # active regions (16 x 4 x 4-node boxes): the fused scatter flags where it lands;
+        # regions_valid says that grid_mass / grid_mom are zero outside the flagged regions
+        # (their last writer was a flagging G2P2G), so the grid update may visit those only
+        self.region_state = torch.zeros(
+            ops.region_state_words(ops.polypic_region_count(grid)), dtype=torch.int32,
+            device=dev)
+        self.regions_valid = False
 
     # -- the four calls of one step
     def sort(self, full: bool = False):
@@ -116,10 +123,12 @@ class ParticleSet:
                         keys_sorted=self.keys if sorted_ else None,
                         ws=self.p2g_ws if sorted_ else None, status_dev=self.status)
         self.grid_current = True
+        self.regions_valid = False
 
     def autotune(self):
         """Sort, then let the library time its P2G configurations on this set (synchronises)."""
         self.sort()
+        self.regions_valid = False
         return ops.polypic_autotune_p2g(self.grid, self.n_modes, self.x, self.coeff, self.grid_mass,
                                         self.grid_mom, mass=self.mass,
                                         uniform_mass=self.uniform_mass, perm=self.perm,
@@ -134,21 +143,33 @@ class ParticleSet:
         if clear:
             self.grid_current = False
 
-    def autotune_fused(self) -> int:
-        """One step in which the library times the fused G2P2G's lane groups on this set and
-        keeps the faster for later calls at this mode count (synchronises); returns it."""
+    def grid_update_active(self):
+        """The grid update with clearing, on the regions the last G2P2G flagged only."""
+        if not self.regions_valid:
+            raise RuntimeError("the grid is not confined to flagged regions")
+        ops.polypic_grid_update_active(self.grid, self.dt, self.gravity, self.bc_layers,
+                                       self.grid_mass, self.grid_mom, self.grid_vel,
+                                       self.region_state)
+        self.grid_current = False
+
+    def autotune_fused(self):
+        """One step in which the library times the fused G2P2G's lane groups and chunk orders
+        on this set and keeps the fastest for later calls at this mode count (synchronises);
+        returns it (ops.FusedChoice)."""
         self.sort()
         if not self.grid_current:
             self.p2g()
         self.grid_update()
-        lg = ops.polypic_autotune_g2p2g(self.grid, self.n_modes, self.dt, self.grid_vel, self.x,
-                                        self.x_next, self.coeff_next, self.grid_mass,
-                                        self.grid_mom, perm=self.perm, F_in=self.F,
-                                        F_out=self.F_next, mass_in=self.mass,
-                                        mass_out=self.mass_next, uniform_mass=self.uniform_mass)
+        choice = ops.polypic_autotune_g2p2g(self.grid, self.n_modes, self.dt, self.grid_vel,
+                                            self.x, self.x_next, self.coeff_next, self.grid_mass,
+                                            self.grid_mom, perm=self.perm, F_in=self.F,
+                                            F_out=self.F_next, mass_in=self.mass,
+                                            mass_out=self.mass_next,
+                                            uniform_mass=self.uniform_mass)
         self._next_grid_current = True
+        self.regions_valid = False  # the timed calls flag nothing
         self.swap()
-        return lg
+        return choice
 
     def g2p(self, use_perm: bool = True, advect: bool = True):
         ops.polypic_g2p(self.grid, self.n_modes, self.dt, self.grid_vel, self.x, self.coeff_next,
@@ -161,14 +182,16 @@ class ParticleSet:
     def g2p2g(self, use_perm: bool = True, accumulate: bool = False):
         """G2P + advection, and the P2G of the new state into grid_mass / grid_mom (the grid
         velocity has been computed from them already).  accumulate=True adds to the two
-        (zeroed by grid_update(clear=True)) instead of clearing them first."""
+        (zeroed by a clearing grid update) instead of clearing them first.  The regions the
+        scatter lands in are flagged."""
         ops.polypic_g2p2g(self.grid, self.n_modes, self.dt, self.grid_vel, self.x, self.x_next,
                           self.coeff_next, self.grid_mass, self.grid_mom,
                           perm=self.perm if use_perm else None, F_in=self.F, F_out=self.F_next,
                           mass_in=self.mass, mass_out=self.mass_next,
                           uniform_mass=self.uniform_mass, status_dev=self.status,
-                          accumulate=accumulate)
+                          accumulate=accumulate, region_state=self.region_state)
         self._next_grid_current = True
+        self.regions_valid = True
 
     def invalidate_grid(self):
         """Call after changing x, coeff or mass directly: the next fused step redoes P2G."""
@@ -198,12 +221,16 @@ class ParticleSet:
         (default), the P2G of a step was done by the G2P of the step before (polypic_g2p2g),
         so a step is sort, grid update, G2P2G -- with a P2G first when the grid is not
         current (the first step).  The grid update zeroes the sums it read, and G2P2G adds
-        into them, so the grid is not cleared in a pass of its own."""
+        into them, so the grid is not cleared in a pass of its own; once a G2P2G has flagged
+        the regions it scattered into, the update visits those regions only."""
         self.sort()
         if self.fused:
             if not self.grid_current:
                 self.p2g()
-            self.grid_update(clear=True)
+            if self.regions_valid:
+                self.grid_update_active()
+            else:
+                self.grid_update(clear=True)
             self.g2p2g(accumulate=True)
         else:
             self.p2g()

@@ -160,6 +160,18 @@ def test_p2g_config_table_validation():
     assert lib.polypic_set_p2g_config(8, _lib.POLYPIC_P2G_DEFAULT, 512, 0, 0) == 0
     assert lib.polypic_get_p2g_config(8, *refs) == 0
     assert path.value == _lib.POLYPIC_P2G_DEFAULT
+    # fused G2P2G: lane group and chunk order
+    lg = ctypes.c_int32(0)
+    assert lib.polypic_set_g2p2g_config(5, 2, 0) == 1                   # bad n_modes
+    assert lib.polypic_set_g2p2g_config(27, 3, 0) == 1                  # bad lane group
+    assert lib.polypic_set_g2p2g_config(27, 2, _lib.POLYPIC_SCHED_PERSISTENT) == 1
+    assert lib.polypic_set_g2p2g_config(27, 4, _lib.POLYPIC_SCHED_XCD) == 0
+    assert lib.polypic_get_g2p2g_config(27, ctypes.byref(lg), ctypes.byref(sched)) == 0
+    assert (lg.value, sched.value) == (4, _lib.POLYPIC_SCHED_XCD)
+    assert lib.polypic_set_g2p2g_config(27, -1, -1) == 0
+    assert lib.polypic_get_g2p2g_config(27, ctypes.byref(lg), ctypes.byref(sched)) == 0
+    assert (lg.value, sched.value) == (2, _lib.POLYPIC_SCHED_LINEAR)
+    assert lib.polypic_get_g2p2g_config(27, ctypes.byref(lg), None) == 1
     # G2P schedule
     assert lib.polypic_set_g2p_schedule(2) == 1
     assert lib.polypic_set_g2p_schedule(_lib.POLYPIC_SCHED_XCD) == 0
@@ -181,6 +193,31 @@ def scene(g, p_off, n, node_off):
     s.grid = g
     s.p_offset, s.n_particles, s.node_offset = p_off, n, node_off
     return s
+
+
+def test_region_count_and_active_update_arguments():
+    """Active regions: 16 x 4 x 4-node boxes, partial at the upper ends; the active update
+    checks its arguments as the clearing update does, and needs the flags."""
+    lib = _lib.load()
+    out = ctypes.c_int64(0)
+    for dims in ((36, 36, 36), (3, 3, 3), (16, 4, 4), (17, 5, 9), (132, 132, 132),
+                 (260, 260, 260), (1026, 3, 1026)):
+        assert lib.polypic_region_count(ctypes.byref(grid(*dims)), ctypes.byref(out)) == 0
+        nx, ny, nz = dims
+        assert out.value == -(-nx // 16) * -(-ny // 4) * -(-nz // 4), dims
+    assert lib.polypic_region_count(ctypes.byref(grid(2, 36, 36)), ctypes.byref(out)) == 1
+    assert lib.polypic_region_count(ctypes.byref(grid()), None) == 1
+    g = grid()
+    grav = (ctypes.c_float * 3)(0.0, -9.8, 0.0)
+    far = lambda k: ctypes.c_void_p(0x10000000 + k * 0x1000000)  # noqa: E731  disjoint, fake
+    act = lib.polypic_grid_update_active
+    assert act(ctypes.byref(g), 1e-4, grav, 1, far(0), far(1), far(2), None, None) == 1
+    assert act(ctypes.byref(g), 1e-4, None, 1, far(0), far(1), far(2), far(3), None) == 1
+    assert act(ctypes.byref(g), 1e-4, grav, -1, far(0), far(1), far(2), far(3), None) == 1
+    assert act(ctypes.byref(g), float("inf"), grav, 1, far(0), far(1), far(2), far(3), None) == 1
+    assert act(ctypes.byref(g), 1e-4, grav, 1, None, far(1), far(2), far(3), None) == 1
+    assert act(ctypes.byref(g), 1e-4, grav, 1, far(0), far(1), far(0), far(3), None) == 1
+    assert act(None, 1e-4, grav, 1, far(0), far(1), far(2), far(3), None) == 1
 
 
 def test_batch_plan_validation():
@@ -229,7 +266,10 @@ def test_batch_calls_reject_unplanned_descriptors():
     assert lib.polypic_batch_g2p(ctypes.byref(b), 27, 1e-4, FAKE, FAKE, None, None, FAKE, None,
                                  None, None, None, None, None) == 1
     assert lib.polypic_batch_g2p2g(ctypes.byref(b), 27, 1e-4, FAKE, FAKE, None, FAKE, FAKE,
-                                   None, None, None, None, 1.0, FAKE, FAKE, None, None) == 1
+                                   None, None, None, None, 1.0, FAKE, FAKE, 0, None, None,
+                                   None) == 1
+    assert lib.polypic_batch_grid_update_active(ctypes.byref(b), 1e-4, grav, 1, FAKE, FAKE, FAKE,
+                                                FAKE, None) == 1
     out = ctypes.c_size_t(0)
     assert lib.polypic_batch_sort_workspace_bytes(ctypes.byref(b), ctypes.byref(out)) == 1
     assert lib.polypic_batch_sort(None, FAKE, FAKE, FAKE, FAKE, 1 << 20, None, None) == 1
@@ -309,7 +349,7 @@ def test_g2p2g_rejects_bad_arguments():
     def call(n_modes=27, dt=1e-4, gv=gv, x=x, perm=None, xo=xo, co=co, fi=None, fo=None,
              mi=None, mo=None, um=1.0, gm=gm, gp=gp, acc=0):
         return lib.polypic_g2p2g(ctypes.byref(g), 10, n_modes, dt, gv, x, perm, xo, co, fi, fo,
-                                 mi, mo, um, gm, gp, acc, None, None)
+                                 mi, mo, um, gm, gp, acc, None, None, None)
     assert call(n_modes=5) == 1
     assert call(dt=float("nan")) == 1
     assert call(xo=None) == 1                   # the scatter needs the advected positions

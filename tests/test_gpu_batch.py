@@ -224,7 +224,24 @@ def test_batched_g2p2g_with_mass_matches_single_scene_calls():
     what the single-scene fused call writes, scene by scene (outputs bit for bit; grids at
     the parity bar, the atomic sums being unordered)."""
     pp = require_gpu()
-    scenes = small_batch(6, n=5)
+    _check_batched_g2p2g_against_single_calls(pp, small_batch(6, n=5))
+
+
+def test_batched_g2p2g_scene_chunks_with_ragged_counts():
+    """The batched fused kernel gives every workgroup a chunk of 256 slots inside one scene
+    (the last chunk of a scene partial): scenes of 0, 1, 255, 256, 257, 513 and 700
+    particles, two of them empty, against the single-scene calls."""
+    pp = require_gpu()
+    scenes = small_batch(12, n=9)
+    counts = [700, 0, 1, 255, 256, 257, 0, 513, scenes[8].P]
+    for s, k in zip(scenes, counts):
+        assert s.P >= k
+        s.x = s.x[:, :k].copy()
+        s.coeff = s.coeff[:, :, :k].copy()
+    _check_batched_g2p2g_against_single_calls(pp, scenes)
+
+
+def _check_batched_g2p2g_against_single_calls(pp, scenes):
     rng = np.random.default_rng(11)
     P_all = sum(s.P for s in scenes)
     mass = (1.0 + rng.random(P_all)).astype(np.float32)
@@ -248,6 +265,10 @@ def test_batched_g2p2g_with_mass_matches_single_scene_calls():
         Pk = sl.stop - sl.start
         g = pp.grid_from_spec(s.grid)
         Nk = ns.stop - ns.start
+        if Pk == 0:  # an empty scene: its grid is cleared and nothing is scattered
+            torch.cuda.synchronize()
+            assert float(gm_b[ns].abs().max()) == 0.0, k
+            continue
         perm_k = (bs.perm[sl] - sl.start).contiguous()
         c_s = torch.empty(3, 27, Pk, device="cuda")
         x_s = torch.empty(3, Pk, device="cuda")

@@ -789,14 +789,16 @@ def test_resort_with_unordered_previous_keys_is_flagged_and_in_range():
     assert p.min() >= 0 and p.max() < P
 
 
+@pytest.mark.parametrize("order", ["linear", "xcd"])
 @pytest.mark.parametrize("n_modes", [4, 27])
 @pytest.mark.parametrize("case", ["parity_8ppc", "fluid_16ppc", "fabric_mass_f_ragged"])
-def test_g2p2g_lane_quads_against_the_oracle(n_modes, case):
-    """polypic_g2p2g with lane groups of 4 (set explicitly, then restored): both halves
-    against the oracle as for pairs, at 8 and 16 particles per cell and with per-point
-    mass and F in input order (a ragged count), so that quads that straddle cells fall
-    back to pairs or single lanes."""
+def test_g2p2g_lane_quads_against_the_oracle(n_modes, case, order):
+    """polypic_g2p2g with lane groups of 4, chunks in launch or XCD order (set explicitly,
+    then restored): both halves against the oracle as for pairs, at 8 and 16 particles per
+    cell and with per-point mass and F in input order (a ragged count), so that quads that
+    straddle cells fall back to pairs or single lanes."""
     pp = require_gpu()
+    sched = pp._lib.POLYPIC_SCHED_XCD if order == "xcd" else pp._lib.POLYPIC_SCHED_LINEAR
     if case == "parity_8ppc":
         s = W.config0(3)
     elif case == "fluid_16ppc":
@@ -807,9 +809,9 @@ def test_g2p2g_lane_quads_against_the_oracle(n_modes, case):
     _, g, ps = particle_set(s, n_modes, dt=1e-3)
     og = oracle_grid(g)
     note(f"g2p2g quads: {case} n_modes={n_modes} P={s.P}")
-    pp.ops.polypic_set_g2p2g_config(n_modes, 4)
+    pp.ops.polypic_set_g2p2g_config(n_modes, 4, sched)
     try:
-        assert pp.ops.polypic_get_g2p2g_config(n_modes) == 4
+        assert tuple(pp.ops.polypic_get_g2p2g_config(n_modes)) == (4, sched)
         if sort:
             ps.sort()
         ps.p2g(use_perm=sort)
@@ -820,8 +822,8 @@ def test_g2p2g_lane_quads_against_the_oracle(n_modes, case):
         ps.g2p2g(use_perm=sort)
         torch.cuda.synchronize()
     finally:
-        pp.ops.polypic_set_g2p2g_config(n_modes, -1)
-    assert pp.ops.polypic_get_g2p2g_config(n_modes) == 2
+        pp.ops.polypic_set_g2p2g_config(n_modes, -1, -1)
+    assert tuple(pp.ops.polypic_get_g2p2g_config(n_modes)) == (2, pp._lib.POLYPIC_SCHED_LINEAR)
     assert ps.status_flags() == 0
     F_in = None if s.F is None else s.F[:, src]
     c_ref, x_ref, F_ref = O.g2p(og, gv, s.x[:, src], n_modes, ps.dt, F_in)
@@ -834,19 +836,22 @@ def test_g2p2g_lane_quads_against_the_oracle(n_modes, case):
 
 
 def test_g2p2g_autotuner_picks_a_lane_group_and_keeps_results():
-    """ParticleSet.autotune_fused: the library times pairs and quads on the set's data, keeps
-    one, and the step it ran is a correct fused step (its P2G half against the oracle)."""
+    """ParticleSet.autotune_fused: the library times pairs and quads, in launch and in XCD
+    chunk order, on the set's data, keeps one, and the step it ran is a correct fused step
+    (its P2G half against the oracle)."""
     pp = require_gpu()
     s = W.config2_fluid(4, n=32)
     _, g, ps = particle_set(s, 27, dt=1e-3)
     og = oracle_grid(g)
     try:
-        lg = ps.autotune_fused()
-        assert lg in (2, 4) and pp.ops.polypic_get_g2p2g_config(27) == lg
+        choice = ps.autotune_fused()
+        assert choice.lane_group in (2, 4)
+        assert choice.schedule in (pp._lib.POLYPIC_SCHED_LINEAR, pp._lib.POLYPIC_SCHED_XCD)
+        assert pp.ops.polypic_get_g2p2g_config(27) == choice
         torch.cuda.synchronize()
         assert ps.status_flags() == 0 and ps.grid_current
         M_ref, Q_ref = O.p2g(og, host(ps.x), host(ps.coeff).reshape(3, 27, s.P), 27)
         assert rel(host(ps.grid_mass).reshape(M_ref.shape), M_ref) <= TOL_NORMWISE
         assert rel(host(ps.grid_mom).reshape(Q_ref.shape), Q_ref) <= TOL_NORMWISE
     finally:
-        pp.ops.polypic_set_g2p2g_config(27, -1)
+        pp.ops.polypic_set_g2p2g_config(27, -1, -1)
