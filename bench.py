@@ -404,7 +404,7 @@ def batch_timing(pp, torch, W, n_modes: int, steps: int, warmup: int):
         "speedup_vs_per_scene": single_wall / graph_wall,
         "event_ms_per_step": {"graph": round(graph_ev, 4), "eager_batched": round(eager_ev, 4),
                               "per_scene": round(single_ev, 4)},
-        "p2g_config": {"block": choice.block, "schedule": choice.schedule,
+        "p2g_config": {"block": choice.block, "schedule": choice.schedule, "brick": choice.brick,
                        "per_cu": choice.per_cu, "chosen_by": "polypic_batch_autotune"},
         "note": "whole fused steps (sort, grid update, G2P2G: G2P + advection + the next "
                 "P2G) of every scene; per-scene form = one ParticleSet.step per scene, "
@@ -434,7 +434,8 @@ def _set_timing(pp, torch, ps, steps: int, warmup: int, bpp: int, workload: str)
         "p2g_g2p_transfers_per_s": ps.P / (transfer_ms(phase) * 1e-3),
         "phase_ms": {k: round(v, 4) for k, v in phase.items()},
         "p2g_config": {"path": "cells" if choice.path == 1 else "bricks",
-                       "block": choice.block, "schedule": choice.schedule},
+                       "block": choice.block, "schedule": choice.schedule,
+                       "brick": choice.brick},
         "g2p2g_config": {"lane_group": fused_choice.lane_group,
                          "schedule": "xcd" if fused_choice.schedule == 1 else "linear"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
@@ -857,7 +858,8 @@ def main():
                 "transfers_per_s": P * args.steps / w4,
                 "p2g_g2p_transfers_per_s": P / (transfer_ms(ph4) * 1e-3),
                 "p2g_config": {"path": "cells" if choice4.path == 1 else "bricks",
-                               "block": choice4.block, "schedule": choice4.schedule},
+                               "block": choice4.block, "schedule": choice4.schedule,
+                               "brick": choice4.brick},
                 "phase_ms": {k: round(v, 4) for k, v in ph4.items()}}
         del ps4, c4
 
@@ -959,6 +961,7 @@ def main():
         "p2g_g2p_transfers_per_s": P / (t_transfer * 1e-3),
         "p2g_config": {"path": "cells" if p2g_choice.path == 1 else "bricks",
                        "block": p2g_choice.block, "schedule": p2g_choice.schedule,
+                       "brick": p2g_choice.brick,
                        "chosen_by": "polypic_autotune_p2g"},
         "g2p2g_config": {"lane_group": fused_choice.lane_group,
                          "schedule": "xcd" if fused_choice.schedule == 1 else "linear",

@@ -210,9 +210,14 @@ int32_t polypic_p2g(const polypic_grid* grid, int64_t P, int32_t n_modes, const 
  * P2G launch configuration and autotuner (a runtime choice, no effect on
  * results beyond float summation order).
  *
- * path   POLYPIC_P2G_BRICKS: per-particle scatter into FP64 LDS bricks of 4^3
- *        cells (needs only perm); POLYPIC_P2G_CELLS: per-cell run sums (needs
- *        keys_sorted).  block: workgroup size of the brick path (256 or 512).
+ * path   POLYPIC_P2G_BRICKS: per-particle scatter into FP64 LDS bricks (needs
+ *        only perm); POLYPIC_P2G_CELLS: per-cell run sums of 4^3-cell tiles
+ *        (needs keys_sorted).  block: workgroup size of the brick path (256 or
+ *        512).
+ * brick  edge of the brick path's tiles in cells: 2, 4 (the default) or 8.  A
+ *        brick holds the (edge + 2)^3 nodes of a tile's stencils; a workgroup
+ *        has 12, 3 or 1 of them in LDS (29 to 37 KB).  Runs of one tile in the
+ *        chunk share a brick; runs beyond the bricks add to HBM.
  * schedule  how the brick path's workgroups take chunks of `block` slots:
  *        POLYPIC_SCHED_LINEAR      one chunk per workgroup, in index order;
  *        POLYPIC_SCHED_XCD         one chunk per workgroup, renumbered so that
@@ -223,8 +228,8 @@ int32_t polypic_p2g(const polypic_grid* grid, int64_t P, int32_t n_modes, const 
  *                                  each looping over a contiguous chunk range.
  *        per_cu is ignored by the other schedules (pass 0).
  * The choice is kept per n_modes in a process-wide, mutex-guarded table.
- * Without an entry polypic_p2g uses the brick path (block 256, linear); the
- * cell path runs only when chosen and keys_sorted is given.
+ * Without an entry polypic_p2g uses the brick path (block 256, linear, 4^3
+ * bricks); the cell path runs only when chosen and keys_sorted is given.
  *
  * polypic_autotune_p2g runs P2G once per candidate configuration on the given
  * inputs (same arguments as polypic_p2g, keys_sorted may be NULL), times each
@@ -243,15 +248,15 @@ int32_t polypic_p2g(const polypic_grid* grid, int64_t P, int32_t n_modes, const 
 #define POLYPIC_SCHED_XCD 1
 #define POLYPIC_SCHED_PERSISTENT 2
 int32_t polypic_set_p2g_config(int32_t n_modes, int32_t path, int32_t block, int32_t schedule,
-                               int32_t per_cu);
+                               int32_t per_cu, int32_t brick);
 int32_t polypic_get_p2g_config(int32_t n_modes, int32_t* path, int32_t* block, int32_t* schedule,
-                               int32_t* per_cu);
+                               int32_t* per_cu, int32_t* brick);
 int32_t polypic_autotune_p2g(const polypic_grid* grid, int64_t P, int32_t n_modes, const float* x,
                              const float* mass, float uniform_mass, const float* coeff,
                              const int32_t* perm, const uint32_t* keys_sorted, void* ws,
                              size_t ws_bytes, float* grid_mass, float* grid_mom,
                              int32_t* path_out, int32_t* block_out, int32_t* schedule_out,
-                             int32_t* per_cu_out, void* stream);
+                             int32_t* per_cu_out, int32_t* brick_out, void* stream);
 int32_t polypic_set_g2p_schedule(int32_t schedule);
 int32_t polypic_get_g2p_schedule(int32_t* schedule);
 
@@ -605,10 +610,11 @@ int32_t polypic_invert_permutation(const int32_t* perm, int32_t* inv, int64_t P,
  *   perm (optional) must keep every particle inside its scene's range, as
  *   the batched sort's does; slot i is processed with the grid of the scene
  *   whose range holds i.
- * polypic_batch_set_config / _get_config / _autotune: block, schedule and
- *   per_cu of the batched P2G (same meaning as for polypic_p2g; default
- *   block 256, POLYPIC_SCHED_XCD), per n_modes, process-wide.  The autotuner
- *   times every candidate on the given inputs and SYNCHRONISES the stream.
+ * polypic_batch_set_config / _get_config / _autotune: block, schedule, per_cu
+ *   and brick edge of the batched P2G (same meaning as for polypic_p2g; default
+ *   block 256, POLYPIC_SCHED_XCD, 4^3 bricks), per n_modes, process-wide.  The
+ *   autotuner times every candidate on the given inputs and SYNCHRONISES the
+ *   stream.
  * ------------------------------------------------------------------------ */
 typedef struct polypic_scene {
   polypic_grid grid;
@@ -678,14 +684,14 @@ int32_t polypic_batch_grid_update_active(const polypic_batch* batch, float dt,
                                          float* grid_mass, float* grid_mom, float* grid_vel,
                                          uint32_t* region_state, void* stream);
 int32_t polypic_batch_set_config(int32_t n_modes, int32_t block, int32_t schedule,
-                                 int32_t per_cu);
+                                 int32_t per_cu, int32_t brick);
 int32_t polypic_batch_get_config(int32_t n_modes, int32_t* block, int32_t* schedule,
-                                 int32_t* per_cu);
+                                 int32_t* per_cu, int32_t* brick);
 int32_t polypic_batch_autotune(const polypic_batch* batch, int32_t n_modes, const float* x,
                                const float* mass, float uniform_mass, const float* coeff,
                                const int32_t* perm, float* grid_mass, float* grid_mom,
                                int32_t* block_out, int32_t* schedule_out, int32_t* per_cu_out,
-                               void* stream);
+                               int32_t* brick_out, void* stream);
 
 #ifdef __cplusplus
 }

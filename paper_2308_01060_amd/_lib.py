@@ -178,13 +178,13 @@ def load() -> ctypes.CDLL:
     lib.polypic_p2g.restype = i32
     lib.polypic_p2g.argtypes = [G, i64, i32, P, P, f32, P, P, P, P, sz, P, P, i32, P, P]
     lib.polypic_set_p2g_config.restype = i32
-    lib.polypic_set_p2g_config.argtypes = [i32, i32, i32, i32, i32]
+    lib.polypic_set_p2g_config.argtypes = [i32, i32, i32, i32, i32, i32]
     pi = ctypes.POINTER(i32)
     lib.polypic_get_p2g_config.restype = i32
-    lib.polypic_get_p2g_config.argtypes = [i32, pi, pi, pi, pi]
+    lib.polypic_get_p2g_config.argtypes = [i32, pi, pi, pi, pi, pi]
     lib.polypic_autotune_p2g.restype = i32
     lib.polypic_autotune_p2g.argtypes = [G, i64, i32, P, P, f32, P, P, P, P, sz, P, P,
-                                         pi, pi, pi, pi, P]
+                                         pi, pi, pi, pi, pi, P]
     lib.polypic_set_g2p_schedule.restype = i32
     lib.polypic_set_g2p_schedule.argtypes = [i32]
     lib.polypic_get_g2p_schedule.restype = i32
@@ -263,11 +263,11 @@ def load() -> ctypes.CDLL:
     lib.polypic_batch_grid_update_active.argtypes = [B, f32, ctypes.POINTER(f32), i32, P, P, P,
                                                      P, P]
     lib.polypic_batch_set_config.restype = i32
-    lib.polypic_batch_set_config.argtypes = [i32, i32, i32, i32]
+    lib.polypic_batch_set_config.argtypes = [i32, i32, i32, i32, i32]
     lib.polypic_batch_get_config.restype = i32
-    lib.polypic_batch_get_config.argtypes = [i32, pi, pi, pi]
+    lib.polypic_batch_get_config.argtypes = [i32, pi, pi, pi, pi]
     lib.polypic_batch_autotune.restype = i32
-    lib.polypic_batch_autotune.argtypes = [B, i32, P, P, f32, P, P, P, P, pi, pi, pi, P]
+    lib.polypic_batch_autotune.argtypes = [B, i32, P, P, f32, P, P, P, P, pi, pi, pi, pi, P]
     _lib = lib
     return lib
 

@@ -90,7 +90,11 @@ struct P2GChoice {
   int block = 256;
   int sched = POLYPIC_SCHED_LINEAR;
   int per_cu = 0;
+  int brick = 4;  // brick edge in cells: 2, 4 or 8
 };
+
+bool valid_brick(int32_t brick) { return brick == 2 || brick == 4 || brick == 8; }
+int brick_log2(int brick) { return brick == 2 ? 1 : brick == 8 ? 3 : 2; }
 
 bool valid_schedule(int32_t schedule, int32_t per_cu) {
   if (schedule == POLYPIC_SCHED_LINEAR || schedule == POLYPIC_SCHED_XCD) return true;
@@ -104,6 +108,7 @@ P2GConfig to_config(const P2GChoice& c) {
               : c.sched == POLYPIC_SCHED_PERSISTENT ? kSchedPersistent
                                                     : kSchedLinear;
   cfg.persist_per_cu = c.sched == POLYPIC_SCHED_PERSISTENT ? c.per_cu : 0;
+  cfg.tile_log2 = brick_log2(c.brick);
   return cfg;
 }
 
@@ -239,6 +244,7 @@ struct BatchChoice {
   int block = 256;
   int sched = POLYPIC_SCHED_XCD;
   int per_cu = 0;
+  int brick = 4;
 };
 BatchChoice g_btune[28];
 
@@ -281,6 +287,7 @@ int32_t run_batch_p2g(const polypic_batch* b, int32_t n_modes, const float* x, c
   pc.block = c.block;
   pc.sched = c.sched;
   pc.per_cu = c.per_cu;
+  pc.brick = c.brick;
   return from_hip(
       launch_p2g_batch(a, batch_table(b), b->n_scenes, n_modes, to_config(pc), s));
 }
@@ -435,29 +442,32 @@ int32_t polypic_p2g(const polypic_grid* grid, int64_t P, int32_t n_modes, const 
 }
 
 int32_t polypic_set_p2g_config(int32_t n_modes, int32_t path, int32_t block, int32_t schedule,
-                               int32_t per_cu) {
+                               int32_t per_cu, int32_t brick) {
   if (!valid_modes(n_modes)) return POLYPIC_EINVAL;
   if (path != POLYPIC_P2G_DEFAULT && path != POLYPIC_P2G_BRICKS && path != POLYPIC_P2G_CELLS)
     return POLYPIC_EINVAL;
   if (block != 256 && block != 512) return POLYPIC_EINVAL;
   if (!valid_schedule(schedule, per_cu)) return POLYPIC_EINVAL;
+  if (!valid_brick(brick)) return POLYPIC_EINVAL;
   P2GChoice c;
   c.path = path;
   c.block = block;
   c.sched = schedule;
   c.per_cu = schedule == POLYPIC_SCHED_PERSISTENT ? per_cu : 0;
+  c.brick = brick;
   set_choice(n_modes, c);
   return POLYPIC_OK;
 }
 
 int32_t polypic_get_p2g_config(int32_t n_modes, int32_t* path, int32_t* block, int32_t* schedule,
-                               int32_t* per_cu) {
+                               int32_t* per_cu, int32_t* brick) {
   if (!valid_modes(n_modes)) return POLYPIC_EINVAL;
   const P2GChoice c = get_choice(n_modes);
   if (path) *path = c.path;
   if (block) *block = c.block;
   if (schedule) *schedule = c.sched;
   if (per_cu) *per_cu = c.per_cu;
+  if (brick) *brick = c.brick;
   return POLYPIC_OK;
 }
 
@@ -478,7 +488,7 @@ int32_t polypic_autotune_p2g(const polypic_grid* grid, int64_t P, int32_t n_mode
                              const int32_t* perm, const uint32_t* keys_sorted, void* ws,
                              size_t ws_bytes, float* grid_mass, float* grid_mom,
                              int32_t* path_out, int32_t* block_out, int32_t* schedule_out,
-                             int32_t* per_cu_out, void* stream) {
+                             int32_t* per_cu_out, int32_t* brick_out, void* stream) {
   int32_t st = check_grid(grid);
   if (st) return st;
   if ((st = check_P(P))) return st;
@@ -492,14 +502,16 @@ int32_t polypic_autotune_p2g(const polypic_grid* grid, int64_t P, int32_t n_mode
   }
   const hipStream_t s = (hipStream_t)stream;
   std::vector<P2GChoice> cand;
-  for (int block : {256, 512})
-    for (int sched : {POLYPIC_SCHED_LINEAR, POLYPIC_SCHED_XCD}) {
-      P2GChoice c;
-      c.path = POLYPIC_P2G_BRICKS;
-      c.block = block;
-      c.sched = sched;
-      cand.push_back(c);
-    }
+  for (int brick : {4, 2, 8})
+    for (int block : {256, 512})
+      for (int sched : {POLYPIC_SCHED_LINEAR, POLYPIC_SCHED_XCD}) {
+        P2GChoice c;
+        c.path = POLYPIC_P2G_BRICKS;
+        c.block = block;
+        c.sched = sched;
+        c.brick = brick;
+        cand.push_back(c);
+      }
   if (keys_sorted) {
     P2GChoice c;
     c.path = POLYPIC_P2G_CELLS;
@@ -521,6 +533,7 @@ int32_t polypic_autotune_p2g(const polypic_grid* grid, int64_t P, int32_t n_mode
   if (block_out) *block_out = best.block;
   if (schedule_out) *schedule_out = best.sched;
   if (per_cu_out) *per_cu_out = best.per_cu;
+  if (brick_out) *brick_out = best.brick;
   return POLYPIC_OK;
 }
 
@@ -1416,25 +1429,28 @@ int32_t polypic_batch_g2p2g(const polypic_batch* batch, int32_t n_modes, float d
 }
 
 int32_t polypic_batch_set_config(int32_t n_modes, int32_t block, int32_t schedule,
-                                 int32_t per_cu) {
+                                 int32_t per_cu, int32_t brick) {
   if (!valid_modes(n_modes)) return POLYPIC_EINVAL;
   if (block != 256 && block != 512) return POLYPIC_EINVAL;
   if (!valid_schedule(schedule, per_cu)) return POLYPIC_EINVAL;
+  if (!valid_brick(brick)) return POLYPIC_EINVAL;
   BatchChoice c;
   c.block = block;
   c.sched = schedule;
   c.per_cu = schedule == POLYPIC_SCHED_PERSISTENT ? per_cu : 0;
+  c.brick = brick;
   set_bchoice(n_modes, c);
   return POLYPIC_OK;
 }
 
 int32_t polypic_batch_get_config(int32_t n_modes, int32_t* block, int32_t* schedule,
-                                 int32_t* per_cu) {
+                                 int32_t* per_cu, int32_t* brick) {
   if (!valid_modes(n_modes)) return POLYPIC_EINVAL;
   const BatchChoice c = get_bchoice(n_modes);
   if (block) *block = c.block;
   if (schedule) *schedule = c.sched;
   if (per_cu) *per_cu = c.per_cu;
+  if (brick) *brick = c.brick;
   return POLYPIC_OK;
 }
 
@@ -1442,7 +1458,7 @@ int32_t polypic_batch_autotune(const polypic_batch* batch, int32_t n_modes, cons
                                const float* mass, float uniform_mass, const float* coeff,
                                const int32_t* perm, float* grid_mass, float* grid_mom,
                                int32_t* block_out, int32_t* schedule_out, int32_t* per_cu_out,
-                               void* stream) {
+                               int32_t* brick_out, void* stream) {
   int32_t st = check_batch(batch);
   if (st) return st;
   if (!valid_modes(n_modes)) return POLYPIC_EINVAL;
@@ -1451,13 +1467,15 @@ int32_t polypic_batch_autotune(const polypic_batch* batch, int32_t n_modes, cons
   if (!mass && !isfinite(uniform_mass)) return POLYPIC_EINVAL;
   std::vector<BatchChoice> cand;
   for (int block : {256, 512}) {
-    for (int sched : {POLYPIC_SCHED_LINEAR, POLYPIC_SCHED_XCD}) {
-      BatchChoice c;
-      c.block = block;
-      c.sched = sched;
-      cand.push_back(c);
-    }
-    for (int per_cu : {2, 4, 8}) {
+    for (int brick : {4, 2, 8})
+      for (int sched : {POLYPIC_SCHED_LINEAR, POLYPIC_SCHED_XCD}) {
+        BatchChoice c;
+        c.block = block;
+        c.sched = sched;
+        c.brick = brick;
+        cand.push_back(c);
+      }
+    for (int per_cu : {2, 4, 8}) {  // (4^3 bricks)
       BatchChoice c;
       c.block = block;
       c.sched = POLYPIC_SCHED_PERSISTENT;
@@ -1480,6 +1498,7 @@ int32_t polypic_batch_autotune(const polypic_batch* batch, int32_t n_modes, cons
   if (block_out) *block_out = cand[bi].block;
   if (schedule_out) *schedule_out = cand[bi].sched;
   if (per_cu_out) *per_cu_out = cand[bi].per_cu;
+  if (brick_out) *brick_out = cand[bi].brick;
   return POLYPIC_OK;
 }
 

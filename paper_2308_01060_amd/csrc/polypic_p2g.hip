@@ -25,32 +25,56 @@
 // * Brick scatter (any order; perm from polypic_sort makes it effective).  One
 //   thread per particle, the lanes of a wavefront spread over the workgroup's
 //   chunk of the processing order so that they fall in different cells; runs
-//   of particles in the same 4^3 tile accumulate into FP64 LDS bricks with LDS
-//   double atomics, and the bricks are added to HBM with one float atomic per
-//   node and channel.  Runs beyond the LDS budget (unsorted input) add
-//   straight to HBM.
+//   of particles in the same tile (of 2^3, 4^3 or 8^3 cells, as configured)
+//   accumulate into FP64 LDS bricks with LDS double atomics, and the bricks are
+//   added to HBM with one float atomic per node and channel.  Runs beyond the
+//   LDS budget (unsorted input) add straight to HBM.
 #include "polypic_internal.hpp"
 
 namespace polypic {
 
 namespace {
 
+// Brick geometry for tiles of T = 2^TL cells per axis: (T + 2)^3 nodes stored as FP64
+// with strides (1, SY, SZ) doubles (V per channel, padding included), and K bricks per
+// workgroup, so that the bricks take 29 to 37 KB of LDS at every edge.  The 4^3 tile is
+// the one the fused kernel and the batched paths use; the autotuner may pick another.
+template <int TL>
+struct BrickGeom;
+template <>
+struct BrickGeom<1> {
+  static constexpr int T = 2, N = 4, SY = 4, SZ = 20, K = 12;
+};
+template <>
+struct BrickGeom<2> {
+  static constexpr int T = kBrickT, N = kBrickN, SY = kBrickSY, SZ = kBrickSZ, K = kBrickKMAX;
+};
+template <>
+struct BrickGeom<3> {
+  static constexpr int T = 8, N = 10, SY = 10, SZ = 104, K = 1;
+};
+
 // Occupancy is bounded by LDS to 4 waves per SIMD (about 40 KB per 256-thread
 // workgroup); the launch bound holds the registers to the 128 that allow it.
-template <int NR, int BS, class Scenes>
+template <int NR, int BS, class Scenes, int TL>
 __global__ __launch_bounds__(BS, BS == 256 ? 4 : 2) void p2g_brick_kernel(P2GArgs a, Scenes sc) {
   constexpr int NW = BS / kWave;
+  using Geo = BrickGeom<TL>;
+  constexpr int T = Geo::T, NB = Geo::N, SY = Geo::SY, SZ = Geo::SZ, K = Geo::K;
+  constexpr int V = (NB - 1) * (1 + SY + SZ) + 1;  // doubles per channel of a brick
+  constexpr int NB3 = NB * NB * NB;
+  static_assert(SY >= NB && SZ >= SY * NB, "brick strides hold a brick");
   // LDS double atomics run at about 8 cycles per wavefront instruction on
   // gfx950 when their addresses avoid bank conflicts; float ones at about 190
   // whatever the addresses.
-  __shared__ double brick[kBrickKMAX * 4 * kBrickV];  // [brick][channel][node]
-  __shared__ uint64_t tile_of[BS];  // by processing slot
-  __shared__ int seg_of[BS];        // by processing slot
-  __shared__ uint64_t seg_tile[kBrickKMAX];
+  __shared__ double brick[K * 4 * V];  // [brick][channel][node]
+  __shared__ uint64_t tile_of[BS];     // by processing slot
+  __shared__ int seg_of[BS];           // by processing slot
+  __shared__ uint64_t seg_tile[K];
   __shared__ int wave_heads[NW];
   // grid of each brick's scene (batches only; one scene folds to constants)
-  __shared__ int seg_dims[kBrickKMAX][3];
-  __shared__ int64_t seg_node_off[kBrickKMAX];
+  __shared__ int seg_dims[K][3];
+  __shared__ int64_t seg_node_off[K];
 
   const int tid = threadIdx.x;
   const int lane = tid & (kWave - 1);
@@ -63,11 +87,19 @@ __global__ __launch_bounds__(BS, BS == 256 ? 4 : 2) void p2g_brick_kernel(P2GArg
   // cells and their brick atomics do not collide.
   constexpr int LG = NR >= 8 ? 2 : 1;  // log2 G
   const int slot = (((lane >> LG) * NW + wv) << LG) | (lane & ((1 << LG) - 1));
-  static_assert(kBrickNodes <= BS, "one brick node per thread");
-  const BrickNode bn = brick_node(tid);
   const size_t Ps = (size_t)a.P;
   const int64_t n_chunks = (a.P + BS - 1) / BS;
   const ChunkRange cr = block_chunks(a.sched, n_chunks);
+  // brick node q of the workgroup's bricks (q < K * NB3): its brick, and its offset in
+  // a channel of that brick
+  auto brick_of = [](int q) { return q / NB3; };
+  auto node_lds = [](int q, int& lx, int& ly, int& lz) {
+    const int n = q % NB3;
+    lz = n / (NB * NB);
+    ly = (n / NB) % NB;
+    lx = n % NB;
+    return lx + SY * ly + SZ * lz;
+  };
 
   for (int64_t chunk = cr.begin; chunk < cr.end; ++chunk) {
     const int64_t i0 = chunk * BS;
@@ -105,10 +137,17 @@ __global__ __launch_bounds__(BS, BS == 256 ? 4 : 2) void p2g_brick_kernel(P2GArg
 #pragma unroll
       for (int r = 0; r < 27; ++r) cfa[r] = (r < NR) ? cp[(size_t)r * Ps] : 0.0f;
     }
-    tile_of[slot] = valid ? brick_tile_id(s - s0, b0, b1, b2) : kNoTile;
-    if (tid < kBrickNodes) {
+    // tile of the base node: T^3-cell tile coordinates (10 bits per axis), plus the
+    // scene relative to the chunk's first scene in the high word
+    tile_of[slot] = valid ? (((uint64_t)(uint32_t)(s - s0) << 32) |
+                             (uint64_t)((uint32_t)(b0 >> TL) | ((uint32_t)(b1 >> TL) << 10) |
+                                        ((uint32_t)(b2 >> TL) << 20)))
+                          : kNoTile;
+    for (int q = tid; q < K * NB3; q += BS) {
+      int lx, ly, lz;
+      double* const dst = brick + brick_of(q) * 4 * V + node_lds(q, lx, ly, lz);
 #pragma unroll
-      for (int k = 0; k < kBrickKMAX * 4; ++k) brick[k * kBrickV + bn.lds] = 0.0;
+      for (int ch = 0; ch < 4; ++ch) dst[ch * V] = 0.0;
     }
     __syncthreads();
 
@@ -124,7 +163,7 @@ __global__ __launch_bounds__(BS, BS == 256 ? 4 : 2) void p2g_brick_kernel(P2GArg
       for (int w = 0; w < NW; ++w) pre += (w < wv) ? wave_heads[w] : 0;
       const int sgi = pre + lanes_below(hb) + (head ? 1 : 0) - 1;
       seg_of[tid] = sgi;
-      if (head && sgi < kBrickKMAX) {
+      if (head && sgi < K) {
         seg_tile[sgi] = tt;
         if constexpr (Scenes::kMany) {
           const SceneGrid fg = sc.grid(s0 + (int)(tt >> 32));
@@ -163,23 +202,23 @@ __global__ __launch_bounds__(BS, BS == 256 ? 4 : 2) void p2g_brick_kernel(P2GArg
       const Rows Rx = p2g_rows_scaled(basis_p2g(t0), m);
       const Rows Ry = p2g_rows_scaled(basis_p2g(t1), 1.0f);
       const Rows Rz = p2g_rows_scaled(basis_p2g(t2), 1.0f);
-      const bool lds = seg < kBrickKMAX;
+      const bool lds = seg < K;
       const int nx = sg.nx, ny = sg.ny;
-      const int lbase = (b0 & 3) + kBrickSY * (b1 & 3) + kBrickSZ * (b2 & 3);
+      const int lbase = (b0 & (T - 1)) + SY * (b1 & (T - 1)) + SZ * (b2 & (T - 1));
       const int64_t gbase = sg.node_off + (int64_t)(b2 * ny + b1) * nx + b0;
-      double* const lb = brick + (lds ? max(seg, 0) : 0) * 4 * kBrickV + lbase;
+      double* const lb = brick + (lds ? max(seg, 0) : 0) * 4 * V + lbase;
       float* const gch[4] = {a.gm + gbase, a.gp0 + gbase, a.gp1 + gbase, a.gp2 + gbase};
       const int nxny = nx * ny;
       // each nodal value goes straight to its brick (or, past the LDS budget, to HBM)
       auto emitter = [&](int ch) {
-        double* const lbc = lb + ch * kBrickV;
+        double* const lbc = lb + ch * V;
         float* const gc = gch[ch];
         return [=](int jx, int jy, int jz, float v) {
           float w = pair_fold(v, pair_f);
           if constexpr (LG == 2) w = quad_fold(w, quad_f);
           if (!emit) return;
           if (lds)
-            atomicAdd(lbc + jx + kBrickSY * jy + kBrickSZ * jz, (double)w);
+            atomicAdd(lbc + jx + SY * jy + SZ * jz, (double)w);
           else
             atomicAdd(gc + jz * nxny + jy * nx + jx, w);
         };
@@ -201,32 +240,33 @@ __global__ __launch_bounds__(BS, BS == 256 ? 4 : 2) void p2g_brick_kernel(P2GArg
     }
     __syncthreads();
 
-    // flush: one global float atomic per channel per non-zero brick node, by the
-    // node's owner thread
-    const int nb = nseg < kBrickKMAX ? nseg : kBrickKMAX;
-    if (tid < kBrickNodes) {
-      for (int sb = 0; sb < nb; ++sb) {
-        const uint32_t tc = (uint32_t)seg_tile[sb];
-        int fnx = sg.nx, fny = sg.ny, fnz = sg.nz;  // one scene: constants
-        int64_t foff = sg.node_off;
-        if constexpr (Scenes::kMany) {
-          fnx = seg_dims[sb][0];
-          fny = seg_dims[sb][1];
-          fnz = seg_dims[sb][2];
-          foff = seg_node_off[sb];
-        }
-        const int gx = (int)(tc & 1023u) * kBrickT + bn.lx;
-        const int gy = (int)((tc >> 10) & 1023u) * kBrickT + bn.ly;
-        const int gz = (int)(tc >> 20) * kBrickT + bn.lz;
-        if (gx >= fnx || gy >= fny || gz >= fnz) continue;
-        const int64_t node = foff + ((int64_t)(gz * fny + gy) * fnx + gx);
-        const double* const src = brick + sb * 4 * kBrickV + bn.lds;
-        float* const dst[4] = {a.gm, a.gp0, a.gp1, a.gp2};
+    // flush: one global float atomic per channel per non-zero brick node, the bricks'
+    // nodes shared out over the threads
+    const int nb = nseg < K ? nseg : K;
+    for (int q = tid; q < nb * NB3; q += BS) {
+      const int sb = brick_of(q);
+      int lx, ly, lz;
+      const int lo = node_lds(q, lx, ly, lz);
+      const uint32_t tc = (uint32_t)seg_tile[sb];
+      int fnx = sg.nx, fny = sg.ny, fnz = sg.nz;  // one scene: constants
+      int64_t foff = sg.node_off;
+      if constexpr (Scenes::kMany) {
+        fnx = seg_dims[sb][0];
+        fny = seg_dims[sb][1];
+        fnz = seg_dims[sb][2];
+        foff = seg_node_off[sb];
+      }
+      const int gx = (int)(tc & 1023u) * T + lx;
+      const int gy = (int)((tc >> 10) & 1023u) * T + ly;
+      const int gz = (int)(tc >> 20) * T + lz;
+      if (gx >= fnx || gy >= fny || gz >= fnz) continue;
+      const int64_t node = foff + ((int64_t)(gz * fny + gy) * fnx + gx);
+      const double* const src = brick + sb * 4 * V + lo;
+      float* const dst[4] = {a.gm, a.gp0, a.gp1, a.gp2};
 #pragma unroll
-        for (int ch = 0; ch < 4; ++ch) {
-          const float v = (float)src[ch * kBrickV];
-          if (v != 0.0f) atomicAdd(dst[ch] + node, v);
-        }
+      for (int ch = 0; ch < 4; ++ch) {
+        const float v = (float)src[ch * V];
+        if (v != 0.0f) atomicAdd(dst[ch] + node, v);
       }
     }
     __syncthreads();  // the next chunk reuses tile_of, seg_tile and the bricks
@@ -446,7 +486,12 @@ hipError_t launch_cfg(const P2GArgs& a0, const Scenes& sc, const P2GConfig& c, h
     if (cap < chunks) blocks = cap;
     else a.sched = kSchedXcd;  // as many workgroups as chunks: one chunk each
   }
-  p2g_brick_kernel<NR, BS, Scenes><<<(unsigned)blocks, BS, 0, stream>>>(a, sc);
+  switch (c.tile_log2) {
+    case 1: p2g_brick_kernel<NR, BS, Scenes, 1><<<(unsigned)blocks, BS, 0, stream>>>(a, sc); break;
+    case 2: p2g_brick_kernel<NR, BS, Scenes, 2><<<(unsigned)blocks, BS, 0, stream>>>(a, sc); break;
+    case 3: p2g_brick_kernel<NR, BS, Scenes, 3><<<(unsigned)blocks, BS, 0, stream>>>(a, sc); break;
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 
@@ -483,7 +528,7 @@ hipError_t launch_cell_nr(const P2GArgs& a, int blocks, hipStream_t stream) {
 P2GConfig p2g_default_config() { return P2GConfig{2, 256, kSchedLinear, 0}; }
 
 bool p2g_config_supported(const P2GConfig& c) {
-  if (c.tile_log2 != 2 || (c.block != 256 && c.block != 512)) return false;
+  if (c.tile_log2 < 1 || c.tile_log2 > 3 || (c.block != 256 && c.block != 512)) return false;
   if (c.sched == kSchedLinear || c.sched == kSchedXcd) return true;
   return c.sched == kSchedPersistent && c.persist_per_cu >= 1 && c.persist_per_cu <= 64;
 }

@@ -146,22 +146,25 @@ def polypic_p2g(grid: polypic_grid, n_modes: int, x: torch.Tensor, coeff: torch.
 
 
 class P2GChoice(NamedTuple):
-    """A P2G launch configuration (include/polypic.h): path, workgroup size, chunk schedule."""
+    """A P2G launch configuration (include/polypic.h): path, workgroup size, chunk schedule,
+    persistent workgroups per CU, brick edge in cells."""
 
     path: int
     block: int
     schedule: int = _lib.POLYPIC_SCHED_LINEAR
     per_cu: int = 0
+    brick: int = 4
 
 
 def polypic_set_p2g_config(n_modes: int, path: int, block: int = 512,
-                           schedule: int = _lib.POLYPIC_SCHED_LINEAR, per_cu: int = 0) -> None:
+                           schedule: int = _lib.POLYPIC_SCHED_LINEAR, per_cu: int = 0,
+                           brick: int = 4) -> None:
     check(_lib.load().polypic_set_p2g_config(int(n_modes), int(path), int(block), int(schedule),
-                                             int(per_cu)), "polypic_set_p2g_config")
+                                             int(per_cu), int(brick)), "polypic_set_p2g_config")
 
 
 def polypic_get_p2g_config(n_modes: int) -> P2GChoice:
-    v = [ctypes.c_int32(0) for _ in range(4)]
+    v = [ctypes.c_int32(0) for _ in range(5)]
     check(_lib.load().polypic_get_p2g_config(int(n_modes), *[ctypes.byref(t) for t in v]),
           "polypic_get_p2g_config")
     return P2GChoice(*(int(t.value) for t in v))
@@ -176,7 +179,7 @@ def polypic_autotune_p2g(grid: polypic_grid, n_modes: int, x: torch.Tensor, coef
     """Times every P2G configuration on these inputs; returns the chosen one."""
     P = x.numel() // 3
     N = n_nodes(grid)
-    v = [ctypes.c_int32(0) for _ in range(4)]
+    v = [ctypes.c_int32(0) for _ in range(5)]
     check(_lib.load().polypic_autotune_p2g(
         ctypes.byref(grid), P, int(n_modes), _ptr(x, torch.float32, 3 * P, "x"),
         _ptr(mass, torch.float32, P, "mass"), float(uniform_mass),
@@ -736,20 +739,24 @@ def polypic_batch_grid_update_active(batch: Batch, dt: float, gravity: Sequence[
 
 
 class BatchChoice(NamedTuple):
-    """Batched P2G launch configuration: workgroup size and chunk schedule."""
+    """Batched P2G launch configuration: workgroup size, chunk schedule, persistent
+    workgroups per CU, brick edge in cells."""
 
     block: int
     schedule: int
     per_cu: int = 0
+    brick: int = 4
 
 
-def polypic_batch_set_config(n_modes: int, block: int, schedule: int, per_cu: int = 0) -> None:
+def polypic_batch_set_config(n_modes: int, block: int, schedule: int, per_cu: int = 0,
+                             brick: int = 4) -> None:
     check(_lib.load().polypic_batch_set_config(int(n_modes), int(block), int(schedule),
-                                               int(per_cu)), "polypic_batch_set_config")
+                                               int(per_cu), int(brick)),
+          "polypic_batch_set_config")
 
 
 def polypic_batch_get_config(n_modes: int) -> BatchChoice:
-    v = [ctypes.c_int32(0) for _ in range(3)]
+    v = [ctypes.c_int32(0) for _ in range(4)]
     check(_lib.load().polypic_batch_get_config(int(n_modes), *[ctypes.byref(t) for t in v]),
           "polypic_batch_get_config")
     return BatchChoice(*(int(t.value) for t in v))
@@ -760,7 +767,7 @@ def polypic_batch_autotune(batch: Batch, n_modes: int, x: torch.Tensor, coeff: t
                            mass: Optional[torch.Tensor] = None, uniform_mass: float = 1.0,
                            perm: Optional[torch.Tensor] = None) -> BatchChoice:
     P, N = batch.P, batch.N
-    v = [ctypes.c_int32(0) for _ in range(3)]
+    v = [ctypes.c_int32(0) for _ in range(4)]
     check(_lib.load().polypic_batch_autotune(
         batch.ref(), int(n_modes), _ptr(x, torch.float32, 3 * P, "x"),
         _ptr(mass, torch.float32, P, "mass"), float(uniform_mass),

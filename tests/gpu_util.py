@@ -24,9 +24,10 @@ def require_gpu():
 
 
 @contextlib.contextmanager
-def p2g_config(pp, n_modes: int, path: int, block: int = 256, schedule: int = 0, per_cu: int = 0):
+def p2g_config(pp, n_modes: int, path: int, block: int = 256, schedule: int = 0, per_cu: int = 0,
+               brick: int = 4):
     """Select a P2G configuration for the block, then restore the default."""
-    pp.polypic_set_p2g_config(n_modes, path, block, schedule, per_cu)
+    pp.polypic_set_p2g_config(n_modes, path, block, schedule, per_cu, brick)
     try:
         yield
     finally:

@@ -141,25 +141,27 @@ def test_grid_update_and_sort_reject_bad_arguments():
 
 def test_p2g_config_table_validation():
     lib = _lib.load()
-    path, block, sched, per_cu = (ctypes.c_int32(0) for _ in range(4))
-    refs = [ctypes.byref(v) for v in (path, block, sched, per_cu)]
-    assert lib.polypic_set_p2g_config(5, 0, 512, 0, 0) == 1            # bad n_modes
-    assert lib.polypic_set_p2g_config(27, 7, 512, 0, 0) == 1           # bad path
-    assert lib.polypic_set_p2g_config(27, 0, 300, 0, 0) == 1           # bad block
-    assert lib.polypic_set_p2g_config(27, 0, 256, 3, 0) == 1           # bad schedule
-    assert lib.polypic_set_p2g_config(27, 0, 256, 2, 0) == 1           # persistent needs per_cu
-    assert lib.polypic_set_p2g_config(27, 0, 256, 2, 65) == 1
+    path, block, sched, per_cu, brick = (ctypes.c_int32(0) for _ in range(5))
+    refs = [ctypes.byref(v) for v in (path, block, sched, per_cu, brick)]
+    assert lib.polypic_set_p2g_config(5, 0, 512, 0, 0, 4) == 1         # bad n_modes
+    assert lib.polypic_set_p2g_config(27, 7, 512, 0, 0, 4) == 1        # bad path
+    assert lib.polypic_set_p2g_config(27, 0, 300, 0, 0, 4) == 1        # bad block
+    assert lib.polypic_set_p2g_config(27, 0, 256, 3, 0, 4) == 1        # bad schedule
+    assert lib.polypic_set_p2g_config(27, 0, 256, 2, 0, 4) == 1        # persistent needs per_cu
+    assert lib.polypic_set_p2g_config(27, 0, 256, 2, 65, 4) == 1
+    for bad in (0, 1, 3, 16):                                           # brick edge 2, 4 or 8
+        assert lib.polypic_set_p2g_config(27, 0, 256, 0, 0, bad) == 1
     assert lib.polypic_set_p2g_config(8, _lib.POLYPIC_P2G_BRICKS, 256, _lib.POLYPIC_SCHED_XCD,
-                                      0) == 0
+                                      0, 8) == 0
     assert lib.polypic_get_p2g_config(8, *refs) == 0
-    assert (path.value, block.value, sched.value, per_cu.value) == (_lib.POLYPIC_P2G_BRICKS, 256,
-                                                                    _lib.POLYPIC_SCHED_XCD, 0)
-    assert lib.polypic_set_p2g_config(8, 0, 512, _lib.POLYPIC_SCHED_PERSISTENT, 4) == 0
+    assert (path.value, block.value, sched.value, per_cu.value, brick.value) == (
+        _lib.POLYPIC_P2G_BRICKS, 256, _lib.POLYPIC_SCHED_XCD, 0, 8)
+    assert lib.polypic_set_p2g_config(8, 0, 512, _lib.POLYPIC_SCHED_PERSISTENT, 4, 2) == 0
     assert lib.polypic_get_p2g_config(8, *refs) == 0
-    assert (sched.value, per_cu.value) == (_lib.POLYPIC_SCHED_PERSISTENT, 4)
-    assert lib.polypic_set_p2g_config(8, _lib.POLYPIC_P2G_DEFAULT, 512, 0, 0) == 0
+    assert (sched.value, per_cu.value, brick.value) == (_lib.POLYPIC_SCHED_PERSISTENT, 4, 2)
+    assert lib.polypic_set_p2g_config(8, _lib.POLYPIC_P2G_DEFAULT, 512, 0, 0, 4) == 0
     assert lib.polypic_get_p2g_config(8, *refs) == 0
-    assert path.value == _lib.POLYPIC_P2G_DEFAULT
+    assert path.value == _lib.POLYPIC_P2G_DEFAULT and brick.value == 4
     # fused G2P2G: lane group and chunk order
     lg = ctypes.c_int32(0)
     assert lib.polypic_set_g2p2g_config(5, 2, 0) == 1                   # bad n_modes
@@ -178,14 +180,15 @@ def test_p2g_config_table_validation():
     assert lib.polypic_get_g2p_schedule(ctypes.byref(sched)) == 0 and sched.value == 1
     assert lib.polypic_set_g2p_schedule(_lib.POLYPIC_SCHED_LINEAR) == 0
     # batched P2G configuration
-    assert lib.polypic_batch_set_config(27, 384, 0, 0) == 1
-    assert lib.polypic_batch_set_config(27, 256, 2, 0) == 1
+    assert lib.polypic_batch_set_config(27, 384, 0, 0, 4) == 1
+    assert lib.polypic_batch_set_config(27, 256, 2, 0, 4) == 1
+    assert lib.polypic_batch_set_config(27, 256, 0, 0, 6) == 1
     assert lib.polypic_batch_get_config(27, *refs[1:]) == 0
-    assert (block.value, sched.value) == (256, _lib.POLYPIC_SCHED_XCD)   # default
-    assert lib.polypic_batch_set_config(4, 512, _lib.POLYPIC_SCHED_PERSISTENT, 8) == 0
+    assert (block.value, sched.value, brick.value) == (256, _lib.POLYPIC_SCHED_XCD, 4)  # default
+    assert lib.polypic_batch_set_config(4, 512, _lib.POLYPIC_SCHED_PERSISTENT, 8, 2) == 0
     assert lib.polypic_batch_get_config(4, *refs[1:]) == 0
-    assert (block.value, sched.value, per_cu.value) == (512, 2, 8)
-    assert lib.polypic_batch_set_config(4, 256, _lib.POLYPIC_SCHED_XCD, 0) == 0
+    assert (block.value, sched.value, per_cu.value, brick.value) == (512, 2, 8, 2)
+    assert lib.polypic_batch_set_config(4, 256, _lib.POLYPIC_SCHED_XCD, 0, 4) == 0
 
 
 def scene(g, p_off, n, node_off):

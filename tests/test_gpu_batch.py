@@ -122,7 +122,8 @@ def test_batched_p2g_every_configuration(n_modes):
         refs.append(O.p2g(O.grid_from_spec(s.grid), s.x, s.coeff, n_modes, mass[off:off + s.P]))
         off += s.P
     bs.sort()
-    configs = [(b, sc, pc) for b in (256, 512) for sc, pc in ((0, 0), (1, 0), (2, 1), (2, 4))]
+    configs = [(b, sc, pc, e) for e in (4, 2, 8) for b in (256, 512)
+               for sc, pc in ((0, 0), (1, 0), (2, 1), (2, 4))]
     try:
         for cfg in configs:
             pp.ops.polypic_batch_set_config(n_modes, *cfg)
@@ -137,11 +138,12 @@ def test_batched_p2g_every_configuration(n_modes):
         choice = bs.autotune()
         assert (choice.block, choice.schedule, choice.per_cu) in \
             [(b, sc, pc) for b in (256, 512) for sc, pc in ((0, 0), (1, 0), (2, 2), (2, 4), (2, 8))]
+        assert choice.brick in (2, 4, 8) and (choice.schedule != 2 or choice.brick == 4)
         gm, gp = host(bs.grid_mass), host(bs.grid_mom)
         for k, (M, Q) in enumerate(refs):
             assert rel(scene_grid_arrays(bs, k, gm, gp, M.shape)[1], Q) <= TOL_NORMWISE
     finally:
-        pp.ops.polypic_batch_set_config(n_modes, 256, pp.POLYPIC_SCHED_XCD, 0)
+        pp.ops.polypic_batch_set_config(n_modes, 256, pp.POLYPIC_SCHED_XCD, 0, 4)
     assert bs.status_flags() == 0
 
 

@@ -527,26 +527,31 @@ def test_cell_path_with_sparse_and_dense_cells():
 
 @pytest.mark.parametrize("n_modes", [4, 27])
 def test_every_p2g_configuration_and_the_autotuner(n_modes):
-    """Each P2G launch configuration (cell runs; FP64 bricks with 256 or 512 threads, in
-    index order, XCD order or persistent) matches the oracle; the autotuner returns one
-    of them and leaves a valid result."""
+    """Each P2G launch configuration (cell runs; FP64 bricks of 2^3, 4^3 or 8^3 cells with
+    256 or 512 threads, in index order, XCD order or persistent) matches the oracle, in sort
+    order and in input order (runs beyond the bricks go to HBM); the autotuner returns one of
+    them and leaves a valid result."""
     pp = require_gpu()
     s = W.config0(4)
     pp_, g, ps = particle_set(s, n_modes)
     ps.sort()
     M_ref, Q_ref = O.p2g(oracle_grid(g), s.x, s.coeff, n_modes)
     try:
-        configs = [(1, 512, 0, 0)] + [(0, b, sc, pc) for b in (256, 512)
-                                      for sc, pc in ((0, 0), (1, 0), (2, 1), (2, 4))]
+        configs = [(1, 512, 0, 0, 4)] + [(0, b, sc, pc, e) for e in (4, 2, 8) for b in (256, 512)
+                                         for sc, pc in ((0, 0), (1, 0), (2, 1), (2, 4))]
         for cfg in configs:
             pp.polypic_set_p2g_config(n_modes, *cfg)
-            ps.p2g()
-            torch.cuda.synchronize()
-            assert rel(host(ps.grid_mass).reshape(M_ref.shape), M_ref) <= TOL_NORMWISE, cfg
-            assert rel(host(ps.grid_mom).reshape(Q_ref.shape), Q_ref) <= TOL_NORMWISE, cfg
+            for use_perm in ((True, False) if cfg[0] == 0 else (True,)):
+                ps.p2g(use_perm=use_perm)
+                torch.cuda.synchronize()
+                M = host(ps.grid_mass).reshape(M_ref.shape)
+                Q = host(ps.grid_mom).reshape(Q_ref.shape)
+                assert rel(M, M_ref) <= TOL_NORMWISE, (cfg, use_perm)
+                assert rel(Q, Q_ref) <= TOL_NORMWISE, (cfg, use_perm)
         choice = ps.autotune()
         assert (choice.path, choice.block) in [(1, 512), (0, 256), (0, 512)]
         assert choice.schedule in (pp.POLYPIC_SCHED_LINEAR, pp.POLYPIC_SCHED_XCD)
+        assert choice.brick in (2, 4, 8)
         assert pp.polypic_get_p2g_config(n_modes) == choice
         assert rel(host(ps.grid_mom).reshape(Q_ref.shape), Q_ref) <= TOL_NORMWISE
     finally:
@@ -582,7 +587,9 @@ def test_p2g_lane_groups_with_every_cell_size(n_modes):
     good = np.setdiff1d(np.arange(P), bad)
     M_ref, Q_ref = O.p2g(oracle_grid(g), x[:, good], c[:, :, good], n_modes, m[good])
     ps.sort()
-    configs = [(0, 256, 0, 0), (0, 512, 0, 0), (0, 256, 1, 0), (0, 256, 2, 2), (1, 512, 0, 0)]
+    configs = [(0, 256, 0, 0, 4), (0, 512, 0, 0, 4), (0, 256, 1, 0, 4), (0, 256, 2, 2, 4),
+               (1, 512, 0, 0, 4), (0, 256, 0, 0, 2), (0, 512, 1, 0, 2), (0, 256, 0, 0, 8),
+               (0, 512, 2, 2, 8)]
     try:
         for cfg in configs:
             pp.polypic_set_p2g_config(n_modes, *cfg)
